@@ -1,0 +1,84 @@
+"""Input generators (closed, outward, stated sizes) and the paper's embedded two-sphere mesh."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen as mg
+import oracle as O
+
+PAPER = "/root/reference/PAPER.md"
+
+
+def closed_oriented(v, t):
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    s = set(map(tuple, e.tolist()))
+    return len(s) == len(e) and all((b, a) in s for a, b in e.tolist())
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 4])
+def test_icosphere_counts_and_orientation(level):
+    v, t = mg.icosphere(level, 50.0)
+    assert t.shape[0] == 20 * 4 ** level and v.shape[0] == 10 * 4 ** level + 2
+    assert closed_oriented(v, t)
+    assert O.volume3d(v, t) > 0
+
+
+def test_q_grids_contain_origin_and_axes():
+    q = mg.q_grid_3d(64, 0.5)
+    assert q.shape == (64 ** 3, 3)
+    assert np.any(np.all(q == 0, axis=1))
+    assert np.any((q[:, 0] == 0) & (q[:, 1] == 0) & (q[:, 2] != 0))
+    assert np.isclose(q.min(), -0.5) and q.max() < 0.5
+    q2 = mg.q_grid_2d(128, 20.0)
+    assert q2.shape == (128 * 128, 2) and np.any(np.all(q2 == 0, axis=1))
+
+
+def test_star_polygon_ccw():
+    v = mg.star_polygon(seed=1, n=64)
+    assert v.shape == (64, 2) and O.area2d(v) > 0
+    r = np.linalg.norm(v, axis=1)
+    assert r.min() >= 0.5 and r.max() <= 1.0
+
+
+def test_batch_generator_small():
+    meshes = mg.batch_config(seed=5, n_meshes=6, max_faces=2000, min_q=64, max_q=256)
+    for m in meshes:
+        assert closed_oriented(m["verts"], m["tris"])
+        assert m["tris"].shape[0] >= 200
+        assert O.volume3d(m["verts"], m["tris"]) > 0
+        assert np.all(np.linalg.norm(m["q"], axis=1) <= 0.5 + 1e-12)
+
+
+def _paper_mesh():
+    if not os.path.exists(PAPER):
+        pytest.skip("paper text not available")
+    text = open(PAPER).read()
+    m = re.search(r'twospheres_surfacemesh = """\\\n(.*?)"""', text, re.S)
+    assert m, "embedded surface mesh not found"
+    return mg.read_netgen_surfacemesh(m.group(1))
+
+
+def test_paper_two_sphere_mesh_facts():
+    """The appendix mesh (union of two unit spheres at x = -0.6, 0.6): closed, outward, genus 0.
+
+    The paper prints no numeric transform values for it; its own F(0) and
+    symmetries are what can be checked (parity beyond these is unpinned).
+    """
+    v, t = _paper_mesh()
+    assert v.shape == (83, 3) and t.shape == (160, 3)
+    used = np.unique(t)
+    assert used.size == 82
+    assert closed_oriented(v, t)
+    V = O.volume3d(v, t)
+    assert 6.5 < V < 7.51   # the exact union volume is 7.5063; the coarse polygon is smaller
+    # the paper's demo grid: 40 x 40 over [-10, 10]^2 at Q_z = 0
+    ax = np.linspace(-10, 10, 40)
+    qx, qy = np.meshgrid(ax, ax, indexing="ij")
+    q = np.stack([qx.ravel(), qy.ravel(), np.zeros(qx.size)], 1)
+    F = O.ft3d(v, t, q)
+    assert np.all(np.isfinite(F))
+    assert abs(O.ft3d(v, t, np.zeros((1, 3)))[0] - V) < 1e-13 * V
+    # the grid is symmetric under Q -> -Q: Hermitian symmetry pairs it with itself reversed
+    assert np.max(np.abs(F[::-1] - np.conj(F))) < 1e-12 * np.max(np.abs(F))
