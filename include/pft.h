@@ -1,0 +1,204 @@
+/*
+ * pft.h -- C ABI of libpft: direct Fourier transform of polygonal areas and
+ * closed triangulated volumes on AMD Instinct MI355X (gfx950).
+ *
+ * Method: B. B. Maranville, "An implementation of an efficient direct Fourier
+ * transform of polygonal areas and volumes". The transform is
+ *
+ *     F(Q) = integral over the region of exp(+i Q.r) dA   (2D polygon)
+ *     F(Q) = integral over the region of exp(+i Q.r) dV   (3D closed mesh)
+ *
+ * (paper: definition of FT_V and the 2D area integral). The divergence theorem
+ * turns it into sums over polygon edges (2D section, eq. line_integral_generic
+ * and its midpoint form) and, in 3D, into sums over faces of in-plane edge
+ * sums (3D section, eq. single_area_integral and eq. sum_elements_3d). No
+ * normalisation: F(0) is the area / volume. Q is in reciprocal units of the
+ * vertex coordinates.
+ *
+ * Common conventions for every entry point:
+ *  - Array arguments are DEVICE pointers owned by the caller, contiguous,
+ *    row-major, unless the argument is documented as a HOST pointer. The
+ *    library never allocates or frees caller memory.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *    legacy default stream) and is asynchronous; outputs are valid once the
+ *    stream has reached that point. Temporary device memory is taken from the
+ *    stream-ordered allocator on the same stream and released in stream order.
+ *  - Return value: PFT_OK after synchronous argument validation and a
+ *    successful launch, or an error code; the message is available from
+ *    pft_last_error() on the calling thread. Device-side faults surface at the
+ *    caller's next synchronisation, as for any HIP work.
+ *  - Counts of zero are valid: nq == 0 does nothing; nf == 0 (empty mesh)
+ *    writes zeros.
+ *  - Complex outputs are interleaved (re, im) pairs.
+ *  - NaN / Inf in inputs propagate to the affected outputs.
+ *  - Triangle indices outside [0, nv) never cause an out-of-bounds access: the
+ *    face is treated as empty (contributes zero) and counted; use
+ *    pft_validate_mesh to check a mesh.
+ *  - Results do not depend on the order of faces in the list except through
+ *    floating-point rounding, and are bitwise reproducible for fixed inputs
+ *    and sizes (fixed reduction order, no floating-point atomics).
+ */
+#ifndef PFT_H
+#define PFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PFT_OK = 0,
+  PFT_EINVAL = -1,        /* invalid argument (null pointer, negative count, misalignment, bad offsets) */
+  PFT_EUNSUPPORTED = -2,  /* unsupported mode / dtype combination */
+  PFT_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+  PFT_ENOMEM = -4         /* stream-ordered temporary allocation failed */
+} pft_status;
+
+/* Arithmetic of the transform.
+ * PFT_FP64  : every step in IEEE binary64; complex128 outputs.
+ * PFT_FP32C : "FP32-compensated": the mesh is re-centred on its vertex mean and
+ *             each face on its centroid in binary64; the per-(Q, face) edge
+ *             arithmetic then runs in binary32 on small local coordinates,
+ *             with the face's origin phase Q.g and the mesh phase Q.t taken in
+ *             binary64, the near-degenerate branches (Q nearly along a face
+ *             normal, |Q| R small) evaluated in binary64, and the sum over
+ *             faces accumulated with compensation; complex64 outputs. */
+typedef enum { PFT_FP64 = 0, PFT_FP32C = 1 } pft_mode;
+
+/* Real element type of an input array. */
+typedef enum { PFT_F32 = 0, PFT_F64 = 1 } pft_dtype;
+
+/*
+ * pft_forward_2d -- F(Q) of a polygon with one or more closed contours
+ * (2D section: divergence theorem with the field -iQ exp(iQ.r)/Q^2, edge normal
+ * eq. line_normal, edge integral eq. line_integral_generic in its midpoint /
+ * sinc form). FP64 only.
+ *
+ *  verts            [nv][2] float64, contour vertices in traversal order.
+ *  contour_offsets  HOST int64 [ncontours + 1], non-decreasing, first 0, last nv;
+ *                   contour c is verts[offsets[c] .. offsets[c+1]). NULL means a
+ *                   single contour of all nv vertices (ncontours is ignored).
+ *                   Counter-clockwise contours add, clockwise ones subtract
+ *                   (holes). A contour with fewer than 3 vertices encloses no area.
+ *  q                [nq][2] float64.
+ *  out              [nq] complex128 (interleaved float64 pairs), overwritten.
+ * Errors: EINVAL for null pointers with non-zero counts, negative counts,
+ * misaligned pointers (8 B), or offsets that are not non-decreasing from 0 to nv.
+ */
+pft_status pft_forward_2d(const double* verts, int64_t nv, const int64_t* contour_offsets, int64_t ncontours,
+                          const double* q, int64_t nq, double* out, void* stream);
+
+/*
+ * pft_forward_3d -- F(Q) of the volume enclosed by a closed triangle mesh
+ * (3D section: eq. divergence3d split over faces, eq. single_area_integral,
+ * eq. sum_elements_3d with the outward in-plane edge normal, edge sums in the
+ * midpoint / sinc form).
+ *
+ *  verts    [nv][3] of vdtype. tris [nf][3] int32, 0-based, each triangle
+ *           counter-clockwise seen from outside (outward normal by the
+ *           right-hand rule). The mesh must be closed (every edge shared by two
+ *           faces with opposite directions); an inward mesh gives -F, an open
+ *           mesh gives an origin-dependent value. Zero-area faces contribute 0.
+ *  q        [nq][3] of qdtype.
+ *  mode     PFT_FP64 : out is [nq] complex128, intensity (optional) [nq] float64.
+ *           PFT_FP32C: out is [nq] complex64,  intensity (optional) [nq] float32.
+ *  out      overwritten. intensity: NULL or |F(Q)|^2, overwritten.
+ * Errors: EINVAL (null pointers with non-zero counts, negative counts,
+ * misalignment to the element size), EUNSUPPORTED (unknown mode / dtype).
+ */
+pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                          const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* intensity,
+                          void* stream);
+
+/*
+ * pft_backward_3d -- adjoint of pft_forward_3d with respect to the vertices.
+ * The paper gives the forward transform only; the derivative follows from the
+ * same volume integral: moving the boundary with velocity field u changes F by
+ * the surface integral of exp(iQ.r) (u . n) dA, and a vertex moves the points
+ * of its incident faces with their barycentric (hat) weight, so
+ *     dF(Q)/dv_k = sum over faces m containing k of n_m * integral over m of lambda_k exp(iQ.r) dA.
+ *
+ *  Mesh and q arguments as in pft_forward_3d.
+ *  grad_out    [nq] complex, dL/dRe F(Q) + i dL/dIm F(Q) for a real loss L
+ *              (complex128 in PFT_FP64 mode, complex64 in PFT_FP32C mode).
+ *  grad_verts  [nv][3] of vdtype, OVERWRITTEN with
+ *              dL/dv_k = sum_Q Re(conj(grad_out(Q)) dF(Q)/dv_k).
+ * Errors: as pft_forward_3d.
+ */
+pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                           const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
+                           void* grad_verts, void* stream);
+
+/*
+ * A batch of independent closed meshes, each with its own Q list, stored as
+ * concatenations. Offsets are HOST int64 arrays of length n_meshes + 1,
+ * non-decreasing from 0; mesh i owns verts[vert_offsets[i] .. vert_offsets[i+1]),
+ * tris[tri_offsets[i] .. tri_offsets[i+1]) with indices LOCAL to mesh i, and
+ * q[q_offsets[i] .. q_offsets[i+1]). Outputs follow q_offsets (forward) and
+ * vert_offsets (backward).
+ */
+typedef struct {
+  int64_t n_meshes;
+  const int64_t* vert_offsets; /* HOST [n_meshes + 1] */
+  const int64_t* tri_offsets;  /* HOST [n_meshes + 1] */
+  const int64_t* q_offsets;    /* HOST [n_meshes + 1] */
+  const void* verts;           /* DEVICE [total_nv][3] of vdtype */
+  pft_dtype vdtype;
+  const int32_t* tris;         /* DEVICE [total_nf][3], local indices */
+  const void* q;               /* DEVICE [total_nq][3] of qdtype */
+  pft_dtype qdtype;
+} pft_mesh_batch;
+
+/*
+ * pft_batch_forward -- pft_forward_3d for every mesh of a batch in one
+ * persistent launch: (mesh, Q-tile, face-chunk) work items ordered by cost,
+ * pulled from a device work counter by a grid sized to the GPU.
+ *  out        [total_nq] complex (complex128 for PFT_FP64, complex64 for PFT_FP32C).
+ *  intensity  NULL or [total_nq] |F|^2 (float64 / float32).
+ * Errors: as pft_forward_3d, plus EINVAL for offsets that are not non-decreasing from 0.
+ */
+pft_status pft_batch_forward(const pft_mesh_batch* batch, pft_mode mode, void* out, void* intensity, void* stream);
+
+/*
+ * pft_batch_backward -- pft_backward_3d for every mesh of a batch.
+ *  grad_out    [total_nq] complex (complex128 / complex64 by mode).
+ *  grad_verts  [total_nv][3] of vdtype, overwritten.
+ */
+pft_status pft_batch_backward(const pft_mesh_batch* batch, pft_mode mode, const void* grad_out, void* grad_verts,
+                              void* stream);
+
+/*
+ * pft_validate_mesh -- count triangle indices outside [0, nv) and faces with a
+ * repeated vertex. Synchronous: blocks until the check has run on `stream`.
+ * Both outputs are HOST pointers (either may be NULL).
+ */
+pft_status pft_validate_mesh(const int32_t* tris, int64_t nf, int64_t nv, int64_t* n_bad_index,
+                             int64_t* n_repeated_vertex, void* stream);
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char* pft_last_error(void);
+
+/* Return cached stream-ordered temporary memory of the current device to the system. */
+pft_status pft_release_workspace(void);
+
+/*
+ * Kernel timing, for measurement. When enabled, each entry point records HIP
+ * events on its stream around its main compute kernel(s); pft_profile_read
+ * synchronises on the recorded events and returns, for the kernel family
+ * `name` ("fwd3d_fp32c", "fwd3d_fp64", "bwd3d_fp32c", "bwd3d_fp64", "fwd2d_fp64",
+ * "batch_fwd", "batch_bwd"), the number of launches and their summed
+ * duration in milliseconds since the last reset. HOST pointers.
+ */
+pft_status pft_profile_enable(int enable);
+pft_status pft_profile_reset(void);
+pft_status pft_profile_read(const char* name, int64_t* launches, double* total_ms);
+
+/* Library version string. */
+const char* pft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFT_H */

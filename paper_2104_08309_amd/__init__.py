@@ -1,0 +1,15 @@
+"""Direct Fourier transform of polygonal areas and closed triangulated volumes on MI355X.
+
+The transform F(Q) = integral of exp(iQ.r) over the region is evaluated by the
+divergence theorem as sums over polygon edges and mesh faces (Maranville,
+"An implementation of an efficient direct Fourier transform of polygonal
+areas and volumes"), in hand-written HIP kernels for gfx950 behind the C ABI
+declared in include/pft.h. This package is the thin Python binding.
+"""
+from .api import (  # noqa: F401
+    forward_2d, forward_3d, backward_3d, batch_forward, batch_backward, validate_mesh,
+    profile_enable, profile_reset, profile_read, release_workspace, version,
+)
+from .autograd import PftFunction, ft3d, intensity_loss  # noqa: F401
+
+__version__ = "0.1.0"

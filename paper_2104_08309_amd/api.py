@@ -1,0 +1,225 @@
+"""PyTorch-facing wrappers over the libpft C ABI.
+
+Argument marshalling only: tensors are checked (device, dtype, shape,
+contiguity), outputs are allocated with torch, and raw device pointers plus
+the current HIP stream are handed to the library. All arithmetic runs in the
+library's HIP kernels; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
+
+__all__ = [
+    "forward_2d", "forward_3d", "backward_3d", "batch_forward", "batch_backward", "validate_mesh",
+    "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
+]
+
+_MODES = {"fp64": PFT_FP64, "fp32c": PFT_FP32C}
+
+
+def mode_id(mode: str) -> int:
+    try:
+        return _MODES[mode.lower()]
+    except (KeyError, AttributeError):
+        raise ValueError(f"mode must be one of {sorted(_MODES)}, got {mode!r}") from None
+
+
+def _real_dtype_id(t: torch.Tensor, name: str) -> int:
+    if t.dtype == torch.float32:
+        return PFT_F32
+    if t.dtype == torch.float64:
+        return PFT_F64
+    raise TypeError(f"{name} must be float32 or float64, got {t.dtype}")
+
+
+def _on_gpu(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU (HIP) tensor; libpft has no CPU path")
+    return t.contiguous()
+
+
+def _stream(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None or t.numel() == 0 else t.data_ptr()
+
+
+def _mesh(verts: torch.Tensor, tris: torch.Tensor):
+    verts = _on_gpu(verts, "verts")
+    tris = _on_gpu(tris, "tris")
+    if verts.dim() != 2 or verts.shape[1] != 3:
+        raise ValueError(f"verts must have shape [nv, 3], got {tuple(verts.shape)}")
+    if tris.dim() != 2 or tris.shape[1] != 3:
+        raise ValueError(f"tris must have shape [nf, 3], got {tuple(tris.shape)}")
+    if tris.dtype != torch.int32:
+        if tris.dtype not in (torch.int64, torch.int16, torch.uint8):
+            raise TypeError(f"tris must be an integer tensor, got {tris.dtype}")
+        tris = tris.to(torch.int32)
+    if tris.device != verts.device:
+        raise ValueError("verts and tris must be on the same device")
+    return verts, tris
+
+
+def _qlist(q: torch.Tensor, device, dim: int = 3) -> torch.Tensor:
+    q = _on_gpu(q, "q")
+    if q.dim() != 2 or q.shape[1] != dim:
+        raise ValueError(f"q must have shape [nq, {dim}], got {tuple(q.shape)}")
+    if q.device != device:
+        raise ValueError("q must be on the same device as the mesh")
+    return q
+
+
+def forward_2d(verts: torch.Tensor, q: torch.Tensor, contour_offsets: Optional[Sequence[int]] = None) -> torch.Tensor:
+    """F(Q) of a polygon (complex128 [nq]); ``contour_offsets`` splits verts into closed contours."""
+    verts = _on_gpu(verts, "verts")
+    if verts.dim() != 2 or verts.shape[1] != 2 or verts.dtype != torch.float64:
+        raise ValueError("verts must be float64 with shape [nv, 2]")
+    q = _qlist(q, verts.device, dim=2)
+    if q.dtype != torch.float64:
+        raise ValueError("q must be float64 for the 2D transform")
+    out = torch.empty(q.shape[0], dtype=torch.complex128, device=verts.device)
+    if contour_offsets is None:
+        off_p, nc = None, 0
+    else:
+        off = np.ascontiguousarray(np.asarray(contour_offsets, dtype=np.int64))
+        nc = off.size - 1
+        off_p = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_forward_2d(_ptr(verts), verts.shape[0], off_p, nc, _ptr(q), q.shape[0], _ptr(out),
+                                         _stream(verts.device)))
+    return out
+
+
+def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: str = "fp32c",
+               intensity: bool = False):
+    """F(Q) of the closed mesh; complex128 for mode 'fp64', complex64 for 'fp32c'.
+
+    Returns F, or (F, |F|^2) when ``intensity`` is True.
+    """
+    verts, tris = _mesh(verts, tris)
+    q = _qlist(q, verts.device)
+    m = mode_id(mode)
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    rdt = torch.float64 if m == PFT_FP64 else torch.float32
+    out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
+    inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_forward_3d(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris),
+                                         tris.shape[0], _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out),
+                                         _ptr(inten), _stream(verts.device)))
+    return (out, inten) if intensity else out
+
+
+def backward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, grad_out: torch.Tensor,
+                mode: str = "fp32c") -> torch.Tensor:
+    """dL/dverts for grad_out = dL/dReF + i dL/dImF; same dtype and shape as verts."""
+    verts, tris = _mesh(verts, tris)
+    q = _qlist(q, verts.device)
+    m = mode_id(mode)
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    g = _on_gpu(grad_out, "grad_out").reshape(-1)
+    if g.shape[0] != q.shape[0]:
+        raise ValueError("grad_out must have one entry per Q")
+    g = g.to(cdt).contiguous()
+    grad = torch.empty_like(verts)
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_backward_3d(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris),
+                                          tris.shape[0], _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(g),
+                                          _ptr(grad), _stream(verts.device)))
+    return grad
+
+
+def _batch_struct(verts, tris, q, vert_offsets, tri_offsets, q_offsets):
+    verts, tris = _mesh(verts, tris)
+    q = _qlist(q, verts.device)
+    offs = [np.ascontiguousarray(np.asarray(o, dtype=np.int64)) for o in (vert_offsets, tri_offsets, q_offsets)]
+    n = offs[0].size - 1
+    if any(o.size != n + 1 for o in offs):
+        raise ValueError("offset arrays must all have n_meshes + 1 entries")
+    if offs[0][-1] != verts.shape[0] or offs[1][-1] != tris.shape[0] or offs[2][-1] != q.shape[0]:
+        raise ValueError("offsets must end at the concatenated sizes")
+    b = PftMeshBatch()
+    b.n_meshes = n
+    b.vert_offsets = offs[0].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    b.tri_offsets = offs[1].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    b.q_offsets = offs[2].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    b.verts = _ptr(verts)
+    b.vdtype = _real_dtype_id(verts, "verts")
+    b.tris = _ptr(tris)
+    b.q = _ptr(q)
+    b.qdtype = _real_dtype_id(q, "q")
+    return b, offs, verts, tris, q
+
+
+def batch_forward(verts, tris, q, vert_offsets, tri_offsets, q_offsets, mode: str = "fp32c",
+                  intensity: bool = False):
+    """Transform of every mesh of a concatenated batch (indices local to each mesh)."""
+    b, offs, verts, tris, q = _batch_struct(verts, tris, q, vert_offsets, tri_offsets, q_offsets)
+    m = mode_id(mode)
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    rdt = torch.float64 if m == PFT_FP64 else torch.float32
+    out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
+    inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_batch_forward(ctypes.byref(b), m, _ptr(out), _ptr(inten), _stream(verts.device)))
+    del offs  # host offsets are read synchronously by the call
+    return (out, inten) if intensity else out
+
+
+def batch_backward(verts, tris, q, vert_offsets, tri_offsets, q_offsets, grad_out, mode: str = "fp32c"):
+    """dL/dverts of every mesh of a batch; [total_nv, 3] like verts."""
+    b, offs, verts, tris, q = _batch_struct(verts, tris, q, vert_offsets, tri_offsets, q_offsets)
+    m = mode_id(mode)
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    g = _on_gpu(grad_out, "grad_out").reshape(-1).to(cdt).contiguous()
+    if g.shape[0] != q.shape[0]:
+        raise ValueError("grad_out must have one entry per Q")
+    grad = torch.empty_like(verts)
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_batch_backward(ctypes.byref(b), m, _ptr(g), _ptr(grad), _stream(verts.device)))
+    del offs
+    return grad
+
+
+def validate_mesh(tris: torch.Tensor, nv: int) -> Tuple[int, int]:
+    """(number of out-of-range indices, number of faces with a repeated vertex)."""
+    tris = _on_gpu(tris, "tris").to(torch.int32)
+    bad, rep = ctypes.c_int64(0), ctypes.c_int64(0)
+    with torch.cuda.device(tris.device):
+        check(_lib.load().pft_validate_mesh(_ptr(tris), tris.shape[0], int(nv), ctypes.byref(bad), ctypes.byref(rep),
+                                            _stream(tris.device)))
+    return int(bad.value), int(rep.value)
+
+
+def profile_enable(on: bool = True) -> None:
+    check(_lib.load().pft_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    check(_lib.load().pft_profile_reset())
+
+
+def profile_read(name: str) -> Tuple[int, float]:
+    """(launches, total milliseconds) of a kernel family since the last reset."""
+    n, ms = ctypes.c_int64(0), ctypes.c_double(0.0)
+    check(_lib.load().pft_profile_read(name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
+
+
+def release_workspace() -> None:
+    check(_lib.load().pft_release_workspace())
+
+
+def version() -> str:
+    return _lib.load().pft_version().decode()

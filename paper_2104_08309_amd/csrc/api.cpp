@@ -1,0 +1,695 @@
+// C ABI of libpft: argument validation, temporary memory, launch sequencing.
+//
+// Every entry point validates its arguments synchronously, takes temporary
+// device memory from the stream-ordered allocator on the caller's stream,
+// enqueues the prologue / compute / finish kernels on that stream and returns.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pft_internal.h"
+
+using namespace pft;
+
+namespace {
+
+thread_local std::string g_err;
+
+pft_status fail(pft_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+pft_status hip_fail(hipError_t e, const char* what) {
+  return fail(PFT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+size_t real_size(int dt) { return dt == PFT_F64 ? 8 : 4; }
+
+// ---------------------------------------------------------------------------
+// stream-ordered temporaries
+// ---------------------------------------------------------------------------
+std::mutex g_pool_mu;
+std::vector<int> g_pool_ready;
+
+void ensure_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (std::find(g_pool_ready.begin(), g_pool_ready.end(), dev) != g_pool_ready.end()) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;  // keep freed blocks cached across calls
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  g_pool_ready.push_back(dev);
+}
+
+struct Arena {
+  explicit Arena(hipStream_t s) : s_(s) {}
+  ~Arena() {
+    for (void* p : ptrs_) (void)hipFreeAsync(p, s_);
+  }
+  template <typename T>
+  T* get(size_t count) {
+    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    void* p = nullptr;
+    if (hipMallocAsync(&p, bytes, s_) != hipSuccess || p == nullptr) {
+      failed = true;
+      return nullptr;
+    }
+    ptrs_.push_back(p);
+    return static_cast<T*>(p);
+  }
+  bool failed = false;
+
+ private:
+  hipStream_t s_;
+  std::vector<void*> ptrs_;
+};
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+struct ProfRec {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> done;
+  hipEvent_t open = nullptr;
+  int64_t launches = 0;
+  double total_ms = 0.0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, ProfRec> g_prof;
+
+// ---------------------------------------------------------------------------
+// heuristics
+// ---------------------------------------------------------------------------
+constexpr int64_t kTargetBlocks = 2048;   // >= 8 blocks of 256 threads per CU on 256 CUs
+constexpr int64_t kMinFacesPerSplit = 512;
+constexpr int64_t kBatchChunkF = 4096;    // faces per batched forward item
+constexpr int64_t kBatchChunkQ = 65536;   // Q per batched adjoint item
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+void choose_face_splits(int64_t nq, int64_t nf, int qpt, int* splits, int64_t* per) {
+  if (nf <= 0) {
+    *splits = 1;
+    *per = 0;
+    return;
+  }
+  const int64_t qblocks = cdiv(nq, (int64_t)kBlock * qpt);
+  int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, qblocks), cdiv(nf, kMinFacesPerSplit)));
+  int64_t p = cdiv(cdiv(nf, s), kTileF) * kTileF;
+  *per = p;
+  *splits = (int)cdiv(nf, p);
+}
+
+void choose_q_splits(int64_t nq, int64_t nf, int* splits, int64_t* per) {
+  const int64_t fblocks = std::max<int64_t>(1, cdiv(nf, kTileFB));
+  int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, fblocks), std::max<int64_t>(1, cdiv(nq, kBlock))));
+  const int64_t p = std::max<int64_t>(1, cdiv(nq, s));
+  *per = p;
+  *splits = (int)std::max<int64_t>(1, cdiv(nq, p));
+}
+
+int num_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+pft_status check_mesh_args(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                           const void* q, int qdtype, int64_t nq, int mode) {
+  if (mode != PFT_FP64 && mode != PFT_FP32C) return fail(PFT_EUNSUPPORTED, "unknown mode");
+  if (vdtype != PFT_F32 && vdtype != PFT_F64) return fail(PFT_EUNSUPPORTED, "unknown vertex dtype");
+  if (qdtype != PFT_F32 && qdtype != PFT_F64) return fail(PFT_EUNSUPPORTED, "unknown q dtype");
+  if (nv < 0 || nf < 0 || nq < 0) return fail(PFT_EINVAL, "negative count");
+  if (nv > INT32_MAX || nf > INT32_MAX / 3) return fail(PFT_EINVAL, "mesh too large for 32-bit indices");
+  if (nv > 0 && verts == nullptr) return fail(PFT_EINVAL, "verts is NULL");
+  if (nf > 0 && tris == nullptr) return fail(PFT_EINVAL, "tris is NULL");
+  if (nq > 0 && q == nullptr) return fail(PFT_EINVAL, "q is NULL");
+  if (verts && !aligned(verts, real_size(vdtype))) return fail(PFT_EINVAL, "verts misaligned");
+  if (tris && !aligned(tris, 4)) return fail(PFT_EINVAL, "tris misaligned");
+  if (q && !aligned(q, real_size(qdtype))) return fail(PFT_EINVAL, "q misaligned");
+  return PFT_OK;
+}
+
+pft_status check_offsets(const int64_t* off, int64_t n, const char* name) {
+  if (off == nullptr) return fail(PFT_EINVAL, std::string(name) + " is NULL");
+  if (off[0] != 0) return fail(PFT_EINVAL, std::string(name) + "[0] must be 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (off[i + 1] < off[i]) return fail(PFT_EINVAL, std::string(name) + " must be non-decreasing");
+  return PFT_OK;
+}
+
+hipError_t zero_bytes(void* p, size_t bytes, hipStream_t s) {
+  // all outputs are multiples of 4 bytes
+  return launch_zero_u32(static_cast<uint32_t*>(p), (int64_t)(bytes / 4), s);
+}
+
+const char* main_name(bool fwd, int mode) {
+  if (fwd) return mode == PFT_FP64 ? "fwd3d_fp64" : "fwd3d_fp32c";
+  return mode == PFT_FP64 ? "bwd3d_fp64" : "bwd3d_fp32c";
+}
+
+// Shared tail of the adjoint: per-corner vectors -> sorted incidence -> vertex gather.
+pft_status gather_tail(Arena& ar, const int32_t* tris, int64_t nf, const int64_t* d_vert_off,
+                       const int32_t* d_face_mesh, int64_t nv_total, const double* contrib, void* grad, int vdtype,
+                       hipStream_t s) {
+  const int64_t ns = nf * 3;
+  uint32_t* keys = ar.get<uint32_t>(ns);
+  uint32_t* vals = ar.get<uint32_t>(ns);
+  uint32_t* keys_s = ar.get<uint32_t>(ns);
+  uint32_t* vals_s = ar.get<uint32_t>(ns);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_incidence_keys(tris, nf, d_vert_off, d_face_mesh, nv_total, keys, vals, s);
+  if (e != hipSuccess) return hip_fail(e, "incidence keys");
+  size_t tb = 0;
+  e = sort_incidence(keys, vals, keys_s, vals_s, ns, nv_total, nullptr, &tb, s);
+  if (e != hipSuccess) return hip_fail(e, "sort size query");
+  void* temp = ar.get<unsigned char>(tb);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  e = sort_incidence(keys, vals, keys_s, vals_s, ns, nv_total, temp, &tb, s);
+  if (e != hipSuccess) return hip_fail(e, "incidence sort");
+  e = launch_gather_vertices(keys_s, vals_s, ns, contrib, nv_total, grad, vdtype, s);
+  if (e != hipSuccess) return hip_fail(e, "vertex gather");
+  return PFT_OK;
+}
+
+}  // namespace
+
+namespace pft {
+
+void prof_begin(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  ProfRec& r = g_prof[name];
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, s);
+  r.open = e;
+}
+
+void prof_end(const char* name, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_on) return;
+  ProfRec& r = g_prof[name];
+  if (!r.open) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, s);
+  r.done.emplace_back(r.open, e);
+  r.open = nullptr;
+}
+
+}  // namespace pft
+
+extern "C" {
+
+const char* pft_version(void) { return "pft 0.1.0 (gfx950)"; }
+
+const char* pft_last_error(void) { return g_err.c_str(); }
+
+pft_status pft_release_workspace(void) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipMemPool_t pool;
+  e = hipDeviceGetDefaultMemPool(&pool, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetDefaultMemPool");
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  e = hipMemPoolTrimTo(pool, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipMemPoolTrimTo");
+  return PFT_OK;
+}
+
+pft_status pft_profile_enable(int enable) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = enable != 0;
+  return PFT_OK;
+}
+
+pft_status pft_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& kv : g_prof) {
+    for (auto& pr : kv.second.done) {
+      (void)hipEventSynchronize(pr.second);
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    if (kv.second.open) (void)hipEventDestroy(kv.second.open);
+  }
+  g_prof.clear();
+  return PFT_OK;
+}
+
+pft_status pft_profile_read(const char* name, int64_t* launches, double* total_ms) {
+  if (!name) return fail(PFT_EINVAL, "name is NULL");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  auto it = g_prof.find(name);
+  int64_t n = 0;
+  double ms = 0.0;
+  if (it != g_prof.end()) {
+    ProfRec& r = it->second;
+    for (auto& pr : r.done) {
+      hipError_t e = hipEventSynchronize(pr.second);
+      if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, pr.first, pr.second);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      r.total_ms += t;
+      r.launches += 1;
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    r.done.clear();
+    n = r.launches;
+    ms = r.total_ms;
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
+  return PFT_OK;
+}
+
+pft_status pft_validate_mesh(const int32_t* tris, int64_t nf, int64_t nv, int64_t* n_bad_index,
+                             int64_t* n_repeated_vertex, void* stream) {
+  if (nf < 0 || nv < 0) return fail(PFT_EINVAL, "negative count");
+  if (nf > 0 && tris == nullptr) return fail(PFT_EINVAL, "tris is NULL");
+  if (tris && !aligned(tris, 4)) return fail(PFT_EINVAL, "tris misaligned");
+  int64_t bad = 0, rep = 0;
+  if (nf > 0) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ensure_pool();
+    unsigned long long host[2] = {0, 0};
+    {
+      Arena ar(s);
+      unsigned long long* d = ar.get<unsigned long long>(2);
+      if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+      hipError_t e = launch_zero_u32(reinterpret_cast<uint32_t*>(d), 4, s);
+      if (e == hipSuccess) e = launch_validate(tris, nf, nv, d, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(host, d, sizeof(host), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return hip_fail(e, "validate");
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    bad = (int64_t)host[0];
+    rep = (int64_t)host[1];
+  }
+  if (n_bad_index) *n_bad_index = bad;
+  if (n_repeated_vertex) *n_repeated_vertex = rep;
+  return PFT_OK;
+}
+
+pft_status pft_forward_2d(const double* verts, int64_t nv, const int64_t* contour_offsets, int64_t ncontours,
+                          const double* q, int64_t nq, double* out, void* stream) {
+  if (nv < 0 || nq < 0) return fail(PFT_EINVAL, "negative count");
+  if (nv > 0 && verts == nullptr) return fail(PFT_EINVAL, "verts is NULL");
+  if (nq > 0 && (q == nullptr || out == nullptr)) return fail(PFT_EINVAL, "q or out is NULL");
+  if ((verts && !aligned(verts, 8)) || (q && !aligned(q, 8)) || (out && !aligned(out, 8)))
+    return fail(PFT_EINVAL, "pointer misaligned (8 bytes required)");
+  if (contour_offsets) {
+    if (ncontours < 0) return fail(PFT_EINVAL, "negative contour count");
+    pft_status st = check_offsets(contour_offsets, ncontours, "contour_offsets");
+    if (st != PFT_OK) return st;
+    if (contour_offsets[ncontours] != nv) return fail(PFT_EINVAL, "contour_offsets must end at nv");
+  }
+  if (nq == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  Arena ar(s);
+  MeshInfo* info = ar.get<MeshInfo>(1);
+  Edge2D* edges = ar.get<Edge2D>(std::max<int64_t>(nv, 1));
+  int64_t* d_off = nullptr;
+  if (contour_offsets) d_off = ar.get<int64_t>(ncontours + 1);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = hipSuccess;
+  if (d_off)
+    e = hipMemcpyAsync(d_off, contour_offsets, sizeof(int64_t) * (ncontours + 1), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "offsets upload");
+  e = launch_edges2d(verts, nv, d_off, ncontours, info, edges, s);
+  if (e != hipSuccess) return hip_fail(e, "2D prologue");
+  prof_begin("fwd2d_fp64", s);
+  e = launch_fwd2d(edges, nv, info, 0.0, q, nq, kTau02D, out, s);
+  prof_end("fwd2d_fp64", s);
+  if (e != hipSuccess) return hip_fail(e, "2D transform");
+  return PFT_OK;
+}
+
+pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                          const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* intensity,
+                          void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
+  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
+  if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
+  if (nq == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  Arena ar(s);
+  MeshInfo* info = ar.get<MeshInfo>(1);
+  Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
+  Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
+  int splits;
+  int64_t per;
+  choose_face_splits(nq, nf, c128 ? 1 : kQPT, &splits, &per);
+  double2* partial = ar.get<double2>((size_t)splits * nq);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
+  if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, c128 ? kTauF64 : kTauF32, f64, s);
+  if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
+  if (e != hipSuccess) return hip_fail(e, "3D prologue");
+  FwdArgs a;
+  a.f64 = f64;
+  a.f32 = f32;
+  a.info = info;
+  a.nf = nf;
+  a.q = q;
+  a.qdtype = qdtype;
+  a.nq = nq;
+  a.splits = splits;
+  a.faces_per_split = per;
+  a.partial = partial;
+  a.out = out;
+  a.intensity = intensity;
+  a.tau0 = c128 ? kTau0F64 : kTau0F32;
+  const char* nm = main_name(true, mode);
+  prof_begin(nm, s);
+  e = c128 ? launch_fwd3d_fp64(a, s) : launch_fwd3d_fp32c(a, s);
+  prof_end(nm, s);
+  if (e != hipSuccess) return hip_fail(e, "3D transform");
+  e = launch_fwd3d_finish(a, c128 ? 1 : 0, s);
+  if (e != hipSuccess) return hip_fail(e, "3D finish");
+  return PFT_OK;
+}
+
+pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                           const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
+                           void* grad_verts, void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  if (nq > 0 && grad_out == nullptr) return fail(PFT_EINVAL, "grad_out is NULL");
+  if (nv > 0 && grad_verts == nullptr) return fail(PFT_EINVAL, "grad_verts is NULL");
+  if (grad_out && !aligned(grad_out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "grad_out misaligned");
+  if (grad_verts && !aligned(grad_verts, real_size(vdtype))) return fail(PFT_EINVAL, "grad_verts misaligned");
+  if (nv == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  if (nq == 0 || nf == 0) {
+    hipError_t e = zero_bytes(grad_verts, (size_t)nv * 3 * real_size(vdtype), s);
+    return e == hipSuccess ? PFT_OK : hip_fail(e, "zero grad");
+  }
+  Arena ar(s);
+  MeshInfo* info = ar.get<MeshInfo>(1);
+  Face64* f64 = ar.get<Face64>(nf);
+  Face32B* f32 = c128 ? nullptr : ar.get<Face32B>(nf);
+  double* gram = c128 ? ar.get<double>((size_t)nf * 8) : nullptr;
+  int qs;
+  int64_t qper;
+  choose_q_splits(nq, nf, &qs, &qper);
+  double* partial = ar.get<double>((size_t)qs * nf * 3);
+  double* contrib = ar.get<double>((size_t)nf * 9);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
+  if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, kTauF64, f64, s);
+  if (e == hipSuccess && !c128) e = launch_face32b(f64, nf, kTauB32, kTauRelB32, f32, s);
+  if (e == hipSuccess && c128) e = launch_gram64(f64, nf, gram, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint prologue");
+  BwdArgs a;
+  a.info = info;
+  a.f64 = f64;
+  a.f32 = f32;
+  a.nf = nf;
+  a.q = q;
+  a.qdtype = qdtype;
+  a.nq = nq;
+  a.grad_out = grad_out;
+  a.qsplits = qs;
+  a.q_per_split = qper;
+  a.partial = partial;
+  const char* nm = main_name(false, mode);
+  prof_begin(nm, s);
+  e = c128 ? launch_bwd3d_fp64(a, gram, s) : launch_bwd3d_fp32c(a, s);
+  prof_end(nm, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint");
+  e = launch_bwd_face_contrib(partial, qs, f64, nf, contrib, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint reduce");
+  return gather_tail(ar, tris, nf, nullptr, nullptr, nv, contrib, grad_verts, vdtype, s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched entry points
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchPrep {
+  int64_t n = 0, nv = 0, nf = 0, nq = 0;
+  int64_t* d_vert_off = nullptr;
+  int64_t* d_tri_off = nullptr;
+  int64_t* d_q_off = nullptr;
+  int32_t* d_face_mesh = nullptr;
+  MeshInfo* info = nullptr;
+  Face64* f64 = nullptr;
+};
+
+pft_status check_batch(const pft_mesh_batch* b, int mode) {
+  if (!b) return fail(PFT_EINVAL, "batch is NULL");
+  if (b->n_meshes < 0) return fail(PFT_EINVAL, "negative mesh count");
+  if (b->n_meshes > INT32_MAX) return fail(PFT_EINVAL, "too many meshes");
+  pft_status st = check_offsets(b->vert_offsets, b->n_meshes, "vert_offsets");
+  if (st == PFT_OK) st = check_offsets(b->tri_offsets, b->n_meshes, "tri_offsets");
+  if (st == PFT_OK) st = check_offsets(b->q_offsets, b->n_meshes, "q_offsets");
+  if (st != PFT_OK) return st;
+  const int64_t n = b->n_meshes;
+  return check_mesh_args(b->verts, b->vdtype, b->vert_offsets[n], b->tris, b->tri_offsets[n], b->q, b->qdtype,
+                         b->q_offsets[n], mode);
+}
+
+pft_status batch_prologue(Arena& ar, const pft_mesh_batch* b, double tau, BatchPrep& p, hipStream_t s) {
+  p.n = b->n_meshes;
+  p.nv = b->vert_offsets[p.n];
+  p.nf = b->tri_offsets[p.n];
+  p.nq = b->q_offsets[p.n];
+  p.d_vert_off = ar.get<int64_t>(p.n + 1);
+  p.d_tri_off = ar.get<int64_t>(p.n + 1);
+  p.d_q_off = ar.get<int64_t>(p.n + 1);
+  p.d_face_mesh = ar.get<int32_t>(std::max<int64_t>(p.nf, 1));
+  p.info = ar.get<MeshInfo>(std::max<int64_t>(p.n, 1));
+  p.f64 = ar.get<Face64>(std::max<int64_t>(p.nf, 1));
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  const size_t ob = sizeof(int64_t) * (p.n + 1);
+  hipError_t e = hipMemcpyAsync(p.d_vert_off, b->vert_offsets, ob, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p.d_tri_off, b->tri_offsets, ob, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p.d_q_off, b->q_offsets, ob, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "offsets upload");
+  if (p.n > 0) e = launch_mesh_info(b->verts, b->vdtype, p.d_vert_off, p.n, p.info, s);
+  if (e == hipSuccess) e = launch_fill_face_mesh(p.d_tri_off, p.n, p.nf, p.d_face_mesh, s);
+  if (e == hipSuccess)
+    e = launch_face64_batch(b->verts, b->vdtype, b->tris, p.d_vert_off, p.d_tri_off, p.d_face_mesh, p.nf, p.info,
+                            tau, p.f64, s);
+  if (e != hipSuccess) return hip_fail(e, "batch prologue");
+  return PFT_OK;
+}
+
+template <typename T>
+pft_status upload(Arena& ar, const std::vector<T>& v, T** d, hipStream_t s) {
+  *d = ar.get<T>(std::max<size_t>(v.size(), 1));
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  if (v.empty()) return PFT_OK;
+  hipError_t e = hipMemcpyAsync(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "upload");
+}
+
+}  // namespace
+
+extern "C" {
+
+pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, void* intensity, void* stream) {
+  pft_status st = check_batch(b, mode);
+  if (st != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  const int64_t n = b->n_meshes, nq_total = b->q_offsets[n];
+  if (nq_total > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
+  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
+  if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
+  if (nq_total == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  Arena ar(s);
+  BatchPrep p;
+  st = batch_prologue(ar, b, c128 ? kTauF64 : kTauF32, p, s);
+  if (st != PFT_OK) return st;
+  Face32* f32 = nullptr;
+  if (!c128) {
+    f32 = ar.get<Face32>(std::max<int64_t>(p.nf, 1));
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    hipError_t e = launch_face32(p.f64, p.nf, kTauF32, kTauRel32, f32, s);
+    if (e != hipSuccess) return hip_fail(e, "batch prologue");
+  }
+  // work items: (mesh, Q-tile, face chunk), longest first
+  std::vector<BatchItemFwd> items;
+  std::vector<int64_t> q_part(n);
+  std::vector<int32_t> q_chunks(n);
+  int64_t P = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t nqi = b->q_offsets[i + 1] - b->q_offsets[i];
+    const int64_t nfi = b->tri_offsets[i + 1] - b->tri_offsets[i];
+    int64_t C = 1, cf = nfi;
+    if (nfi > 0) {
+      C = cdiv(nfi, kBatchChunkF);
+      cf = cdiv(cdiv(nfi, C), kTileF) * kTileF;
+      C = cdiv(nfi, cf);
+    }
+    q_part[i] = P;
+    q_chunks[i] = (int32_t)C;
+    for (int64_t c = 0; c < C; ++c) {
+      for (int64_t t = 0; t < nqi; t += kBlock) {
+        BatchItemFwd it;
+        it.mesh = (int32_t)i;
+        it.chunk = (int32_t)c;
+        it.q0 = b->q_offsets[i] + t;
+        it.nq = (int32_t)std::min<int64_t>(kBlock, nqi - t);
+        it.pad = 0;
+        it.f0 = b->tri_offsets[i] + c * cf;
+        it.nf = nfi > 0 ? std::min<int64_t>(cf, nfi - c * cf) : 0;
+        it.part = P + c * nqi + t;
+        items.push_back(it);
+      }
+    }
+    P += C * nqi;
+  }
+  std::stable_sort(items.begin(), items.end(), [](const BatchItemFwd& x, const BatchItemFwd& y) {
+    return x.nf * (int64_t)x.nq > y.nf * (int64_t)y.nq;
+  });
+  BatchItemFwd* d_items;
+  int64_t* d_q_part;
+  int32_t* d_q_chunks;
+  if ((st = upload(ar, items, &d_items, s)) != PFT_OK) return st;
+  if ((st = upload(ar, q_part, &d_q_part, s)) != PFT_OK) return st;
+  if ((st = upload(ar, q_chunks, &d_q_chunks, s)) != PFT_OK) return st;
+  double2* partial = ar.get<double2>(std::max<int64_t>(P, 1));
+  uint32_t* counter = ar.get<uint32_t>(1);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_zero_u32(counter, 1, s);
+  if (e != hipSuccess) return hip_fail(e, "counter reset");
+  const int64_t n_items = (int64_t)items.size();
+  const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
+                                          (int64_t)num_cus() * batch_fwd_blocks_per_cu(mode));
+  const double tau0 = c128 ? kTau0F64 : kTau0F32;
+  prof_begin("batch_fwd", s);
+  e = launch_batch_fwd(mode, d_items, n_items, counter, p.f64, f32, b->q, b->qdtype, partial, p.info, tau0, grid, s);
+  prof_end("batch_fwd", s);
+  if (e != hipSuccess) return hip_fail(e, "batch forward");
+  e = launch_batch_fwd_finish(partial, p.d_q_off, n, d_q_part, d_q_chunks, p.info, b->q, b->qdtype, nq_total, tau0,
+                              c128 ? 1 : 0, out, intensity, s);
+  if (e != hipSuccess) return hip_fail(e, "batch finish");
+  return PFT_OK;
+}
+
+pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void* grad_out, void* grad_verts,
+                              void* stream) {
+  pft_status st = check_batch(b, mode);
+  if (st != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  const int64_t n = b->n_meshes, nv_total = b->vert_offsets[n], nq_total = b->q_offsets[n];
+  const int64_t nf_total = b->tri_offsets[n];
+  if (nq_total > 0 && grad_out == nullptr) return fail(PFT_EINVAL, "grad_out is NULL");
+  if (nv_total > 0 && grad_verts == nullptr) return fail(PFT_EINVAL, "grad_verts is NULL");
+  if (grad_out && !aligned(grad_out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "grad_out misaligned");
+  if (grad_verts && !aligned(grad_verts, real_size(b->vdtype))) return fail(PFT_EINVAL, "grad_verts misaligned");
+  if (nv_total == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  if (nf_total == 0) {
+    hipError_t e = zero_bytes(grad_verts, (size_t)nv_total * 3 * real_size(b->vdtype), s);
+    return e == hipSuccess ? PFT_OK : hip_fail(e, "zero grad");
+  }
+  Arena ar(s);
+  BatchPrep p;
+  st = batch_prologue(ar, b, kTauF64, p, s);
+  if (st != PFT_OK) return st;
+  Face32B* f32b = nullptr;
+  double* gram = nullptr;
+  hipError_t e = hipSuccess;
+  if (c128) {
+    gram = ar.get<double>((size_t)p.nf * 8);
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    e = launch_gram64(p.f64, p.nf, gram, s);
+  } else {
+    f32b = ar.get<Face32B>(p.nf);
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    e = launch_face32b(p.f64, p.nf, kTauB32, kTauRelB32, f32b, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "batch adjoint prologue");
+  std::vector<BatchItemBwd> items;
+  std::vector<int64_t> face_base(n);
+  std::vector<int32_t> face_nchunks(n);
+  int64_t B = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t nqi = b->q_offsets[i + 1] - b->q_offsets[i];
+    const int64_t nfi = b->tri_offsets[i + 1] - b->tri_offsets[i];
+    const int64_t S = std::max<int64_t>(1, cdiv(nqi, kBatchChunkQ));
+    const int64_t cq = std::max<int64_t>(1, cdiv(nqi, S));
+    face_base[i] = B;
+    face_nchunks[i] = (int32_t)S;
+    for (int64_t sc = 0; sc < S; ++sc) {
+      for (int64_t ft = 0; ft < nfi; ft += kTileFB) {
+        BatchItemBwd it;
+        it.mesh = (int32_t)i;
+        it.qchunk = (int32_t)sc;
+        it.f0 = b->tri_offsets[i] + ft;
+        it.nf = (int32_t)std::min<int64_t>(kTileFB, nfi - ft);
+        it.pad = 0;
+        it.q0 = b->q_offsets[i] + std::min(nqi, sc * cq);
+        it.nq = std::max<int64_t>(0, std::min(cq, nqi - sc * cq));
+        it.part = B + sc * nfi + ft;
+        items.push_back(it);
+      }
+    }
+    B += S * nfi;
+  }
+  std::stable_sort(items.begin(), items.end(), [](const BatchItemBwd& x, const BatchItemBwd& y) {
+    return (int64_t)x.nf * x.nq > (int64_t)y.nf * y.nq;
+  });
+  BatchItemBwd* d_items;
+  int64_t* d_face_base;
+  int32_t* d_face_nchunks;
+  if ((st = upload(ar, items, &d_items, s)) != PFT_OK) return st;
+  if ((st = upload(ar, face_base, &d_face_base, s)) != PFT_OK) return st;
+  if ((st = upload(ar, face_nchunks, &d_face_nchunks, s)) != PFT_OK) return st;
+  double* partial = ar.get<double>((size_t)std::max<int64_t>(B, 1) * 3);
+  double* contrib = ar.get<double>((size_t)p.nf * 9);
+  uint32_t* counter = ar.get<uint32_t>(1);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  e = launch_zero_u32(counter, 1, s);
+  if (e != hipSuccess) return hip_fail(e, "counter reset");
+  const int64_t n_items = (int64_t)items.size();
+  const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
+                                          (int64_t)num_cus() * batch_bwd_blocks_per_cu(mode));
+  prof_begin("batch_bwd", s);
+  e = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, b->q, b->qdtype, grad_out, p.info, partial,
+                       grid, s);
+  prof_end("batch_bwd", s);
+  if (e != hipSuccess) return hip_fail(e, "batch adjoint");
+  e = launch_batch_bwd_reduce(partial, d_face_base, d_face_nchunks, p.d_tri_off, p.d_face_mesh, p.f64, p.nf, contrib,
+                              s);
+  if (e != hipSuccess) return hip_fail(e, "batch adjoint reduce");
+  return gather_tail(ar, b->tris, p.nf, p.d_vert_off, p.d_face_mesh, nv_total, contrib, grad_verts, b->vdtype, s);
+}
+
+}  // extern "C"

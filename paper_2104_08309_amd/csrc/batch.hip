@@ -1,0 +1,269 @@
+// Batched transform of many independent meshes in one persistent launch.
+//
+// The host cuts every mesh into work items -- (mesh, Q-tile of <= 256 Q,
+// face chunk) for the forward, (mesh, face tile of <= kTileFB faces, Q chunk)
+// for the adjoint -- and orders them by decreasing cost (longest processing
+// time first). A grid sized to the GPU's resident capacity pulls items from a
+// device counter until the list is exhausted; every block reaches the exit
+// test on each iteration, so the grid always drains. Each item writes its own
+// partial slot, and a finish kernel adds the partials of each Q (or face) in a
+// fixed order, so results do not depend on which block ran which item.
+#include "adj_terms.h"
+#include "fwd_terms.h"
+
+namespace pft {
+namespace {
+
+// Fetch the next work item index for the whole block (vector atomic from one lane).
+__device__ __forceinline__ int64_t next_item(uint32_t* counter, int* slot) {
+  if (threadIdx.x == 0) *slot = (int)atomicAdd(counter, 1u);
+  __syncthreads();
+  const int64_t it = *slot;
+  __syncthreads();
+  return it;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* __restrict__ items, int64_t n_items,
+                                                          uint32_t* counter, const Face64* __restrict__ f64,
+                                                          const Face32* __restrict__ f32, const void* q, int qdtype,
+                                                          double2* partial, const MeshInfo* __restrict__ info,
+                                                          double tau0) {
+  __shared__ __align__(16) unsigned char smem[kTileF * sizeof(Face64)];
+  __shared__ int slot;
+  for (;;) {
+    const int64_t idx = next_item(counter, &slot);
+    if (idx >= n_items) break;
+    const BatchItemFwd it = items[idx];
+    const int lane = threadIdx.x;
+    const bool active = lane < it.nq;
+    double Qd[3] = {0.0, 0.0, 0.0};
+    if (active) load_q3(q, qdtype, it.q0 + lane, Qd);
+    const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
+    const bool small = sqrt(Q2d) * info[it.mesh].R < tau0;
+    const int64_t f_end = it.f0 + it.nf;
+    double2 res;
+    if (MODE == PFT_FP64) {
+      Face64* tile = reinterpret_cast<Face64*>(smem);
+      double xr = 0.0, xi = 0.0;
+      for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
+        const int nt = (int)min((int64_t)kTileF, f_end - t0);
+        __syncthreads();
+        for (int i = lane; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
+          reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f64 + t0)[i];
+        __syncthreads();
+        if (!small) {
+          for (int j = 0; j < nt; ++j) {
+            double Tr, Ti;
+            face_term_f64(tile[j], Qd, Tr, Ti);
+            xr += Tr;
+            xi += Ti;
+          }
+        } else {
+          for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Qd, xr, xi);
+        }
+      }
+      res = make_double2(xr, xi);
+    } else {
+      Face32* tile = reinterpret_cast<Face32*>(smem);
+      const float qx = (float)Qd[0], qy = (float)Qd[1], qz = (float)Qd[2];
+      const float Q2 = qx * qx + qy * qy + qz * qz;
+      float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
+      double xr = 0.0, xi = 0.0;
+      for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
+        const int nt = (int)min((int64_t)kTileF, f_end - t0);
+        __syncthreads();
+        for (int i = lane; i < nt * (int)(sizeof(Face32) / 16); i += kBlock)
+          reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f32 + t0)[i];
+        __syncthreads();
+        if (!small) {
+          float tr = 0.0f, ti = 0.0f;
+          for (int j = 0; j < nt; ++j) {
+            float Tr, Ti;
+            face_term_fp32c(tile[j], f64 + t0 + j, qx, qy, qz, Q2, Qd, Tr, Ti);
+            tr += Tr;
+            ti += Ti;
+          }
+          kahan_add(sr, cr, tr);
+          kahan_add(si, ci, ti);
+        } else {
+          for (int j = 0; j < nt; ++j) tet_term_f64(f64[t0 + j], Qd, xr, xi);
+        }
+      }
+      res = small ? make_double2(xr, xi) : make_double2((double)sr - (double)cr, (double)si - (double)ci);
+    }
+    if (active) partial[it.part + lane] = res;
+  }
+}
+
+// One thread per Q of the batch: add the face-chunk partials of its mesh, apply
+// exp(iQ.t) / |Q|^2, write F (and |F|^2).
+__global__ __launch_bounds__(256) void batch_fwd_finish_kernel(const double2* partial, const int64_t* q_off,
+                                                               int64_t n_meshes, const int64_t* q_part,
+                                                               const int32_t* q_chunks, const MeshInfo* info,
+                                                               const void* q, int qdtype, int64_t nq_total,
+                                                               double tau0, int out_c128, void* out,
+                                                               void* intensity) {
+  const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (qi >= nq_total) return;
+  int64_t lo = 0, hi = n_meshes;  // last mesh with q_off[mesh] <= qi
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) / 2;
+    if (q_off[mid] <= qi) lo = mid; else hi = mid;
+  }
+  const int64_t mesh = lo;
+  const int64_t nqm = q_off[mesh + 1] - q_off[mesh];
+  const int64_t j = qi - q_off[mesh];
+  double xr = 0.0, xi = 0.0;
+  for (int c = 0; c < q_chunks[mesh]; ++c) {
+    const double2 v = partial[q_part[mesh] + (int64_t)c * nqm + j];
+    xr += v.x;
+    xi += v.y;
+  }
+  double Q[3];
+  load_q3(q, qdtype, qi, Q);
+  const MeshInfo mi = info[mesh];
+  const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+  if (!(sqrt(Q2) * mi.R < tau0)) {
+    xr /= Q2;
+    xi /= Q2;
+  }
+  double st, ct;
+  sincos(Q[0] * mi.t[0] + Q[1] * mi.t[1] + Q[2] * mi.t[2], &st, &ct);
+  const double Fr = ct * xr - st * xi;
+  const double Fi = ct * xi + st * xr;
+  if (out_c128) {
+    static_cast<double2*>(out)[qi] = make_double2(Fr, Fi);
+    if (intensity) static_cast<double*>(intensity)[qi] = Fr * Fr + Fi * Fi;
+  } else {
+    static_cast<float2*>(out)[qi] = make_float2((float)Fr, (float)Fi);
+    if (intensity) static_cast<float*>(intensity)[qi] = (float)(Fr * Fr + Fi * Fi);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void batch_bwd_kernel(const BatchItemBwd* __restrict__ items, int64_t n_items,
+                                                          uint32_t* counter, const Face64* __restrict__ f64,
+                                                          const double* __restrict__ gram,
+                                                          const Face32B* __restrict__ f32b, const void* q,
+                                                          int qdtype, const void* grad_out,
+                                                          const MeshInfo* __restrict__ info, double* partial) {
+  __shared__ __align__(16) unsigned char smem[kTileFB * sizeof(Face64)];
+  __shared__ double gtile[kTileFB][8];
+  __shared__ double wacc[kBlock / 64][kTileFB * 3];
+  __shared__ int slot;
+  const int tid = threadIdx.x;
+  for (;;) {
+    const int64_t idx = next_item(counter, &slot);
+    if (idx >= n_items) break;
+    const BatchItemBwd it = items[idx];
+    const int nt = it.nf;
+    if (MODE == PFT_FP64) {
+      for (int i = tid; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
+        reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(f64 + it.f0)[i];
+      for (int i = tid; i < nt * 8; i += kBlock) gtile[i / 8][i % 8] = gram[(it.f0 + i / 8) * 8 + i % 8];
+    } else {
+      for (int i = tid; i < nt * (int)(sizeof(Face32B) / 16); i += kBlock)
+        reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(f32b + it.f0)[i];
+    }
+    for (int i = tid; i < (kBlock / 64) * kTileFB * 3; i += kBlock) (&wacc[0][0])[i] = 0.0;
+    __syncthreads();
+    const MeshInfo mi = info[it.mesh];
+    const double tc[3] = {mi.t[0], mi.t[1], mi.t[2]};
+    adj_tile_accumulate<MODE>(smem, gtile, nt, tc, it.q0, it.q0 + it.nq, q, qdtype, grad_out, wacc);
+    __syncthreads();
+    if (tid < nt * 3) {
+      double v = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) v += wacc[w][tid];
+      partial[it.part * 3 + tid] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Per face corner: sum the Q-chunk partials of its mesh and form N_m R_{m,k}.
+__global__ __launch_bounds__(256) void batch_bwd_reduce_kernel(const double* partial, const int64_t* face_base,
+                                                               const int32_t* face_nchunks, const int64_t* tri_off,
+                                                               const int32_t* face_mesh, const Face64* f64,
+                                                               int64_t nf_total, double* contrib) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // corner slot 3m + k
+  if (i >= nf_total * 3) return;
+  const int64_t m = i / 3;
+  const int k = (int)(i % 3);
+  const int32_t mesh = face_mesh[m];
+  const int64_t nfm = tri_off[mesh + 1] - tri_off[mesh];
+  const int64_t fl = m - tri_off[mesh];
+  double R = 0.0;
+  for (int c = 0; c < face_nchunks[mesh]; ++c) R += partial[(face_base[mesh] + (int64_t)c * nfm + fl) * 3 + k];
+  const Face64& f = f64[m];
+  contrib[i * 3 + 0] = f.N[0] * R;
+  contrib[i * 3 + 1] = f.N[1] * R;
+  contrib[i * 3 + 2] = f.N[2] * R;
+}
+
+}  // namespace
+
+int batch_fwd_blocks_per_cu(int mode) {
+  int nb = 0;
+  if (mode == PFT_FP64)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP64>, kBlock, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP32C>, kBlock, 0);
+  return nb > 0 ? nb : 1;
+}
+
+int batch_bwd_blocks_per_cu(int mode) {
+  int nb = 0;
+  if (mode == PFT_FP64)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_bwd_kernel<PFT_FP64>, kBlock, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_bwd_kernel<PFT_FP32C>, kBlock, 0);
+  return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
+                            const Face64* f64, const Face32* f32, const void* q, int qdtype, double2* partial,
+                            const MeshInfo* info, double tau0, int grid, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (mode == PFT_FP64)
+    batch_fwd_kernel<PFT_FP64><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, partial, info,
+                                                       tau0);
+  else
+    batch_fwd_kernel<PFT_FP32C><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, partial,
+                                                        info, tau0);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_off, int64_t n_meshes,
+                                   const int64_t* d_q_part, const int32_t* d_q_chunks, const MeshInfo* info,
+                                   const void* q, int qdtype, int64_t nq_total, double tau0, int out_c128, void* out,
+                                   void* intensity, hipStream_t s) {
+  if (nq_total <= 0) return hipSuccess;
+  batch_fwd_finish_kernel<<<(unsigned)((nq_total + 255) / 256), 256, 0, s>>>(
+      partial, d_q_off, n_meshes, d_q_part, d_q_chunks, info, q, qdtype, nq_total, tau0, out_c128, out, intensity);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
+                            const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
+                            const void* grad_out, const MeshInfo* info, double* partial, int grid, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (mode == PFT_FP64)
+    batch_bwd_kernel<PFT_FP64><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, gram, f32b, q, qdtype, grad_out,
+                                                       info, partial);
+  else
+    batch_bwd_kernel<PFT_FP32C><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, gram, f32b, q, qdtype,
+                                                        grad_out, info, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_bwd_reduce(const double* partial, const int64_t* d_face_base, const int32_t* d_face_nchunks,
+                                   const int64_t* d_tri_off, const int32_t* d_face_mesh, const Face64* f64,
+                                   int64_t nf_total, double* contrib, hipStream_t s) {
+  if (nf_total <= 0) return hipSuccess;
+  batch_bwd_reduce_kernel<<<(unsigned)((nf_total * 3 + 255) / 256), 256, 0, s>>>(
+      partial, d_face_base, d_face_nchunks, d_tri_off, d_face_mesh, f64, nf_total, contrib);
+  return hipGetLastError();
+}
+
+}  // namespace pft

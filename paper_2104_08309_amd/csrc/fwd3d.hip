@@ -1,0 +1,183 @@
+// Forward 3D transform of a closed triangle mesh: F(Q) for a list of Q.
+//
+// Layout: one thread per Q (a Q-tile of 256 per block), faces streamed
+// through LDS in tiles of kTileF records and broadcast to the wavefront. The
+// face range can be split over blockIdx.y when there are too few Q to fill
+// the GPU; each split writes a binary64 partial sum, and the finish kernel
+// adds the splits in a fixed order and applies exp(i Q.t) / |Q|^2.
+//
+// Two arithmetic forms:
+//  * fwd3d_fp64_kernel  -- IEEE binary64 throughout.
+//  * fwd3d_fp32c_kernel -- edge arithmetic in binary32 on face-local
+//    coordinates, the face origin phase Q.g reduced in binary64 and
+//    evaluated in turns, the near-degenerate series branch in binary64, the
+//    sum over faces blocked per LDS tile and compensated (Kahan) across tiles.
+#include "fwd_terms.h"
+
+namespace pft {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
+  __shared__ Face64 tile[kTileF];
+  const int64_t qi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = qi < a.nq;
+  double Q[3] = {0.0, 0.0, 0.0};
+  if (active) load_q3(a.q, a.qdtype, qi, Q);
+  const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+  const bool small = sqrt(Q2) * a.info[0].R < a.tau0;
+  const int64_t f_begin = (int64_t)blockIdx.y * a.faces_per_split;
+  const int64_t f_end = min(a.nf, f_begin + a.faces_per_split);
+  double xr = 0.0, xi = 0.0;
+  for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
+    const int nt = (int)min((int64_t)kTileF, f_end - t0);
+    __syncthreads();
+    {
+      const uint4* src = reinterpret_cast<const uint4*>(a.f64 + t0);
+      uint4* dst = reinterpret_cast<uint4*>(tile);
+      for (int i = threadIdx.x; i < nt * (int)(sizeof(Face64) / 16); i += kBlock) dst[i] = src[i];
+    }
+    __syncthreads();
+    if (!small) {
+      for (int j = 0; j < nt; ++j) {
+        double Tr, Ti;
+        face_term_f64(tile[j], Q, Tr, Ti);
+        xr += Tr;
+        xi += Ti;
+      }
+    } else {
+      for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Q, xr, xi);
+    }
+  }
+  if (active) a.partial[(int64_t)blockIdx.y * a.nq + qi] = make_double2(xr, xi);
+}
+
+// Each thread evaluates kQPT Q points (strided by the block size, so loads stay
+// coalesced) against every face record it reads from LDS: the record is loaded
+// once per kQPT terms and the kQPT evaluations are independent instruction
+// streams the scheduler can interleave.
+__global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
+  __shared__ Face32 tile[kTileF];
+  const int64_t qbase = (int64_t)blockIdx.x * (kBlock * kQPT) + threadIdx.x;
+  const double R = a.info[0].R;
+  double Qd[kQPT][3];
+  float qx[kQPT], qy[kQPT], qz[kQPT], Q2[kQPT];
+  bool small[kQPT], active[kQPT];
+  bool any_small = false;
+#pragma unroll
+  for (int k = 0; k < kQPT; ++k) {
+    const int64_t qi = qbase + (int64_t)k * kBlock;
+    active[k] = qi < a.nq;
+    Qd[k][0] = Qd[k][1] = Qd[k][2] = 0.0;
+    if (active[k]) load_q3(a.q, a.qdtype, qi, Qd[k]);
+    qx[k] = (float)Qd[k][0];
+    qy[k] = (float)Qd[k][1];
+    qz[k] = (float)Qd[k][2];
+    Q2[k] = qx[k] * qx[k] + qy[k] * qy[k] + qz[k] * qz[k];
+    const double Q2d = Qd[k][0] * Qd[k][0] + Qd[k][1] * Qd[k][1] + Qd[k][2] * Qd[k][2];
+    small[k] = sqrt(Q2d) * R < a.tau0;
+    any_small |= small[k];
+  }
+  const int64_t f_begin = (int64_t)blockIdx.y * a.faces_per_split;
+  const int64_t f_end = min(a.nf, f_begin + a.faces_per_split);
+  float sr[kQPT], si[kQPT], cr[kQPT], ci[kQPT];
+  double xr[kQPT], xi[kQPT];
+#pragma unroll
+  for (int k = 0; k < kQPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
+  for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
+    const int nt = (int)min((int64_t)kTileF, f_end - t0);
+    __syncthreads();
+    {
+      const uint4* src = reinterpret_cast<const uint4*>(a.f32 + t0);
+      uint4* dst = reinterpret_cast<uint4*>(tile);
+      for (int i = threadIdx.x; i < nt * (int)(sizeof(Face32) / 16); i += kBlock) dst[i] = src[i];
+    }
+    __syncthreads();
+    float tr[kQPT], ti[kQPT];
+#pragma unroll
+    for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
+    for (int j = 0; j < nt; ++j) {
+#pragma unroll
+      for (int k = 0; k < kQPT; ++k) {
+        if (!small[k]) {
+          float Tr, Ti;
+          face_term_fp32c(tile[j], a.f64 + t0 + j, qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr, Ti);
+          tr[k] += Tr;
+          ti[k] += Ti;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kQPT; ++k) {
+      kahan_add(sr[k], cr[k], tr[k]);
+      kahan_add(si[k], ci[k], ti[k]);
+    }
+    if (any_small) {
+#pragma unroll
+      for (int k = 0; k < kQPT; ++k)
+        if (small[k])
+          for (int j = 0; j < nt; ++j) tet_term_f64(a.f64[t0 + j], Qd[k], xr[k], xi[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kQPT; ++k) {
+    if (active[k]) {
+      const double2 v = small[k] ? make_double2(xr[k], xi[k])
+                                 : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
+      a.partial[(int64_t)blockIdx.y * a.nq + qbase + (int64_t)k * kBlock] = v;
+    }
+  }
+}
+
+// Sum the splits in order, apply exp(i Q.t) and 1/|Q|^2, write F and |F|^2.
+__global__ __launch_bounds__(256) void fwd3d_finish_kernel(FwdArgs a, int out_c128) {
+  const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (qi >= a.nq) return;
+  double Q[3];
+  load_q3(a.q, a.qdtype, qi, Q);
+  double xr = 0.0, xi = 0.0;
+  for (int s = 0; s < a.splits; ++s) {
+    const double2 v = a.partial[(int64_t)s * a.nq + qi];
+    xr += v.x;
+    xi += v.y;
+  }
+  const MeshInfo mi = a.info[0];
+  const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+  const bool small = sqrt(Q2) * mi.R < a.tau0;
+  if (!small) {
+    xr /= Q2;
+    xi /= Q2;
+  }
+  double st, ct;
+  sincos(Q[0] * mi.t[0] + Q[1] * mi.t[1] + Q[2] * mi.t[2], &st, &ct);
+  const double Fr = ct * xr - st * xi;
+  const double Fi = ct * xi + st * xr;
+  if (out_c128) {
+    static_cast<double2*>(a.out)[qi] = make_double2(Fr, Fi);
+    if (a.intensity) static_cast<double*>(a.intensity)[qi] = Fr * Fr + Fi * Fi;
+  } else {
+    const float fr = (float)Fr, fi = (float)Fi;
+    static_cast<float2*>(a.out)[qi] = make_float2(fr, fi);
+    if (a.intensity) static_cast<float*>(a.intensity)[qi] = (float)(Fr * Fr + Fi * Fi);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s) {
+  dim3 grid((unsigned)((a.nq + kBlock - 1) / kBlock), (unsigned)a.splits);
+  fwd3d_fp64_kernel<<<grid, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s) {
+  dim3 grid((unsigned)((a.nq + kBlock * kQPT - 1) / (kBlock * kQPT)), (unsigned)a.splits);
+  fwd3d_fp32c_kernel<<<grid, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd3d_finish(const FwdArgs& a, int out_c128, hipStream_t s) {
+  fwd3d_finish_kernel<<<(unsigned)((a.nq + 255) / 256), 256, 0, s>>>(a, out_c128);
+  return hipGetLastError();
+}
+
+}  // namespace pft

@@ -1,0 +1,210 @@
+// Internal declarations shared by the libpft HIP sources: per-face / per-edge
+// records written by the prologue kernels, tuning constants, and the launcher
+// functions that the C ABI layer calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pft.h"
+
+namespace pft {
+
+// ---------------------------------------------------------------------------
+// Tuning constants
+// ---------------------------------------------------------------------------
+constexpr int kBlock = 256;        // threads per block for the Q-parallel kernels
+constexpr int kTileF = 64;         // faces staged in LDS per tile (forward)
+constexpr int kTileFB = 16;        // faces per block in the adjoint
+#ifndef PFT_QPT
+#define PFT_QPT 2
+#endif
+constexpr int kQPT = PFT_QPT;      // Q per thread in the FP32C forward
+constexpr int kTileE = 64;         // 2D edges staged in LDS per tile
+
+// Series thresholds (dimensionless). A (Q, face) pair uses the face's simplex
+// series instead of the edge sum when |Q_perp| L_face < tau (absolute test) or
+// |Q_perp| < tau_rel |Q| (relative test, guards the rounding of Q x N in FP32).
+constexpr double kTauF64 = 0.05;     // forward and adjoint, FP64 mode
+constexpr double kTauF32 = 0.1;      // forward, FP32C mode (series in FP64)
+constexpr double kTauRel32 = 0.02;   // forward, FP32C mode, relative test
+constexpr double kTauB32 = 1.5;      // adjoint, FP32C mode (series in FP32)
+constexpr double kTauRelB32 = 0.05;  // adjoint, FP32C mode, relative test
+// Whole-mesh series (fan of tetrahedra from the vertex mean) when |Q| R < tau0.
+constexpr double kTau0F64 = 0.01;
+constexpr double kTau0F32 = 0.2;
+// 2D fan series when |Q| R < tau0.
+constexpr double kTau02D = 0.01;
+
+// ---------------------------------------------------------------------------
+// Records
+// ---------------------------------------------------------------------------
+// Per-mesh quantities (device): vertex mean t, radius R = max |v - t|.
+struct MeshInfo {
+  double t[3];
+  double R;
+};
+
+// FP64 face record: geometry relative to the mesh centre t.
+struct alignas(16) Face64 {
+  double g[3];    // centroid
+  double u0[3];   // a - g
+  double u1[3];   // b - g          (c - g = -u0 - u1)
+  double N[3];    // (b - a) x (c - a) = 2 A n
+  double thr;     // series when |Q x N|^2 < thr  (tau^2 |N|^2 / L^2; -1 for an empty face)
+  double pad[3];
+};
+static_assert(sizeof(Face64) == 128, "Face64 layout");
+
+// FP32C forward face record (staged in LDS).
+struct alignas(16) Face32 {
+  double gt[3];   // centroid / (2 pi), binary64: face origin phase in turns is Q . gt
+  float N[3];     // (b - a) x (c - a)
+  float d0[3];    // b - a
+  float d1[3];    // c - b
+  float h0[3];    // (a - g) / (4 pi): half-vertex phase in turns is Q . h
+  float h1[3];    // (b - g) / (4 pi)
+  float thr;      // tau^2 |N|^2 / L^2
+  float kap;      // tau_rel^2 |N|^2
+};
+static_assert(sizeof(Face32) == 96, "Face32 layout");
+
+// FP32C adjoint face record.
+struct alignas(16) Face32B {
+  double gt[3];   // centroid / (2 pi)
+  float N[3];
+  float d0[3];    // b - a
+  float d1[3];    // c - b
+  float h0[3];    // (a - g) / (4 pi)
+  float h1[3];    // (b - g) / (4 pi)
+  float G[6];     // d0.d0, d1.d1, d2.d2, d0.d1, d1.d2, d2.d0
+  float thr;      // tau_b^2 |N|^2 / L^2
+  float kap;      // tau_relb^2 |N|^2
+  float pad[2];
+};
+static_assert(sizeof(Face32B) == 128, "Face32B layout");
+
+// 2D edge record (FP64), relative to the polygon's vertex mean.
+struct alignas(16) Edge2D {
+  double a[2];    // start vertex
+  double b[2];    // end vertex
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files). All enqueue on `s` and return the
+// HIP status of the launch.
+// ---------------------------------------------------------------------------
+// prologue.hip
+hipError_t launch_mesh_info(const void* verts, int vdtype, const int64_t* d_vert_off, int64_t n_meshes,
+                            MeshInfo* info, hipStream_t s);
+hipError_t launch_mesh_info_single(const void* verts, int vdtype, int dim, int64_t nv, MeshInfo* info,
+                                   hipStream_t s);
+hipError_t launch_face64(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                         const MeshInfo* info, double tau, Face64* out, hipStream_t s);
+hipError_t launch_face32(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32* out, hipStream_t s);
+hipError_t launch_face32b(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32B* out, hipStream_t s);
+hipError_t launch_face64_batch(const void* verts, int vdtype, const int32_t* tris, const int64_t* d_vert_off,
+                               const int64_t* d_tri_off, const int32_t* d_face_mesh, int64_t nf_total,
+                               const MeshInfo* info, double tau, Face64* out, hipStream_t s);
+hipError_t launch_fill_face_mesh(const int64_t* d_tri_off, int64_t n_meshes, int64_t nf_total, int32_t* face_mesh,
+                                 hipStream_t s);
+hipError_t launch_edges2d(const double* verts, int64_t nv, const int64_t* d_off, int64_t ncont, MeshInfo* info,
+                          Edge2D* edges, hipStream_t s);
+hipError_t launch_validate(const int32_t* tris, int64_t nf, int64_t nv, unsigned long long* counts, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+
+// fwd3d.hip
+struct FwdArgs {
+  const Face64* f64;
+  const Face32* f32;
+  const MeshInfo* info;
+  int64_t nf;
+  const void* q;
+  int qdtype;
+  int64_t nq;
+  int splits;
+  int64_t faces_per_split;
+  double2* partial;   // [splits][nq] when splits > 1
+  void* out;
+  void* intensity;
+  double tau0;
+};
+hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s);
+hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s);
+hipError_t launch_fwd3d_finish(const FwdArgs& a, int out_c128, hipStream_t s);
+
+// bwd3d.hip
+struct BwdArgs {
+  const MeshInfo* info;  // mesh centre t: the cotangent is taken relative to the centred mesh
+  const Face64* f64;
+  const Face32B* f32;
+  int64_t nf;
+  const void* q;
+  int qdtype;
+  int64_t nq;
+  const void* grad_out;
+  int qsplits;
+  int64_t q_per_split;
+  double* partial;    // [qsplits][nf][3]
+};
+hipError_t launch_gram64(const Face64* f64, int64_t nf, double* gram /*[nf][8]*/, hipStream_t s);
+hipError_t launch_bwd3d_fp64(const BwdArgs& a, const double* gram, hipStream_t s);
+hipError_t launch_bwd3d_fp32c(const BwdArgs& a, hipStream_t s);
+// Sum the per-split adjoint weights, form per-corner vectors N_m R_{m,k} and
+// gather them per vertex through the sorted incidence list.
+hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, int64_t nf,
+                                   double* contrib /*[nf*3][3]*/, hipStream_t s);
+hipError_t launch_incidence_keys(const int32_t* tris, int64_t nf, const int64_t* d_vert_off,
+                                 const int32_t* d_face_mesh, int64_t nv_total, uint32_t* keys, uint32_t* vals,
+                                 hipStream_t s);
+hipError_t sort_incidence(uint32_t* keys_in, uint32_t* vals_in, uint32_t* keys_out, uint32_t* vals_out, int64_t n,
+                          int64_t nv_total, void* temp, size_t* temp_bytes, hipStream_t s);
+hipError_t launch_gather_vertices(const uint32_t* keys_sorted, const uint32_t* vals_sorted, int64_t nslots,
+                                  const double* contrib, int64_t nv, void* grad, int vdtype, hipStream_t s);
+
+// fwd2d.hip
+hipError_t launch_fwd2d(const Edge2D* edges, int64_t ne, const MeshInfo* info, double area_hint, const double* q,
+                        int64_t nq, double tau0, double* out, hipStream_t s);
+
+// batch.hip
+struct BatchItemFwd {   // one (mesh, Q-tile, face-chunk) work item
+  int32_t mesh;
+  int32_t chunk;        // face-chunk index within the mesh
+  int64_t q0;           // first global Q index of the tile
+  int32_t nq;           // Q in the tile (<= kBlock)
+  int32_t pad;
+  int64_t f0;           // first global face index of the chunk
+  int64_t nf;           // faces in the chunk
+  int64_t part;         // partial slot base (in units of Q): partial[part + lane]
+};
+struct BatchItemBwd {   // one (mesh, face-tile, Q-chunk) work item
+  int32_t mesh;
+  int32_t qchunk;
+  int64_t f0;           // first global face index of the tile
+  int32_t nf;           // faces in the tile (<= kTileFB)
+  int32_t pad;
+  int64_t q0;           // first global Q index of the chunk
+  int64_t nq;           // Q in the chunk
+  int64_t part;         // partial slot base (in units of face corners): partial[(part + j) * 3 + k]
+};
+int batch_fwd_blocks_per_cu(int mode);
+int batch_bwd_blocks_per_cu(int mode);
+hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
+                            const Face64* f64, const Face32* f32, const void* q, int qdtype, double2* partial,
+                            const MeshInfo* info, double tau0, int grid, hipStream_t s);
+hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_off, int64_t n_meshes,
+                                   const int64_t* d_q_part, const int32_t* d_q_chunks, const MeshInfo* info,
+                                   const void* q, int qdtype, int64_t nq_total, double tau0, int out_c128, void* out,
+                                   void* intensity, hipStream_t s);
+hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
+                            const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
+                            const void* grad_out, const MeshInfo* info, double* partial, int grid, hipStream_t s);
+hipError_t launch_batch_bwd_reduce(const double* partial, const int64_t* d_face_base, const int32_t* d_face_nchunks,
+                                   const int64_t* d_tri_off, const int32_t* d_face_mesh, const Face64* f64,
+                                   int64_t nf_total, double* contrib, hipStream_t s);
+
+// Profiling hooks (api.cpp)
+void prof_begin(const char* name, hipStream_t s);
+void prof_end(const char* name, hipStream_t s);
+
+}  // namespace pft

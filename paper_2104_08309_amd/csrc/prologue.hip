@@ -1,0 +1,340 @@
+// Prologue kernels: per-mesh centre and radius, per-face and per-edge records.
+//
+// The records carry the geometry each (Q, face) evaluation needs, relative to
+// local origins, so that the hot loops see small coordinates: the mesh is
+// re-centred on its vertex mean t, each face on its centroid g. Everything here
+// runs once per call in binary64 and is O(V + F).
+#include "pft_internal.h"
+
+namespace pft {
+namespace {
+
+__device__ inline void load_vertex(const void* verts, int vdtype, int dim, int64_t i, double* out) {
+  if (vdtype == PFT_F64) {
+    const double* v = static_cast<const double*>(verts) + i * dim;
+    for (int k = 0; k < dim; ++k) out[k] = v[k];
+  } else {
+    const float* v = static_cast<const float*>(verts) + i * dim;
+    for (int k = 0; k < dim; ++k) out[k] = (double)v[k];
+  }
+}
+
+// One block per mesh: t = vertex mean, R = max |v - t|. Fixed reduction order.
+__global__ __launch_bounds__(256) void mesh_info_kernel(const void* verts, int vdtype, int dim, int64_t nv_single,
+                                                        const int64_t* vert_off, MeshInfo* info) {
+  __shared__ double red[256][3];
+  const int64_t mesh = blockIdx.x;
+  const int64_t v0 = vert_off ? vert_off[mesh] : 0;
+  const int64_t v1 = vert_off ? vert_off[mesh + 1] : nv_single;
+  const int tid = threadIdx.x;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = v0 + tid; i < v1; i += blockDim.x) {
+    double p[3] = {0.0, 0.0, 0.0};
+    load_vertex(verts, vdtype, dim, i, p);
+    for (int k = 0; k < 3; ++k) s[k] += p[k];
+  }
+  for (int k = 0; k < 3; ++k) red[tid][k] = s[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int k = 0; k < 3; ++k) red[tid][k] += red[tid + w][k];
+    __syncthreads();
+  }
+  const int64_t n = v1 - v0;
+  double t[3];
+  for (int k = 0; k < 3; ++k) t[k] = n > 0 ? red[0][k] / (double)n : 0.0;
+  __syncthreads();
+  double r2 = 0.0;
+  for (int64_t i = v0 + tid; i < v1; i += blockDim.x) {
+    double p[3] = {0.0, 0.0, 0.0};
+    load_vertex(verts, vdtype, dim, i, p);
+    double d2 = 0.0;
+    for (int k = 0; k < dim; ++k) d2 += (p[k] - t[k]) * (p[k] - t[k]);
+    r2 = fmax(r2, d2);
+  }
+  red[tid][0] = r2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid][0] = fmax(red[tid][0], red[tid + w][0]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    MeshInfo m;
+    for (int k = 0; k < 3; ++k) m.t[k] = t[k];
+    m.R = sqrt(red[0][0]);
+    info[mesh] = m;
+  }
+}
+
+__device__ inline void make_face64(const double* a, const double* b, const double* c, double tau, Face64& f) {
+  double g[3], u0[3], u1[3], e0[3], e1[3], e2[3];
+  for (int k = 0; k < 3; ++k) {
+    g[k] = (a[k] + b[k] + c[k]) / 3.0;
+    u0[k] = a[k] - g[k];
+    u1[k] = b[k] - g[k];
+    e0[k] = b[k] - a[k];
+    e1[k] = c[k] - b[k];
+    e2[k] = a[k] - c[k];
+  }
+  // N = (b - a) x (c - a) = e0 x (-e2)
+  double N[3] = {e0[1] * (c[2] - a[2]) - e0[2] * (c[1] - a[1]),
+                 e0[2] * (c[0] - a[0]) - e0[0] * (c[2] - a[2]),
+                 e0[0] * (c[1] - a[1]) - e0[1] * (c[0] - a[0])};
+  double N2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+  double L2 = 0.0;
+  L2 = fmax(L2, e0[0] * e0[0] + e0[1] * e0[1] + e0[2] * e0[2]);
+  L2 = fmax(L2, e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  L2 = fmax(L2, e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+  for (int k = 0; k < 3; ++k) {
+    f.g[k] = g[k];
+    f.u0[k] = u0[k];
+    f.u1[k] = u1[k];
+    f.N[k] = N[k];
+  }
+  f.thr = (N2 > 0.0 && L2 > 0.0) ? tau * tau * N2 / L2 : -1.0;
+  f.pad[0] = L2;
+  f.pad[1] = N2;
+  f.pad[2] = 0.0;
+}
+
+__device__ inline void empty_face64(Face64& f) {
+  for (int k = 0; k < 3; ++k) f.g[k] = f.u0[k] = f.u1[k] = f.N[k] = 0.0;
+  f.thr = -1.0;
+  f.pad[0] = f.pad[1] = f.pad[2] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdtype, int64_t nv, const int32_t* tris,
+                                                     int64_t nf, const MeshInfo* info, double tau, Face64* out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  const int32_t ia = tris[3 * m], ib = tris[3 * m + 1], ic = tris[3 * m + 2];
+  Face64 f;
+  if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) {
+    empty_face64(f);
+  } else {
+    double a[3], b[3], c[3];
+    load_vertex(verts, vdtype, 3, ia, a);
+    load_vertex(verts, vdtype, 3, ib, b);
+    load_vertex(verts, vdtype, 3, ic, c);
+    const MeshInfo mi = info[0];
+    for (int k = 0; k < 3; ++k) {
+      a[k] -= mi.t[k];
+      b[k] -= mi.t[k];
+      c[k] -= mi.t[k];
+    }
+    make_face64(a, b, c, tau, f);
+  }
+  out[m] = f;
+}
+
+__global__ __launch_bounds__(256) void face_mesh_kernel(const int64_t* tri_off, int64_t n_meshes, int64_t nf_total,
+                                                        int32_t* face_mesh) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf_total) return;
+  // last mesh i with tri_off[i] <= f (meshes may be empty)
+  int64_t lo = 0, hi = n_meshes;  // invariant: tri_off[lo] <= f < tri_off[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) / 2;
+    if (tri_off[mid] <= f) lo = mid; else hi = mid;
+  }
+  face_mesh[f] = (int32_t)lo;
+}
+
+__global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, int vdtype, const int32_t* tris,
+                                                           const int64_t* vert_off, const int64_t* tri_off,
+                                                           const int32_t* face_mesh, int64_t nf_total,
+                                                           const MeshInfo* info, double tau, Face64* out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf_total) return;
+  const int32_t mesh = face_mesh[m];
+  const int64_t vb = vert_off[mesh];
+  const int64_t nv = vert_off[mesh + 1] - vb;
+  const int32_t ia = tris[3 * m], ib = tris[3 * m + 1], ic = tris[3 * m + 2];
+  Face64 f;
+  if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) {
+    empty_face64(f);
+  } else {
+    double a[3], b[3], c[3];
+    load_vertex(verts, vdtype, 3, vb + ia, a);
+    load_vertex(verts, vdtype, 3, vb + ib, b);
+    load_vertex(verts, vdtype, 3, vb + ic, c);
+    const MeshInfo mi = info[mesh];
+    for (int k = 0; k < 3; ++k) {
+      a[k] -= mi.t[k];
+      b[k] -= mi.t[k];
+      c[k] -= mi.t[k];
+    }
+    make_face64(a, b, c, tau, f);
+  }
+  out[m] = f;
+}
+
+constexpr double kInv2Pi = 0.15915494309189533577;
+constexpr double kInv4Pi = 0.07957747154594766788;
+
+__global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t nf, double tau, double tau_rel,
+                                                     Face32* out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  const Face64 f = in[m];
+  Face32 r;
+  const double L2 = f.pad[0], N2 = f.pad[1];
+  for (int k = 0; k < 3; ++k) {
+    r.gt[k] = f.g[k] * kInv2Pi;
+    r.N[k] = (float)f.N[k];
+    r.d0[k] = (float)(f.u1[k] - f.u0[k]);
+    r.d1[k] = (float)(-f.u0[k] - 2.0 * f.u1[k]);
+    r.h0[k] = (float)(f.u0[k] * kInv4Pi);
+    r.h1[k] = (float)(f.u1[k] * kInv4Pi);
+  }
+  const bool ok = f.thr >= 0.0;
+  r.thr = ok ? (float)(tau * tau * N2 / L2) : -1.0f;
+  r.kap = ok ? (float)(tau_rel * tau_rel * N2) : -1.0f;
+  out[m] = r;
+}
+
+__global__ __launch_bounds__(256) void face32b_kernel(const Face64* in, int64_t nf, double tau, double tau_rel,
+                                                      Face32B* out) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  const Face64 f = in[m];
+  Face32B r;
+  const double L2 = f.pad[0], N2 = f.pad[1];
+  double d0[3], d1[3], d2[3];
+  for (int k = 0; k < 3; ++k) {
+    d0[k] = f.u1[k] - f.u0[k];
+    d1[k] = -f.u0[k] - 2.0 * f.u1[k];
+    d2[k] = 2.0 * f.u0[k] + f.u1[k];
+    r.gt[k] = f.g[k] * kInv2Pi;
+    r.N[k] = (float)f.N[k];
+    r.d0[k] = (float)d0[k];
+    r.d1[k] = (float)d1[k];
+    r.h0[k] = (float)(f.u0[k] * kInv4Pi);
+    r.h1[k] = (float)(f.u1[k] * kInv4Pi);
+  }
+  auto dot = [](const double* x, const double* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+  r.G[0] = (float)dot(d0, d0);
+  r.G[1] = (float)dot(d1, d1);
+  r.G[2] = (float)dot(d2, d2);
+  r.G[3] = (float)dot(d0, d1);
+  r.G[4] = (float)dot(d1, d2);
+  r.G[5] = (float)dot(d2, d0);
+  const bool ok = f.thr >= 0.0;
+  r.thr = ok ? (float)(tau * tau * N2 / L2) : -1.0f;
+  r.kap = ok ? (float)(tau_rel * tau_rel * N2) : -1.0f;
+  r.pad[0] = r.pad[1] = 0.0f;
+  out[m] = r;
+}
+
+__global__ __launch_bounds__(256) void edges2d_kernel(const double* verts, int64_t nv, const int64_t* off,
+                                                      int64_t ncont, const MeshInfo* info, Edge2D* edges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  int64_t start = 0, end = nv;
+  if (off) {
+    int64_t lo = 0, hi = ncont;  // last contour c with off[c] <= i
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) / 2;
+      if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    start = off[lo];
+    end = off[lo + 1];
+  }
+  const int64_t j = (i + 1 < end) ? i + 1 : start;
+  const MeshInfo mi = info[0];
+  Edge2D e;
+  e.a[0] = verts[2 * i] - mi.t[0];
+  e.a[1] = verts[2 * i + 1] - mi.t[1];
+  e.b[0] = verts[2 * j] - mi.t[0];
+  e.b[1] = verts[2 * j + 1] - mi.t[1];
+  edges[i] = e;
+}
+
+__global__ __launch_bounds__(256) void validate_kernel(const int32_t* tris, int64_t nf, int64_t nv,
+                                                       unsigned long long* counts) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  const int32_t a = tris[3 * m], b = tris[3 * m + 1], c = tris[3 * m + 2];
+  const int bad = (a < 0 || a >= nv) + (b < 0 || b >= nv) + (c < 0 || c >= nv);
+  if (bad) atomicAdd(&counts[0], (unsigned long long)bad);
+  if (a == b || b == c || c == a) atomicAdd(&counts[1], 1ull);
+}
+
+__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_mesh_info(const void* verts, int vdtype, const int64_t* d_vert_off, int64_t n_meshes,
+                            MeshInfo* info, hipStream_t s) {
+  mesh_info_kernel<<<(unsigned)n_meshes, 256, 0, s>>>(verts, vdtype, 3, 0, d_vert_off, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_info_single(const void* verts, int vdtype, int dim, int64_t nv, MeshInfo* info,
+                                   hipStream_t s) {
+  mesh_info_kernel<<<1, 256, 0, s>>>(verts, vdtype, dim, nv, nullptr, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_face64(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                         const MeshInfo* info, double tau, Face64* out, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  face64_kernel<<<grid_for(nf), 256, 0, s>>>(verts, vdtype, nv, tris, nf, info, tau, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_face32(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32* out, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  face32_kernel<<<grid_for(nf), 256, 0, s>>>(f64, nf, tau, tau_rel, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_face32b(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32B* out, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  face32b_kernel<<<grid_for(nf), 256, 0, s>>>(f64, nf, tau, tau_rel, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_face_mesh(const int64_t* d_tri_off, int64_t n_meshes, int64_t nf_total, int32_t* face_mesh,
+                                 hipStream_t s) {
+  if (nf_total <= 0) return hipSuccess;
+  face_mesh_kernel<<<grid_for(nf_total), 256, 0, s>>>(d_tri_off, n_meshes, nf_total, face_mesh);
+  return hipGetLastError();
+}
+
+hipError_t launch_face64_batch(const void* verts, int vdtype, const int32_t* tris, const int64_t* d_vert_off,
+                               const int64_t* d_tri_off, const int32_t* d_face_mesh, int64_t nf_total,
+                               const MeshInfo* info, double tau, Face64* out, hipStream_t s) {
+  if (nf_total <= 0) return hipSuccess;
+  face64_batch_kernel<<<grid_for(nf_total), 256, 0, s>>>(verts, vdtype, tris, d_vert_off, d_tri_off, d_face_mesh,
+                                                         nf_total, info, tau, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_edges2d(const double* verts, int64_t nv, const int64_t* d_off, int64_t ncont, MeshInfo* info,
+                          Edge2D* edges, hipStream_t s) {
+  mesh_info_kernel<<<1, 256, 0, s>>>(verts, PFT_F64, 2, nv, nullptr, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nv <= 0) return e;
+  edges2d_kernel<<<grid_for(nv), 256, 0, s>>>(verts, nv, d_off, ncont, info, edges);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const int32_t* tris, int64_t nf, int64_t nv, unsigned long long* counts, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  validate_kernel<<<grid_for(nf), 256, 0, s>>>(tris, nf, nv, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  zero_u32_kernel<<<grid_for(n), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+}  // namespace pft

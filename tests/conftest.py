@@ -16,7 +16,7 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def dev():
+def gpu():
     """The GPU device for parity tests; fails (never skips) when no GPU is present."""
     import torch
 

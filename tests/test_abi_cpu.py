@@ -1,0 +1,142 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad arguments on the host.
+
+No compute call is made here: every call below fails (or returns early) in the
+library's synchronous argument validation, before any HIP API call.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2104_08309_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2104_08309_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "pft.h")).read()
+    return sorted(set(re.findall(r"\b(pft_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(_lib.EXPORTS)
+
+
+def test_version_and_last_error(lib):
+    assert lib.pft_version().decode().startswith("pft")
+    assert isinstance(lib.pft_last_error(), bytes)
+
+
+def V(x):
+    return ctypes.c_void_p(x)
+
+
+def test_forward_3d_validation(lib):
+    good = 0x10000  # never dereferenced: validation fails first
+    f = lib.pft_forward_3d
+    # negative counts
+    assert f(V(good), 1, -1, V(good), 1, V(good), 1, 1, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert b"negative" in lib.pft_last_error()
+    assert f(V(good), 1, 3, V(good), 1, V(good), 1, -5, 0, V(good), None, None) == _lib.PFT_EINVAL
+    # NULL with non-zero count
+    assert f(None, 1, 3, V(good), 1, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, None, 1, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good), 1, 4, 0, None, None, None) == _lib.PFT_EINVAL
+    # misalignment
+    assert f(V(good + 4), 1, 3, V(good), 1, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert b"misaligned" in lib.pft_last_error()
+    assert f(V(good), 1, 3, V(good), 1, V(good), 1, 4, 0, V(good + 8), None, None) == _lib.PFT_EINVAL  # c128 needs 16
+    # unsupported mode / dtype
+    assert f(V(good), 1, 3, V(good), 1, V(good), 1, 4, 7, V(good), None, None) == _lib.PFT_EUNSUPPORTED
+    assert f(V(good), 5, 3, V(good), 1, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EUNSUPPORTED
+    # nq == 0 is a valid no-op
+    assert f(V(good), 1, 3, V(good), 1, None, 1, 0, 0, None, None, None) == _lib.PFT_OK
+
+
+def test_backward_3d_validation(lib):
+    good = 0x10000
+    f = lib.pft_backward_3d
+    assert f(V(good), 1, 3, V(good), 1, V(good), 1, 4, 1, None, V(good), None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good), 1, 4, 1, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 0, 3, V(good), 1, V(good), 1, 4, 1, V(good), V(good + 2), None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 0, V(good), 1, V(good), 1, 4, 1, V(good), None, None) == _lib.PFT_OK  # nv == 0
+
+
+def test_forward_2d_validation(lib):
+    good = 0x10000
+    f = lib.pft_forward_2d
+    bad = (ctypes.c_int64 * 3)(0, 5, 3)          # decreasing
+    assert f(V(good), 3, bad, 2, V(good), 4, V(good), None) == _lib.PFT_EINVAL
+    wrong_end = (ctypes.c_int64 * 2)(0, 2)        # must end at nv
+    assert f(V(good), 3, wrong_end, 1, V(good), 4, V(good), None) == _lib.PFT_EINVAL
+    nonzero = (ctypes.c_int64 * 2)(1, 3)
+    assert f(V(good), 3, nonzero, 1, V(good), 4, V(good), None) == _lib.PFT_EINVAL
+    assert f(V(good), -1, None, 0, V(good), 4, V(good), None) == _lib.PFT_EINVAL
+    assert f(V(good + 4), 3, None, 0, V(good), 4, V(good), None) == _lib.PFT_EINVAL
+    assert f(V(good), 3, None, 0, V(good), 0, None, None) == _lib.PFT_OK
+
+
+def _batch(vo, to, qo):
+    b = _lib.PftMeshBatch()
+    arrs = [np.asarray(x, dtype=np.int64) for x in (vo, to, qo)]
+    b.n_meshes = arrs[0].size - 1
+    b.vert_offsets = arrs[0].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    b.tri_offsets = arrs[1].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    b.q_offsets = arrs[2].ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    b.verts = 0x10000
+    b.vdtype = 1
+    b.tris = 0x10000
+    b.q = 0x10000
+    b.qdtype = 1
+    return b, arrs
+
+
+def test_batch_validation(lib):
+    b, keep = _batch([0, 3, 6], [0, 1, 2], [1, 4, 8])  # q_offsets must start at 0
+    assert lib.pft_batch_forward(ctypes.byref(b), 0, V(0x10000), None, None) == _lib.PFT_EINVAL
+    b, keep = _batch([0, 3, 2], [0, 1, 2], [0, 4, 8])  # decreasing
+    assert lib.pft_batch_backward(ctypes.byref(b), 1, V(0x10000), V(0x10000), None) == _lib.PFT_EINVAL
+    assert lib.pft_batch_forward(None, 0, V(0x10000), None, None) == _lib.PFT_EINVAL
+    b, keep = _batch([0, 3, 6], [0, 1, 2], [0, 0, 0])  # no Q: no-op
+    assert lib.pft_batch_forward(ctypes.byref(b), 0, None, None, None) == _lib.PFT_OK
+
+
+def test_validate_mesh_and_profile_host_paths(lib):
+    n1, n2 = ctypes.c_int64(7), ctypes.c_int64(7)
+    assert lib.pft_validate_mesh(None, -1, 3, ctypes.byref(n1), ctypes.byref(n2), None) == _lib.PFT_EINVAL
+    assert lib.pft_validate_mesh(None, 0, 3, ctypes.byref(n1), ctypes.byref(n2), None) == _lib.PFT_OK
+    assert n1.value == 0 and n2.value == 0
+    assert lib.pft_profile_enable(1) == _lib.PFT_OK
+    cnt, ms = ctypes.c_int64(-1), ctypes.c_double(-1)
+    assert lib.pft_profile_read(b"fwd3d_fp32c", ctypes.byref(cnt), ctypes.byref(ms)) == _lib.PFT_OK
+    assert cnt.value == 0 and ms.value == 0.0
+    assert lib.pft_profile_reset() == _lib.PFT_OK
+    assert lib.pft_profile_enable(0) == _lib.PFT_OK
+
+
+def test_python_binding_rejects_cpu_tensors():
+    import torch
+
+    from paper_2104_08309_amd import api
+
+    v = torch.zeros(4, 3, dtype=torch.float64)
+    t = torch.zeros(2, 3, dtype=torch.int32)
+    q = torch.zeros(5, 3, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU"):
+        api.forward_3d(v, t, q)
+    with pytest.raises(ValueError):
+        api.mode_id("fp16")

@@ -1,0 +1,109 @@
+"""GPU parity of pft_backward_3d (vertex adjoint) and the autograd wrapper against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import meshgen as mg
+import oracle as O
+import paper_2104_08309_amd as pft
+from gpu_util import TOL_FP32C, dev, host, nrel, step
+
+pytestmark = pytest.mark.gpu
+
+TOL_GRAD64 = 1e-10
+
+
+def run_bwd(v, t, q, g, mode, vdt=torch.float64):
+    cdt = torch.complex128 if mode == "fp64" else torch.complex64
+    r = pft.backward_3d(dev(v, vdt), dev(t, torch.int32), dev(q), dev(g).to(cdt), mode=mode)
+    torch.cuda.synchronize()
+    return host(r).astype(np.float64)
+
+
+def test_small_meshes_random_cotangent(gpu):
+    rng = np.random.default_rng(0)
+    meshes = [mg.box(1.0, 1.3, 0.7, origin=(0.2, 0.1, -0.3)),
+              mg.ellipsoid_uv([3.0, 2.0, 1.5], 9, centre=(0.5, -1.0, 2.0)),
+              mg.icosphere(2, 2.0)]
+    for i, (v, t) in enumerate(meshes):
+        q = np.concatenate([mg.q_random_ball(700, 3.5, rng), [[0, 0, 0], [0, 0, 1.0], [1e-5, 0, 0]]])
+        g = rng.normal(size=q.shape[0]) + 1j * rng.normal(size=q.shape[0])
+        want = O.grad3d(v, t, q, g)
+        step(f"bwd mesh {i} fp64")
+        assert nrel(run_bwd(v, t, q, g, "fp64"), want) < TOL_GRAD64
+        step(f"bwd mesh {i} fp32c")
+        e = nrel(run_bwd(v, t, q, g.astype(np.complex64), "fp32c"), O.grad3d(v, t, q, g.astype(np.complex64)))
+        print(f"mesh {i} fp32c grad rel err {e:.3e}")
+        assert e < TOL_FP32C
+
+
+def test_f32_vertices(gpu):
+    v, t = mg.icosphere(2, 2.0)
+    v32 = v.astype(np.float32)
+    rng = np.random.default_rng(1)
+    q = mg.q_random_ball(500, 3.0, rng)
+    g = (rng.normal(size=500) + 1j * rng.normal(size=500)).astype(np.complex64)
+    want = O.grad3d(v32.astype(np.float64), t, q, g)
+    step("bwd f32 vertices fp32c")
+    got = run_bwd(v32, t, q, g, "fp32c", vdt=torch.float32)
+    assert nrel(got, want) < TOL_FP32C
+
+
+def test_autograd_intensity_loss(gpu):
+    """L = sum w (|F|^2 - I)^2 through PftFunction: gradient matches the oracle's chain rule."""
+    v0, t = mg.icosphere(3, 5.0)
+    rng = np.random.default_rng(2)
+    v = mg.perturb_radial(v0, 0.02, rng)
+    q = mg.q_slice_z(32, 0.8)
+    target = np.abs(O.ft3d(v0, t, q)) ** 2
+    w = 1.0 / (q.shape[0] * O.volume3d(v0, t) ** 4)
+    F = O.ft3d(v, t, q)
+    want = O.grad3d(v, t, q, 4 * w * (np.abs(F) ** 2 - target) * F)
+    for mode, tol in (("fp64", 1e-9), ("fp32c", 1e-4)):
+        step(f"autograd loss {mode}")
+        vt = dev(v).requires_grad_(True)
+        Fg = pft.ft3d(vt, dev(t, torch.int32), dev(q), mode)
+        loss = pft.intensity_loss(Fg.to(torch.complex128), dev(target), w)
+        loss.backward()
+        got = host(vt.grad)
+        e = nrel(got, want)
+        print(f"autograd {mode}: rel err {e:.3e}")
+        assert e < tol
+        # translation invariance of |F|^2: the vertex gradients sum to zero
+        assert np.max(np.abs(got.sum(axis=0))) < 1e-3 * np.max(np.abs(got))
+
+
+def test_deterministic_repeat(gpu):
+    v, t = mg.icosphere(3, 1.0)
+    rng = np.random.default_rng(3)
+    q = mg.q_random_ball(2000, 6.0, rng)
+    g = rng.normal(size=2000) + 1j * rng.normal(size=2000)
+    for mode in ("fp64", "fp32c"):
+        step(f"bwd determinism {mode}")
+        a, b = run_bwd(v, t, q, g, mode), run_bwd(v, t, q, g, mode)
+        assert np.array_equal(a, b)
+
+
+def test_config4_full_size_sampled_vertices(gpu):
+    """Icosphere L6 with radial noise, 256^2 Q slice: full adjoint on the GPU, oracle on sampled vertices."""
+    cfg = mg.config4()
+    v, t, q = cfg["verts"], cfg["tris"], cfg["q"]
+    rng = np.random.default_rng(4)
+    g = (rng.normal(size=q.shape[0]) + 1j * rng.normal(size=q.shape[0])) / q.shape[0]
+    ids = rng.choice(v.shape[0], 10, replace=False)
+    want = O.grad3d_vertices(v, t, q, g.astype(np.complex64), ids)
+    step("config4 bwd fp32c (81920 faces x 65536 Q)")
+    got = run_bwd(v, t, q, g.astype(np.complex64), "fp32c")
+    e = nrel(got[ids], want)
+    print(f"config4 fp32c sampled grad rel err {e:.3e}")
+    assert e < TOL_FP32C
+    step("config4 bwd fp64")
+    got64 = run_bwd(v, t, q, g, "fp64")
+    want64 = O.grad3d_vertices(v, t, q, g, ids)
+    assert nrel(got64[ids], want64) < TOL_GRAD64
+    # sum of all vertex gradients = Re sum_Q conj(g) i Q F(Q): the translation identity at full size
+    step("config4 fwd fp64 for the identity")
+    F = host(pft.forward_3d(dev(v), dev(t, torch.int32), dev(q), mode="fp64"))
+    lhs = got64.sum(axis=0)
+    rhs = np.real(np.sum(np.conj(g)[:, None] * 1j * q * F[:, None], axis=0))
+    assert np.max(np.abs(lhs - rhs)) < 1e-9 * np.max(np.abs(got64)) * np.sqrt(v.shape[0])

@@ -1,0 +1,141 @@
+"""GPU parity of pft_forward_3d (both arithmetic forms) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import meshgen as mg
+import oracle as O
+import paper_2104_08309_amd as pft
+from gpu_util import TOL_FP32C, TOL_FP64, dev, host, maxrel, nrel, special_q, step
+
+pytestmark = pytest.mark.gpu
+
+
+def run(v, t, q, mode, vdt=torch.float64, qdt=torch.float64, intensity=False):
+    r = pft.forward_3d(dev(v, vdt), dev(t, torch.int32), dev(q, qdt), mode=mode, intensity=intensity)
+    torch.cuda.synchronize()
+    if intensity:
+        return host(r[0]), host(r[1])
+    return host(r)
+
+
+def test_box_all_forms_and_degenerate_q(gpu):
+    v, t = mg.box(1.0, 1.3, 0.7, origin=(0.3, -0.2, 0.1))
+    rng = np.random.default_rng(0)
+    q = np.concatenate([rng.normal(size=(600, 3)) * 4.0, special_q(3.0), [[1e-6, 0, 0], [0, 0, 2.0]]])
+    want = O.ft3d(v, t, q)
+    step("box fp64")
+    assert nrel(run(v, t, q, "fp64"), want) < TOL_FP64
+    step("box fp32c")
+    got = run(v, t, q, "fp32c")
+    assert nrel(got, want) < TOL_FP32C and maxrel(got, want) < TOL_FP32C
+
+
+def test_ragged_tiles_ellipsoid(gpu):
+    """288 faces (4.5 LDS tiles) and 1000 Q (3.9 blocks): ragged tails on both axes."""
+    rng = np.random.default_rng(1)
+    v, t = mg.ellipsoid_uv([3.0, 2.0, 1.5], 9, rot=np.linalg.qr(rng.normal(size=(3, 3)))[0], centre=(1.0, 2.0, -1.0))
+    assert t.shape[0] == 288
+    q = np.concatenate([mg.q_random_ball(990, 3.0, rng), special_q(2.0, 3)])
+    want = O.ft3d(v, t, q)
+    for mode, tol in (("fp64", TOL_FP64), ("fp32c", TOL_FP32C)):
+        step(f"ellipsoid {mode}")
+        got = run(v, t, q, mode)
+        assert nrel(got, want) < tol, mode
+
+
+def test_input_dtypes(gpu):
+    v, t = mg.icosphere(2, 2.0)
+    rng = np.random.default_rng(2)
+    q = mg.q_random_ball(700, 4.0, rng)
+    v32, q32 = v.astype(np.float32), q.astype(np.float32)
+    want32 = O.ft3d(v32.astype(np.float64), t, q32.astype(np.float64))
+    step("dtypes fp64 mode, f32 inputs")
+    assert nrel(run(v32, t, q32, "fp64", torch.float32, torch.float32), want32) < TOL_FP64
+    step("dtypes fp32c mode, f32 inputs")
+    assert nrel(run(v32, t, q32, "fp32c", torch.float32, torch.float32), want32) < TOL_FP32C
+    step("dtypes fp32c mode, mixed")
+    want = O.ft3d(v32.astype(np.float64), t, q)
+    assert nrel(run(v32, t, q, "fp32c", torch.float32, torch.float64), want) < TOL_FP32C
+
+
+def test_intensity_output(gpu):
+    v, t = mg.icosphere(2, 2.0)
+    q = mg.q_random_ball(500, 3.0, np.random.default_rng(3))
+    for mode in ("fp64", "fp32c"):
+        step(f"intensity {mode}")
+        F, I = run(v, t, q, mode, intensity=True)
+        assert np.allclose(I, np.abs(F.astype(np.complex128)) ** 2, rtol=1e-6 if mode == "fp32c" else 1e-14)
+
+
+def test_empty_and_degenerate_meshes(gpu):
+    q = mg.q_random_ball(300, 2.0, np.random.default_rng(4))
+    q[0] = 0
+    # no faces at all
+    v0 = np.zeros((3, 3))
+    for mode in ("fp64", "fp32c"):
+        step(f"empty mesh {mode}")
+        got = pft.forward_3d(dev(v0), torch.zeros((0, 3), dtype=torch.int32, device="cuda:0"), dev(q), mode=mode)
+        assert torch.count_nonzero(got).item() == 0
+    # zero-area faces and an out-of-range index contribute nothing
+    v, t = mg.box(1.0, 1.0, 1.0)
+    v2 = np.concatenate([v, [[0.5, 0.5, 0.5]]])
+    t2 = np.concatenate([t, [[0, 1, 1], [8, 8, 8], [0, 8, 0], [0, 1, 99]]]).astype(np.int32)
+    want = O.ft3d(v, t, q)
+    for mode, tol in (("fp64", TOL_FP64), ("fp32c", TOL_FP32C)):
+        step(f"degenerate faces {mode}")
+        assert nrel(run(v2, t2, q, mode), want) < tol
+    step("validate_mesh")
+    bad, rep = pft.validate_mesh(dev(t2, torch.int32), v2.shape[0])
+    assert bad == 1 and rep == 3
+
+
+def test_empty_q_list(gpu):
+    v, t = mg.box()
+    step("nq = 0")
+    out = pft.forward_3d(dev(v), dev(t, torch.int32), torch.zeros((0, 3), dtype=torch.float64, device="cuda:0"))
+    assert out.shape == (0,)
+
+
+def test_deterministic_repeat(gpu):
+    v, t = mg.icosphere(3, 1.0)
+    q = mg.q_random_ball(3000, 8.0, np.random.default_rng(5))
+    for mode in ("fp64", "fp32c"):
+        step(f"determinism {mode}")
+        a, b = run(v, t, q, mode), run(v, t, q, mode)
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def test_config2_full_size_sampled(gpu):
+    """Icosphere L4 (5120 faces), full 64^3 grid on the GPU; oracle on a seeded sample incl. 0, axes, diagonal."""
+    cfg = mg.config2()
+    v, t, q = cfg["verts"], cfg["tris"], cfg["q"]
+    rng = np.random.default_rng(2)
+    idx = np.concatenate([rng.choice(q.shape[0], 1200, replace=False),
+                          np.nonzero(np.sum(q != 0, axis=1) <= 1)[0][::8],                  # 0 and the axes
+                          np.nonzero((q[:, 0] == q[:, 1]) & (q[:, 1] == q[:, 2]))[0]])      # the diagonal
+    want = O.ft3d(v, t, q[idx])
+    for mode, tol in (("fp64", TOL_FP64), ("fp32c", TOL_FP32C)):
+        step(f"config2 {mode} (262144 Q)")
+        got = run(v, t, q, mode)
+        assert np.all(np.isfinite(got))
+        e = nrel(got[idx], want)
+        print(f"config2 {mode}: rel err {e:.3e}, max rel {maxrel(got[idx], want):.3e}")
+        assert e < tol
+
+
+def test_config3_full_size_sampled(gpu):
+    """Union of 20 balls (~1e5 faces) on the full 128^3 grid (FP32C, c64 + |F|^2); oracle on a sample."""
+    cfg = mg.config3()
+    v, t, q = cfg["verts"], cfg["tris"], cfg["q"]
+    assert abs(t.shape[0] - 100_000) <= 5000
+    step("config3 fp32c (2097152 Q)")
+    F, I = run(v, t, q, "fp32c", qdt=torch.float32, intensity=True)
+    assert np.all(np.isfinite(F))
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([[np.nonzero(np.all(q == 0, axis=1))[0][0]], rng.choice(q.shape[0], 100, replace=False)])
+    want = O.ft3d(v, t, q[idx].astype(np.float32).astype(np.float64))
+    e = nrel(F[idx], want)
+    print(f"config3 fp32c: rel err {e:.3e}")
+    assert e < TOL_FP32C
+    assert np.allclose(I[idx], np.abs(F[idx].astype(np.complex128)) ** 2, rtol=1e-5)
