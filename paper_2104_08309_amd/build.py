@@ -38,10 +38,11 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libpft)")
 
 
-def _compile(src: str, hipcc: str, verbose: bool, build_dir: str, defines) -> str:
+def _compile(src: str, hipcc: str, verbose: bool, build_dir: str, defines, src_dir: str) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]
-    cmd = [hipcc] + lang + COMMON + [f"-D{d}" for d in defines] + ["-c", os.path.join(CSRC, src), "-o", obj]
+    flags = [f if f != CSRC else src_dir for f in COMMON]
+    cmd = [hipcc] + lang + flags + [f"-D{d}" for d in defines] + ["-c", os.path.join(src_dir, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,7 +51,8 @@ def _compile(src: str, hipcc: str, verbose: bool, build_dir: str, defines) -> st
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 8, out: str = LIB, defines=(), build_dir: str = BUILD) -> str:
+def build(verbose: bool = False, jobs: int = 8, out: str = LIB, defines=(), build_dir: str = BUILD,
+          src_dir: str = CSRC) -> str:
     """Compile all sources and link the library (default: libpft.so in the package); returns its path.
 
     ``defines`` are extra preprocessor definitions (tuning constants such as PFT_QPT=2).
@@ -58,7 +60,7 @@ def build(verbose: bool = False, jobs: int = 8, out: str = LIB, defines=(), buil
     hipcc = _hipcc()
     os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(SOURCES)))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, hipcc, verbose, build_dir, defines), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, hipcc, verbose, build_dir, defines, src_dir), SOURCES))
     tmp = out + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:

@@ -17,35 +17,74 @@ PFT_HD __forceinline__ double dsinc_series(double x) {
              x2 * (-1.0 / 3991680.0 + x2 * (1.0 / 518918400.0))))));
 }
 
-// Barycentric simplex series: sum_n i^n h_n(d0, d1, d2, dk) / (n+3)!, d0 + d1 + d2 = 0.
-// h4_n = H_n + dk h4_{n-1} where H_n = h_n(d0, d1, d2) = -e2 H_{n-2} + e3 H_{n-3}.
-PFT_HD inline void bary_series_f64(double e2, double e3, double m, double dk, double& yr, double& yi) {
-  double Hm3 = 0.0, Hm2 = 0.0, Hm1 = 1.0;  // H_{n-3}, H_{n-2}, H_{n-1} at n = 1 (H_0 = 1)
-  double h4 = 1.0;                         // h4_0
-  double inv = 1.0 / 24.0;                 // 1/(n+3)! at n = 1
-  yr = 1.0 / 6.0;
-  yi = 0.0;
-  const double mm = fmax(m, fabs(dk));
-  double mn = 1.0;
-  for (int n = 1; n < 90; ++n) {
-    const double H = -e2 * Hm2 + e3 * Hm3;
-    h4 = H + dk * h4;
-    const double term = h4 * inv;
-    switch (n & 3) {
-      case 0: yr += term; break;
-      case 1: yi += term; break;
-      case 2: yr -= term; break;
-      default: yi -= term; break;
+// 1/n! for n = 0..40 (device constant memory; a host copy for host builds of the binary64 math)
+#define PFT_INV_FACT_VALUES 1.0, 1.0, 5.0e-1, 1.6666666666666666e-1, 4.1666666666666664e-2, 8.3333333333333332e-3, \
+    1.3888888888888889e-3, 1.9841269841269841e-4, 2.4801587301587302e-5, 2.7557319223985893e-6, \
+    2.7557319223985888e-7, 2.5052108385441720e-8, 2.0876756987868100e-9, 1.6059043836821613e-10, \
+    1.1470745597729725e-11, 7.6471637318198164e-13, 4.7794773323873853e-14, 2.8114572543455206e-15, \
+    1.5619206968586225e-16, 8.2206352466243295e-18, 4.1103176233121648e-19, 1.9572941063391263e-20, \
+    8.8967913924505741e-22, 3.8681701706306835e-23, 1.6117375710961184e-24, 6.4469502843844736e-26, \
+    2.4795962632247972e-27, 9.1836898637955460e-29, 3.2798892370698378e-30, 1.1309962886447717e-31, \
+    3.7699876288159054e-33, 1.2161250415535181e-34, 3.8003907548547440e-36, 1.1516335620771951e-37, \
+    3.3871575355211618e-39, 9.6775929586318906e-41, 2.6882202662866363e-42, 7.2654601791530714e-44, \
+    1.9119632050402819e-45, 4.9024697565135435e-47, 1.2256174391283858e-48
+__constant__ const double kInvFactD[41] = {PFT_INV_FACT_VALUES};
+static const double kInvFactH[41] = {PFT_INV_FACT_VALUES};
+
+PFT_HD __forceinline__ double inv_fact(int n) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return kInvFactD[n];
+#else
+  return kInvFactH[n];
+#endif
+}
+
+// Barycentric moments of a triangle from its centred vertex phases
+// d0 + d1 + d2 = 0 (d_k = Q.(v_k - g)):
+//   Y_k = sum_n i^n h_n(d0, d1, d2, d_k) / (n+3)!   (k = 0, 1),
+//   J   = sum_n i^n h_n(d0, d1, d2) / (n+2)!         (so Y_2 = J - Y_0 - Y_1),
+// with H_n = h_n(d0, d1, d2) = -e2 H_{n-2} + e3 H_{n-3} and
+// h_n(d0, d1, d2, d_k) = H_n + d_k h_{n-1}(d0, d1, d2, d_k). Terms are added four
+// at a time until m^n / n! < tol (m = max |d_k|; the next term of Y is below
+// (1/6) m^n / n!, of J below (1/2) m^n / n!), or n reaches nmax.
+template <typename T>
+PFT_HD __forceinline__ void bary_moments(T d0, T d1, T m, T tol, int nmax, T* yr, T* yi, T& jr, T& ji) {
+  const T d2 = -d0 - d1;
+  const T e2 = d0 * d1 + d2 * (d0 + d1);
+  const T e3 = d0 * d1 * d2;
+  T Hm3 = T(0), Hm2 = T(0), Hm1 = T(1);  // H_{n-3}, H_{n-2}, H_{n-1} at n = 1
+  T a0 = T(1), a1 = T(1);                // h_{n-1}(d0,d1,d2,d0), h_{n-1}(d0,d1,d2,d1)
+  T y0r = T(1.0 / 6.0), y0i = T(0), y1r = T(1.0 / 6.0), y1i = T(0);
+  jr = T(0.5);
+  ji = T(0);
+  const T m2 = m * m, m4 = m2 * m2;
+  T mn = m;  // m^n at the start of each chunk
+  for (int n = 1;; n += 4) {
+    // i^n cycles (+i, -1, -i, +1) over n = 1, 2, 3, 4 (mod 4)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const T H = -e2 * Hm2 + e3 * Hm3;
+      a0 = H + d0 * a0;
+      a1 = H + d1 * a1;
+      const T c3 = T(inv_fact(n + r + 3)), c2 = T(inv_fact(n + r + 2));
+      if (r == 0) {
+        y0i += c3 * a0; y1i += c3 * a1; ji += c2 * H;
+      } else if (r == 1) {
+        y0r -= c3 * a0; y1r -= c3 * a1; jr -= c2 * H;
+      } else if (r == 2) {
+        y0i -= c3 * a0; y1i -= c3 * a1; ji -= c2 * H;
+      } else {
+        y0r += c3 * a0; y1r += c3 * a1; jr += c2 * H;
+      }
+      Hm3 = Hm2;
+      Hm2 = Hm1;
+      Hm1 = H;
     }
-    Hm3 = Hm2;
-    Hm2 = Hm1;
-    Hm1 = H;
-    mn *= mm;
-    // |h4_n| <= C(n+3, 3) mm^n
-    const double bound = mn * (double)((n + 1) * (n + 2) * (n + 3)) / 6.0 * inv;
-    if (n >= 3 && bound < 1e-17 * (fabs(yr) + fabs(yi))) break;
-    inv /= (double)(n + 4);
+    mn *= m4;
+    if (n + 4 >= nmax || mn * T(inv_fact(n + 4)) < tol) break;
   }
+  yr[0] = y0r; yi[0] = y0i;
+  yr[1] = y1r; yi[1] = y1i;
 }
 
 PFT_HD __forceinline__ void adj_term_f64(const Face64& f, const double* G, const double* Q, double gr,
@@ -67,17 +106,14 @@ PFT_HD __forceinline__ void adj_term_f64(const Face64& f, const double* G, const
     R[0] = R[1] = R[2] = 0.0;
     return;
   }
-  if (P2 < f.thr) {
-    const double e2 = q0 * q1 + q0 * q2 + q1 * q2;
-    const double e3 = q0 * q1 * q2;
-    const double m = fmax(fabs(q0), fmax(fabs(q1), fabs(q2)));
-    const double dk[3] = {q0, q1, q2};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      double yr, yi;
-      bary_series_f64(e2, e3, m, dk[k], yr, yi);
-      R[k] = zr * yr - zi * yi;
-    }
+  const double m = fmax(fabs(q0), fmax(fabs(q1), fabs(q2)));
+  if (m <= kSeriesMaxPhase) {
+    // barycentric moments by their series (no cancellation for |delta| <= 3)
+    double yr[2], yi[2], jr, ji;
+    bary_moments<double>(q0, q1, m, 1e-17, 33, yr, yi, jr, ji);
+    R[0] = zr * yr[0] - zi * yi[0];
+    R[1] = zr * yr[1] - zi * yi[1];
+    R[2] = (zr * jr - zi * ji) - R[0] - R[1];
     return;
   }
   const double p0 = 0.5 * q0, p1 = 0.5 * q1, p2 = 0.5 * q2;
@@ -144,45 +180,6 @@ PFT_HD __forceinline__ void adj_term_f64(const Face64& f, const double* G, const
 // ---------------------------------------------------------------------------
 // FP32-compensated
 // ---------------------------------------------------------------------------
-// Barycentric series in binary32, fixed number of terms chosen from the
-// largest |delta| of the lane (the series is only taken for |delta| <= 3).
-__device__ __forceinline__ void bary_series_f32(float e2, float e3, int nterms, float d0, float d1, float d2,
-                                                float* yr, float* yi) {
-  // 1/(n+3)! for n = 0..23
-  constexpr float kInvF[24] = {
-      1.6666667e-01f, 4.1666668e-02f, 8.3333338e-03f, 1.3888889e-03f, 1.9841270e-04f, 2.4801588e-05f,
-      2.7557319e-06f, 2.7557319e-07f, 2.5052108e-08f, 2.0876757e-09f, 1.6059044e-10f, 1.1470746e-11f,
-      7.6471636e-13f, 4.7794773e-14f, 2.8114573e-15f, 1.5619207e-16f, 8.2206352e-18f, 4.1103176e-19f,
-      1.9572941e-20f, 8.8967911e-22f, 3.8681702e-23f, 1.6117376e-24f, 6.4469503e-26f, 2.4795963e-27f};
-  float Hm3 = 0.0f, Hm2 = 0.0f, Hm1 = 1.0f;
-  float h0 = 1.0f, h1 = 1.0f, h2 = 1.0f;
-  float r0 = kInvF[0], r1 = kInvF[0], r2 = kInvF[0];
-  float i0 = 0.0f, i1 = 0.0f, i2 = 0.0f;
-  for (int n = 1; n < nterms; ++n) {
-    const float H = -e2 * Hm2 + e3 * Hm3;
-    h0 = H + d0 * h0;
-    h1 = H + d1 * h1;
-    h2 = H + d2 * h2;
-    const float c = kInvF[n];
-    const int ph = n & 3;
-    const float sgn = (ph < 2) ? c : -c;
-    if (ph & 1) {
-      i0 += sgn * h0;
-      i1 += sgn * h1;
-      i2 += sgn * h2;
-    } else {
-      r0 += sgn * h0;
-      r1 += sgn * h1;
-      r2 += sgn * h2;
-    }
-    Hm3 = Hm2;
-    Hm2 = Hm1;
-    Hm1 = H;
-  }
-  yr[0] = r0; yr[1] = r1; yr[2] = r2;
-  yi[0] = i0; yi[1] = i1; yi[2] = i2;
-}
-
 // sin(x)/x for |x| < 1 (Taylor series to x^10)
 __device__ __forceinline__ float sinc_series_f(float x) {
   const float x2 = x * x;
@@ -219,16 +216,14 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
     R[0] = R[1] = R[2] = 0.0f;
     return;
   }
-  if (P2 < fmaxf(f.thr, f.kap * Q2) && m <= 3.0f) {
-    const float e2 = q0 * q1 + q0 * q2 + q1 * q2;
-    const float e3 = q0 * q1 * q2;
-    // terms for a truncation error below 1e-9 of the leading 1/6 at the lane's largest |delta|
-    const int nterms = m < 0.35f ? 9 : (m < 0.8f ? 12 : (m < 1.2f ? 14 : (m < 1.6f ? 16 : 21)));
-    float yr[3], yi[3];
-    bary_series_f32(e2, e3, nterms, q0, q1, q2, yr, yi);
+  if (m <= (float)kSeriesMaxPhase) {
+    // barycentric moments by their series in binary32 (terms decrease from the
+    // start for |delta| <= 3; no cancellation with the face's size in Q)
+    float yr[2], yi[2], jr, ji;
+    bary_moments<float>(q0, q1, m, 1e-8f, 29, yr, yi, jr, ji);
     R[0] = zr * yr[0] - zi * yi[0];
     R[1] = zr * yr[1] - zi * yi[1];
-    R[2] = zr * yr[2] - zi * yi[2];
+    R[2] = (zr * jr - zi * ji) - R[0] - R[1];
     return;
   }
   const float w0 = Px * f.d0[0] + Py * f.d0[1] + Pz * f.d0[2];
@@ -287,67 +282,114 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
 }
 
 // ---------------------------------------------------------------------------
-// One block's share of the adjoint: the faces staged in LDS (`nt` of them)
-// against the Q range [qb, qe), one Q per thread per pass. For each face the
-// three real weights of the 256 Q of a pass are summed across each wavefront
-// by lane shuffles and lane 0 adds them to that wavefront's binary64 slot in
-// `wacc[wave][3 j + k]` (zeroed by the caller). Faces are visited one at a
-// time, so the working set stays that of a single (Q, face) term.
+// Wavefront sum by DPP: row shifts 1, 2, 4, 8 leave each 16-lane row's sum in
+// its last lane, the row broadcasts 15 and 31 fold rows 0..3 into lane 63.
+// Lanes shifted in from outside a row read as zero (bound control).
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true);
+  return v + __int_as_float(s);
+}
+
+__device__ __forceinline__ float wave_total(float v) {
+  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+  // binary64 path (FP64 mode): shuffles through the LDS crossbar
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// One block's share of the adjoint: the faces staged in LDS (`nt` of them)
+// against the Q range [qb, qe), kQPTB Q per thread per pass (strided by the
+// block size). For each face the real weights of a pass are summed per thread,
+// then across the wavefront, and lane 0 adds the wavefront's sum to its
+// binary64 slot `wacc[wave][3 j + k]` (zeroed by the caller). Faces are
+// visited one at a time, so the working set stays that of kQPTB terms.
+// ---------------------------------------------------------------------------
 template <int MODE>
 __device__ __forceinline__ void adj_tile_accumulate(const unsigned char* smem_tile, const double (*gtile)[8], int nt,
                                                     const double* tc, int64_t qb, int64_t qe, const void* q,
                                                     int qdtype, const void* grad_out,
                                                     double (*wacc)[kTileFB * 3]) {
+  constexpr int P = kQPTB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int64_t q0 = qb; q0 < qe; q0 += kBlock) {
-    const int64_t qi = q0 + tid;
-    double Qd[3] = {0.0, 0.0, 0.0};
-    double hr = 0.0, hi = 0.0;
-    if (qi < qe) {
-      load_q3(q, qdtype, qi, Qd);
-      double gr, gi;
-      if (MODE == PFT_FP64) {
-        const double2 g = static_cast<const double2*>(grad_out)[qi];
-        gr = g.x;
-        gi = g.y;
-      } else {
-        const float2 g = static_cast<const float2*>(grad_out)[qi];
-        gr = (double)g.x;
-        gi = (double)g.y;
+  for (int64_t q0 = qb; q0 < qe; q0 += (int64_t)kBlock * P) {
+    double Qd[P][3];
+    double hr[P], hi[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int64_t qi = q0 + (int64_t)p * kBlock + tid;
+      Qd[p][0] = Qd[p][1] = Qd[p][2] = 0.0;
+      hr[p] = hi[p] = 0.0;
+      if (qi < qe) {
+        load_q3(q, qdtype, qi, Qd[p]);
+        double gr, gi;
+        if (MODE == PFT_FP64) {
+          const double2 g = static_cast<const double2*>(grad_out)[qi];
+          gr = g.x;
+          gi = g.y;
+        } else {
+          const float2 g = static_cast<const float2*>(grad_out)[qi];
+          gr = (double)g.x;
+          gi = (double)g.y;
+        }
+        centred_cotangent(gr, gi, Qd[p], tc, hr[p], hi[p]);
       }
-      centred_cotangent(gr, gi, Qd, tc, hr, hi);
     }
     if (MODE == PFT_FP64) {
       const Face64* tile = reinterpret_cast<const Face64*>(smem_tile);
 #pragma unroll 1
       for (int j = 0; j < nt; ++j) {
-        double R[3];
-        adj_term_f64(tile[j], gtile[j], Qd, hr, hi, R);
+        double S[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          double R[3];
+          adj_term_f64(tile[j], gtile[j], Qd[p], hr[p], hi[p], R);
+          S[0] += R[0];
+          S[1] += R[1];
+          S[2] += R[2];
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const double v = wave_sum(R[k]);
+          const double v = wave_total(S[k]);
           if (lane == 0) wacc[wave][3 * j + k] += v;
         }
       }
     } else {
       const Face32B* tile = reinterpret_cast<const Face32B*>(smem_tile);
-      const float qx = (float)Qd[0], qy = (float)Qd[1], qz = (float)Qd[2];
-      const float Q2 = qx * qx + qy * qy + qz * qz;
+      float qx[P], qy[P], qz[P], Q2[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        qx[p] = (float)Qd[p][0];
+        qy[p] = (float)Qd[p][1];
+        qz[p] = (float)Qd[p][2];
+        Q2[p] = qx[p] * qx[p] + qy[p] * qy[p] + qz[p] * qz[p];
+      }
 #pragma unroll 1
       for (int j = 0; j < nt; ++j) {
-        float R[3];
-        adj_term_fp32c(tile[j], qx, qy, qz, Q2, Qd, (float)hr, (float)hi, R);
+        float S[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          float R[3];
+          adj_term_fp32c(tile[j], qx[p], qy[p], qz[p], Q2[p], Qd[p], (float)hr[p], (float)hi[p], R);
+          S[0] += R[0];
+          S[1] += R[1];
+          S[2] += R[2];
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const float v = wave_sum(R[k]);
+          const float v = wave_total(S[k]);
           if (lane == 0) wacc[wave][3 * j + k] += (double)v;
         }
       }

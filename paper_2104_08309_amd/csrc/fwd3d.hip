@@ -96,14 +96,18 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
     for (int j = 0; j < nt; ++j) {
+      // the edge form for every lane (no per-Q branch, so the kQPT streams
+      // interleave); small-|Q| lanes discard this sum and use the series below
+      float Tr[kQPT], Ti[kQPT], cf[kQPT], sf[kQPT];
+      bool ser[kQPT];
+#pragma unroll
+      for (int k = 0; k < kQPT; ++k)
+        face_term_fp32c(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr[k], Ti[k], ser[k], cf[k], sf[k]);
 #pragma unroll
       for (int k = 0; k < kQPT; ++k) {
-        if (!small[k]) {
-          float Tr, Ti;
-          face_term_fp32c(tile[j], a.f64 + t0 + j, qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr, Ti);
-          tr[k] += Tr;
-          ti[k] += Ti;
-        }
+        if (ser[k] && !small[k]) face_series_fp32c(a.f64 + t0 + j, Qd[k], cf[k], sf[k], Tr[k], Ti[k]);
+        tr[k] += Tr[k];
+        ti[k] += Ti[k];
       }
     }
 #pragma unroll

@@ -65,8 +65,14 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 // ---------------------------------------------------------------------------
 // FP32-compensated per-(Q, face) term
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void face_term_fp32c(const Face32& f, const Face64* __restrict__ fa, float qx, float qy,
-                                                float qz, float Q2, const double* Qd, float& Tr, float& Ti) {
+// Edge-sum form of the FP32-compensated face term. Sets `need_series` when the
+// pair is near-degenerate (Q close to the face normal) so that the caller
+// replaces the result with face_series_fp32c; keeping the branch out of this
+// function leaves straight-line code that the compiler can interleave across
+// the several Q a thread evaluates.
+__device__ __forceinline__ void face_term_fp32c(const Face32& f, float qx, float qy, float qz, float Q2,
+                                                const double* Qd, float& Tr, float& Ti, bool& need_series,
+                                                float& cf_out, float& sf_out) {
   const float N0 = f.N[0], N1 = f.N[1], N2 = f.N[2];
   const float QN = qx * N0 + qy * N1 + qz * N2;
   const float Px = qy * N2 - qz * N1;
@@ -90,25 +96,32 @@ __device__ __forceinline__ void face_term_fp32c(const Face32& f, const Face64* _
   const float a2 = w2 * sinc2pi_turns(p0 - p2);
   const float Sr = a0 * c2 + a1 * c0 + a2 * c1;
   const float Si = -(a0 * s2 + a1 * s0 + a2 * s1);
-  // face origin phase Q.g in turns, reduced to [-1/2, 1/2] in binary64
+  // face origin phase Q.g in turns, reduced in binary64
   const double ph = Qd[0] * f.gt[0] + Qd[1] * f.gt[1] + Qd[2] * f.gt[2];
-  const float r = (float)(ph - rint(ph));
+  const float r = (float)__builtin_amdgcn_fract(ph);  // fractional turns in [0, 1)
   const float cf = cos_turns(r), sf = sin_turns(r);
-  const float co = QN * rcp_f(fmaxf(P2, 1e-30f)) * kInv2PiF;
+  // w_l carry 1/(2 pi) from the record, cancelling the 2 pi of sinc2pi_turns
+  const float co = QN * rcp_f(fmaxf(P2, 1e-30f));
   const float Ur = co * cf, Ui = co * sf;
   Tr = Ur * Sr - Ui * Si;
   Ti = Ur * Si + Ui * Sr;
-  if (P2 < fmaxf(f.thr, f.kap * Q2)) {
-    // Q nearly along the face normal: binary64 simplex series of the face.
-    const Face64 F = *fa;
-    const double QNd = Qd[0] * F.N[0] + Qd[1] * F.N[1] + Qd[2] * F.N[2];
-    const double q0 = Qd[0] * F.u0[0] + Qd[1] * F.u0[1] + Qd[2] * F.u0[2];
-    const double q1 = Qd[0] * F.u1[0] + Qd[1] * F.u1[1] + Qd[2] * F.u1[2];
-    double sr, si;
-    face_series_f64(q0, q1, -q0 - q1, sr, si);
-    Tr = (float)(QNd * ((double)cf * si + (double)sf * sr));
-    Ti = (float)(-QNd * ((double)cf * sr - (double)sf * si));
-  }
+  need_series = P2 < fmaxf(f.thr, f.kap * Q2);
+  cf_out = cf;
+  sf_out = sf;
+}
+
+// Q nearly along the face normal: binary64 simplex series of the face,
+// T = -i (Q.N) exp(i Q.g) sum_n i^n h_n(delta) / (n+2)!.
+__device__ __forceinline__ void face_series_fp32c(const Face64* __restrict__ fa, const double* Qd, float cf, float sf,
+                                               float& Tr, float& Ti) {
+  const Face64 F = *fa;
+  const double QNd = Qd[0] * F.N[0] + Qd[1] * F.N[1] + Qd[2] * F.N[2];
+  const double q0 = Qd[0] * F.u0[0] + Qd[1] * F.u0[1] + Qd[2] * F.u0[2];
+  const double q1 = Qd[0] * F.u1[0] + Qd[1] * F.u1[1] + Qd[2] * F.u1[2];
+  double sr, si;
+  face_series_f64(q0, q1, -q0 - q1, sr, si);
+  Tr = (float)(QNd * ((double)cf * si + (double)sf * sr));
+  Ti = (float)(-QNd * ((double)cf * sr - (double)sf * si));
 }
 
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {

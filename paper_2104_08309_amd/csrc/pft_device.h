@@ -63,11 +63,11 @@ __device__ __forceinline__ float sin_turns(float x) { return __builtin_amdgcn_si
 __device__ __forceinline__ float cos_turns(float x) { return __builtin_amdgcn_cosf(x); }
 __device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// sin(2 pi x) / x for x in turns, i.e. 2 pi sinc(2 pi x); the removable point x = 0 gives 2 pi.
-__device__ __forceinline__ float sinc2pi_turns(float x) {
-  const float v = sin_turns(x) * rcp_f(x);
-  return x != 0.0f ? v : kTwoPiF;
-}
+// sin(2 pi x) / x for x in turns, i.e. 2 pi sinc(2 pi x). At the removable point
+// x = 0 the product is 0 * inf = NaN, and the IEEE minimum with 2 pi (which
+// returns the non-NaN operand) yields the limit 2 pi; elsewhere the quotient is
+// at most 2 pi, so the minimum leaves it unchanged.
+__device__ __forceinline__ float sinc2pi_turns(float x) { return fminf(sin_turns(x) * rcp_f(x), kTwoPiF); }
 
 // Complete homogeneous series with centred arguments (d0 + d1 + d2 = 0):
 // sum_{n>=0} i^n h_n(d0, d1, d2) / (n + 2)!, binary64, terms added until they

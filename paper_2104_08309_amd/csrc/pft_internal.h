@@ -17,9 +17,13 @@ constexpr int kBlock = 256;        // threads per block for the Q-parallel kerne
 constexpr int kTileF = 64;         // faces staged in LDS per tile (forward)
 constexpr int kTileFB = 16;        // faces per block in the adjoint
 #ifndef PFT_QPT
-#define PFT_QPT 2
+#define PFT_QPT 3
 #endif
 constexpr int kQPT = PFT_QPT;      // Q per thread in the FP32C forward
+#ifndef PFT_QPTB
+#define PFT_QPTB 3
+#endif
+constexpr int kQPTB = PFT_QPTB;    // Q per thread per pass in the adjoint
 constexpr int kTileE = 64;         // 2D edges staged in LDS per tile
 
 // Series thresholds (dimensionless). A (Q, face) pair uses the face's simplex
@@ -28,7 +32,11 @@ constexpr int kTileE = 64;         // 2D edges staged in LDS per tile
 constexpr double kTauF64 = 0.05;     // forward and adjoint, FP64 mode
 constexpr double kTauF32 = 0.1;      // forward, FP32C mode (series in FP64)
 constexpr double kTauRel32 = 0.02;   // forward, FP32C mode, relative test
-constexpr double kTauB32 = 1.5;      // adjoint, FP32C mode (series in FP32)
+constexpr double kTauB32 = 1.5;      // (record field of the FP32C adjoint; empty-face flag)
+// The adjoint evaluates each face's barycentric moments by their series when the
+// largest centred vertex phase |Q.(v_k - g)| is at most this, by the
+// differentiated edge sums otherwise (there |Q_perp| L > 4.5).
+constexpr double kSeriesMaxPhase = 3.0;
 constexpr double kTauRelB32 = 0.05;  // adjoint, FP32C mode, relative test
 // Whole-mesh series (fan of tetrahedra from the vertex mean) when |Q| R < tau0.
 constexpr double kTau0F64 = 0.01;
@@ -60,8 +68,8 @@ static_assert(sizeof(Face64) == 128, "Face64 layout");
 struct alignas(16) Face32 {
   double gt[3];   // centroid / (2 pi), binary64: face origin phase in turns is Q . gt
   float N[3];     // (b - a) x (c - a)
-  float d0[3];    // b - a
-  float d1[3];    // c - b
+  float d0[3];    // (b - a) / (2 pi)
+  float d1[3];    // (c - b) / (2 pi)
   float h0[3];    // (a - g) / (4 pi): half-vertex phase in turns is Q . h
   float h1[3];    // (b - g) / (4 pi)
   float thr;      // tau^2 |N|^2 / L^2

@@ -182,8 +182,8 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
   for (int k = 0; k < 3; ++k) {
     r.gt[k] = f.g[k] * kInv2Pi;
     r.N[k] = (float)f.N[k];
-    r.d0[k] = (float)(f.u1[k] - f.u0[k]);
-    r.d1[k] = (float)(-f.u0[k] - 2.0 * f.u1[k]);
+    r.d0[k] = (float)((f.u1[k] - f.u0[k]) * kInv2Pi);
+    r.d1[k] = (float)((-f.u0[k] - 2.0 * f.u1[k]) * kInv2Pi);
     r.h0[k] = (float)(f.u0[k] * kInv4Pi);
     r.h1[k] = (float)(f.u1[k] * kInv4Pi);
   }
