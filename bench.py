@@ -26,14 +26,45 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic operation counts per (triangle, Q) pair (FMA = 2 flops; sin, cos,
-# reciprocal = 1 each), derived op by op from the edge-sum formulas:
-#   forward  = 104 flop  (edge form of one face term, incl. the face-origin phase)
-#   adjoint  = 232 flop  (recomputed face term + the three barycentric moments)
+# Algorithmic operation counts per (triangle, Q) pair (multiply or add = 1,
+# FMA = 2; sin, cos, reciprocal = 1 each):
+#   forward  = 104 flop: one face term of the edge sum (cross and dot products with
+#              Q, three edge sincs, two half-vertex phases, the face-origin phase,
+#              the complex products and the accumulation);
+#   adjoint  = 200 flop: the same recomputed terms plus the derivative of the edge
+#              sum in Q that gives the three barycentric moments and their real
+#              weights against the cotangent.
 FLOP_FWD = 104.0
-FLOP_BWD = 232.0
+FLOP_BWD = 200.0
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (AMD published)
 PEAK_FP64_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+KERNEL_SOURCES = os.path.join(ROOT, "paper_2104_08309_amd", "csrc")
+
+
+def kernel_source_digest():
+    """sha256 over the HIP sources: ties a traffic measurement to the code it was taken on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_SOURCES)):
+        with open(os.path.join(KERNEL_SOURCES, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None if stale."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.loads(f.read())
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != kernel_source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def _oracle_chunk(args):
@@ -71,8 +102,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="Q points of the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=8192, help="Q points of the oracle's timed sample")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the transform shards by Q across GPUs "
@@ -155,15 +188,23 @@ def main():
         acc["fwd_rel_err_vs_fp64_gpu"] = float(np.linalg.norm(F32h - F64) / np.linalg.norm(F64))
         acc["bwd_rel_err_vs_fp64_gpu"] = float(np.linalg.norm(dV32h - dV64) / np.linalg.norm(dV64))
 
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # roofline of the dominant kernel (the longer of the forward and adjoint kernels)
-    if bwd_ms >= fwd_ms:
-        dom, dom_ms, flop = "bwd3d_fp32c", bwd_ms, FLOP_BWD
-    else:
-        dom, dom_ms, flop = "fwd3d_fp32c", fwd_ms, FLOP_FWD
-    achieved = flop * nf * nq / (dom_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                "kernel_ms": dom_ms, "flop_per_face_q": flop}
+    def roof(kernel, ms, flop):
+        achieved = flop * nf * nq / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(kernel), "kernel": kernel,
+                "kernel_ms": ms, "flop_per_face_q": flop, "launch_face_q": nf * nq}
+
+    r_fwd = roof("fwd3d_fp32c", fwd_ms, FLOP_FWD)
+    r_bwd = roof("bwd3d_fp32c", bwd_ms, FLOP_BWD)
+    roofline, other = (r_bwd, r_fwd) if bwd_ms >= fwd_ms else (r_fwd, r_bwd)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -206,6 +247,7 @@ def main():
         "speedup_vs_fp64_gpu": (fp64["ms_per_step"] / (dt32 * 1e3)) if fp64 else None,
         "accuracy": acc,
         "roofline": roofline,
+        "roofline_other_kernel": other,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
