@@ -17,28 +17,6 @@ PFT_HD __forceinline__ double dsinc_series(double x) {
              x2 * (-1.0 / 3991680.0 + x2 * (1.0 / 518918400.0))))));
 }
 
-// 1/n! for n = 0..40 (device constant memory; a host copy for host builds of the binary64 math)
-#define PFT_INV_FACT_VALUES 1.0, 1.0, 5.0e-1, 1.6666666666666666e-1, 4.1666666666666664e-2, 8.3333333333333332e-3, \
-    1.3888888888888889e-3, 1.9841269841269841e-4, 2.4801587301587302e-5, 2.7557319223985893e-6, \
-    2.7557319223985888e-7, 2.5052108385441720e-8, 2.0876756987868100e-9, 1.6059043836821613e-10, \
-    1.1470745597729725e-11, 7.6471637318198164e-13, 4.7794773323873853e-14, 2.8114572543455206e-15, \
-    1.5619206968586225e-16, 8.2206352466243295e-18, 4.1103176233121648e-19, 1.9572941063391263e-20, \
-    8.8967913924505741e-22, 3.8681701706306835e-23, 1.6117375710961184e-24, 6.4469502843844736e-26, \
-    2.4795962632247972e-27, 9.1836898637955460e-29, 3.2798892370698378e-30, 1.1309962886447717e-31, \
-    3.7699876288159054e-33, 1.2161250415535181e-34, 3.8003907548547440e-36, 1.1516335620771951e-37, \
-    3.3871575355211618e-39, 9.6775929586318906e-41, 2.6882202662866363e-42, 7.2654601791530714e-44, \
-    1.9119632050402819e-45, 4.9024697565135435e-47, 1.2256174391283858e-48
-__constant__ const double kInvFactD[41] = {PFT_INV_FACT_VALUES};
-static const double kInvFactH[41] = {PFT_INV_FACT_VALUES};
-
-PFT_HD __forceinline__ double inv_fact(int n) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  return kInvFactD[n];
-#else
-  return kInvFactH[n];
-#endif
-}
-
 // Barycentric moments of a triangle from its centred vertex phases
 // d0 + d1 + d2 = 0 (d_k = Q.(v_k - g)):
 //   Y_k = sum_n i^n h_n(d0, d1, d2, d_k) / (n+3)!   (k = 0, 1),

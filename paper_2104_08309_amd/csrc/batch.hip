@@ -79,10 +79,10 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         if (!small) {
           float tr = 0.0f, ti = 0.0f;
           for (int j = 0; j < nt; ++j) {
-            float Tr, Ti, cf, sf;
+            float Tr, Ti, ph;
             bool ser;
-            face_term_fp32c(tile[j], qx, qy, qz, Q2, Qd, Tr, Ti, ser, cf, sf);
-            if (ser) face_series_fp32c(f64 + t0 + j, Qd, cf, sf, Tr, Ti);
+            face_term_fp32c(tile[j], qx, qy, qz, Q2, Qd, Tr, Ti, ser, ph);
+            if (ser) face_series_fp32c(f64 + t0 + j, Qd, ph, Tr, Ti);
             tr += Tr;
             ti += Ti;
           }

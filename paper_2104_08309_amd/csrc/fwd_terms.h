@@ -72,7 +72,7 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 // the several Q a thread evaluates.
 __device__ __forceinline__ void face_term_fp32c(const Face32& f, float qx, float qy, float qz, float Q2,
                                                 const double* Qd, float& Tr, float& Ti, bool& need_series,
-                                                float& cf_out, float& sf_out) {
+                                                float& phase_out) {
   const float N0 = f.N[0], N1 = f.N[1], N2 = f.N[2];
   const float QN = qx * N0 + qy * N1 + qz * N2;
   const float Px = qy * N2 - qz * N1;
@@ -86,34 +86,29 @@ __device__ __forceinline__ void face_term_fp32c(const Face32& f, float qx, float
   const float p0 = qx * f.h0[0] + qy * f.h0[1] + qz * f.h0[2];
   const float p1 = qx * f.h1[0] + qy * f.h1[1] + qz * f.h1[2];
   const float p2 = -p0 - p1;
-  const float s0 = sin_turns(p0), c0 = cos_turns(p0);
-  const float s1 = sin_turns(p1), c1 = cos_turns(p1);
-  const float c2 = c0 * c1 - s0 * s1;
-  const float s2 = -(s0 * c1 + c0 * s1);
   // 2 pi sinc(eta_l), eta_l = psi_{l+1} - psi_l (turns)
   const float a0 = w0 * sinc2pi_turns(p1 - p0);
   const float a1 = w1 * sinc2pi_turns(p2 - p1);
   const float a2 = w2 * sinc2pi_turns(p0 - p2);
-  const float Sr = a0 * c2 + a1 * c0 + a2 * c1;
-  const float Si = -(a0 * s2 + a1 * s0 + a2 * s1);
-  // face origin phase Q.g in turns, reduced in binary64
+  // face origin phase Q.g in turns, reduced to [-1/2, 1/2] in binary64; the edge
+  // midpoint phases are Q.m_l = Q.g - psi_{l+2}
   const double ph = Qd[0] * f.gt[0] + Qd[1] * f.gt[1] + Qd[2] * f.gt[2];
-  const float r = (float)__builtin_amdgcn_fract(ph);  // fractional turns in [0, 1)
-  const float cf = cos_turns(r), sf = sin_turns(r);
-  // w_l carry 1/(2 pi) from the record, cancelling the 2 pi of sinc2pi_turns
+  const float r = (float)(ph - rint(ph));
+  const float t0 = r - p2, t1 = r - p0, t2 = r - p1;
+  const float Sr = a0 * cos_turns(t0) + a1 * cos_turns(t1) + a2 * cos_turns(t2);
+  const float Si = a0 * sin_turns(t0) + a1 * sin_turns(t1) + a2 * sin_turns(t2);
   const float co = QN * rcp_f(fmaxf(P2, 1e-30f));
-  const float Ur = co * cf, Ui = co * sf;
-  Tr = Ur * Sr - Ui * Si;
-  Ti = Ur * Si + Ui * Sr;
+  Tr = co * Sr;
+  Ti = co * Si;
   need_series = P2 < fmaxf(f.thr, f.kap * Q2);
-  cf_out = cf;
-  sf_out = sf;
+  phase_out = r;  // the series fix-up forms exp(i Q.g) itself (rare path)
 }
 
 // Q nearly along the face normal: binary64 simplex series of the face,
 // T = -i (Q.N) exp(i Q.g) sum_n i^n h_n(delta) / (n+2)!.
-__device__ __forceinline__ void face_series_fp32c(const Face64* __restrict__ fa, const double* Qd, float cf, float sf,
+__device__ __forceinline__ void face_series_fp32c(const Face64* __restrict__ fa, const double* Qd, float r,
                                                float& Tr, float& Ti) {
+  const float cf = cos_turns(r), sf = sin_turns(r);
   const Face64 F = *fa;
   const double QNd = Qd[0] * F.N[0] + Qd[1] * F.N[1] + Qd[2] * F.N[2];
   const double q0 = Qd[0] * F.u0[0] + Qd[1] * F.u0[1] + Qd[2] * F.u0[2];
