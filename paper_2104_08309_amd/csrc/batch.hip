@@ -79,10 +79,11 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         if (!small) {
           float tr = 0.0f, ti = 0.0f;
           for (int j = 0; j < nt; ++j) {
-            float Tr, Ti, ph;
+            float Tr, Ti;
+            SeriesInputs sd;
             bool ser;
-            face_term_fp32c(tile[j], qx, qy, qz, Q2, Qd, Tr, Ti, ser, ph);
-            if (ser) face_series_fp32c(f64 + t0 + j, Qd, ph, Tr, Ti);
+            face_term_fp32c(tile[j], qx, qy, qz, Q2, Qd, Tr, Ti, ser, sd);
+            if (ser) face_series_fp32c(sd, Tr, Ti);
             tr += Tr;
             ti += Ti;
           }

@@ -98,14 +98,15 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
     for (int j = 0; j < nt; ++j) {
       // the edge form for every lane (no per-Q branch, so the kQPT streams
       // interleave); small-|Q| lanes discard this sum and use the series below
-      float Tr[kQPT], Ti[kQPT], ph[kQPT];
+      float Tr[kQPT], Ti[kQPT];
+      SeriesInputs sd[kQPT];
       bool ser[kQPT];
 #pragma unroll
       for (int k = 0; k < kQPT; ++k)
-        face_term_fp32c(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr[k], Ti[k], ser[k], ph[k]);
+        face_term_fp32c(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr[k], Ti[k], ser[k], sd[k]);
 #pragma unroll
       for (int k = 0; k < kQPT; ++k) {
-        if (ser[k] && !small[k]) face_series_fp32c(a.f64 + t0 + j, Qd[k], ph[k], Tr[k], Ti[k]);
+        if (ser[k] && !small[k]) face_series_fp32c(sd[k], Tr[k], Ti[k]);
         tr[k] += Tr[k];
         ti[k] += Ti[k];
       }

@@ -32,7 +32,7 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
   const double q1 = Q[0] * f.u1[0] + Q[1] * f.u1[1] + Q[2] * f.u1[2];
   if (P2 < f.thr) {
     double sr, si;
-    face_series_f64(q0, q1, -q0 - q1, sr, si);
+    face_series_f64(q0, q1, -q0 - q1, sr, si, 1e-17);
     // T = -i (Q.N) exp(i phi) s
     Tr = QN * (cf * si + sf * sr);
     Ti = -QN * (cf * sr - sf * si);
@@ -69,22 +69,29 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 // pair is near-degenerate (Q close to the face normal) so that the caller
 // replaces the result with face_series_fp32c; keeping the branch out of this
 // function leaves straight-line code that the compiler can interleave across
-// the several Q a thread evaluates.
+// the several Q a thread evaluates. The quantities the series needs (the
+// half-vertex phases, Q.N and the reduced face phase) are returned in `sd`.
+struct SeriesInputs {
+  float p0, p1;  // half-vertex phases psi_0, psi_1 in turns
+  float QN;      // Q . N
+  float r;       // face origin phase Q.g in turns, reduced to [-1/2, 1/2]
+};
+
 __device__ __forceinline__ void face_term_fp32c(const Face32& f, float qx, float qy, float qz, float Q2,
                                                 const double* Qd, float& Tr, float& Ti, bool& need_series,
-                                                float& phase_out) {
-  const float N0 = f.N[0], N1 = f.N[1], N2 = f.N[2];
-  const float QN = qx * N0 + qy * N1 + qz * N2;
-  const float Px = qy * N2 - qz * N1;
-  const float Py = qz * N0 - qx * N2;
-  const float Pz = qx * N1 - qy * N0;
-  const float P2 = Px * Px + Py * Py + Pz * Pz;
-  const float w0 = Px * f.d0[0] + Py * f.d0[1] + Pz * f.d0[2];
-  const float w1 = Px * f.d1[0] + Py * f.d1[1] + Pz * f.d1[2];
+                                                SeriesInputs& sd) {
+  const float QN = qx * f.N[0] + qy * f.N[1] + qz * f.N[2];
+  // in-plane components of Q (times |N|); P = Q x N = s2 e1 - s1 e2
+  const float s1 = qx * f.E1[0] + qy * f.E1[1] + qz * f.E1[2];
+  const float s2 = qx * f.E2[0] + qy * f.E2[1] + qz * f.E2[2];
+  const float P2 = s1 * s1 + s2 * s2;
+  // edge weights w_l = P . d_l (over 2 pi)
+  const float w0 = s2 * f.al[0] + s1 * f.be[0];
+  const float w1 = s2 * f.al[1] + s1 * f.be[1];
   const float w2 = -w0 - w1;
   // half-vertex phases psi_k in turns
-  const float p0 = qx * f.h0[0] + qy * f.h0[1] + qz * f.h0[2];
-  const float p1 = qx * f.h1[0] + qy * f.h1[1] + qz * f.h1[2];
+  const float p0 = s1 * f.ga[0] + s2 * f.de[0];
+  const float p1 = s1 * f.ga[1] + s2 * f.de[1];
   const float p2 = -p0 - p1;
   // 2 pi sinc(eta_l), eta_l = psi_{l+1} - psi_l (turns)
   const float a0 = w0 * sinc2pi_turns(p1 - p0);
@@ -101,22 +108,26 @@ __device__ __forceinline__ void face_term_fp32c(const Face32& f, float qx, float
   Tr = co * Sr;
   Ti = co * Si;
   need_series = P2 < fmaxf(f.thr, f.kap * Q2);
-  phase_out = r;  // the series fix-up forms exp(i Q.g) itself (rare path)
+  sd.p0 = p0;
+  sd.p1 = p1;
+  sd.QN = QN;
+  sd.r = r;
 }
 
-// Q nearly along the face normal: binary64 simplex series of the face,
-// T = -i (Q.N) exp(i Q.g) sum_n i^n h_n(delta) / (n+2)!.
-__device__ __forceinline__ void face_series_fp32c(const Face64* __restrict__ fa, const double* Qd, float r,
-                                               float& Tr, float& Ti) {
-  const float cf = cos_turns(r), sf = sin_turns(r);
-  const Face64 F = *fa;
-  const double QNd = Qd[0] * F.N[0] + Qd[1] * F.N[1] + Qd[2] * F.N[2];
-  const double q0 = Qd[0] * F.u0[0] + Qd[1] * F.u0[1] + Qd[2] * F.u0[2];
-  const double q1 = Qd[0] * F.u1[0] + Qd[1] * F.u1[1] + Qd[2] * F.u1[2];
+// Q nearly along the face normal: simplex series of the face in binary64,
+// T = -i (Q.N) exp(i Q.g) sum_n i^n h_n(delta) / (n+2)!, delta_k = 4 pi psi_k,
+// from the binary32 phases of the edge form (their rounding is that of the
+// edge form's own inputs). Terms stop at 1e-10 of the sum, far below binary32
+// resolution.
+__device__ __forceinline__ void face_series_fp32c(const SeriesInputs& sd, float& Tr, float& Ti) {
+  constexpr double kFourPi = 12.566370614359172954;
+  const double q0 = kFourPi * (double)sd.p0, q1 = kFourPi * (double)sd.p1;
   double sr, si;
-  face_series_f64(q0, q1, -q0 - q1, sr, si);
-  Tr = (float)(QNd * ((double)cf * si + (double)sf * sr));
-  Ti = (float)(-QNd * ((double)cf * sr - (double)sf * si));
+  face_series_f64(q0, q1, -q0 - q1, sr, si, 1e-10);
+  const double cf = (double)cos_turns(sd.r), sf = (double)sin_turns(sd.r);
+  const double QN = (double)sd.QN;
+  Tr = (float)(QN * (cf * si + sf * sr));
+  Ti = (float)(-QN * (cf * sr - sf * si));
 }
 
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {

@@ -113,9 +113,9 @@ PFT_HD __forceinline__ double inv_fact(int n) {
 // h_n obeys h_n = -e2 h_{n-2} + e3 h_{n-3} (generating function
 // 1 / prod(1 - d_k t) = 1 / (1 + e2 t^2 - e3 t^3) when e1 = 0). Terms are added
 // four at a time (one of each power of i) until the bound m^n / (2 n!) on the
-// next term, m = max |d_k| (|h_n| <= m^n (n+1)(n+2)/2), falls below 1e-17 of
+// next term, m = max |d_k| (|h_n| <= m^n (n+1)(n+2)/2), falls below `tol` times
 // the partial sum, or n reaches 84.
-PFT_HD inline void face_series_f64(double d0, double d1, double d2, double& sr, double& si) {
+PFT_HD inline void face_series_f64(double d0, double d1, double d2, double& sr, double& si, double tol) {
   const double e2 = d0 * d1 + d0 * d2 + d1 * d2;
   const double e3 = d0 * d1 * d2;
   const double m = fmax(fabs(d0), fmax(fabs(d1), fabs(d2)));
@@ -136,7 +136,7 @@ PFT_HD inline void face_series_f64(double d0, double d1, double d2, double& sr, 
     h2 = c;
     h3 = d;
     mn *= m4;
-    if (mn * 0.5 * inv_fact(n + 4) < 1e-17 * (fabs(sr) + fabs(si))) break;
+    if (mn * 0.5 * inv_fact(n + 4) < tol * (fabs(sr) + fabs(si))) break;
   }
 }
 

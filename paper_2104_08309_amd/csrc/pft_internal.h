@@ -64,18 +64,25 @@ struct alignas(16) Face64 {
 };
 static_assert(sizeof(Face64) == 128, "Face64 layout");
 
-// FP32C forward face record (staged in LDS).
+// FP32C forward face record (staged in LDS). The in-plane geometry is held in
+// an orthonormal basis e1, e2 of the face plane (e1 along b - a, e2 = n x e1):
+// with s_j = Q . (|N| e_j), the in-plane part of Q, P = Q x N = s2 e1 - s1 e2,
+// so |P|^2 = s1^2 + s2^2, P . d_l = s2 (e1 . d_l) - s1 (e2 . d_l) and the
+// vertex phases Q . u_k = s1 (e1 . u_k)/|N| + s2 (e2 . u_k)/|N|.
 struct alignas(16) Face32 {
   double gt[3];   // centroid / (2 pi), binary64: face origin phase in turns is Q . gt
   float N[3];     // (b - a) x (c - a)
-  float d0[3];    // (b - a) / (2 pi)
-  float d1[3];    // (c - b) / (2 pi)
-  float h0[3];    // (a - g) / (4 pi): half-vertex phase in turns is Q . h
-  float h1[3];    // (b - g) / (4 pi)
+  float E1[3];    // |N| e1
+  float E2[3];    // |N| e2
+  float al[2];    // (e1 . d_l) / (2 pi), l = 0, 1 (d_0 = b - a, d_1 = c - b)
+  float be[2];    // -(e2 . d_l) / (2 pi)
+  float ga[2];    // (e1 . u_k) / (4 pi |N|), k = 0, 1 (u_0 = a - g, u_1 = b - g)
+  float de[2];    // (e2 . u_k) / (4 pi |N|)
   float thr;      // tau^2 |N|^2 / L^2
   float kap;      // tau_rel^2 |N|^2
+  float pad[3];
 };
-static_assert(sizeof(Face32) == 96, "Face32 layout");
+static_assert(sizeof(Face32) == 112, "Face32 layout");
 
 // FP32C adjoint face record.
 struct alignas(16) Face32B {

@@ -179,17 +179,43 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
   const Face64 f = in[m];
   Face32 r;
   const double L2 = f.pad[0], N2 = f.pad[1];
+  const bool ok = f.thr >= 0.0;
+  double d0[3], d1[3], e1[3], e2[3];
   for (int k = 0; k < 3; ++k) {
     r.gt[k] = f.g[k] * kInv2Pi;
     r.N[k] = (float)f.N[k];
-    r.d0[k] = (float)((f.u1[k] - f.u0[k]) * kInv2Pi);
-    r.d1[k] = (float)((-f.u0[k] - 2.0 * f.u1[k]) * kInv2Pi);
-    r.h0[k] = (float)(f.u0[k] * kInv4Pi);
-    r.h1[k] = (float)(f.u1[k] * kInv4Pi);
+    d0[k] = f.u1[k] - f.u0[k];
+    d1[k] = -f.u0[k] - 2.0 * f.u1[k];
   }
-  const bool ok = f.thr >= 0.0;
-  r.thr = ok ? (float)(tau * tau * N2 / L2) : -1.0f;
-  r.kap = ok ? (float)(tau_rel * tau_rel * N2) : -1.0f;
+  auto dot = [](const double* x, const double* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+  const double nN = sqrt(N2), nd0 = sqrt(dot(d0, d0));
+  if (ok && nd0 > 0.0) {
+    for (int k = 0; k < 3; ++k) e1[k] = d0[k] / nd0;
+    // e2 = n x e1 = (N x d0) / (|N| |d0|)
+    e2[0] = (f.N[1] * d0[2] - f.N[2] * d0[1]) / (nN * nd0);
+    e2[1] = (f.N[2] * d0[0] - f.N[0] * d0[2]) / (nN * nd0);
+    e2[2] = (f.N[0] * d0[1] - f.N[1] * d0[0]) / (nN * nd0);
+    for (int k = 0; k < 3; ++k) {
+      r.E1[k] = (float)(nN * e1[k]);
+      r.E2[k] = (float)(nN * e2[k]);
+    }
+    r.al[0] = (float)(dot(e1, d0) * kInv2Pi);
+    r.al[1] = (float)(dot(e1, d1) * kInv2Pi);
+    r.be[0] = (float)(-dot(e2, d0) * kInv2Pi);
+    r.be[1] = (float)(-dot(e2, d1) * kInv2Pi);
+    r.ga[0] = (float)(dot(e1, f.u0) * kInv4Pi / nN);
+    r.ga[1] = (float)(dot(e1, f.u1) * kInv4Pi / nN);
+    r.de[0] = (float)(dot(e2, f.u0) * kInv4Pi / nN);
+    r.de[1] = (float)(dot(e2, f.u1) * kInv4Pi / nN);
+    r.thr = (float)(tau * tau * N2 / L2);
+    r.kap = (float)(tau_rel * tau_rel * N2);
+  } else {
+    // empty face: every weight is zero, so its term is exactly zero
+    for (int k = 0; k < 3; ++k) r.N[k] = r.E1[k] = r.E2[k] = 0.0f;
+    r.al[0] = r.al[1] = r.be[0] = r.be[1] = r.ga[0] = r.ga[1] = r.de[0] = r.de[1] = 0.0f;
+    r.thr = r.kap = -1.0f;
+  }
+  r.pad[0] = r.pad[1] = r.pad[2] = 0.0f;
   out[m] = r;
 }
 
