@@ -24,9 +24,17 @@ PFT_HD __forceinline__ double dsinc_series(double x) {
 // with H_n = h_n(d0, d1, d2) = -e2 H_{n-2} + e3 H_{n-3} and
 // h_n(d0, d1, d2, d_k) = H_n + d_k h_{n-1}(d0, d1, d2, d_k). Terms are added four
 // at a time until m^n / n! < tol (m = max |d_k|; the next term of Y is below
-// (1/6) m^n / n!, of J below (1/2) m^n / n!), or n reaches nmax.
+// (1/6) m^n / n!, of J below (1/2) m^n / n!), or n reaches NMAX. The loop is
+// unrolled, so the factorial coefficients are compile-time constants folded into
+// the instructions rather than values held in registers.
 template <typename T>
-PFT_HD __forceinline__ void bary_moments(T d0, T d1, T m, T tol, int nmax, T* yr, T* yi, T& jr, T& ji) {
+PFT_HD constexpr T inv_fact_c(int n) {
+  constexpr double t[kInvFactCount] = {PFT_INV_FACT_VALUES};
+  return T(t[n]);
+}
+
+template <typename T, int NMAX>
+PFT_HD __forceinline__ void bary_moments(T d0, T d1, T m, T tol, T* yr, T* yi, T& jr, T& ji) {
   const T d2 = -d0 - d1;
   const T e2 = d0 * d1 + d2 * (d0 + d1);
   const T e3 = d0 * d1 * d2;
@@ -37,14 +45,15 @@ PFT_HD __forceinline__ void bary_moments(T d0, T d1, T m, T tol, int nmax, T* yr
   ji = T(0);
   const T m2 = m * m, m4 = m2 * m2;
   T mn = m;  // m^n at the start of each chunk
-  for (int n = 1;; n += 4) {
+#pragma unroll
+  for (int n = 1; n < NMAX; n += 4) {
     // i^n cycles (+i, -1, -i, +1) over n = 1, 2, 3, 4 (mod 4)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const T H = -e2 * Hm2 + e3 * Hm3;
       a0 = H + d0 * a0;
       a1 = H + d1 * a1;
-      const T c3 = T(inv_fact(n + r + 3)), c2 = T(inv_fact(n + r + 2));
+      const T c3 = inv_fact_c<T>(n + r + 3), c2 = inv_fact_c<T>(n + r + 2);
       if (r == 0) {
         y0i += c3 * a0; y1i += c3 * a1; ji += c2 * H;
       } else if (r == 1) {
@@ -59,7 +68,7 @@ PFT_HD __forceinline__ void bary_moments(T d0, T d1, T m, T tol, int nmax, T* yr
       Hm1 = H;
     }
     mn *= m4;
-    if (n + 4 >= nmax || mn * T(inv_fact(n + 4)) < tol) break;
+    if (mn * inv_fact_c<T>(n + 4) < tol) break;
   }
   yr[0] = y0r; yi[0] = y0i;
   yr[1] = y1r; yi[1] = y1i;
@@ -88,7 +97,7 @@ PFT_HD __forceinline__ void adj_term_f64(const Face64& f, const double* G, const
   if (m <= kSeriesMaxPhase) {
     // barycentric moments by their series (no cancellation for |delta| <= 3)
     double yr[2], yi[2], jr, ji;
-    bary_moments<double>(q0, q1, m, 1e-17, 33, yr, yi, jr, ji);
+    bary_moments<double, 33>(q0, q1, m, 1e-17, yr, yi, jr, ji);
     R[0] = zr * yr[0] - zi * yi[0];
     R[1] = zr * yr[1] - zi * yi[1];
     R[2] = (zr * jr - zi * ji) - R[0] - R[1];
@@ -198,7 +207,7 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
     // barycentric moments by their series in binary32 (terms decrease from the
     // start for |delta| <= 3; no cancellation with the face's size in Q)
     float yr[2], yi[2], jr, ji;
-    bary_moments<float>(q0, q1, m, 1e-8f, 29, yr, yi, jr, ji);
+    bary_moments<float, 29>(q0, q1, m, 1e-8f, yr, yi, jr, ji);
     R[0] = zr * yr[0] - zi * yi[0];
     R[1] = zr * yr[1] - zi * yi[1];
     R[2] = (zr * jr - zi * ji) - R[0] - R[1];
