@@ -546,6 +546,7 @@ pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, 
   std::vector<int64_t> q_part(n);
   std::vector<int32_t> q_chunks(n);
   int64_t P = 0;
+  const int64_t qtile = c128 ? kBlock : (int64_t)kBlock * kQPTBatch;  // Q per item (one block)
   for (int64_t i = 0; i < n; ++i) {
     const int64_t nqi = b->q_offsets[i + 1] - b->q_offsets[i];
     const int64_t nfi = b->tri_offsets[i + 1] - b->tri_offsets[i];
@@ -558,12 +559,12 @@ pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, 
     q_part[i] = P;
     q_chunks[i] = (int32_t)C;
     for (int64_t c = 0; c < C; ++c) {
-      for (int64_t t = 0; t < nqi; t += kBlock) {
+      for (int64_t t = 0; t < nqi; t += qtile) {
         BatchItemFwd it;
         it.mesh = (int32_t)i;
         it.chunk = (int32_t)c;
         it.q0 = b->q_offsets[i] + t;
-        it.nq = (int32_t)std::min<int64_t>(kBlock, nqi - t);
+        it.nq = (int32_t)std::min<int64_t>(qtile, nqi - t);
         it.pad = 0;
         it.f0 = b->tri_offsets[i] + c * cf;
         it.nf = nfi > 0 ? std::min<int64_t>(cf, nfi - c * cf) : 0;

@@ -36,14 +36,15 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
     if (idx >= n_items) break;
     const BatchItemFwd it = items[idx];
     const int lane = threadIdx.x;
-    const bool active = lane < it.nq;
-    double Qd[3] = {0.0, 0.0, 0.0};
-    if (active) load_q3(q, qdtype, it.q0 + lane, Qd);
-    const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
-    const bool small = sqrt(Q2d) * info[it.mesh].R < tau0;
     const int64_t f_end = it.f0 + it.nf;
-    double2 res;
+    const double R = info[it.mesh].R;
     if (MODE == PFT_FP64) {
+      // one Q per thread
+      const bool active = lane < it.nq;
+      double Qd[3] = {0.0, 0.0, 0.0};
+      if (active) load_q3(q, qdtype, it.q0 + lane, Qd);
+      const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
+      const bool small = sqrt(Q2d) * R < tau0;
       Face64* tile = reinterpret_cast<Face64*>(smem);
       double xr = 0.0, xi = 0.0;
       for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
@@ -63,39 +64,63 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
           for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Qd, xr, xi);
         }
       }
-      res = make_double2(xr, xi);
+      if (active) partial[it.part + lane] = make_double2(xr, xi);
     } else {
+      // kQPTBatch Q per thread, strided by the block size
       Face32* tile = reinterpret_cast<Face32*>(smem);
-      const float qx = (float)Qd[0], qy = (float)Qd[1], qz = (float)Qd[2];
-      const float Q2 = qx * qx + qy * qy + qz * qz;
-      float sr = 0.0f, si = 0.0f, cr = 0.0f, ci = 0.0f;
-      double xr = 0.0, xi = 0.0;
+      double Qd[kQPTBatch][3];
+      float qx[kQPTBatch], qy[kQPTBatch], qz[kQPTBatch], Q2[kQPTBatch];
+      bool small[kQPTBatch], active[kQPTBatch];
+      bool any_small = false;
+#pragma unroll
+      for (int k = 0; k < kQPTBatch; ++k) {
+        const int qo = lane + k * kBlock;
+        active[k] = qo < it.nq;
+        Qd[k][0] = Qd[k][1] = Qd[k][2] = 0.0;
+        if (active[k]) load_q3(q, qdtype, it.q0 + qo, Qd[k]);
+        qx[k] = (float)Qd[k][0];
+        qy[k] = (float)Qd[k][1];
+        qz[k] = (float)Qd[k][2];
+        Q2[k] = qx[k] * qx[k] + qy[k] * qy[k] + qz[k] * qz[k];
+        const double Q2d = Qd[k][0] * Qd[k][0] + Qd[k][1] * Qd[k][1] + Qd[k][2] * Qd[k][2];
+        small[k] = sqrt(Q2d) * R < tau0;
+        any_small |= small[k];
+      }
+      float sr[kQPTBatch], si[kQPTBatch], cr[kQPTBatch], ci[kQPTBatch];
+      double xr[kQPTBatch], xi[kQPTBatch];
+#pragma unroll
+      for (int k = 0; k < kQPTBatch; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
       for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
         const int nt = (int)min((int64_t)kTileF, f_end - t0);
         __syncthreads();
         for (int i = lane; i < nt * (int)(sizeof(Face32) / 16); i += kBlock)
           reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f32 + t0)[i];
         __syncthreads();
-        if (!small) {
-          float tr = 0.0f, ti = 0.0f;
-          for (int j = 0; j < nt; ++j) {
-            float Tr, Ti;
-            SeriesInputs sd;
-            bool ser;
-            face_term_fp32c(tile[j], qx, qy, qz, Q2, Qd, Tr, Ti, ser, sd);
-            if (ser) face_series_fp32c(sd, Tr, Ti);
-            tr += Tr;
-            ti += Ti;
-          }
-          kahan_add(sr, cr, tr);
-          kahan_add(si, ci, ti);
-        } else {
-          for (int j = 0; j < nt; ++j) tet_term_f64(f64[t0 + j], Qd, xr, xi);
+        float tr[kQPTBatch], ti[kQPTBatch];
+#pragma unroll
+        for (int k = 0; k < kQPTBatch; ++k) tr[k] = ti[k] = 0.0f;
+        fwd_tile_fp32c<kQPTBatch>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti);
+#pragma unroll
+        for (int k = 0; k < kQPTBatch; ++k) {
+          kahan_add(sr[k], cr[k], tr[k]);
+          kahan_add(si[k], ci[k], ti[k]);
+        }
+        if (any_small) {
+#pragma unroll
+          for (int k = 0; k < kQPTBatch; ++k)
+            if (small[k])
+              for (int j = 0; j < nt; ++j) tet_term_f64(f64[t0 + j], Qd[k], xr[k], xi[k]);
         }
       }
-      res = small ? make_double2(xr, xi) : make_double2((double)sr - (double)cr, (double)si - (double)ci);
+#pragma unroll
+      for (int k = 0; k < kQPTBatch; ++k) {
+        if (active[k]) {
+          const double2 v = small[k] ? make_double2(xr[k], xi[k])
+                                     : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
+          partial[it.part + lane + k * kBlock] = v;
+        }
+      }
     }
-    if (active) partial[it.part + lane] = res;
   }
 }
 

@@ -95,22 +95,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
     float tr[kQPT], ti[kQPT];
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
-    for (int j = 0; j < nt; ++j) {
-      // the edge form for every lane (no per-Q branch, so the kQPT streams
-      // interleave); small-|Q| lanes discard this sum and use the series below
-      float Tr[kQPT], Ti[kQPT];
-      SeriesInputs sd[kQPT];
-      bool ser[kQPT];
-#pragma unroll
-      for (int k = 0; k < kQPT; ++k)
-        face_term_fp32c(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr[k], Ti[k], ser[k], sd[k]);
-#pragma unroll
-      for (int k = 0; k < kQPT; ++k) {
-        if (ser[k] && !small[k]) face_series_fp32c(sd[k], Tr[k], Ti[k]);
-        tr[k] += Tr[k];
-        ti[k] += Ti[k];
-      }
-    }
+    fwd_tile_fp32c<kQPT>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti);
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) {
       kahan_add(sr[k], cr[k], tr[k]);

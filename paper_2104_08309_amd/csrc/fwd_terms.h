@@ -130,6 +130,31 @@ __device__ __forceinline__ void face_series_fp32c(const SeriesInputs& sd, float&
   Ti = (float)(-QN * (cf * sr - sf * si));
 }
 
+// One LDS tile of FP32C face records against the NQ Q points of a thread:
+// adds each face's term to tr[k], ti[k] (plain binary32 inside the tile). The
+// edge form is evaluated for every lane (no per-Q branch, so the NQ streams
+// interleave); pairs flagged near-degenerate are replaced by the series, and
+// lanes with small[k] set are left for the caller's small-|Q| path.
+template <int NQ>
+__device__ __forceinline__ void fwd_tile_fp32c(const Face32* tile, int nt, const float* qx, const float* qy,
+                                               const float* qz, const float* Q2, const double (*Qd)[3],
+                                               const bool* small, float* tr, float* ti) {
+  for (int j = 0; j < nt; ++j) {
+    float Tr[NQ], Ti[NQ];
+    SeriesInputs sd[NQ];
+    bool ser[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+      face_term_fp32c(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr[k], Ti[k], ser[k], sd[k]);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      if (ser[k] && !small[k]) face_series_fp32c(sd[k], Tr[k], Ti[k]);
+      tr[k] += Tr[k];
+      ti[k] += Ti[k];
+    }
+  }
+}
+
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
   const float y = x - comp;
   const float t = sum + y;

@@ -20,6 +20,10 @@ constexpr int kTileFB = 16;        // faces per block in the adjoint
 #define PFT_QPT 3
 #endif
 constexpr int kQPT = PFT_QPT;      // Q per thread in the FP32C forward
+#ifndef PFT_QPT_BATCH
+#define PFT_QPT_BATCH 1
+#endif
+constexpr int kQPTBatch = PFT_QPT_BATCH;  // Q per thread in the batched FP32C forward
 #ifndef PFT_QPTB
 #define PFT_QPTB 3
 #endif
@@ -186,11 +190,11 @@ struct BatchItemFwd {   // one (mesh, Q-tile, face-chunk) work item
   int32_t mesh;
   int32_t chunk;        // face-chunk index within the mesh
   int64_t q0;           // first global Q index of the tile
-  int32_t nq;           // Q in the tile (<= kBlock)
+  int32_t nq;           // Q in the tile (<= kBlock for FP64, <= kBlock * kQPTBatch for FP32C)
   int32_t pad;
   int64_t f0;           // first global face index of the chunk
   int64_t nf;           // faces in the chunk
-  int64_t part;         // partial slot base (in units of Q): partial[part + lane]
+  int64_t part;         // partial slot base (in units of Q): partial[part + Q offset in the tile]
 };
 struct BatchItemBwd {   // one (mesh, face-tile, Q-chunk) work item
   int32_t mesh;
