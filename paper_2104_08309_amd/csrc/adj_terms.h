@@ -269,46 +269,24 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront sum by DPP: row shifts 1, 2, 4, 8 leave each 16-lane row's sum in
-// its last lane, the row broadcasts 15 and 31 fold rows 0..3 into lane 63.
-// Lanes shifted in from outside a row read as zero (bound control).
+// Wavefront sum in binary64 (shuffles through the LDS crossbar).
 // ---------------------------------------------------------------------------
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_add(float v) {
-  const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true);
-  return v + __int_as_float(s);
-}
-
-__device__ __forceinline__ float wave_total(float v) {
-  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
-  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
-  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
-  v = dpp_add<0x118, 0xf>(v);  // row_shr:8
-  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-
 __device__ __forceinline__ double wave_total(double v) {
-  // binary64 path (FP64 mode): shuffles through the LDS crossbar
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
 // ---------------------------------------------------------------------------
-// One block's share of the adjoint: the faces staged in LDS (`nt` of them)
+// binary64 adjoint, one block's share: the faces staged in LDS (`nt` of them)
 // against the Q range [qb, qe), kQPTB Q per thread per pass (strided by the
-// block size). For each face the real weights of a pass are summed per thread,
-// then across the wavefront, and lane 0 adds the wavefront's sum to its
-// binary64 slot `wacc[wave][3 j + k]` (zeroed by the caller). Faces are
-// visited one at a time, so the working set stays that of kQPTB terms.
+// block size). For each face the real weights of a pass are summed per
+// thread, then across the wavefront, and lane 0 adds the wavefront's sum to
+// its slot `wacc[wave][3 j + k]` (zeroed by the caller).
 // ---------------------------------------------------------------------------
-template <int MODE>
-__device__ __forceinline__ void adj_tile_accumulate(const unsigned char* smem_tile, const double (*gtile)[8], int nt,
-                                                    const double* tc, int64_t qb, int64_t qe, const void* q,
-                                                    int qdtype, const void* grad_out,
-                                                    double (*wacc)[kTileFB * 3]) {
+__device__ __forceinline__ void adj_tile_f64(const Face64* tile, const double (*gtile)[8], int nt, const double* tc,
+                                             int64_t qb, int64_t qe, const void* q, int qdtype,
+                                             const void* grad_out, double (*wacc)[kTileFB * 3]) {
   constexpr int P = kQPTB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int64_t q0 = qb; q0 < qe; q0 += (int64_t)kBlock * P) {
@@ -321,66 +299,90 @@ __device__ __forceinline__ void adj_tile_accumulate(const unsigned char* smem_ti
       hr[p] = hi[p] = 0.0;
       if (qi < qe) {
         load_q3(q, qdtype, qi, Qd[p]);
-        double gr, gi;
-        if (MODE == PFT_FP64) {
-          const double2 g = static_cast<const double2*>(grad_out)[qi];
-          gr = g.x;
-          gi = g.y;
-        } else {
-          const float2 g = static_cast<const float2*>(grad_out)[qi];
-          gr = (double)g.x;
-          gi = (double)g.y;
-        }
-        centred_cotangent(gr, gi, Qd[p], tc, hr[p], hi[p]);
+        const double2 g = static_cast<const double2*>(grad_out)[qi];
+        centred_cotangent(g.x, g.y, Qd[p], tc, hr[p], hi[p]);
       }
     }
-    if (MODE == PFT_FP64) {
-      const Face64* tile = reinterpret_cast<const Face64*>(smem_tile);
 #pragma unroll 1
-      for (int j = 0; j < nt; ++j) {
-        double S[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          double R[3];
-          adj_term_f64(tile[j], gtile[j], Qd[p], hr[p], hi[p], R);
-          S[0] += R[0];
-          S[1] += R[1];
-          S[2] += R[2];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const double v = wave_total(S[k]);
-          if (lane == 0) wacc[wave][3 * j + k] += v;
-        }
-      }
-    } else {
-      const Face32B* tile = reinterpret_cast<const Face32B*>(smem_tile);
-      float qx[P], qy[P], qz[P], Q2[P];
+    for (int j = 0; j < nt; ++j) {
+      double S[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        qx[p] = (float)Qd[p][0];
-        qy[p] = (float)Qd[p][1];
-        qz[p] = (float)Qd[p][2];
-        Q2[p] = qx[p] * qx[p] + qy[p] * qy[p] + qz[p] * qz[p];
+        double R[3];
+        adj_term_f64(tile[j], gtile[j], Qd[p], hr[p], hi[p], R);
+        S[0] += R[0];
+        S[1] += R[1];
+        S[2] += R[2];
       }
-#pragma unroll 1
-      for (int j = 0; j < nt; ++j) {
-        float S[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-          float R[3];
-          adj_term_fp32c(tile[j], qx[p], qy[p], qz[p], Q2[p], Qd[p], (float)hr[p], (float)hi[p], R);
-          S[0] += R[0];
-          S[1] += R[1];
-          S[2] += R[2];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const float v = wave_total(S[k]);
-          if (lane == 0) wacc[wave][3 * j + k] += (double)v;
-        }
+      for (int k = 0; k < 3; ++k) {
+        const double v = wave_total(S[k]);
+        if (lane == 0) wacc[wave][3 * j + k] += v;
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32C adjoint, one block's share: `nt` face records in LDS against the Q
+// range [qb, qe), kQPTB Q per thread per pass. Each thread adds its weights
+// for face j to its own binary32 slots acc[3 j + k][thread] (zeroed by the
+// caller); adj_block_sum32 reduces the slots once the range is done, so no
+// cross-lane traffic happens per face. `cot` holds the centred cotangent per Q.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void adj_tile_fp32c(const Face32B* tile, int nt, int64_t qb, int64_t qe, const void* q,
+                                               int qdtype, const float2* __restrict__ cot,
+                                               float (*acc)[kBlock]) {
+  constexpr int P = kQPTB;
+  const int tid = threadIdx.x;
+  for (int64_t q0 = qb; q0 < qe; q0 += (int64_t)kBlock * P) {
+    double Qd[P][3];
+    float qx[P], qy[P], qz[P], Q2[P], hr[P], hi[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int64_t qi = q0 + (int64_t)p * kBlock + tid;
+      Qd[p][0] = Qd[p][1] = Qd[p][2] = 0.0;
+      hr[p] = hi[p] = 0.0f;
+      if (qi < qe) {
+        load_q3(q, qdtype, qi, Qd[p]);
+        const float2 h = cot[qi];
+        hr[p] = h.x;
+        hi[p] = h.y;
+      }
+      qx[p] = (float)Qd[p][0];
+      qy[p] = (float)Qd[p][1];
+      qz[p] = (float)Qd[p][2];
+      Q2[p] = qx[p] * qx[p] + qy[p] * qy[p] + qz[p] * qz[p];
+    }
+#pragma unroll 1
+    for (int j = 0; j < nt; ++j) {
+      float S[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        float R[3];
+        adj_term_fp32c(tile[j], qx[p], qy[p], qz[p], Q2[p], Qd[p], hr[p], hi[p], R);
+        S[0] += R[0];
+        S[1] += R[1];
+        S[2] += R[2];
+      }
+      // private slots: a plain read-modify-write (an LDS atomic add is far slower)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc[3 * j + k][tid] += S[k];
+    }
+  }
+}
+
+// Sum of the per-thread slots of adj_tile_fp32c for each of the nt * 3 weights,
+// in binary64 and a fixed order; wave w handles weights w, w + 4, ... and lane
+// 0 writes out[v]. Call after a barrier.
+__device__ __forceinline__ void adj_block_sum32(float (*acc)[kBlock], int nt, double* out) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int v = wave; v < nt * 3; v += kBlock / 64) {
+    double x = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) x += (double)acc[v][lane + 64 * i];
+    x = wave_total(x);
+    if (lane == 0) out[v] = x;
   }
 }
 

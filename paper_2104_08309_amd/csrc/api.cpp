@@ -110,8 +110,8 @@ void choose_face_splits(int64_t nq, int64_t nf, int qpt, int* splits, int64_t* p
   *splits = (int)cdiv(nf, p);
 }
 
-void choose_q_splits(int64_t nq, int64_t nf, int* splits, int64_t* per) {
-  const int64_t fblocks = std::max<int64_t>(1, cdiv(nf, kTileFB));
+void choose_q_splits(int64_t nq, int64_t nf, int tile, int* splits, int64_t* per) {
+  const int64_t fblocks = std::max<int64_t>(1, cdiv(nf, tile));
   int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, fblocks), std::max<int64_t>(1, cdiv(nq, kBlock))));
   const int64_t p = std::max<int64_t>(1, cdiv(nq, s));
   *per = p;
@@ -417,15 +417,17 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   Face64* f64 = ar.get<Face64>(nf);
   Face32B* f32 = c128 ? nullptr : ar.get<Face32B>(nf);
   double* gram = c128 ? ar.get<double>((size_t)nf * 8) : nullptr;
+  float2* cot = c128 ? nullptr : ar.get<float2>(nq);
   int qs;
   int64_t qper;
-  choose_q_splits(nq, nf, &qs, &qper);
+  choose_q_splits(nq, nf, c128 ? kTileFB : kTileFB32, &qs, &qper);
   double* partial = ar.get<double>((size_t)qs * nf * 3);
   double* contrib = ar.get<double>((size_t)nf * 9);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
   hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
   if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, kTauF64, f64, s);
   if (e == hipSuccess && !c128) e = launch_face32b(f64, nf, kTauB32, kTauRelB32, f32, s);
+  if (e == hipSuccess && !c128) e = launch_cotangent32(q, qdtype, grad_out, nq, info, nullptr, 1, cot, s);
   if (e == hipSuccess && c128) e = launch_gram64(f64, nf, gram, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint prologue");
   BwdArgs a;
@@ -437,6 +439,7 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   a.qdtype = qdtype;
   a.nq = nq;
   a.grad_out = grad_out;
+  a.cot = cot;
   a.qsplits = qs;
   a.q_per_split = qper;
   a.partial = partial;
@@ -625,6 +628,7 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
   st = batch_prologue(ar, b, kTauF64, p, s);
   if (st != PFT_OK) return st;
   Face32B* f32b = nullptr;
+  float2* cot = nullptr;
   double* gram = nullptr;
   hipError_t e = hipSuccess;
   if (c128) {
@@ -633,11 +637,15 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
     e = launch_gram64(p.f64, p.nf, gram, s);
   } else {
     f32b = ar.get<Face32B>(p.nf);
+    cot = ar.get<float2>(nq_total);
     if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
     e = launch_face32b(p.f64, p.nf, kTauB32, kTauRelB32, f32b, s);
+    if (e == hipSuccess)
+      e = launch_cotangent32(b->q, b->qdtype, grad_out, nq_total, p.info, p.d_q_off, n, cot, s);
   }
   if (e != hipSuccess) return hip_fail(e, "batch adjoint prologue");
   std::vector<BatchItemBwd> items;
+  const int64_t ftile = c128 ? kTileFB : kTileFB32;  // faces per item (one block)
   std::vector<int64_t> face_base(n);
   std::vector<int32_t> face_nchunks(n);
   int64_t B = 0;
@@ -649,12 +657,12 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
     face_base[i] = B;
     face_nchunks[i] = (int32_t)S;
     for (int64_t sc = 0; sc < S; ++sc) {
-      for (int64_t ft = 0; ft < nfi; ft += kTileFB) {
+      for (int64_t ft = 0; ft < nfi; ft += ftile) {
         BatchItemBwd it;
         it.mesh = (int32_t)i;
         it.qchunk = (int32_t)sc;
         it.f0 = b->tri_offsets[i] + ft;
-        it.nf = (int32_t)std::min<int64_t>(kTileFB, nfi - ft);
+        it.nf = (int32_t)std::min<int64_t>(ftile, nfi - ft);
         it.pad = 0;
         it.q0 = b->q_offsets[i] + std::min(nqi, sc * cq);
         it.nq = std::max<int64_t>(0, std::min(cq, nqi - sc * cq));
@@ -683,8 +691,8 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
                                           (int64_t)num_cus() * batch_bwd_blocks_per_cu(mode));
   prof_begin("batch_bwd", s);
-  e = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, b->q, b->qdtype, grad_out, p.info, partial,
-                       grid, s);
+  e = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, b->q, b->qdtype, grad_out, cot, p.info,
+                       partial, grid, s);
   prof_end("batch_bwd", s);
   if (e != hipSuccess) return hip_fail(e, "batch adjoint");
   e = launch_batch_bwd_reduce(partial, d_face_base, d_face_nchunks, p.d_tri_off, p.d_face_mesh, p.f64, p.nf, contrib,

@@ -169,14 +169,13 @@ __global__ __launch_bounds__(256) void batch_fwd_finish_kernel(const double2* pa
   }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void batch_bwd_kernel(const BatchItemBwd* __restrict__ items, int64_t n_items,
-                                                          uint32_t* counter, const Face64* __restrict__ f64,
-                                                          const double* __restrict__ gram,
-                                                          const Face32B* __restrict__ f32b, const void* q,
-                                                          int qdtype, const void* grad_out,
-                                                          const MeshInfo* __restrict__ info, double* partial) {
-  __shared__ __align__(16) unsigned char smem[kTileFB * sizeof(Face64)];
+__global__ __launch_bounds__(kBlock) void batch_bwd_fp64_kernel(const BatchItemBwd* __restrict__ items,
+                                                               int64_t n_items, uint32_t* counter,
+                                                               const Face64* __restrict__ f64,
+                                                               const double* __restrict__ gram, const void* q,
+                                                               int qdtype, const void* grad_out,
+                                                               const MeshInfo* __restrict__ info, double* partial) {
+  __shared__ Face64 tile[kTileFB];
   __shared__ double gtile[kTileFB][8];
   __shared__ double wacc[kBlock / 64][kTileFB * 3];
   __shared__ int slot;
@@ -186,25 +185,45 @@ __global__ __launch_bounds__(kBlock) void batch_bwd_kernel(const BatchItemBwd* _
     if (idx >= n_items) break;
     const BatchItemBwd it = items[idx];
     const int nt = it.nf;
-    if (MODE == PFT_FP64) {
-      for (int i = tid; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
-        reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(f64 + it.f0)[i];
-      for (int i = tid; i < nt * 8; i += kBlock) gtile[i / 8][i % 8] = gram[(it.f0 + i / 8) * 8 + i % 8];
-    } else {
-      for (int i = tid; i < nt * (int)(sizeof(Face32B) / 16); i += kBlock)
-        reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(f32b + it.f0)[i];
-    }
+    for (int i = tid; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
+      reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f64 + it.f0)[i];
+    for (int i = tid; i < nt * 8; i += kBlock) gtile[i / 8][i % 8] = gram[(it.f0 + i / 8) * 8 + i % 8];
     for (int i = tid; i < (kBlock / 64) * kTileFB * 3; i += kBlock) (&wacc[0][0])[i] = 0.0;
     __syncthreads();
     const MeshInfo mi = info[it.mesh];
     const double tc[3] = {mi.t[0], mi.t[1], mi.t[2]};
-    adj_tile_accumulate<MODE>(smem, gtile, nt, tc, it.q0, it.q0 + it.nq, q, qdtype, grad_out, wacc);
+    adj_tile_f64(tile, gtile, nt, tc, it.q0, it.q0 + it.nq, q, qdtype, grad_out, wacc);
     __syncthreads();
     if (tid < nt * 3) {
       double v = 0.0;
       for (int w = 0; w < kBlock / 64; ++w) v += wacc[w][tid];
       partial[it.part * 3 + tid] = v;
     }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void batch_bwd_fp32c_kernel(const BatchItemBwd* __restrict__ items,
+                                                                int64_t n_items, uint32_t* counter,
+                                                                const Face32B* __restrict__ f32b, const void* q,
+                                                                int qdtype, const float2* __restrict__ cot,
+                                                                double* partial) {
+  __shared__ Face32B tile[kTileFB32];
+  __shared__ float acc[kTileFB32 * 3][kBlock];
+  __shared__ int slot;
+  const int tid = threadIdx.x;
+  for (;;) {
+    const int64_t idx = next_item(counter, &slot);
+    if (idx >= n_items) break;
+    const BatchItemBwd it = items[idx];
+    const int nt = it.nf;
+    for (int i = tid; i < nt * (int)(sizeof(Face32B) / 16); i += kBlock)
+      reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f32b + it.f0)[i];
+    for (int v = 0; v < nt * 3; ++v) acc[v][tid] = 0.0f;
+    __syncthreads();
+    adj_tile_fp32c(tile, nt, it.q0, it.q0 + it.nq, q, qdtype, cot, acc);
+    __syncthreads();
+    adj_block_sum32(acc, nt, partial + it.part * 3);
     __syncthreads();
   }
 }
@@ -243,9 +262,9 @@ int batch_fwd_blocks_per_cu(int mode) {
 int batch_bwd_blocks_per_cu(int mode) {
   int nb = 0;
   if (mode == PFT_FP64)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_bwd_kernel<PFT_FP64>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_bwd_fp64_kernel, kBlock, 0);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_bwd_kernel<PFT_FP32C>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_bwd_fp32c_kernel, kBlock, 0);
   return nb > 0 ? nb : 1;
 }
 
@@ -274,14 +293,14 @@ hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_of
 
 hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
-                            const void* grad_out, const MeshInfo* info, double* partial, int grid, hipStream_t s) {
+                            const void* grad_out, const float2* cot, const MeshInfo* info, double* partial, int grid,
+                            hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (mode == PFT_FP64)
-    batch_bwd_kernel<PFT_FP64><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, gram, f32b, q, qdtype, grad_out,
-                                                       info, partial);
+    batch_bwd_fp64_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, gram, q, qdtype, grad_out, info,
+                                                  partial);
   else
-    batch_bwd_kernel<PFT_FP32C><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, gram, f32b, q, qdtype,
-                                                        grad_out, info, partial);
+    batch_bwd_fp32c_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f32b, q, qdtype, cot, partial);
   return hipGetLastError();
 }
 

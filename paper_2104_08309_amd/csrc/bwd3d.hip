@@ -20,9 +20,14 @@
 // The series is used where |Q_perp| L is small (it has no cancellation there;
 // the edge form cancels like 1/(|Q_perp| L)^2).
 //
-// Layout: a block owns kTileFB faces (records in LDS) and loops over a range
-// of Q in steps of 256 (one Q per thread), accumulating R in binary64
-// registers; a fixed-order block reduction writes per-split partials.
+// Layout: a block owns a tile of faces (records in LDS) and loops over a
+// range of Q (the Q-split on blockIdx.y), kQPTB Q per thread per pass.
+//  * binary64: per face and pass the thread's weights are summed across the
+//    wavefront into binary64 per-wave slots.
+//  * FP32C: each thread adds its weights to private binary32 slots in LDS
+//    (one per face and corner), and a fixed-order binary64 block sum at the
+//    end writes the per-split partials; the cotangent g exp(-iQ.t) is formed
+//    once per Q beforehand (cotangent32_kernel).
 #include <hipcub/hipcub.hpp>
 
 #include "adj_terms.h"
@@ -30,35 +35,70 @@
 namespace pft {
 namespace {
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void bwd3d_kernel(BwdArgs a, const double* gram) {
-  __shared__ __align__(16) unsigned char smem[kTileFB * sizeof(Face64)];
+__global__ __launch_bounds__(kBlock) void bwd3d_fp64_kernel(BwdArgs a, const double* gram) {
+  __shared__ Face64 tile[kTileFB];
   __shared__ double gtile[kTileFB][8];
   __shared__ double wacc[kBlock / 64][kTileFB * 3];
   const int tid = threadIdx.x;
   const int64_t f0 = (int64_t)blockIdx.x * kTileFB;
   const int nt = (int)min((int64_t)kTileFB, a.nf - f0);
-  if (MODE == PFT_FP64) {
-    for (int i = tid; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
-      reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(a.f64 + f0)[i];
-    for (int i = tid; i < nt * 8; i += kBlock) gtile[i / 8][i % 8] = gram[(f0 + i / 8) * 8 + i % 8];
-  } else {
-    for (int i = tid; i < nt * (int)(sizeof(Face32B) / 16); i += kBlock)
-      reinterpret_cast<uint4*>(smem)[i] = reinterpret_cast<const uint4*>(a.f32 + f0)[i];
-  }
+  for (int i = tid; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
+    reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(a.f64 + f0)[i];
+  for (int i = tid; i < nt * 8; i += kBlock) gtile[i / 8][i % 8] = gram[(f0 + i / 8) * 8 + i % 8];
   for (int i = tid; i < (kBlock / 64) * kTileFB * 3; i += kBlock) (&wacc[0][0])[i] = 0.0;
   __syncthreads();
   const MeshInfo mi = a.info[0];
   const double tc[3] = {mi.t[0], mi.t[1], mi.t[2]};
   const int64_t qb = (int64_t)blockIdx.y * a.q_per_split;
   const int64_t qe = min(a.nq, qb + a.q_per_split);
-  adj_tile_accumulate<MODE>(smem, gtile, nt, tc, qb, qe, a.q, a.qdtype, a.grad_out, wacc);
+  adj_tile_f64(tile, gtile, nt, tc, qb, qe, a.q, a.qdtype, a.grad_out, wacc);
   __syncthreads();
   if (tid < nt * 3) {
     double v = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) v += wacc[w][tid];
     a.partial[((int64_t)blockIdx.y * a.nf + f0) * 3 + tid] = v;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void bwd3d_fp32c_kernel(BwdArgs a) {
+  __shared__ Face32B tile[kTileFB32];
+  __shared__ float acc[kTileFB32 * 3][kBlock];
+  const int tid = threadIdx.x;
+  const int64_t f0 = (int64_t)blockIdx.x * kTileFB32;
+  const int nt = (int)min((int64_t)kTileFB32, a.nf - f0);
+  for (int i = tid; i < nt * (int)(sizeof(Face32B) / 16); i += kBlock)
+    reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(a.f32 + f0)[i];
+  for (int v = 0; v < nt * 3; ++v) acc[v][tid] = 0.0f;
+  __syncthreads();
+  const int64_t qb = (int64_t)blockIdx.y * a.q_per_split;
+  const int64_t qe = min(a.nq, qb + a.q_per_split);
+  adj_tile_fp32c(tile, nt, qb, qe, a.q, a.qdtype, a.cot, acc);
+  __syncthreads();
+  adj_block_sum32(acc, nt, a.partial + ((int64_t)blockIdx.y * a.nf + f0) * 3);
+}
+
+// Centred cotangent per Q in binary32 (see centred_cotangent); the owning
+// mesh of Q_i is found by bisection over the Q offsets when there are several.
+__global__ __launch_bounds__(256) void cotangent32_kernel(const void* q, int qdtype, const float2* grad_out,
+                                                          int64_t nq, const MeshInfo* info, const int64_t* q_off,
+                                                          int64_t n_meshes, float2* cot) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  int64_t mesh = 0;
+  if (q_off) {
+    int64_t lo = 0, hi = n_meshes;  // last mesh with q_off[mesh] <= i
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) / 2;
+      if (q_off[mid] <= i) lo = mid; else hi = mid;
+    }
+    mesh = lo;
+  }
+  double Q[3];
+  load_q3(q, qdtype, i, Q);
+  const float2 g = grad_out[i];
+  double hr, hi;
+  centred_cotangent((double)g.x, (double)g.y, Q, info[mesh].t, hr, hi);
+  cot[i] = make_float2((float)hr, (float)hi);
 }
 
 __global__ __launch_bounds__(256) void gram64_kernel(const Face64* f64, int64_t nf, double* gram) {
@@ -155,13 +195,21 @@ hipError_t launch_gram64(const Face64* f64, int64_t nf, double* gram, hipStream_
 
 hipError_t launch_bwd3d_fp64(const BwdArgs& a, const double* gram, hipStream_t s) {
   dim3 grid((unsigned)((a.nf + kTileFB - 1) / kTileFB), (unsigned)a.qsplits);
-  bwd3d_kernel<PFT_FP64><<<grid, kBlock, 0, s>>>(a, gram);
+  bwd3d_fp64_kernel<<<grid, kBlock, 0, s>>>(a, gram);
   return hipGetLastError();
 }
 
 hipError_t launch_bwd3d_fp32c(const BwdArgs& a, hipStream_t s) {
-  dim3 grid((unsigned)((a.nf + kTileFB - 1) / kTileFB), (unsigned)a.qsplits);
-  bwd3d_kernel<PFT_FP32C><<<grid, kBlock, 0, s>>>(a, nullptr);
+  dim3 grid((unsigned)((a.nf + kTileFB32 - 1) / kTileFB32), (unsigned)a.qsplits);
+  bwd3d_fp32c_kernel<<<grid, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cotangent32(const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
+                              const int64_t* d_q_off, int64_t n_meshes, float2* cot, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  cotangent32_kernel<<<grid_for(nq), 256, 0, s>>>(q, qdtype, static_cast<const float2*>(grad_out), nq, info, d_q_off,
+                                                  n_meshes, cot);
   return hipGetLastError();
 }
 

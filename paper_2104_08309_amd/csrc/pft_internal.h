@@ -28,6 +28,10 @@ constexpr int kQPTBatch = PFT_QPT_BATCH;  // Q per thread in the batched FP32C f
 #define PFT_QPTB 3
 #endif
 constexpr int kQPTB = PFT_QPTB;    // Q per thread per pass in the adjoint
+#ifndef PFT_TILEFB32
+#define PFT_TILEFB32 8
+#endif
+constexpr int kTileFB32 = PFT_TILEFB32;  // faces per block in the FP32C adjoint
 constexpr int kTileE = 64;         // 2D edges staged in LDS per tile
 
 // Series thresholds (dimensionless). A (Q, face) pair uses the face's simplex
@@ -162,6 +166,7 @@ struct BwdArgs {
   int qdtype;
   int64_t nq;
   const void* grad_out;
+  const float2* cot;  // FP32C: centred cotangent per Q (see launch_cotangent32)
   int qsplits;
   int64_t q_per_split;
   double* partial;    // [qsplits][nf][3]
@@ -169,6 +174,10 @@ struct BwdArgs {
 hipError_t launch_gram64(const Face64* f64, int64_t nf, double* gram /*[nf][8]*/, hipStream_t s);
 hipError_t launch_bwd3d_fp64(const BwdArgs& a, const double* gram, hipStream_t s);
 hipError_t launch_bwd3d_fp32c(const BwdArgs& a, hipStream_t s);
+// cot[i] = conj-ready cotangent g(Q_i) exp(-i Q_i.t) in binary32, t the centre of
+// the mesh that owns Q_i (d_q_off: CSR offsets of Q per mesh, or NULL for one mesh).
+hipError_t launch_cotangent32(const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
+                              const int64_t* d_q_off, int64_t n_meshes, float2* cot, hipStream_t s);
 // Sum the per-split adjoint weights, form per-corner vectors N_m R_{m,k} and
 // gather them per vertex through the sorted incidence list.
 hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, int64_t nf,
@@ -200,7 +209,7 @@ struct BatchItemBwd {   // one (mesh, face-tile, Q-chunk) work item
   int32_t mesh;
   int32_t qchunk;
   int64_t f0;           // first global face index of the tile
-  int32_t nf;           // faces in the tile (<= kTileFB)
+  int32_t nf;           // faces in the tile (<= kTileFB for FP64, <= kTileFB32 for FP32C)
   int32_t pad;
   int64_t q0;           // first global Q index of the chunk
   int64_t nq;           // Q in the chunk
@@ -217,7 +226,8 @@ hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_of
                                    void* intensity, hipStream_t s);
 hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
-                            const void* grad_out, const MeshInfo* info, double* partial, int grid, hipStream_t s);
+                            const void* grad_out, const float2* cot, const MeshInfo* info, double* partial, int grid,
+                            hipStream_t s);
 hipError_t launch_batch_bwd_reduce(const double* partial, const int64_t* d_face_base, const int32_t* d_face_nchunks,
                                    const int64_t* d_tri_off, const int32_t* d_face_mesh, const Face64* f64,
                                    int64_t nf_total, double* contrib, hipStream_t s);
