@@ -38,37 +38,53 @@ PFT_HD __forceinline__ void bary_moments(T d0, T d1, T m, T tol, T* yr, T* yi, T
   const T d2 = -d0 - d1;
   const T e2 = d0 * d1 + d2 * (d0 + d1);
   const T e3 = d0 * d1 * d2;
-  T Hm3 = T(0), Hm2 = T(0), Hm1 = T(1);  // H_{n-3}, H_{n-2}, H_{n-1} at n = 1
-  T a0 = T(1), a1 = T(1);                // h_{n-1}(d0,d1,d2,d0), h_{n-1}(d0,d1,d2,d1)
-  T y0r = T(1.0 / 6.0), y0i = T(0), y1r = T(1.0 / 6.0), y1i = T(0);
-  jr = T(0.5);
-  ji = T(0);
   const T m2 = m * m, m4 = m2 * m2;
-  T mn = m;  // m^n at the start of each chunk
+  // n = 1..4 written out: H_1 = 0, H_2 = -e2, H_3 = e3, H_4 = e2^2
+  const T H2 = -e2, H3 = e3, H4 = e2 * e2;
+  T a0 = d0, a1 = d1;  // h_{n}(d0,d1,d2,d0), h_{n}(d0,d1,d2,d1) at n = 1
+  T y0i = inv_fact_c<T>(4) * a0, y1i = inv_fact_c<T>(4) * a1;
+  a0 = H2 + d0 * a0;
+  a1 = H2 + d1 * a1;
+  T y0r = T(1.0 / 6.0) - inv_fact_c<T>(5) * a0, y1r = T(1.0 / 6.0) - inv_fact_c<T>(5) * a1;
+  jr = T(0.5) - inv_fact_c<T>(4) * H2;
+  a0 = H3 + d0 * a0;
+  a1 = H3 + d1 * a1;
+  y0i -= inv_fact_c<T>(6) * a0;
+  y1i -= inv_fact_c<T>(6) * a1;
+  ji = -inv_fact_c<T>(5) * H3;
+  a0 = H4 + d0 * a0;
+  a1 = H4 + d1 * a1;
+  y0r += inv_fact_c<T>(7) * a0;
+  y1r += inv_fact_c<T>(7) * a1;
+  jr += inv_fact_c<T>(6) * H4;
+  T Hm3 = H2, Hm2 = H3, Hm1 = H4;  // H_{n-3}, H_{n-2}, H_{n-1} at n = 5
+  T mn = m * m4;                   // m^n at the start of each chunk
+  if (!(mn * inv_fact_c<T>(5) < tol)) {
 #pragma unroll
-  for (int n = 1; n < NMAX; n += 4) {
-    // i^n cycles (+i, -1, -i, +1) over n = 1, 2, 3, 4 (mod 4)
+    for (int n = 5; n < NMAX; n += 4) {
+      // i^n cycles (+i, -1, -i, +1) over n = 1, 2, 3, 4 (mod 4)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const T H = -e2 * Hm2 + e3 * Hm3;
-      a0 = H + d0 * a0;
-      a1 = H + d1 * a1;
-      const T c3 = inv_fact_c<T>(n + r + 3), c2 = inv_fact_c<T>(n + r + 2);
-      if (r == 0) {
-        y0i += c3 * a0; y1i += c3 * a1; ji += c2 * H;
-      } else if (r == 1) {
-        y0r -= c3 * a0; y1r -= c3 * a1; jr -= c2 * H;
-      } else if (r == 2) {
-        y0i -= c3 * a0; y1i -= c3 * a1; ji -= c2 * H;
-      } else {
-        y0r += c3 * a0; y1r += c3 * a1; jr += c2 * H;
+      for (int r = 0; r < 4; ++r) {
+        const T H = -e2 * Hm2 + e3 * Hm3;
+        a0 = H + d0 * a0;
+        a1 = H + d1 * a1;
+        const T c3 = inv_fact_c<T>(n + r + 3), c2 = inv_fact_c<T>(n + r + 2);
+        if (r == 0) {
+          y0i += c3 * a0; y1i += c3 * a1; ji += c2 * H;
+        } else if (r == 1) {
+          y0r -= c3 * a0; y1r -= c3 * a1; jr -= c2 * H;
+        } else if (r == 2) {
+          y0i -= c3 * a0; y1i -= c3 * a1; ji -= c2 * H;
+        } else {
+          y0r += c3 * a0; y1r += c3 * a1; jr += c2 * H;
+        }
+        Hm3 = Hm2;
+        Hm2 = Hm1;
+        Hm1 = H;
       }
-      Hm3 = Hm2;
-      Hm2 = Hm1;
-      Hm1 = H;
+      mn *= m4;
+      if (mn * inv_fact_c<T>(n + 4) < tol) break;
     }
-    mn *= m4;
-    if (mn * inv_fact_c<T>(n + 4) < tol) break;
   }
   yr[0] = y0r; yi[0] = y0i;
   yr[1] = y1r; yi[1] = y1i;
@@ -193,16 +209,11 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
   const float cf = cos_turns(r), sf = sin_turns(r);
   const float zr = gr * cf + gi * sf;
   const float zi = gr * sf - gi * cf;
-  const float p0 = qx * f.h0[0] + qy * f.h0[1] + qz * f.h0[2];  // psi_k in turns
-  const float p1 = qx * f.h1[0] + qy * f.h1[1] + qz * f.h1[2];
-  const float p2 = -p0 - p1;
-  const float kFourPi = 2.0f * kTwoPiF;
-  const float q0 = kFourPi * p0, q1 = kFourPi * p1, q2 = -q0 - q1;  // delta_k = Q.u_k
+  const float q0 = qx * f.u0[0] + qy * f.u0[1] + qz * f.u0[2];  // delta_k = Q.u_k
+  const float q1 = qx * f.u1[0] + qy * f.u1[1] + qz * f.u1[2];
+  const float q2 = -q0 - q1;
   const float m = fmaxf(fabsf(q0), fmaxf(fabsf(q1), fabsf(q2)));
-  if (f.thr < 0.0f) {  // empty face
-    R[0] = R[1] = R[2] = 0.0f;
-    return;
-  }
+  // (an empty face has an all-zero record: m = 0, finite weights, times N = 0 later)
   if (m <= (float)kSeriesMaxPhase) {
     // barycentric moments by their series in binary32 (terms decrease from the
     // start for |delta| <= 3; no cancellation with the face's size in Q)
@@ -216,6 +227,7 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
   const float w0 = Px * f.d0[0] + Py * f.d0[1] + Pz * f.d0[2];
   const float w1 = Px * f.d1[0] + Py * f.d1[1] + Pz * f.d1[2];
   const float w[3] = {w0, w1, -w0 - w1};
+  const float p0 = q0 * (0.5f * kInv2PiF), p1 = q1 * (0.5f * kInv2PiF), p2 = -p0 - p1;  // psi_k in turns
   const float s0 = sin_turns(p0), c0 = cos_turns(p0);
   const float s1 = sin_turns(p1), c1 = cos_turns(p1);
   const float c2 = c0 * c1 - s0 * s1;

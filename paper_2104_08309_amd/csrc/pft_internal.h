@@ -98,10 +98,10 @@ struct alignas(16) Face32B {
   float N[3];
   float d0[3];    // b - a
   float d1[3];    // c - b
-  float h0[3];    // (a - g) / (4 pi)
-  float h1[3];    // (b - g) / (4 pi)
+  float u0[3];    // a - g: vertex phase delta_0 = Q . u0
+  float u1[3];    // b - g
   float G[6];     // d0.d0, d1.d1, d2.d2, d0.d1, d1.d2, d2.d0
-  float thr;      // tau_b^2 |N|^2 / L^2
+  float thr;      // tau_b^2 |N|^2 / L^2 (-1 for an empty face, whose record is otherwise all zero)
   float kap;      // tau_relb^2 |N|^2
   float pad[2];
 };

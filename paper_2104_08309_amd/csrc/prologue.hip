@@ -226,26 +226,28 @@ __global__ __launch_bounds__(256) void face32b_kernel(const Face64* in, int64_t 
   const Face64 f = in[m];
   Face32B r;
   const double L2 = f.pad[0], N2 = f.pad[1];
+  const bool ok = f.thr >= 0.0;
   double d0[3], d1[3], d2[3];
   for (int k = 0; k < 3; ++k) {
     d0[k] = f.u1[k] - f.u0[k];
     d1[k] = -f.u0[k] - 2.0 * f.u1[k];
     d2[k] = 2.0 * f.u0[k] + f.u1[k];
     r.gt[k] = f.g[k] * kInv2Pi;
-    r.N[k] = (float)f.N[k];
-    r.d0[k] = (float)d0[k];
-    r.d1[k] = (float)d1[k];
-    r.h0[k] = (float)(f.u0[k] * kInv4Pi);
-    r.h1[k] = (float)(f.u1[k] * kInv4Pi);
+    // an empty face gets an all-zero record: its weights stay finite and the
+    // vertex gather multiplies them by N = 0
+    r.N[k] = ok ? (float)f.N[k] : 0.0f;
+    r.d0[k] = ok ? (float)d0[k] : 0.0f;
+    r.d1[k] = ok ? (float)d1[k] : 0.0f;
+    r.u0[k] = ok ? (float)f.u0[k] : 0.0f;
+    r.u1[k] = ok ? (float)f.u1[k] : 0.0f;
   }
   auto dot = [](const double* x, const double* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
-  r.G[0] = (float)dot(d0, d0);
-  r.G[1] = (float)dot(d1, d1);
-  r.G[2] = (float)dot(d2, d2);
-  r.G[3] = (float)dot(d0, d1);
-  r.G[4] = (float)dot(d1, d2);
-  r.G[5] = (float)dot(d2, d0);
-  const bool ok = f.thr >= 0.0;
+  r.G[0] = ok ? (float)dot(d0, d0) : 0.0f;
+  r.G[1] = ok ? (float)dot(d1, d1) : 0.0f;
+  r.G[2] = ok ? (float)dot(d2, d2) : 0.0f;
+  r.G[3] = ok ? (float)dot(d0, d1) : 0.0f;
+  r.G[4] = ok ? (float)dot(d1, d2) : 0.0f;
+  r.G[5] = ok ? (float)dot(d2, d0) : 0.0f;
   r.thr = ok ? (float)(tau * tau * N2 / L2) : -1.0f;
   r.kap = ok ? (float)(tau_rel * tau_rel * N2) : -1.0f;
   r.pad[0] = r.pad[1] = 0.0f;
