@@ -336,15 +336,14 @@ __device__ __forceinline__ void adj_tile_f64(const Face64* tile, const double (*
 }
 
 // ---------------------------------------------------------------------------
-// FP32C adjoint, one block's share: `nt` face records in LDS against the Q
-// range [qb, qe), kQPTB Q per thread per pass. Each thread adds its weights
-// for face j to its own binary32 slots acc[3 j + k][thread] (zeroed by the
-// caller); adj_block_sum32 reduces the slots once the range is done, so no
-// cross-lane traffic happens per face. `cot` holds the centred cotangent per Q.
+// FP32C adjoint, one block's share: `nt` face records in LDS against the
+// reordered Q records [qb, qe), kQPTB Q per thread per pass. Each thread adds
+// its weights for face j to its own binary32 slots acc[3 j + k][thread] (zeroed
+// by the caller); adj_block_sum32 reduces the slots once the range is done, so
+// no cross-lane traffic happens per face.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void adj_tile_fp32c(const Face32B* tile, int nt, int64_t qb, int64_t qe, const void* q,
-                                               int qdtype, const float2* __restrict__ cot,
-                                               float (*acc)[kBlock]) {
+__device__ __forceinline__ void adj_tile_fp32c(const Face32B* tile, int nt, int64_t qb, int64_t qe,
+                                               const QRec32* __restrict__ rec, float (*acc)[kBlock]) {
   constexpr int P = kQPTB;
   const int tid = threadIdx.x;
   for (int64_t q0 = qb; q0 < qe; q0 += (int64_t)kBlock * P) {
@@ -356,10 +355,12 @@ __device__ __forceinline__ void adj_tile_fp32c(const Face32B* tile, int nt, int6
       Qd[p][0] = Qd[p][1] = Qd[p][2] = 0.0;
       hr[p] = hi[p] = 0.0f;
       if (qi < qe) {
-        load_q3(q, qdtype, qi, Qd[p]);
-        const float2 h = cot[qi];
-        hr[p] = h.x;
-        hi[p] = h.y;
+        const QRec32 r = rec[qi];
+        Qd[p][0] = r.q[0];
+        Qd[p][1] = r.q[1];
+        Qd[p][2] = r.q[2];
+        hr[p] = r.hr;
+        hi[p] = r.hi;
       }
       qx[p] = (float)Qd[p][0];
       qy[p] = (float)Qd[p][1];

@@ -163,6 +163,27 @@ const char* main_name(bool fwd, int mode) {
 }
 
 // Shared tail of the adjoint: per-corner vectors -> sorted incidence -> vertex gather.
+// Reordered Q records with their centred cotangents for the FP32C adjoint.
+pft_status build_qrec32(Arena& ar, const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
+                        const int64_t* d_q_off, int64_t n_meshes, QRec32** rec, hipStream_t s) {
+  if (nq > INT32_MAX) return fail(PFT_EINVAL, "FP32C adjoint: more than 2^31-1 Q points");
+  QRecScratch w;
+  w.box_partial = ar.get<double>(256 * 6);
+  w.box = ar.get<double>(6);
+  w.keys = ar.get<uint64_t>(nq);
+  w.keys_sorted = ar.get<uint64_t>(nq);
+  w.vals = ar.get<uint32_t>(nq);
+  w.perm = ar.get<uint32_t>(nq);
+  *rec = ar.get<QRec32>(nq);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = qrec32_sort_bytes(nq, n_meshes, &w.sort_bytes);
+  if (e != hipSuccess) return hip_fail(e, "Q sort size query");
+  w.sort_temp = ar.get<unsigned char>(w.sort_bytes);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  e = launch_qrec32(q, qdtype, grad_out, nq, info, d_q_off, n_meshes, w, *rec, s);
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "Q records");
+}
+
 pft_status gather_tail(Arena& ar, const int32_t* tris, int64_t nf, const int64_t* d_vert_off,
                        const int32_t* d_face_mesh, int64_t nv_total, const double* contrib, void* grad, int vdtype,
                        hipStream_t s) {
@@ -417,7 +438,6 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   Face64* f64 = ar.get<Face64>(nf);
   Face32B* f32 = c128 ? nullptr : ar.get<Face32B>(nf);
   double* gram = c128 ? ar.get<double>((size_t)nf * 8) : nullptr;
-  float2* cot = c128 ? nullptr : ar.get<float2>(nq);
   int qs;
   int64_t qper;
   choose_q_splits(nq, nf, c128 ? kTileFB : kTileFB32, &qs, &qper);
@@ -427,9 +447,10 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
   if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, kTauF64, f64, s);
   if (e == hipSuccess && !c128) e = launch_face32b(f64, nf, kTauB32, kTauRelB32, f32, s);
-  if (e == hipSuccess && !c128) e = launch_cotangent32(q, qdtype, grad_out, nq, info, nullptr, 1, cot, s);
   if (e == hipSuccess && c128) e = launch_gram64(f64, nf, gram, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint prologue");
+  QRec32* rec = nullptr;
+  if (!c128 && (st = build_qrec32(ar, q, qdtype, grad_out, nq, info, nullptr, 1, &rec, s)) != PFT_OK) return st;
   BwdArgs a;
   a.info = info;
   a.f64 = f64;
@@ -439,7 +460,7 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   a.qdtype = qdtype;
   a.nq = nq;
   a.grad_out = grad_out;
-  a.cot = cot;
+  a.rec = rec;
   a.qsplits = qs;
   a.q_per_split = qper;
   a.partial = partial;
@@ -628,7 +649,7 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
   st = batch_prologue(ar, b, kTauF64, p, s);
   if (st != PFT_OK) return st;
   Face32B* f32b = nullptr;
-  float2* cot = nullptr;
+  QRec32* rec = nullptr;
   double* gram = nullptr;
   hipError_t e = hipSuccess;
   if (c128) {
@@ -637,13 +658,12 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
     e = launch_gram64(p.f64, p.nf, gram, s);
   } else {
     f32b = ar.get<Face32B>(p.nf);
-    cot = ar.get<float2>(nq_total);
     if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
     e = launch_face32b(p.f64, p.nf, kTauB32, kTauRelB32, f32b, s);
-    if (e == hipSuccess)
-      e = launch_cotangent32(b->q, b->qdtype, grad_out, nq_total, p.info, p.d_q_off, n, cot, s);
   }
   if (e != hipSuccess) return hip_fail(e, "batch adjoint prologue");
+  if (!c128 && (st = build_qrec32(ar, b->q, b->qdtype, grad_out, nq_total, p.info, p.d_q_off, n, &rec, s)) != PFT_OK)
+    return st;
   std::vector<BatchItemBwd> items;
   const int64_t ftile = c128 ? kTileFB : kTileFB32;  // faces per item (one block)
   std::vector<int64_t> face_base(n);
@@ -691,7 +711,7 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
                                           (int64_t)num_cus() * batch_bwd_blocks_per_cu(mode));
   prof_begin("batch_bwd", s);
-  e = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, b->q, b->qdtype, grad_out, cot, p.info,
+  e = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, b->q, b->qdtype, grad_out, rec, p.info,
                        partial, grid, s);
   prof_end("batch_bwd", s);
   if (e != hipSuccess) return hip_fail(e, "batch adjoint");

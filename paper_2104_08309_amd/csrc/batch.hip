@@ -205,9 +205,8 @@ __global__ __launch_bounds__(kBlock) void batch_bwd_fp64_kernel(const BatchItemB
 
 __global__ __launch_bounds__(kBlock) void batch_bwd_fp32c_kernel(const BatchItemBwd* __restrict__ items,
                                                                 int64_t n_items, uint32_t* counter,
-                                                                const Face32B* __restrict__ f32b, const void* q,
-                                                                int qdtype, const float2* __restrict__ cot,
-                                                                double* partial) {
+                                                                const Face32B* __restrict__ f32b,
+                                                                const QRec32* __restrict__ rec, double* partial) {
   __shared__ Face32B tile[kTileFB32];
   __shared__ float acc[kTileFB32 * 3][kBlock];
   __shared__ int slot;
@@ -221,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void batch_bwd_fp32c_kernel(const BatchItem
       reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f32b + it.f0)[i];
     for (int v = 0; v < nt * 3; ++v) acc[v][tid] = 0.0f;
     __syncthreads();
-    adj_tile_fp32c(tile, nt, it.q0, it.q0 + it.nq, q, qdtype, cot, acc);
+    adj_tile_fp32c(tile, nt, it.q0, it.q0 + it.nq, rec, acc);
     __syncthreads();
     adj_block_sum32(acc, nt, partial + it.part * 3);
     __syncthreads();
@@ -293,14 +292,14 @@ hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_of
 
 hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
-                            const void* grad_out, const float2* cot, const MeshInfo* info, double* partial, int grid,
+                            const void* grad_out, const QRec32* rec, const MeshInfo* info, double* partial, int grid,
                             hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (mode == PFT_FP64)
     batch_bwd_fp64_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, gram, q, qdtype, grad_out, info,
                                                   partial);
   else
-    batch_bwd_fp32c_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f32b, q, qdtype, cot, partial);
+    batch_bwd_fp32c_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f32b, rec, partial);
   return hipGetLastError();
 }
 

@@ -26,8 +26,8 @@
 //    wavefront into binary64 per-wave slots.
 //  * FP32C: each thread adds its weights to private binary32 slots in LDS
 //    (one per face and corner), and a fixed-order binary64 block sum at the
-//    end writes the per-split partials; the cotangent g exp(-iQ.t) is formed
-//    once per Q beforehand (cotangent32_kernel).
+//    end writes the per-split partials; the Q list is reordered and paired
+//    with its cotangent g exp(-iQ.t) beforehand (qorder.hip).
 #include <hipcub/hipcub.hpp>
 
 #include "adj_terms.h"
@@ -72,33 +72,9 @@ __global__ __launch_bounds__(kBlock) void bwd3d_fp32c_kernel(BwdArgs a) {
   __syncthreads();
   const int64_t qb = (int64_t)blockIdx.y * a.q_per_split;
   const int64_t qe = min(a.nq, qb + a.q_per_split);
-  adj_tile_fp32c(tile, nt, qb, qe, a.q, a.qdtype, a.cot, acc);
+  adj_tile_fp32c(tile, nt, qb, qe, a.rec, acc);
   __syncthreads();
   adj_block_sum32(acc, nt, a.partial + ((int64_t)blockIdx.y * a.nf + f0) * 3);
-}
-
-// Centred cotangent per Q in binary32 (see centred_cotangent); the owning
-// mesh of Q_i is found by bisection over the Q offsets when there are several.
-__global__ __launch_bounds__(256) void cotangent32_kernel(const void* q, int qdtype, const float2* grad_out,
-                                                          int64_t nq, const MeshInfo* info, const int64_t* q_off,
-                                                          int64_t n_meshes, float2* cot) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nq) return;
-  int64_t mesh = 0;
-  if (q_off) {
-    int64_t lo = 0, hi = n_meshes;  // last mesh with q_off[mesh] <= i
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) / 2;
-      if (q_off[mid] <= i) lo = mid; else hi = mid;
-    }
-    mesh = lo;
-  }
-  double Q[3];
-  load_q3(q, qdtype, i, Q);
-  const float2 g = grad_out[i];
-  double hr, hi;
-  centred_cotangent((double)g.x, (double)g.y, Q, info[mesh].t, hr, hi);
-  cot[i] = make_float2((float)hr, (float)hi);
 }
 
 __global__ __launch_bounds__(256) void gram64_kernel(const Face64* f64, int64_t nf, double* gram) {
@@ -205,13 +181,6 @@ hipError_t launch_bwd3d_fp32c(const BwdArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_cotangent32(const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
-                              const int64_t* d_q_off, int64_t n_meshes, float2* cot, hipStream_t s) {
-  if (nq <= 0) return hipSuccess;
-  cotangent32_kernel<<<grid_for(nq), 256, 0, s>>>(q, qdtype, static_cast<const float2*>(grad_out), nq, info, d_q_off,
-                                                  n_meshes, cot);
-  return hipGetLastError();
-}
 
 hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, int64_t nf,
                                    double* contrib, hipStream_t s) {

@@ -107,6 +107,15 @@ struct alignas(16) Face32B {
 };
 static_assert(sizeof(Face32B) == 128, "Face32B layout");
 
+// One Q of the FP32C adjoint's reordered list (qorder.hip): the Q vector and the
+// centred cotangent g(Q) exp(-iQ.t) of the mesh that owns it.
+struct alignas(16) QRec32 {
+  double q[3];
+  float hr, hi;
+};
+static_assert(sizeof(QRec32) == 32, "QRec32 layout");
+
+
 // 2D edge record (FP64), relative to the polygon's vertex mean.
 struct alignas(16) Edge2D {
   double a[2];    // start vertex
@@ -166,7 +175,7 @@ struct BwdArgs {
   int qdtype;
   int64_t nq;
   const void* grad_out;
-  const float2* cot;  // FP32C: centred cotangent per Q (see launch_cotangent32)
+  const QRec32* rec;  // FP32C: reordered Q with their centred cotangents (launch_qrec32)
   int qsplits;
   int64_t q_per_split;
   double* partial;    // [qsplits][nf][3]
@@ -174,10 +183,25 @@ struct BwdArgs {
 hipError_t launch_gram64(const Face64* f64, int64_t nf, double* gram /*[nf][8]*/, hipStream_t s);
 hipError_t launch_bwd3d_fp64(const BwdArgs& a, const double* gram, hipStream_t s);
 hipError_t launch_bwd3d_fp32c(const BwdArgs& a, hipStream_t s);
-// cot[i] = conj-ready cotangent g(Q_i) exp(-i Q_i.t) in binary32, t the centre of
-// the mesh that owns Q_i (d_q_off: CSR offsets of Q per mesh, or NULL for one mesh).
-hipError_t launch_cotangent32(const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
-                              const int64_t* d_q_off, int64_t n_meshes, float2* cot, hipStream_t s);
+
+// qorder.hip: the FP32C adjoint's Q list, reordered (by mesh, then by the Morton
+// code of Q) and gathered with the centred cotangent g(Q) exp(-iQ.t), t the
+// centre of the mesh that owns Q (d_q_off: CSR offsets of Q per mesh, or NULL
+// for one mesh). Each mesh's Q keep their index range.
+struct QRecScratch {     // device temporaries of launch_qrec32
+  double* box_partial;   // [256 * 6]
+  double* box;           // [6]
+  uint64_t* keys;        // [nq]
+  uint64_t* keys_sorted; // [nq]
+  uint32_t* vals;        // [nq]
+  uint32_t* perm;        // [nq]
+  void* sort_temp;       // [sort_bytes]
+  size_t sort_bytes;
+};
+hipError_t qrec32_sort_bytes(int64_t nq, int64_t n_meshes, size_t* bytes);
+hipError_t launch_qrec32(const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
+                         const int64_t* d_q_off, int64_t n_meshes, const QRecScratch& w, QRec32* rec,
+                         hipStream_t s);
 // Sum the per-split adjoint weights, form per-corner vectors N_m R_{m,k} and
 // gather them per vertex through the sorted incidence list.
 hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, int64_t nf,
@@ -226,7 +250,7 @@ hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_of
                                    void* intensity, hipStream_t s);
 hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
-                            const void* grad_out, const float2* cot, const MeshInfo* info, double* partial, int grid,
+                            const void* grad_out, const QRec32* rec, const MeshInfo* info, double* partial, int grid,
                             hipStream_t s);
 hipError_t launch_batch_bwd_reduce(const double* partial, const int64_t* d_face_base, const int32_t* d_face_nchunks,
                                    const int64_t* d_tri_off, const int32_t* d_face_mesh, const Face64* f64,
