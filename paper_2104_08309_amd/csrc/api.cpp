@@ -90,7 +90,10 @@ std::map<std::string, ProfRec> g_prof;
 // ---------------------------------------------------------------------------
 // heuristics
 // ---------------------------------------------------------------------------
-constexpr int64_t kTargetBlocks = 2048;   // >= 8 blocks of 256 threads per CU on 256 CUs
+#ifndef PFT_TARGET_BLOCKS
+#define PFT_TARGET_BLOCKS 8192
+#endif
+constexpr int64_t kTargetBlocks = PFT_TARGET_BLOCKS;  // 32 blocks of 256 threads per CU on 256 CUs: short tails
 constexpr int64_t kMinFacesPerSplit = 512;
 constexpr int64_t kBatchChunkF = 4096;    // faces per batched forward item
 constexpr int64_t kBatchChunkQ = 65536;   // Q per batched adjoint item
@@ -162,28 +165,54 @@ const char* main_name(bool fwd, int mode) {
   return mode == PFT_FP64 ? "bwd3d_fp64" : "bwd3d_fp32c";
 }
 
-// Shared tail of the adjoint: per-corner vectors -> sorted incidence -> vertex gather.
-// Reordered Q records with their centred cotangents for the FP32C adjoint.
-pft_status build_qrec32(Arena& ar, const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
-                        const int64_t* d_q_off, int64_t n_meshes, QRec32** rec, hipStream_t s) {
-  if (nq > INT32_MAX) return fail(PFT_EINVAL, "FP32C adjoint: more than 2^31-1 Q points");
-  QRecScratch w;
+// Visiting order of Q (qorder.hip): nearby Q share wavefronts. Below kQOrderMin Q
+// the caller's order is kept (the sort would cost more than it saves).
+#ifndef PFT_QORDER_MIN
+#define PFT_QORDER_MIN 8192
+#endif
+constexpr int64_t kQOrderMin = PFT_QORDER_MIN;
+
+pft_status build_qorder(Arena& ar, const void* q, int qdtype, int64_t nq, const int64_t* d_q_off, int64_t n_meshes,
+                        uint32_t** perm, hipStream_t s) {
+  *perm = nullptr;
+  if (nq < kQOrderMin || nq > INT32_MAX) return PFT_OK;
+  QOrderScratch w;
   w.box_partial = ar.get<double>(256 * 6);
   w.box = ar.get<double>(6);
   w.keys = ar.get<uint64_t>(nq);
   w.keys_sorted = ar.get<uint64_t>(nq);
   w.vals = ar.get<uint32_t>(nq);
   w.perm = ar.get<uint32_t>(nq);
-  *rec = ar.get<QRec32>(nq);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
-  hipError_t e = qrec32_sort_bytes(nq, n_meshes, &w.sort_bytes);
+  hipError_t e = qorder_sort_bytes(nq, n_meshes, &w.sort_bytes);
   if (e != hipSuccess) return hip_fail(e, "Q sort size query");
   w.sort_temp = ar.get<unsigned char>(w.sort_bytes);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
-  e = launch_qrec32(q, qdtype, grad_out, nq, info, d_q_off, n_meshes, w, *rec, s);
+  e = launch_qorder(q, qdtype, nq, d_q_off, n_meshes, w, s);
+  if (e != hipSuccess) return hip_fail(e, "Q order");
+  *perm = w.perm;
+  return PFT_OK;
+}
+
+// The FP32C adjoint's Q records: Q in visiting order with their centred cotangents.
+pft_status build_qrec32(Arena& ar, const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
+                        const int64_t* d_q_off, int64_t n_meshes, QRec32** rec, hipStream_t s) {
+  uint32_t* perm = nullptr;
+  pft_status st = build_qorder(ar, q, qdtype, nq, d_q_off, n_meshes, &perm, s);
+  if (st != PFT_OK) return st;
+  if (!perm) {  // identity order
+    perm = ar.get<uint32_t>(nq);
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    hipError_t e = launch_iota_u32(perm, nq, s);
+    if (e != hipSuccess) return hip_fail(e, "Q order");
+  }
+  *rec = ar.get<QRec32>(nq);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_qrec32_gather(q, qdtype, grad_out, nq, perm, info, d_q_off, n_meshes, *rec, s);
   return e == hipSuccess ? PFT_OK : hip_fail(e, "Q records");
 }
 
+// Shared tail of the adjoint: per-corner vectors -> sorted incidence -> vertex gather.
 pft_status gather_tail(Arena& ar, const int32_t* tris, int64_t nf, const int64_t* d_vert_off,
                        const int32_t* d_face_mesh, int64_t nv_total, const double* contrib, void* grad, int vdtype,
                        hipStream_t s) {
@@ -392,6 +421,8 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
   if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, c128 ? kTauF64 : kTauF32, f64, s);
   if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
   if (e != hipSuccess) return hip_fail(e, "3D prologue");
+  uint32_t* perm = nullptr;
+  if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
   FwdArgs a;
   a.f64 = f64;
   a.f32 = f32;
@@ -400,6 +431,7 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
   a.q = q;
   a.qdtype = qdtype;
   a.nq = nq;
+  a.perm = perm;
   a.splits = splits;
   a.faces_per_split = per;
   a.partial = partial;
@@ -617,11 +649,14 @@ pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, 
                                           (int64_t)num_cus() * batch_fwd_blocks_per_cu(mode));
   const double tau0 = c128 ? kTau0F64 : kTau0F32;
   prof_begin("batch_fwd", s);
-  e = launch_batch_fwd(mode, d_items, n_items, counter, p.f64, f32, b->q, b->qdtype, partial, p.info, tau0, grid, s);
+  uint32_t* perm = nullptr;
+  if ((st = build_qorder(ar, b->q, b->qdtype, nq_total, p.d_q_off, n, &perm, s)) != PFT_OK) return st;
+  e = launch_batch_fwd(mode, d_items, n_items, counter, p.f64, f32, b->q, b->qdtype, perm, partial, p.info, tau0, grid,
+                       s);
   prof_end("batch_fwd", s);
   if (e != hipSuccess) return hip_fail(e, "batch forward");
-  e = launch_batch_fwd_finish(partial, p.d_q_off, n, d_q_part, d_q_chunks, p.info, b->q, b->qdtype, nq_total, tau0,
-                              c128 ? 1 : 0, out, intensity, s);
+  e = launch_batch_fwd_finish(partial, p.d_q_off, n, d_q_part, d_q_chunks, p.info, b->q, b->qdtype, perm, nq_total,
+                              tau0, c128 ? 1 : 0, out, intensity, s);
   if (e != hipSuccess) return hip_fail(e, "batch finish");
   return PFT_OK;
 }

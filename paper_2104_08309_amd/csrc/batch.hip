@@ -27,8 +27,8 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* __restrict__ items, int64_t n_items,
                                                           uint32_t* counter, const Face64* __restrict__ f64,
                                                           const Face32* __restrict__ f32, const void* q, int qdtype,
-                                                          double2* partial, const MeshInfo* __restrict__ info,
-                                                          double tau0) {
+                                                          const uint32_t* __restrict__ perm, double2* partial,
+                                                          const MeshInfo* __restrict__ info, double tau0) {
   __shared__ __align__(16) unsigned char smem[kTileF * sizeof(Face64)];
   __shared__ int slot;
   for (;;) {
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
       // one Q per thread
       const bool active = lane < it.nq;
       double Qd[3] = {0.0, 0.0, 0.0};
-      if (active) load_q3(q, qdtype, it.q0 + lane, Qd);
+      if (active) load_q3(q, qdtype, perm ? (int64_t)perm[it.q0 + lane] : it.q0 + lane, Qd);
       const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
       const bool small = sqrt(Q2d) * R < tau0;
       Face64* tile = reinterpret_cast<Face64*>(smem);
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         const int qo = lane + k * kBlock;
         active[k] = qo < it.nq;
         Qd[k][0] = Qd[k][1] = Qd[k][2] = 0.0;
-        if (active[k]) load_q3(q, qdtype, it.q0 + qo, Qd[k]);
+        if (active[k]) load_q3(q, qdtype, perm ? (int64_t)perm[it.q0 + qo] : it.q0 + qo, Qd[k]);
         qx[k] = (float)Qd[k][0];
         qy[k] = (float)Qd[k][1];
         qz[k] = (float)Qd[k][2];
@@ -129,11 +129,13 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
 __global__ __launch_bounds__(256) void batch_fwd_finish_kernel(const double2* partial, const int64_t* q_off,
                                                                int64_t n_meshes, const int64_t* q_part,
                                                                const int32_t* q_chunks, const MeshInfo* info,
-                                                               const void* q, int qdtype, int64_t nq_total,
+                                                               const void* q, int qdtype,
+                                                               const uint32_t* perm, int64_t nq_total,
                                                                double tau0, int out_c128, void* out,
                                                                void* intensity) {
   const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (qi >= nq_total) return;
+  const int64_t dst = perm ? (int64_t)perm[qi] : qi;  // the permutation keeps each mesh's range
   int64_t lo = 0, hi = n_meshes;  // last mesh with q_off[mesh] <= qi
   while (hi - lo > 1) {
     const int64_t mid = (lo + hi) / 2;
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(256) void batch_fwd_finish_kernel(const double2* pa
     xi += v.y;
   }
   double Q[3];
-  load_q3(q, qdtype, qi, Q);
+  load_q3(q, qdtype, dst, Q);
   const MeshInfo mi = info[mesh];
   const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
   if (!(sqrt(Q2) * mi.R < tau0)) {
@@ -161,11 +163,11 @@ __global__ __launch_bounds__(256) void batch_fwd_finish_kernel(const double2* pa
   const double Fr = ct * xr - st * xi;
   const double Fi = ct * xi + st * xr;
   if (out_c128) {
-    static_cast<double2*>(out)[qi] = make_double2(Fr, Fi);
-    if (intensity) static_cast<double*>(intensity)[qi] = Fr * Fr + Fi * Fi;
+    static_cast<double2*>(out)[dst] = make_double2(Fr, Fi);
+    if (intensity) static_cast<double*>(intensity)[dst] = Fr * Fr + Fi * Fi;
   } else {
-    static_cast<float2*>(out)[qi] = make_float2((float)Fr, (float)Fi);
-    if (intensity) static_cast<float*>(intensity)[qi] = (float)(Fr * Fr + Fi * Fi);
+    static_cast<float2*>(out)[dst] = make_float2((float)Fr, (float)Fi);
+    if (intensity) static_cast<float*>(intensity)[dst] = (float)(Fr * Fr + Fi * Fi);
   }
 }
 
@@ -268,25 +270,26 @@ int batch_bwd_blocks_per_cu(int mode) {
 }
 
 hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
-                            const Face64* f64, const Face32* f32, const void* q, int qdtype, double2* partial,
-                            const MeshInfo* info, double tau0, int grid, hipStream_t s) {
+                            const Face64* f64, const Face32* f32, const void* q, int qdtype, const uint32_t* perm,
+                            double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (mode == PFT_FP64)
-    batch_fwd_kernel<PFT_FP64><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, partial, info,
-                                                       tau0);
+    batch_fwd_kernel<PFT_FP64><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial,
+                                                       info, tau0);
   else
-    batch_fwd_kernel<PFT_FP32C><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, partial,
+    batch_fwd_kernel<PFT_FP32C><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial,
                                                         info, tau0);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_off, int64_t n_meshes,
                                    const int64_t* d_q_part, const int32_t* d_q_chunks, const MeshInfo* info,
-                                   const void* q, int qdtype, int64_t nq_total, double tau0, int out_c128, void* out,
-                                   void* intensity, hipStream_t s) {
+                                   const void* q, int qdtype, const uint32_t* perm, int64_t nq_total, double tau0,
+                                   int out_c128, void* out, void* intensity, hipStream_t s) {
   if (nq_total <= 0) return hipSuccess;
   batch_fwd_finish_kernel<<<(unsigned)((nq_total + 255) / 256), 256, 0, s>>>(
-      partial, d_q_off, n_meshes, d_q_part, d_q_chunks, info, q, qdtype, nq_total, tau0, out_c128, out, intensity);
+      partial, d_q_off, n_meshes, d_q_part, d_q_chunks, info, q, qdtype, perm, nq_total, tau0, out_c128, out,
+      intensity);
   return hipGetLastError();
 }
 

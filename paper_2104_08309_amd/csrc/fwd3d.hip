@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
   const int64_t qi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = qi < a.nq;
   double Q[3] = {0.0, 0.0, 0.0};
-  if (active) load_q3(a.q, a.qdtype, qi, Q);
+  if (active) load_q3(a.q, a.qdtype, a.perm ? (int64_t)a.perm[qi] : qi, Q);
   const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
   const bool small = sqrt(Q2) * a.info[0].R < a.tau0;
   const int64_t f_begin = (int64_t)blockIdx.y * a.faces_per_split;
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
     const int64_t qi = qbase + (int64_t)k * kBlock;
     active[k] = qi < a.nq;
     Qd[k][0] = Qd[k][1] = Qd[k][2] = 0.0;
-    if (active[k]) load_q3(a.q, a.qdtype, qi, Qd[k]);
+    if (active[k]) load_q3(a.q, a.qdtype, a.perm ? (int64_t)a.perm[qi] : qi, Qd[k]);
     qx[k] = (float)Qd[k][0];
     qy[k] = (float)Qd[k][1];
     qz[k] = (float)Qd[k][2];
@@ -118,12 +118,14 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
   }
 }
 
-// Sum the splits in order, apply exp(i Q.t) and 1/|Q|^2, write F and |F|^2.
+// Sum the splits in order, apply exp(i Q.t) and 1/|Q|^2, write F and |F|^2 at
+// the caller's index of the visited Q.
 __global__ __launch_bounds__(256) void fwd3d_finish_kernel(FwdArgs a, int out_c128) {
   const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (qi >= a.nq) return;
+  const int64_t dst = a.perm ? (int64_t)a.perm[qi] : qi;
   double Q[3];
-  load_q3(a.q, a.qdtype, qi, Q);
+  load_q3(a.q, a.qdtype, dst, Q);
   double xr = 0.0, xi = 0.0;
   for (int s = 0; s < a.splits; ++s) {
     const double2 v = a.partial[(int64_t)s * a.nq + qi];
@@ -142,12 +144,12 @@ __global__ __launch_bounds__(256) void fwd3d_finish_kernel(FwdArgs a, int out_c1
   const double Fr = ct * xr - st * xi;
   const double Fi = ct * xi + st * xr;
   if (out_c128) {
-    static_cast<double2*>(a.out)[qi] = make_double2(Fr, Fi);
-    if (a.intensity) static_cast<double*>(a.intensity)[qi] = Fr * Fr + Fi * Fi;
+    static_cast<double2*>(a.out)[dst] = make_double2(Fr, Fi);
+    if (a.intensity) static_cast<double*>(a.intensity)[dst] = Fr * Fr + Fi * Fi;
   } else {
     const float fr = (float)Fr, fi = (float)Fi;
-    static_cast<float2*>(a.out)[qi] = make_float2(fr, fi);
-    if (a.intensity) static_cast<float*>(a.intensity)[qi] = (float)(Fr * Fr + Fi * Fi);
+    static_cast<float2*>(a.out)[dst] = make_float2(fr, fi);
+    if (a.intensity) static_cast<float*>(a.intensity)[dst] = (float)(Fr * Fr + Fi * Fi);
   }
 }
 

@@ -144,6 +144,7 @@ hipError_t launch_edges2d(const double* verts, int64_t nv, const int64_t* d_off,
                           Edge2D* edges, hipStream_t s);
 hipError_t launch_validate(const int32_t* tris, int64_t nf, int64_t nv, unsigned long long* counts, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 
 // fwd3d.hip
 struct FwdArgs {
@@ -156,6 +157,7 @@ struct FwdArgs {
   int64_t nq;
   int splits;
   int64_t faces_per_split;
+  const uint32_t* perm;  // visiting order of Q (NULL: the caller's order); partials follow it
   double2* partial;   // [splits][nq] when splits > 1
   void* out;
   void* intensity;
@@ -184,24 +186,27 @@ hipError_t launch_gram64(const Face64* f64, int64_t nf, double* gram /*[nf][8]*/
 hipError_t launch_bwd3d_fp64(const BwdArgs& a, const double* gram, hipStream_t s);
 hipError_t launch_bwd3d_fp32c(const BwdArgs& a, hipStream_t s);
 
-// qorder.hip: the FP32C adjoint's Q list, reordered (by mesh, then by the Morton
-// code of Q) and gathered with the centred cotangent g(Q) exp(-iQ.t), t the
-// centre of the mesh that owns Q (d_q_off: CSR offsets of Q per mesh, or NULL
-// for one mesh). Each mesh's Q keep their index range.
-struct QRecScratch {     // device temporaries of launch_qrec32
+// qorder.hip: a permutation of the Q list (by mesh, then by the Morton code of
+// Q) that groups nearby Q into wavefronts; each mesh's Q keep their index range
+// (d_q_off: CSR offsets of Q per mesh, or NULL for one mesh). perm[i] is the
+// caller's index of the i-th visited Q.
+struct QOrderScratch {   // device temporaries of launch_qorder
   double* box_partial;   // [256 * 6]
   double* box;           // [6]
   uint64_t* keys;        // [nq]
   uint64_t* keys_sorted; // [nq]
   uint32_t* vals;        // [nq]
-  uint32_t* perm;        // [nq]
+  uint32_t* perm;        // [nq] result
   void* sort_temp;       // [sort_bytes]
   size_t sort_bytes;
 };
-hipError_t qrec32_sort_bytes(int64_t nq, int64_t n_meshes, size_t* bytes);
-hipError_t launch_qrec32(const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
-                         const int64_t* d_q_off, int64_t n_meshes, const QRecScratch& w, QRec32* rec,
-                         hipStream_t s);
+hipError_t qorder_sort_bytes(int64_t nq, int64_t n_meshes, size_t* bytes);
+hipError_t launch_qorder(const void* q, int qdtype, int64_t nq, const int64_t* d_q_off, int64_t n_meshes,
+                         const QOrderScratch& w, hipStream_t s);
+// rec[i] = Q[perm[i]] with its centred cotangent g exp(-iQ.t), t the centre of the owning mesh.
+hipError_t launch_qrec32_gather(const void* q, int qdtype, const void* grad_out, int64_t nq, const uint32_t* perm,
+                                const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, QRec32* rec,
+                                hipStream_t s);
 // Sum the per-split adjoint weights, form per-corner vectors N_m R_{m,k} and
 // gather them per vertex through the sorted incidence list.
 hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, int64_t nf,
@@ -242,12 +247,12 @@ struct BatchItemBwd {   // one (mesh, face-tile, Q-chunk) work item
 int batch_fwd_blocks_per_cu(int mode);
 int batch_bwd_blocks_per_cu(int mode);
 hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
-                            const Face64* f64, const Face32* f32, const void* q, int qdtype, double2* partial,
-                            const MeshInfo* info, double tau0, int grid, hipStream_t s);
+                            const Face64* f64, const Face32* f32, const void* q, int qdtype, const uint32_t* perm,
+                            double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s);
 hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_off, int64_t n_meshes,
                                    const int64_t* d_q_part, const int32_t* d_q_chunks, const MeshInfo* info,
-                                   const void* q, int qdtype, int64_t nq_total, double tau0, int out_c128, void* out,
-                                   void* intensity, hipStream_t s);
+                                   const void* q, int qdtype, const uint32_t* perm, int64_t nq_total, double tau0,
+                                   int out_c128, void* out, void* intensity, hipStream_t s);
 hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
                             const void* grad_out, const QRec32* rec, const MeshInfo* info, double* partial, int grid,

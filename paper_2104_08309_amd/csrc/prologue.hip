@@ -172,6 +172,11 @@ __global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, in
 constexpr double kInv2Pi = 0.15915494309189533577;
 constexpr double kInv4Pi = 0.07957747154594766788;
 
+__global__ __launch_bounds__(256) void iota_u32_kernel(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (uint32_t)i;
+}
+
 __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t nf, double tau, double tau_rel,
                                                      Face32* out) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -356,6 +361,12 @@ hipError_t launch_edges2d(const double* verts, int64_t nv, const int64_t* d_off,
 hipError_t launch_validate(const int32_t* tris, int64_t nf, int64_t nv, unsigned long long* counts, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   validate_kernel<<<grid_for(nf), 256, 0, s>>>(tris, nf, nv, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  iota_u32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
   return hipGetLastError();
 }
 

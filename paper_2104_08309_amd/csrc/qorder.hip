@@ -1,12 +1,16 @@
-// Q ordering for the FP32C adjoint.
+// Q ordering.
 //
-// The adjoint sums over Q, so it may visit the Q list in any order. Its
-// per-(Q, face) cost depends on the largest vertex phase |Q.(v - g)| of the
-// lanes of a wavefront (the series runs until that lane has converged), so
-// wavefronts of nearby Q waste less work than wavefronts spanning a grid row.
-// The Q points are sorted by mesh, then by the Morton code of their
-// coordinates quantised to 10 bits per axis inside the bounding box of all Q,
-// and gathered with their centred cotangents into QRec32 records.
+// Each Q is evaluated independently, so the kernels may visit the Q list in any
+// order. Their cost per (Q, face) follows the worst lane of a wavefront: the
+// adjoint's series runs until its largest vertex phase |Q.(v - g)| has
+// converged, and the forward's near-degenerate branch (Q nearly along a face
+// normal) runs whenever one lane needs it. Wavefronts of nearby Q waste less
+// work than wavefronts spanning a grid row or a random set. The Q points are
+// sorted by mesh, then by the Morton code of their coordinates quantised
+// inside the bounding box of all Q (10 bits per axis; 5 for a single mesh,
+// which keeps the sort key at 16 bits); the forward reads Q
+// through the permutation and writes F back to the caller's order, the FP32C
+// adjoint gathers Q with their centred cotangents into QRec32 records.
 #include <hipcub/hipcub.hpp>
 
 #include "pft_device.h"
@@ -45,11 +49,19 @@ __global__ __launch_bounds__(256) void qbox_partial_kernel(const void* q, int qd
 }
 
 __global__ __launch_bounds__(256) void qbox_final_kernel(const double* partial, int nb, double* box) {
-  if (threadIdx.x >= 6) return;
-  const int k = threadIdx.x;
-  double v = k < 3 ? INFINITY : -INFINITY;
-  for (int b = 0; b < nb; ++b) v = k < 3 ? fmin(v, partial[b * 6 + k]) : fmax(v, partial[b * 6 + k]);
-  box[k] = v;
+  __shared__ double red[6][256];
+  const int tid = threadIdx.x;
+  for (int k = 0; k < 6; ++k) red[k][tid] = tid < nb ? partial[tid * 6 + k] : (k < 3 ? INFINITY : -INFINITY);
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s)
+      for (int k = 0; k < 3; ++k) {
+        red[k][tid] = fmin(red[k][tid], red[k][tid + s]);
+        red[3 + k][tid] = fmax(red[3 + k][tid], red[3 + k][tid + s]);
+      }
+    __syncthreads();
+  }
+  if (tid < 6) box[tid] = red[tid][0];
 }
 
 // spread the low 10 bits of x to every third bit
@@ -90,6 +102,26 @@ __global__ __launch_bounds__(256) void qkey_kernel(const void* q, int qdtype, in
   vals[i] = (uint32_t)i;
 }
 
+// One mesh: a 15-bit Morton code (5 bits per axis). 16-bit keys let the radix
+// sort use its one-sweep passes at every size above 1e5 (its merge-based path,
+// taken for wider keys up to 2^20 items, costs several times more).
+__global__ __launch_bounds__(256) void qkey16_kernel(const void* q, int qdtype, int64_t nq, const double* box,
+                                                     uint16_t* keys, uint32_t* vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  double Q[3];
+  load_q3(q, qdtype, i, Q);
+  uint64_t code = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double ext = box[3 + k] - box[k];
+    double u = ext > 0.0 ? (Q[k] - box[k]) / ext * 32.0 : 0.0;
+    u = fmin(fmax(u, 0.0), 31.0);
+    code |= spread3((uint32_t)u) << k;
+  }
+  keys[i] = (uint16_t)code;
+  vals[i] = (uint32_t)i;
+}
+
 __global__ __launch_bounds__(256) void qrec32_kernel(const void* q, int qdtype, const float2* grad_out, int64_t nq,
                                                      const uint32_t* perm, const MeshInfo* info,
                                                      const int64_t* q_off, int64_t n_meshes, QRec32* rec) {
@@ -114,31 +146,49 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-hipError_t qrec32_sort_bytes(int64_t nq, int64_t n_meshes, size_t* bytes) {
+int qorder_end_bit(int64_t n_meshes) {
   int end_bit = 30;
   while (end_bit < 64 && ((uint64_t)1 << (end_bit - 30)) < (uint64_t)std::max<int64_t>(n_meshes, 1)) ++end_bit;
-  *bytes = 0;
-  return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                            (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)nq, 0, end_bit);
+  return end_bit;
 }
 
-hipError_t launch_qrec32(const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
-                         const int64_t* d_q_off, int64_t n_meshes, const QRecScratch& w, QRec32* rec,
-                         hipStream_t s) {
+hipError_t qorder_sort_bytes(int64_t nq, int64_t n_meshes, size_t* bytes) {
+  *bytes = 0;
+  if (n_meshes <= 1)
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint16_t*)nullptr, (uint16_t*)nullptr,
+                                              (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)nq, 0, 15);
+  return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                            (const uint32_t*)nullptr, (uint32_t*)nullptr, (int)nq, 0,
+                                            qorder_end_bit(n_meshes));
+}
+
+hipError_t launch_qorder(const void* q, int qdtype, int64_t nq, const int64_t* d_q_off, int64_t n_meshes,
+                         const QOrderScratch& w, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   const int nb = (int)std::min<int64_t>(kBoxBlocks, (nq + 255) / 256);
   qbox_partial_kernel<<<nb, 256, 0, s>>>(q, qdtype, nq, w.box_partial);
   qbox_final_kernel<<<1, 256, 0, s>>>(w.box_partial, nb, w.box);
+  size_t tb = w.sort_bytes;
+  if (n_meshes <= 1) {
+    uint16_t* k16 = reinterpret_cast<uint16_t*>(w.keys);
+    uint16_t* k16s = reinterpret_cast<uint16_t*>(w.keys_sorted);
+    qkey16_kernel<<<grid_for(nq), 256, 0, s>>>(q, qdtype, nq, w.box, k16, w.vals);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceRadixSort::SortPairs(w.sort_temp, tb, k16, k16s, w.vals, w.perm, (int)nq, 0, 15, s);
+  }
   qkey_kernel<<<grid_for(nq), 256, 0, s>>>(q, qdtype, nq, w.box, d_q_off, n_meshes, w.keys, w.vals);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int end_bit = 30;
-  while (end_bit < 64 && ((uint64_t)1 << (end_bit - 30)) < (uint64_t)std::max<int64_t>(n_meshes, 1)) ++end_bit;
-  size_t tb = w.sort_bytes;
-  e = hipcub::DeviceRadixSort::SortPairs(w.sort_temp, tb, w.keys, w.keys_sorted, w.vals, w.perm, (int)nq, 0, end_bit,
-                                         s);
-  if (e != hipSuccess) return e;
-  qrec32_kernel<<<grid_for(nq), 256, 0, s>>>(q, qdtype, static_cast<const float2*>(grad_out), nq, w.perm, info,
+  return hipcub::DeviceRadixSort::SortPairs(w.sort_temp, tb, w.keys, w.keys_sorted, w.vals, w.perm, (int)nq, 0,
+                                            qorder_end_bit(n_meshes), s);
+}
+
+hipError_t launch_qrec32_gather(const void* q, int qdtype, const void* grad_out, int64_t nq, const uint32_t* perm,
+                                const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, QRec32* rec,
+                                hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  qrec32_kernel<<<grid_for(nq), 256, 0, s>>>(q, qdtype, static_cast<const float2*>(grad_out), nq, perm, info,
                                              d_q_off, n_meshes, rec);
   return hipGetLastError();
 }
