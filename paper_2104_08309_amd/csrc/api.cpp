@@ -91,10 +91,13 @@ std::map<std::string, ProfRec> g_prof;
 // heuristics
 // ---------------------------------------------------------------------------
 #ifndef PFT_TARGET_BLOCKS
-#define PFT_TARGET_BLOCKS 8192
+#define PFT_TARGET_BLOCKS 16384
 #endif
-constexpr int64_t kTargetBlocks = PFT_TARGET_BLOCKS;  // 32 blocks of 256 threads per CU on 256 CUs: short tails
-constexpr int64_t kMinFacesPerSplit = 512;
+constexpr int64_t kTargetBlocks = PFT_TARGET_BLOCKS;  // 64 blocks of 256 threads per CU on 256 CUs: short tails
+#ifndef PFT_MIN_FACES_PER_SPLIT
+#define PFT_MIN_FACES_PER_SPLIT 128
+#endif
+constexpr int64_t kMinFacesPerSplit = PFT_MIN_FACES_PER_SPLIT;
 constexpr int64_t kBatchChunkF = 4096;    // faces per batched forward item
 constexpr int64_t kBatchChunkQ = 65536;   // Q per batched adjoint item
 

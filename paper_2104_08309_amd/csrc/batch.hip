@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
           for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Qd, xr, xi);
         }
       }
-      if (active) partial[it.part + lane] = make_double2(xr, xi);
+      if (active) store_stream(partial + it.part + lane, make_double2(xr, xi));
     } else {
       // kQPTBatch Q per thread, strided by the block size
       Face32* tile = reinterpret_cast<Face32*>(smem);
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         if (active[k]) {
           const double2 v = small[k] ? make_double2(xr[k], xi[k])
                                      : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
-          partial[it.part + lane + k * kBlock] = v;
+          store_stream(partial + it.part + lane + k * kBlock, v);
         }
       }
     }
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void batch_fwd_finish_kernel(const double2* pa
   const int64_t j = qi - q_off[mesh];
   double xr = 0.0, xi = 0.0;
   for (int c = 0; c < q_chunks[mesh]; ++c) {
-    const double2 v = partial[q_part[mesh] + (int64_t)c * nqm + j];
+    const double2 v = load_stream(partial + q_part[mesh] + (int64_t)c * nqm + j);
     xr += v.x;
     xi += v.y;
   }

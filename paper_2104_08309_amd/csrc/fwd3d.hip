@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
       for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Q, xr, xi);
     }
   }
-  if (active) a.partial[(int64_t)blockIdx.y * a.nq + qi] = make_double2(xr, xi);
+  if (active) store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qi, make_double2(xr, xi));
 }
 
 // Each thread evaluates kQPT Q points (strided by the block size, so loads stay
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
     if (active[k]) {
       const double2 v = small[k] ? make_double2(xr[k], xi[k])
                                  : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
-      a.partial[(int64_t)blockIdx.y * a.nq + qbase + (int64_t)k * kBlock] = v;
+      store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qbase + (int64_t)k * kBlock, v);
     }
   }
 }
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void fwd3d_finish_kernel(FwdArgs a, int out_c1
   load_q3(a.q, a.qdtype, dst, Q);
   double xr = 0.0, xi = 0.0;
   for (int s = 0; s < a.splits; ++s) {
-    const double2 v = a.partial[(int64_t)s * a.nq + qi];
+    const double2 v = load_stream(a.partial + (int64_t)s * a.nq + qi);
     xr += v.x;
     xi += v.y;
   }

@@ -58,6 +58,16 @@ PFT_HD __forceinline__ void centred_cotangent(double gr, double gi, const double
   hi = gi * ct - gr * st;
 }
 
+// Partial sums written by one kernel and read once by the next: streaming
+// (non-temporal) accesses keep them from displacing the face records in L2.
+__device__ __forceinline__ void store_stream(double2* p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+__device__ __forceinline__ double2 load_stream(const double2* p) {
+  return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+
 // sin(2 pi x), cos(2 pi x) for x in turns (hardware transcendental unit; valid for |x| <= 256).
 __device__ __forceinline__ float sin_turns(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ float cos_turns(float x) { return __builtin_amdgcn_cosf(x); }
