@@ -84,6 +84,26 @@ def test_deterministic_repeat(gpu):
         assert np.array_equal(a, b)
 
 
+def test_q_order_at_sorted_sizes(gpu):
+    """At >= 8192 Q the FP32C adjoint visits Q in Morton order: parity against the oracle, and a
+    permuted Q list (with its cotangents) gives the same gradient up to binary32 summation order."""
+    rng = np.random.default_rng(12)
+    v, t = mg.icosphere(1, 1.5)
+    v = v + np.array([-0.2, 0.5, 0.1])
+    q = mg.q_random_ball(10000, 4.0, rng)
+    g = (rng.normal(size=q.shape[0]) + 1j * rng.normal(size=q.shape[0])).astype(np.complex64)
+    want = O.grad3d(v, t, q, g)
+    step("bwd sorted-size fp32c")
+    got = run_bwd(v, t, q, g, "fp32c")
+    assert nrel(got, want) < TOL_FP32C
+    perm = rng.permutation(q.shape[0])
+    step("bwd sorted-size fp32c permuted")
+    got_p = run_bwd(v, t, q[perm], g[perm], "fp32c")
+    assert nrel(got_p, got) < 1e-6
+    step("bwd sorted-size fp64")
+    assert nrel(run_bwd(v, t, q, g.astype(np.complex128), "fp64"), want) < TOL_GRAD64
+
+
 def test_config4_full_size_sampled_vertices(gpu):
     """Icosphere L6 with radial noise, 256^2 Q slice: full adjoint on the GPU, oracle on sampled vertices."""
     cfg = mg.config4()

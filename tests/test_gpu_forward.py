@@ -106,6 +106,25 @@ def test_deterministic_repeat(gpu):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
 
 
+def test_q_order_invariance_at_sorted_sizes(gpu):
+    """At >= 8192 Q the kernels visit Q in Morton order and write F back to the caller's index: parity
+    against the oracle, and a permuted Q list gives the same values permuted (bitwise: each Q is
+    evaluated independently of the others)."""
+    rng = np.random.default_rng(11)
+    v, t = mg.icosphere(2, 2.0)
+    v = v + np.array([0.4, -0.3, 0.2])
+    q = np.concatenate([mg.q_random_ball(12000, 4.0, rng), special_q(3.0)])
+    want = O.ft3d(v, t, q)
+    perm = rng.permutation(q.shape[0])
+    for mode, tol in (("fp64", TOL_FP64), ("fp32c", TOL_FP32C)):
+        step(f"sorted-size parity {mode} ({q.shape[0]} Q)")
+        got = run(v, t, q, mode)
+        assert nrel(got, want) < tol, mode
+        step(f"sorted-size permuted {mode}")
+        got_p = run(v, t, q[perm], mode)
+        assert np.array_equal(got_p, got[perm]), mode
+
+
 def test_config2_full_size_sampled(gpu):
     """Icosphere L4 (5120 faces), full 64^3 grid on the GPU; oracle on a seeded sample incl. 0, axes, diagonal."""
     cfg = mg.config2()
