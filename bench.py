@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192, help="Q points of the oracle's timed sample")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU baseline")
+    ap.add_argument("--no-orient", action="store_true", help="skip the orientation-average measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -195,6 +196,37 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # orientation-averaged intensity on the same mesh: 256 magnitudes in (0, 0.5] x a 32 x 32 direction
+    # rule, i.e. the same 262144 face-Q work per call as the forward above (FP32C and FP64 forms)
+    orient = None
+    if not args.no_orient:
+        print("[bench] orientation average", file=sys.stderr, flush=True)
+        qabs = np.linspace(0.5 / 256, 0.5, 256)
+        dirs, wts = mg.sphere_quadrature(32, 32)
+        qa_t = torch.tensor(qabs, device=dev)
+        d_t = torch.tensor(dirs, device=dev)
+        w_t = torch.tensor(wts, device=dev)
+
+        def orient_call(mode):
+            return pft.orientation_average(V64, T, qa_t, d_t, w_t, mode=mode)
+
+        o_steps = max(3, args.steps // 4)
+        t32, I32 = timed(lambda: orient_call("fp32c"), o_steps, 1)
+        t64, I64 = timed(lambda: orient_call("fp64"), max(2, o_steps // 2), 1)
+        I32, I64 = I32.cpu().numpy(), I64.cpu().numpy()
+        npair = nf * qabs.size * dirs.shape[0]
+        orient = {"workload": f"icosphere L4 mesh, {qabs.size} |Q| in (0, 0.5] x {dirs.shape[0]} directions "
+                              f"(Gauss-Legendre 32 x uniform 32)",
+                  "value_fp32c": npair / t32, "ms_per_call_fp32c": t32 * 1e3,
+                  "value_fp64": npair / t64, "ms_per_call_fp64": t64 * 1e3, "unit": "face*Q/s",
+                  "rel_err_fp32c_vs_fp64_gpu": float(np.linalg.norm(I32 - I64) / np.linalg.norm(I64))}
+        if not args.no_cpu_baseline:
+            import oracle as O
+            pick = [37]
+            Io = O.orientation_average(v, t, qabs[pick], dirs, wts)
+            orient["rel_err_fp32c_vs_oracle_sample"] = float(np.max(np.abs(I32[pick] - Io) / np.abs(Io)))
+            orient["oracle_sample"] = f"|Q| = {qabs[pick[0]]:.5f}, all {dirs.shape[0]} directions"
+
     # roofline of the dominant kernel (the longer of the forward and adjoint kernels)
     def roof(kernel, ms, flop):
         achieved = flop * nf * nq / (ms * 1e-3) / 1e12
@@ -249,6 +281,7 @@ def main():
         "roofline": roofline,
         "roofline_other_kernel": other,
         "cpu_baseline": cpu,
+        "orientation_average": orient,
     }
     print(json.dumps(line), flush=True)
 

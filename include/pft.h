@@ -112,6 +112,30 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
                           void* stream);
 
 /*
+ * pft_orientation_average -- orientation-averaged intensity of a closed mesh,
+ *     I(q_i) = sum_j w_j |F(q_i s_j)|^2,
+ * the powder / solution-scattering quantity that motivates the method (the
+ * paper's introduction), with F as in pft_forward_3d evaluated at every
+ * (magnitude, direction) pair in the given arithmetic form.
+ *
+ *  Mesh arguments as in pft_forward_3d.
+ *  qabs     [nqa] float64 magnitudes |Q| (DEVICE).
+ *  dirs     [ndir][3] float64 unit directions s_j (DEVICE).
+ *  weights  [ndir] float64 quadrature weights w_j (DEVICE); for the average
+ *           over the sphere they sum to 1 (a product Gauss-Legendre x uniform
+ *           quadrature is exact for spherical harmonics up to its degree).
+ *  mode     PFT_FP64 or PFT_FP32C for the transform; the weighted sum is
+ *           formed in binary64 in a fixed order either way.
+ *  out      [nqa] float64 (DEVICE), overwritten; 0 when ndir == 0.
+ * Temporaries: nqa * ndir Q points (24 B each) and intensities.
+ * Errors: as pft_forward_3d; EINVAL also for nqa > 2^31 - 1 or
+ * nqa * ndir * 3 beyond int64.
+ */
+pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                   const double* qabs, int64_t nqa, const double* dirs, const double* weights,
+                                   int64_t ndir, pft_mode mode, double* out, void* stream);
+
+/*
  * pft_backward_3d -- adjoint of pft_forward_3d with respect to the vertices.
  * The paper gives the forward transform only; the derivative follows from the
  * same volume integral: moving the boundary with velocity field u changes F by

@@ -66,6 +66,22 @@ def q_random_ball(n: int, qmax: float, rng: np.random.Generator) -> np.ndarray:
     return d * r[:, None]
 
 
+def sphere_quadrature(n_theta: int, n_phi: int):
+    """Product quadrature on the unit sphere: Gauss-Legendre in cos(theta) x uniform in phi.
+
+    Returns (dirs [n_theta * n_phi, 3], weights [n_theta * n_phi]) with the
+    weights summing to 1, so sum_j w_j f(s_j) approximates the average of f
+    over directions; exact for spherical harmonics of degree < 2 n_theta with
+    |m| < n_phi.
+    """
+    x, wx = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2.0 * math.pi * (np.arange(n_phi) + 0.5) / n_phi
+    st = np.sqrt(1.0 - x * x)
+    dirs = np.stack([np.outer(st, np.cos(phi)), np.outer(st, np.sin(phi)), np.outer(x, np.ones(n_phi))], axis=-1)
+    w = np.outer(0.5 * wx, np.full(n_phi, 1.0 / n_phi))
+    return dirs.reshape(-1, 3), w.reshape(-1)
+
+
 # ----------------------------------------------------------------------------
 # 2D shapes
 # ----------------------------------------------------------------------------

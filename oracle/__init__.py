@@ -18,6 +18,8 @@ Fourier transform of polygonal areas and volumes"):
   the in-plane edge normal corrected; see ``ft3d``).
 * ``grad3d`` -- dL/dvertices for a real loss L(F) given dL/dReF + i dL/dImF,
   from the derivative of the same volume integral (transport theorem).
+* ``orientation_average`` -- sum_j w_j |F(q s_j)|^2 over a direction
+  quadrature (the orientation-averaged scattering intensity).
 
 Removable singularities (Q = 0, Q parallel to a face normal, Q perpendicular
 to an edge) are handled by series that follow from the same integrals.
@@ -29,5 +31,5 @@ force quadrature, invariants and finite differences).
 from .pft_oracle import (  # noqa: F401
     area2d, volume3d, hsym, simplex_exp_series,
     ft2d, ft2d_edge_terms, ft3d, ft3d_face_terms, face_integrals,
-    face_vertex_moments, dft3d_dverts, grad3d, grad3d_vertices,
+    face_vertex_moments, dft3d_dverts, grad3d, grad3d_vertices, orientation_average,
 )

@@ -17,7 +17,8 @@ from . import _lib
 from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
 
 __all__ = [
-    "forward_2d", "forward_3d", "backward_3d", "batch_forward", "batch_backward", "validate_mesh",
+    "forward_2d", "forward_3d", "backward_3d", "batch_forward", "batch_backward", "orientation_average",
+    "validate_mesh",
     "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
 ]
 
@@ -119,6 +120,37 @@ def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: s
                                          tris.shape[0], _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out),
                                          _ptr(inten), _stream(verts.device)))
     return (out, inten) if intensity else out
+
+
+def orientation_average(verts: torch.Tensor, tris: torch.Tensor, qabs: torch.Tensor, dirs: torch.Tensor,
+                        weights: torch.Tensor, mode: str = "fp32c") -> torch.Tensor:
+    """I(|Q|) = sum_j w_j |F(|Q| s_j)|^2 for each magnitude in ``qabs`` (float64 result).
+
+    ``dirs`` [ndir, 3] unit vectors and ``weights`` [ndir] form the direction
+    quadrature (float64, on the mesh's device).
+    """
+    verts, tris = _mesh(verts, tris)
+    qabs = _on_gpu(qabs, "qabs")
+    dirs = _on_gpu(dirs, "dirs")
+    weights = _on_gpu(weights, "weights")
+    for name, t in (("qabs", qabs), ("dirs", dirs), ("weights", weights)):
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64, got {t.dtype}")
+        if t.device != verts.device:
+            raise ValueError(f"{name} must be on the same device as the mesh")
+    if qabs.dim() != 1:
+        raise ValueError(f"qabs must have shape [nqa], got {tuple(qabs.shape)}")
+    if dirs.dim() != 2 or dirs.shape[1] != 3:
+        raise ValueError(f"dirs must have shape [ndir, 3], got {tuple(dirs.shape)}")
+    if weights.dim() != 1 or weights.shape[0] != dirs.shape[0]:
+        raise ValueError("weights must have shape [ndir] matching dirs")
+    out = torch.empty(qabs.shape[0], dtype=torch.float64, device=verts.device)
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_orientation_average(
+            _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(qabs),
+            qabs.shape[0], _ptr(dirs), _ptr(weights), dirs.shape[0], mode_id(mode), _ptr(out),
+            _stream(verts.device)))
+    return out
 
 
 def backward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, grad_out: torch.Tensor,

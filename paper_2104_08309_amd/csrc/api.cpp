@@ -399,19 +399,17 @@ pft_status pft_forward_2d(const double* verts, int64_t nv, const int64_t* contou
   return PFT_OK;
 }
 
-pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
-                          const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* intensity,
-                          void* stream) {
-  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
-  if (st != PFT_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// The 3D forward after validation: prologue, Q order, transform, finish.
+// `out` may be NULL when only |F|^2 is wanted.
+pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                          const void* q, int qdtype, int64_t nq, int mode, void* out, void* intensity,
+                          hipStream_t s) {
   const bool c128 = mode == PFT_FP64;
-  if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
-  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
-  if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
-  if (nq == 0) return PFT_OK;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  ensure_pool();
-  Arena ar(s);
+  pft_status st = PFT_OK;
   MeshInfo* info = ar.get<MeshInfo>(1);
   Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
   Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
@@ -449,6 +447,62 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
   e = launch_fwd3d_finish(a, c128 ? 1 : 0, s);
   if (e != hipSuccess) return hip_fail(e, "3D finish");
   return PFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                          const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* intensity,
+                          void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
+  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
+  if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
+  if (nq == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  Arena ar(s);
+  return forward3d_core(ar, verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, out, intensity, s);
+}
+
+pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                   const double* qabs, int64_t nqa, const double* dirs, const double* weights,
+                                   int64_t ndir, pft_mode mode, double* out, void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, nullptr, PFT_F64, 0, mode);
+  if (st != PFT_OK) return st;
+  if (nqa < 0 || ndir < 0) return fail(PFT_EINVAL, "negative count");
+  if (nqa > 0 && (qabs == nullptr || out == nullptr)) return fail(PFT_EINVAL, "qabs or out is NULL");
+  if (ndir > 0 && (dirs == nullptr || weights == nullptr)) return fail(PFT_EINVAL, "dirs or weights is NULL");
+  if ((qabs && !aligned(qabs, 8)) || (dirs && !aligned(dirs, 8)) || (weights && !aligned(weights, 8)) ||
+      (out && !aligned(out, 8)))
+    return fail(PFT_EINVAL, "argument misaligned");
+  if (ndir > 0 && nqa > INT64_MAX / 3 / ndir) return fail(PFT_EINVAL, "nqa * ndir too large");
+  if (nqa > INT32_MAX) return fail(PFT_EINVAL, "too many magnitudes");
+  if (nqa == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  if (ndir == 0) {  // empty quadrature: the sum is 0
+    hipError_t e = zero_bytes(out, (size_t)nqa * sizeof(double), s);
+    return e == hipSuccess ? PFT_OK : hip_fail(e, "zero out");
+  }
+  const bool c128 = mode == PFT_FP64;
+  const int64_t nq = nqa * ndir;
+  Arena ar(s);
+  double* Q = ar.get<double>((size_t)nq * 3);
+  void* I = c128 ? (void*)ar.get<double>(nq) : (void*)ar.get<float>(nq);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_qdirs(qabs, nqa, dirs, ndir, Q, s);
+  if (e != hipSuccess) return hip_fail(e, "orientation Q list");
+  st = forward3d_core(ar, verts, vdtype, nv, tris, nf, Q, PFT_F64, nq, mode, nullptr, I, s);
+  if (st != PFT_OK) return st;
+  prof_begin("orient_sum", s);
+  e = launch_dir_sum(I, c128 ? PFT_F64 : PFT_F32, weights, nqa, ndir, out, s);
+  prof_end("orient_sum", s);
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "orientation sum");
 }
 
 pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,

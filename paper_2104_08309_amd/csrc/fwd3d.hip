@@ -144,11 +144,10 @@ __global__ __launch_bounds__(256) void fwd3d_finish_kernel(FwdArgs a, int out_c1
   const double Fr = ct * xr - st * xi;
   const double Fi = ct * xi + st * xr;
   if (out_c128) {
-    static_cast<double2*>(a.out)[dst] = make_double2(Fr, Fi);
+    if (a.out) static_cast<double2*>(a.out)[dst] = make_double2(Fr, Fi);
     if (a.intensity) static_cast<double*>(a.intensity)[dst] = Fr * Fr + Fi * Fi;
   } else {
-    const float fr = (float)Fr, fi = (float)Fi;
-    static_cast<float2*>(a.out)[dst] = make_float2(fr, fi);
+    if (a.out) static_cast<float2*>(a.out)[dst] = make_float2((float)Fr, (float)Fi);
     if (a.intensity) static_cast<float*>(a.intensity)[dst] = (float)(Fr * Fr + Fi * Fi);
   }
 }

@@ -261,6 +261,11 @@ hipError_t launch_batch_bwd_reduce(const double* partial, const int64_t* d_face_
                                    const int64_t* d_tri_off, const int32_t* d_face_mesh, const Face64* f64,
                                    int64_t nf_total, double* contrib, hipStream_t s);
 
+// orient.hip
+hipError_t launch_qdirs(const double* qabs, int64_t nqa, const double* dirs, int64_t ndir, double* Q, hipStream_t s);
+hipError_t launch_dir_sum(const void* I, int idtype, const double* w, int64_t nqa, int64_t ndir, double* out,
+                          hipStream_t s);
+
 // Profiling hooks (api.cpp)
 void prof_begin(const char* name, hipStream_t s);
 void prof_end(const char* name, hipStream_t s);
