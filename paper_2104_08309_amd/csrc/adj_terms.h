@@ -290,17 +290,16 @@ __device__ __forceinline__ double wave_total(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// binary64 adjoint, one block's share: the faces staged in LDS (`nt` of them)
-// against the Q range [qb, qe), kQPTB Q per thread per pass (strided by the
-// block size). For each face the real weights of a pass are summed per
-// thread, then across the wavefront, and lane 0 adds the wavefront's sum to
-// its slot `wacc[wave][3 j + k]` (zeroed by the caller).
+// binary64 adjoint, one block's share: `nt` face records in LDS (with their
+// edge Gram matrices) against the reordered Q records [qb, qe), kQPTB Q per
+// thread per pass. Each thread adds its weights for face j to its own
+// binary64 slots acc[3 j + k][thread] (zeroed by the caller); adj_block_sum
+// reduces the slots once the range is done.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void adj_tile_f64(const Face64* tile, const double (*gtile)[8], int nt, const double* tc,
-                                             int64_t qb, int64_t qe, const void* q, int qdtype,
-                                             const void* grad_out, double (*wacc)[kTileFB * 3]) {
+__device__ __forceinline__ void adj_tile_f64(const Face64* tile, const double (*gtile)[8], int nt, int64_t qb,
+                                             int64_t qe, const QRec64* __restrict__ rec, double (*acc)[kBlock]) {
   constexpr int P = kQPTB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   for (int64_t q0 = qb; q0 < qe; q0 += (int64_t)kBlock * P) {
     double Qd[P][3];
     double hr[P], hi[P];
@@ -310,9 +309,12 @@ __device__ __forceinline__ void adj_tile_f64(const Face64* tile, const double (*
       Qd[p][0] = Qd[p][1] = Qd[p][2] = 0.0;
       hr[p] = hi[p] = 0.0;
       if (qi < qe) {
-        load_q3(q, qdtype, qi, Qd[p]);
-        const double2 g = static_cast<const double2*>(grad_out)[qi];
-        centred_cotangent(g.x, g.y, Qd[p], tc, hr[p], hi[p]);
+        const QRec64 r = rec[qi];
+        Qd[p][0] = r.q[0];
+        Qd[p][1] = r.q[1];
+        Qd[p][2] = r.q[2];
+        hr[p] = r.hr;
+        hi[p] = r.hi;
       }
     }
 #pragma unroll 1
@@ -327,10 +329,7 @@ __device__ __forceinline__ void adj_tile_f64(const Face64* tile, const double (*
         S[2] += R[2];
       }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double v = wave_total(S[k]);
-        if (lane == 0) wacc[wave][3 * j + k] += v;
-      }
+      for (int k = 0; k < 3; ++k) acc[3 * j + k][tid] += S[k];
     }
   }
 }
@@ -385,10 +384,11 @@ __device__ __forceinline__ void adj_tile_fp32c(const Face32B* tile, int nt, int6
   }
 }
 
-// Sum of the per-thread slots of adj_tile_fp32c for each of the nt * 3 weights,
-// in binary64 and a fixed order; wave w handles weights w, w + 4, ... and lane
-// 0 writes out[v]. Call after a barrier.
-__device__ __forceinline__ void adj_block_sum32(float (*acc)[kBlock], int nt, double* out) {
+// Sum of the per-thread slots of adj_tile_fp32c / adj_tile_f64 for each of the
+// nt * 3 weights, in binary64 and a fixed order; wave w handles weights w,
+// w + 4, ... and lane 0 writes out[v]. Call after a barrier.
+template <typename T>
+__device__ __forceinline__ void adj_block_sum(T (*acc)[kBlock], int nt, double* out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int v = wave; v < nt * 3; v += kBlock / 64) {
     double x = 0.0;

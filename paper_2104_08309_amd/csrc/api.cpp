@@ -197,9 +197,13 @@ pft_status build_qorder(Arena& ar, const void* q, int qdtype, int64_t nq, const 
   return PFT_OK;
 }
 
-// The FP32C adjoint's Q records: Q in visiting order with their centred cotangents.
-pft_status build_qrec32(Arena& ar, const void* q, int qdtype, const void* grad_out, int64_t nq, const MeshInfo* info,
-                        const int64_t* d_q_off, int64_t n_meshes, QRec32** rec, hipStream_t s) {
+// The adjoint's Q records: Q in visiting order with their centred cotangents
+// (binary32 records for FP32C, binary64 records for FP64; the other is NULL).
+pft_status build_qrecs(Arena& ar, int mode, const void* q, int qdtype, const void* grad_out, int64_t nq,
+                       const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, QRec32** rec,
+                       QRec64** rec64, hipStream_t s) {
+  *rec = nullptr;
+  *rec64 = nullptr;
   uint32_t* perm = nullptr;
   pft_status st = build_qorder(ar, q, qdtype, nq, d_q_off, n_meshes, &perm, s);
   if (st != PFT_OK) return st;
@@ -209,9 +213,16 @@ pft_status build_qrec32(Arena& ar, const void* q, int qdtype, const void* grad_o
     hipError_t e = launch_iota_u32(perm, nq, s);
     if (e != hipSuccess) return hip_fail(e, "Q order");
   }
-  *rec = ar.get<QRec32>(nq);
-  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
-  hipError_t e = launch_qrec32_gather(q, qdtype, grad_out, nq, perm, info, d_q_off, n_meshes, *rec, s);
+  hipError_t e;
+  if (mode == PFT_FP64) {
+    *rec64 = ar.get<QRec64>(nq);
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    e = launch_qrec64_gather(q, qdtype, grad_out, nq, perm, info, d_q_off, n_meshes, *rec64, s);
+  } else {
+    *rec = ar.get<QRec32>(nq);
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    e = launch_qrec32_gather(q, qdtype, grad_out, nq, perm, info, d_q_off, n_meshes, *rec, s);
+  }
   return e == hipSuccess ? PFT_OK : hip_fail(e, "Q records");
 }
 
@@ -539,7 +550,8 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   if (e == hipSuccess && c128) e = launch_gram64(f64, nf, gram, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint prologue");
   QRec32* rec = nullptr;
-  if (!c128 && (st = build_qrec32(ar, q, qdtype, grad_out, nq, info, nullptr, 1, &rec, s)) != PFT_OK) return st;
+  QRec64* rec64 = nullptr;
+  if ((st = build_qrecs(ar, mode, q, qdtype, grad_out, nq, info, nullptr, 1, &rec, &rec64, s)) != PFT_OK) return st;
   BwdArgs a;
   a.info = info;
   a.f64 = f64;
@@ -550,6 +562,7 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   a.nq = nq;
   a.grad_out = grad_out;
   a.rec = rec;
+  a.rec64 = rec64;
   a.qsplits = qs;
   a.q_per_split = qper;
   a.partial = partial;
@@ -754,7 +767,9 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
     e = launch_face32b(p.f64, p.nf, kTauB32, kTauRelB32, f32b, s);
   }
   if (e != hipSuccess) return hip_fail(e, "batch adjoint prologue");
-  if (!c128 && (st = build_qrec32(ar, b->q, b->qdtype, grad_out, nq_total, p.info, p.d_q_off, n, &rec, s)) != PFT_OK)
+  QRec64* rec64 = nullptr;
+  if ((st = build_qrecs(ar, mode, b->q, b->qdtype, grad_out, nq_total, p.info, p.d_q_off, n, &rec, &rec64, s)) !=
+      PFT_OK)
     return st;
   std::vector<BatchItemBwd> items;
   const int64_t ftile = c128 ? kTileFB : kTileFB32;  // faces per item (one block)
@@ -803,8 +818,7 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
                                           (int64_t)num_cus() * batch_bwd_blocks_per_cu(mode));
   prof_begin("batch_bwd", s);
-  e = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, b->q, b->qdtype, grad_out, rec, p.info,
-                       partial, grid, s);
+  e = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, rec, rec64, partial, grid, s);
   prof_end("batch_bwd", s);
   if (e != hipSuccess) return hip_fail(e, "batch adjoint");
   e = launch_batch_bwd_reduce(partial, d_face_base, d_face_nchunks, p.d_tri_off, p.d_face_mesh, p.f64, p.nf, contrib,

@@ -174,12 +174,11 @@ __global__ __launch_bounds__(256) void batch_fwd_finish_kernel(const double2* pa
 __global__ __launch_bounds__(kBlock) void batch_bwd_fp64_kernel(const BatchItemBwd* __restrict__ items,
                                                                int64_t n_items, uint32_t* counter,
                                                                const Face64* __restrict__ f64,
-                                                               const double* __restrict__ gram, const void* q,
-                                                               int qdtype, const void* grad_out,
-                                                               const MeshInfo* __restrict__ info, double* partial) {
+                                                               const double* __restrict__ gram,
+                                                               const QRec64* __restrict__ rec, double* partial) {
   __shared__ Face64 tile[kTileFB];
   __shared__ double gtile[kTileFB][8];
-  __shared__ double wacc[kBlock / 64][kTileFB * 3];
+  __shared__ double acc[kTileFB * 3][kBlock];
   __shared__ int slot;
   const int tid = threadIdx.x;
   for (;;) {
@@ -190,17 +189,11 @@ __global__ __launch_bounds__(kBlock) void batch_bwd_fp64_kernel(const BatchItemB
     for (int i = tid; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
       reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f64 + it.f0)[i];
     for (int i = tid; i < nt * 8; i += kBlock) gtile[i / 8][i % 8] = gram[(it.f0 + i / 8) * 8 + i % 8];
-    for (int i = tid; i < (kBlock / 64) * kTileFB * 3; i += kBlock) (&wacc[0][0])[i] = 0.0;
+    for (int v = 0; v < nt * 3; ++v) acc[v][tid] = 0.0;
     __syncthreads();
-    const MeshInfo mi = info[it.mesh];
-    const double tc[3] = {mi.t[0], mi.t[1], mi.t[2]};
-    adj_tile_f64(tile, gtile, nt, tc, it.q0, it.q0 + it.nq, q, qdtype, grad_out, wacc);
+    adj_tile_f64(tile, gtile, nt, it.q0, it.q0 + it.nq, rec, acc);
     __syncthreads();
-    if (tid < nt * 3) {
-      double v = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) v += wacc[w][tid];
-      partial[it.part * 3 + tid] = v;
-    }
+    adj_block_sum(acc, nt, partial + it.part * 3);
     __syncthreads();
   }
 }
@@ -224,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void batch_bwd_fp32c_kernel(const BatchItem
     __syncthreads();
     adj_tile_fp32c(tile, nt, it.q0, it.q0 + it.nq, rec, acc);
     __syncthreads();
-    adj_block_sum32(acc, nt, partial + it.part * 3);
+    adj_block_sum(acc, nt, partial + it.part * 3);
     __syncthreads();
   }
 }
@@ -294,13 +287,11 @@ hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_of
 }
 
 hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
-                            const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
-                            const void* grad_out, const QRec32* rec, const MeshInfo* info, double* partial, int grid,
-                            hipStream_t s) {
+                            const Face64* f64, const double* gram, const Face32B* f32b, const QRec32* rec,
+                            const QRec64* rec64, double* partial, int grid, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (mode == PFT_FP64)
-    batch_bwd_fp64_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, gram, q, qdtype, grad_out, info,
-                                                  partial);
+    batch_bwd_fp64_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, gram, rec64, partial);
   else
     batch_bwd_fp32c_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f32b, rec, partial);
   return hipGetLastError();

@@ -22,12 +22,10 @@
 //
 // Layout: a block owns a tile of faces (records in LDS) and loops over a
 // range of Q (the Q-split on blockIdx.y), kQPTB Q per thread per pass.
-//  * binary64: per face and pass the thread's weights are summed across the
-//    wavefront into binary64 per-wave slots.
-//  * FP32C: each thread adds its weights to private binary32 slots in LDS
-//    (one per face and corner), and a fixed-order binary64 block sum at the
-//    end writes the per-split partials; the Q list is reordered and paired
-//    with its cotangent g exp(-iQ.t) beforehand (qorder.hip).
+// Each thread adds its weights to private slots in LDS (one per face and
+// corner; binary64 or binary32 by form), and a fixed-order binary64 block sum
+// at the end writes the per-split partials. The Q list is reordered and paired
+// with its cotangent g exp(-iQ.t) beforehand (qorder.hip).
 #include <hipcub/hipcub.hpp>
 
 #include "adj_terms.h"
@@ -38,26 +36,20 @@ namespace {
 __global__ __launch_bounds__(kBlock) void bwd3d_fp64_kernel(BwdArgs a, const double* gram) {
   __shared__ Face64 tile[kTileFB];
   __shared__ double gtile[kTileFB][8];
-  __shared__ double wacc[kBlock / 64][kTileFB * 3];
+  __shared__ double acc[kTileFB * 3][kBlock];
   const int tid = threadIdx.x;
   const int64_t f0 = (int64_t)blockIdx.x * kTileFB;
   const int nt = (int)min((int64_t)kTileFB, a.nf - f0);
   for (int i = tid; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
     reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(a.f64 + f0)[i];
   for (int i = tid; i < nt * 8; i += kBlock) gtile[i / 8][i % 8] = gram[(f0 + i / 8) * 8 + i % 8];
-  for (int i = tid; i < (kBlock / 64) * kTileFB * 3; i += kBlock) (&wacc[0][0])[i] = 0.0;
+  for (int v = 0; v < nt * 3; ++v) acc[v][tid] = 0.0;
   __syncthreads();
-  const MeshInfo mi = a.info[0];
-  const double tc[3] = {mi.t[0], mi.t[1], mi.t[2]};
   const int64_t qb = (int64_t)blockIdx.y * a.q_per_split;
   const int64_t qe = min(a.nq, qb + a.q_per_split);
-  adj_tile_f64(tile, gtile, nt, tc, qb, qe, a.q, a.qdtype, a.grad_out, wacc);
+  adj_tile_f64(tile, gtile, nt, qb, qe, a.rec64, acc);
   __syncthreads();
-  if (tid < nt * 3) {
-    double v = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) v += wacc[w][tid];
-    a.partial[((int64_t)blockIdx.y * a.nf + f0) * 3 + tid] = v;
-  }
+  adj_block_sum(acc, nt, a.partial + ((int64_t)blockIdx.y * a.nf + f0) * 3);
 }
 
 __global__ __launch_bounds__(kBlock) void bwd3d_fp32c_kernel(BwdArgs a) {
@@ -74,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void bwd3d_fp32c_kernel(BwdArgs a) {
   const int64_t qe = min(a.nq, qb + a.q_per_split);
   adj_tile_fp32c(tile, nt, qb, qe, a.rec, acc);
   __syncthreads();
-  adj_block_sum32(acc, nt, a.partial + ((int64_t)blockIdx.y * a.nf + f0) * 3);
+  adj_block_sum(acc, nt, a.partial + ((int64_t)blockIdx.y * a.nf + f0) * 3);
 }
 
 __global__ __launch_bounds__(256) void gram64_kernel(const Face64* f64, int64_t nf, double* gram) {

@@ -15,7 +15,7 @@ namespace pft {
 // ---------------------------------------------------------------------------
 constexpr int kBlock = 256;        // threads per block for the Q-parallel kernels
 constexpr int kTileF = 64;         // faces staged in LDS per tile (forward)
-constexpr int kTileFB = 16;        // faces per block in the adjoint
+constexpr int kTileFB = 8;         // faces per block in the binary64 adjoint
 #ifndef PFT_QPT
 #define PFT_QPT 3
 #endif
@@ -114,6 +114,13 @@ struct alignas(16) QRec32 {
   float hr, hi;
 };
 static_assert(sizeof(QRec32) == 32, "QRec32 layout");
+// The same for the binary64 adjoint (cotangent in binary64).
+struct alignas(16) QRec64 {
+  double q[3];
+  double pad;
+  double hr, hi;
+};
+static_assert(sizeof(QRec64) == 48, "QRec64 layout");
 
 
 // 2D edge record (FP64), relative to the polygon's vertex mean.
@@ -177,7 +184,8 @@ struct BwdArgs {
   int qdtype;
   int64_t nq;
   const void* grad_out;
-  const QRec32* rec;  // FP32C: reordered Q with their centred cotangents (launch_qrec32)
+  const QRec32* rec;    // FP32C: reordered Q with their centred cotangents (launch_qrec32_gather)
+  const QRec64* rec64;  // FP64: the same in binary64 (launch_qrec64_gather)
   int qsplits;
   int64_t q_per_split;
   double* partial;    // [qsplits][nf][3]
@@ -206,6 +214,10 @@ hipError_t launch_qorder(const void* q, int qdtype, int64_t nq, const int64_t* d
 // rec[i] = Q[perm[i]] with its centred cotangent g exp(-iQ.t), t the centre of the owning mesh.
 hipError_t launch_qrec32_gather(const void* q, int qdtype, const void* grad_out, int64_t nq, const uint32_t* perm,
                                 const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, QRec32* rec,
+                                hipStream_t s);
+// The same with a binary64 cotangent (grad_out complex128).
+hipError_t launch_qrec64_gather(const void* q, int qdtype, const void* grad_out, int64_t nq, const uint32_t* perm,
+                                const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, QRec64* rec,
                                 hipStream_t s);
 // Sum the per-split adjoint weights, form per-corner vectors N_m R_{m,k} and
 // gather them per vertex through the sorted incidence list.
@@ -254,9 +266,8 @@ hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_of
                                    const void* q, int qdtype, const uint32_t* perm, int64_t nq_total, double tau0,
                                    int out_c128, void* out, void* intensity, hipStream_t s);
 hipError_t launch_batch_bwd(int mode, const BatchItemBwd* items, int64_t n_items, uint32_t* counter,
-                            const Face64* f64, const double* gram, const Face32B* f32b, const void* q, int qdtype,
-                            const void* grad_out, const QRec32* rec, const MeshInfo* info, double* partial, int grid,
-                            hipStream_t s);
+                            const Face64* f64, const double* gram, const Face32B* f32b, const QRec32* rec,
+                            const QRec64* rec64, double* partial, int grid, hipStream_t s);
 hipError_t launch_batch_bwd_reduce(const double* partial, const int64_t* d_face_base, const int32_t* d_face_nchunks,
                                    const int64_t* d_tri_off, const int32_t* d_face_mesh, const Face64* f64,
                                    int64_t nf_total, double* contrib, hipStream_t s);

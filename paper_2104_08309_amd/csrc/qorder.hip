@@ -142,6 +142,24 @@ __global__ __launch_bounds__(256) void qrec32_kernel(const void* q, int qdtype, 
   rec[i] = r;
 }
 
+__global__ __launch_bounds__(256) void qrec64_kernel(const void* q, int qdtype, const double2* grad_out, int64_t nq,
+                                                     const uint32_t* perm, const MeshInfo* info,
+                                                     const int64_t* q_off, int64_t n_meshes, QRec64* rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const int64_t j = perm[i];
+  double Q[3];
+  load_q3(q, qdtype, j, Q);
+  const double2 g = grad_out[j];
+  QRec64 r;
+  centred_cotangent(g.x, g.y, Q, info[mesh_of(q_off, n_meshes, j)].t, r.hr, r.hi);
+  r.q[0] = Q[0];
+  r.q[1] = Q[1];
+  r.q[2] = Q[2];
+  r.pad = 0.0;
+  rec[i] = r;
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -189,6 +207,15 @@ hipError_t launch_qrec32_gather(const void* q, int qdtype, const void* grad_out,
                                 hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   qrec32_kernel<<<grid_for(nq), 256, 0, s>>>(q, qdtype, static_cast<const float2*>(grad_out), nq, perm, info,
+                                             d_q_off, n_meshes, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_qrec64_gather(const void* q, int qdtype, const void* grad_out, int64_t nq, const uint32_t* perm,
+                                const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, QRec64* rec,
+                                hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  qrec64_kernel<<<grid_for(nq), 256, 0, s>>>(q, qdtype, static_cast<const double2*>(grad_out), nq, perm, info,
                                              d_q_off, n_meshes, rec);
   return hipGetLastError();
 }
