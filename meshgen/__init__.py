@@ -215,6 +215,55 @@ def _rotation(rng: np.random.Generator) -> np.ndarray:
     return q
 
 
+# ----------------------------------------------------------------------------
+# 3D meshes with planar polygon faces (lists of CCW vertex indices)
+# ----------------------------------------------------------------------------
+def box_quads(a: float = 1.0, b: float = 1.0, c: float = 1.0, origin=(0.0, 0.0, 0.0)):
+    """Axis-aligned box [0,a]x[0,b]x[0,c] + origin as 6 outward quads (face 0: z = 0, face 1: z = c)."""
+    o = np.asarray(origin, dtype=np.float64)
+    v = np.array([[x, y, z] for z in (0.0, c) for y in (0.0, b) for x in (0.0, a)]) + o
+    faces = [[0, 2, 3, 1], [4, 5, 7, 6], [0, 1, 5, 4], [2, 6, 7, 3], [0, 4, 6, 2], [1, 3, 7, 5]]
+    return v, faces
+
+
+def prism_polygon(poly2d: np.ndarray, h: float, z0: float = 0.0):
+    """Right prism over a counter-clockwise simple polygon (in the xy plane) from z0 to z0 + h:
+    bottom and top nu-gons and nu side quads, all outward."""
+    p = np.asarray(poly2d, dtype=np.float64)
+    n = p.shape[0]
+    v = np.concatenate([np.c_[p, np.full(n, z0)], np.c_[p, np.full(n, z0 + h)]])
+    faces = [list(range(n - 1, -1, -1)), list(range(n, 2 * n))]
+    for i in range(n):
+        j = (i + 1) % n
+        faces.append([i, j, n + j, n + i])
+    return v, faces
+
+
+def ellipsoid_quads(semi_axes, n_lat: int, n_lon: int, rot=None, centre=(0.0, 0.0, 0.0)):
+    """Latitude-longitude ellipsoid with planar faces: quads between circles of latitude of the unit
+    sphere (isosceles trapezoids, so planar), triangle fans at the poles, then scaled by the semi-axes
+    (an affine map keeps faces planar), rotated and moved. Returns (verts, faces) of 4-gons and 3-gons,
+    2 * n_lon triangles and (n_lat - 3) * n_lon quads."""
+    th = np.linspace(0.0, math.pi, n_lat + 1)[1:-1]
+    ph = 2.0 * math.pi * np.arange(n_lon) / n_lon
+    ring = np.array([[math.sin(t) * math.cos(f), math.sin(t) * math.sin(f), math.cos(t)] for t in th for f in ph])
+    v = np.concatenate([[[0.0, 0.0, 1.0]], ring, [[0.0, 0.0, -1.0]]])
+    top, bot = 0, v.shape[0] - 1
+    idx = lambda i, j: 1 + i * n_lon + (j % n_lon)
+    faces = []
+    for j in range(n_lon):
+        faces.append([top, idx(0, j), idx(0, j + 1)])
+    for i in range(n_lat - 3):
+        for j in range(n_lon):
+            faces.append([idx(i, j), idx(i + 1, j), idx(i + 1, j + 1), idx(i, j + 1)])
+    for j in range(n_lon):
+        faces.append([bot, idx(n_lat - 3, j + 1), idx(n_lat - 3, j)])
+    v = v * np.asarray(semi_axes, dtype=np.float64)
+    if rot is not None:
+        v = v @ np.asarray(rot).T
+    return v + np.asarray(centre, dtype=np.float64), faces
+
+
 def ellipsoid_uv(semi_axes, n_lat: int, rot=None, centre=(0.0, 0.0, 0.0)):
     """UV-tessellated ellipsoid: n_lat latitude bands, 2*n_lat longitudes, pole fans.
 

@@ -16,6 +16,8 @@ Fourier transform of polygonal areas and volumes"):
   mesh, as the sum over faces of eq. single_area_integral with the in-plane
   integral from the 2D result (eq. sum_elements_3d, with the orientation of
   the in-plane edge normal corrected; see ``ft3d``).
+* ``ft3d_poly`` -- the same for a closed mesh of planar polygon faces with nu_m
+  edges each (eq. sum_elements_3d in its general form).
 * ``grad3d`` -- dL/dvertices for a real loss L(F) given dL/dReF + i dL/dImF,
   from the derivative of the same volume integral (transport theorem).
 * ``orientation_average`` -- sum_j w_j |F(q s_j)|^2 over a direction
@@ -30,6 +32,6 @@ force quadrature, invariants and finite differences).
 """
 from .pft_oracle import (  # noqa: F401
     area2d, volume3d, hsym, simplex_exp_series,
-    ft2d, ft2d_edge_terms, ft3d, ft3d_face_terms, face_integrals,
+    ft2d, ft2d_edge_terms, ft3d, ft3d_face_terms, face_integrals, ft3d_poly, ft3d_poly_face_terms,
     face_vertex_moments, dft3d_dverts, grad3d, grad3d_vertices, orientation_average,
 )
