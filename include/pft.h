@@ -112,6 +112,27 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
                           void* stream);
 
 /*
+ * pft_forward_3d_poly -- F(Q) of the volume enclosed by planar polygon faces
+ * (3D section: eq. sum_elements_3d with nu_m edges per face, evaluated natively:
+ * nu edge terms per face).
+ *
+ *  verts        [nv][3] of vdtype (DEVICE).
+ *  face_offsets HOST int64 [nf + 1], non-decreasing from 0; face i is
+ *               face_verts[face_offsets[i] .. face_offsets[i+1]), 3 to 256
+ *               vertices, counter-clockwise seen from outside. Faces must be
+ *               planar (the normal is taken from the polygon's area vector) and
+ *               simple; the mesh closed as in pft_forward_3d.
+ *  face_verts   DEVICE int32, 0-based vertex indices. A face with an
+ *               out-of-range index or zero area contributes 0.
+ *  q, mode, out, intensity as in pft_forward_3d.
+ * Errors: as pft_forward_3d; EINVAL also for bad offsets, a face with fewer
+ * than 3 or more than 256 vertices, or more than 2^31 - 1 vertex references.
+ */
+pft_status pft_forward_3d_poly(const void* verts, pft_dtype vdtype, int64_t nv, const int64_t* face_offsets,
+                               const int32_t* face_verts, int64_t nf, const void* q, pft_dtype qdtype, int64_t nq,
+                               pft_mode mode, void* out, void* intensity, void* stream);
+
+/*
  * pft_orientation_average -- orientation-averaged intensity of a closed mesh,
  *     I(q_i) = sum_j w_j |F(q_i s_j)|^2,
  * the powder / solution-scattering quantity that motivates the method (the

@@ -7,7 +7,8 @@ areas and volumes"), in hand-written HIP kernels for gfx950 behind the C ABI
 declared in include/pft.h. This package is the thin Python binding.
 """
 from .api import (  # noqa: F401
-    forward_2d, forward_3d, backward_3d, batch_forward, batch_backward, orientation_average, validate_mesh,
+    forward_2d, forward_3d, forward_3d_poly, backward_3d, batch_forward, batch_backward, orientation_average,
+    validate_mesh,
     profile_enable, profile_reset, profile_read, release_workspace, version,
 )
 from .autograd import PftFunction, ft3d, intensity_loss  # noqa: F401

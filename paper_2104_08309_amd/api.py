@@ -17,7 +17,8 @@ from . import _lib
 from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
 
 __all__ = [
-    "forward_2d", "forward_3d", "backward_3d", "batch_forward", "batch_backward", "orientation_average",
+    "forward_2d", "forward_3d", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
+    "orientation_average",
     "validate_mesh",
     "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
 ]
@@ -119,6 +120,34 @@ def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: s
         check(_lib.load().pft_forward_3d(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris),
                                          tris.shape[0], _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out),
                                          _ptr(inten), _stream(verts.device)))
+    return (out, inten) if intensity else out
+
+
+def forward_3d_poly(verts: torch.Tensor, faces: Sequence[Sequence[int]], q: torch.Tensor, mode: str = "fp32c",
+                    intensity: bool = False):
+    """F(Q) of a closed mesh of planar polygon faces (each a CCW list of vertex indices, 3 to 256).
+
+    Returns F (complex128 for 'fp64', complex64 for 'fp32c'), or (F, |F|^2) when ``intensity``.
+    """
+    verts = _on_gpu(verts, "verts")
+    if verts.dim() != 2 or verts.shape[1] != 3:
+        raise ValueError(f"verts must have shape [nv, 3], got {tuple(verts.shape)}")
+    off = np.zeros(len(faces) + 1, dtype=np.int64)
+    for i, f in enumerate(faces):
+        off[i + 1] = off[i] + len(f)
+    flat = np.fromiter((int(x) for f in faces for x in f), dtype=np.int32, count=int(off[-1]))
+    fv = torch.from_numpy(flat).to(verts.device)
+    q = _qlist(q, verts.device)
+    m = mode_id(mode)
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    rdt = torch.float64 if m == PFT_FP64 else torch.float32
+    out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
+    inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_forward_3d_poly(
+            _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0],
+            off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _ptr(fv), len(faces), _ptr(q),
+            _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(inten), _stream(verts.device)))
     return (out, inten) if intensity else out
 
 

@@ -168,6 +168,15 @@ const char* main_name(bool fwd, int mode) {
   return mode == PFT_FP64 ? "bwd3d_fp64" : "bwd3d_fp32c";
 }
 
+template <typename T>
+pft_status upload(Arena& ar, const std::vector<T>& v, T** d, hipStream_t s) {
+  *d = ar.get<T>(std::max<size_t>(v.size(), 1));
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  if (v.empty()) return PFT_OK;
+  hipError_t e = hipMemcpyAsync(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "upload");
+}
+
 // Visiting order of Q (qorder.hip): nearby Q share wavefronts. Below kQOrderMin Q
 // the caller's order is kept (the sort would cost more than it saves).
 #ifndef PFT_QORDER_MIN
@@ -480,6 +489,96 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
   return forward3d_core(ar, verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, out, intensity, s);
 }
 
+pft_status pft_forward_3d_poly(const void* verts, pft_dtype vdtype, int64_t nv, const int64_t* face_offsets,
+                               const int32_t* face_verts, int64_t nf, const void* q, pft_dtype qdtype, int64_t nq,
+                               pft_mode mode, void* out, void* intensity, void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, nullptr, 0, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  if (nf < 0) return fail(PFT_EINVAL, "negative count");
+  if (nf > INT32_MAX) return fail(PFT_EINVAL, "too many faces");
+  if ((st = check_offsets(face_offsets, nf, "face_offsets")) != PFT_OK) return st;
+  for (int64_t i = 0; i < nf; ++i) {
+    const int64_t n = face_offsets[i + 1] - face_offsets[i];
+    if (n < 3 || n > kTileV) return fail(PFT_EINVAL, "each face needs 3 .. 256 vertices");
+  }
+  const int64_t nref = face_offsets[nf];
+  if (nref > INT32_MAX) return fail(PFT_EINVAL, "too many face vertex references");
+  if (nref > 0 && face_verts == nullptr) return fail(PFT_EINVAL, "face_verts is NULL");
+  if (face_verts && !aligned(face_verts, 4)) return fail(PFT_EINVAL, "face_verts misaligned");
+  const bool c128 = mode == PFT_FP64;
+  if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
+  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
+  if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
+  if (nq == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  // tiles of consecutive faces: at most kTileFP faces and kTileV vertex records each
+  std::vector<PolyTile> tiles;
+  for (int64_t f = 0; f < nf;) {
+    PolyTile t;
+    t.f0 = (int32_t)f;
+    t.v0 = (int32_t)face_offsets[f];
+    while (f < nf && f - t.f0 < kTileFP && face_offsets[f + 1] - t.v0 <= kTileV) ++f;
+    t.f1 = (int32_t)f;
+    t.v1 = (int32_t)face_offsets[f];
+    tiles.push_back(t);
+  }
+  const int64_t ntiles = (int64_t)tiles.size();
+  Arena ar(s);
+  MeshInfo* info = ar.get<MeshInfo>(1);
+  int64_t* d_off = ar.get<int64_t>(nf + 1);
+  FaceP64* f64 = ar.get<FaceP64>(std::max<int64_t>(nf, 1));
+  VtxP64* v64 = ar.get<VtxP64>(std::max<int64_t>(nref, 1));
+  FaceP32* f32 = c128 ? nullptr : ar.get<FaceP32>(std::max<int64_t>(nf, 1));
+  VtxP32* v32 = c128 ? nullptr : ar.get<VtxP32>(std::max<int64_t>(nref, 1));
+  const int64_t qblocks = cdiv(nq, (int64_t)kBlock * (c128 ? 1 : kQPT));
+  const int64_t sp = std::max<int64_t>(1, std::min<int64_t>(cdiv(kTargetBlocks, qblocks), ntiles));
+  const int64_t per = std::max<int64_t>(1, cdiv(ntiles, sp));
+  const int splits = (int)std::max<int64_t>(1, cdiv(ntiles, per));
+  double2* partial = ar.get<double2>((size_t)splits * nq);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  PolyTile* d_tiles = nullptr;
+  if ((st = upload(ar, tiles, &d_tiles, s)) != PFT_OK) return st;
+  hipError_t e = hipMemcpyAsync(d_off, face_offsets, sizeof(int64_t) * (nf + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
+  if (e == hipSuccess)
+    e = launch_poly_records(verts, vdtype, nv, d_off, face_verts, nf, info, c128 ? kTauF64 : kTauF32, f64, v64, s);
+  if (e == hipSuccess && !c128) e = launch_poly_records32(f64, v64, nf, kTauRel32, f32, v32, s);
+  if (e != hipSuccess) return hip_fail(e, "polygon prologue");
+  uint32_t* perm = nullptr;
+  if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
+  FwdArgs a;
+  a.f64 = nullptr;
+  a.f32 = nullptr;
+  a.info = info;
+  a.nf = nf;
+  a.q = q;
+  a.qdtype = qdtype;
+  a.nq = nq;
+  a.perm = perm;
+  a.splits = splits;
+  a.faces_per_split = 0;
+  a.partial = partial;
+  a.out = out;
+  a.intensity = intensity;
+  a.tau0 = c128 ? kTau0F64 : kTau0F32;
+  PolyArgs pa;
+  pa.f64 = f64;
+  pa.v64 = v64;
+  pa.f32 = f32;
+  pa.v32 = v32;
+  pa.tiles = d_tiles;
+  pa.ntiles = ntiles;
+  pa.tiles_per_split = per;
+  const char* nm = c128 ? "fwdpoly_fp64" : "fwdpoly_fp32c";
+  prof_begin(nm, s);
+  e = c128 ? launch_fwdpoly_fp64(a, pa, s) : launch_fwdpoly_fp32c(a, pa, s);
+  prof_end(nm, s);
+  if (e != hipSuccess) return hip_fail(e, "polygon transform");
+  e = launch_fwd3d_finish(a, c128 ? 1 : 0, s);
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "3D finish");
+}
+
 pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                    const double* qabs, int64_t nqa, const double* dirs, const double* weights,
                                    int64_t ndir, pft_mode mode, double* out, void* stream) {
@@ -632,14 +731,6 @@ pft_status batch_prologue(Arena& ar, const pft_mesh_batch* b, double tau, BatchP
   return PFT_OK;
 }
 
-template <typename T>
-pft_status upload(Arena& ar, const std::vector<T>& v, T** d, hipStream_t s) {
-  *d = ar.get<T>(std::max<size_t>(v.size(), 1));
-  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
-  if (v.empty()) return PFT_OK;
-  hipError_t e = hipMemcpyAsync(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
-  return e == hipSuccess ? PFT_OK : hip_fail(e, "upload");
-}
 
 }  // namespace
 

@@ -153,6 +153,74 @@ hipError_t launch_validate(const int32_t* tris, int64_t nf, int64_t nv, unsigned
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Planar polygon faces (fwdpoly.hip): a face header plus one record per vertex
+// (the edge from vertex k to k+1, wrapping, belongs to vertex k). Faces are
+// processed in tiles of consecutive faces holding at most kTileV vertices.
+// ---------------------------------------------------------------------------
+constexpr int kTileV = 256;       // vertex records per polygon tile (and the largest face)
+constexpr int kTileFP = 64;       // faces per polygon tile
+
+struct alignas(16) FaceP64 {      // relative to the mesh centre t
+  double g[3];                    // vertex mean of the polygon
+  double N[3];                    // area vector sum_k u_k x u_{k+1} = 2 A n
+  double thr;                     // series when |Q x N|^2 < thr (tau^2 |N|^2 / L^2; -1 for an empty face)
+  double invN;                    // 1 / |N| (0 for an empty face)
+  int32_t v0;                     // first vertex record
+  int32_t nv;                     // vertex count
+  int32_t pad[2];
+};
+static_assert(sizeof(FaceP64) == 80, "FaceP64 layout");
+
+struct alignas(16) VtxP64 {
+  double u[3];                    // r_k - g
+  double pad;
+};
+static_assert(sizeof(VtxP64) == 32, "VtxP64 layout");
+
+struct alignas(16) FaceP32 {      // FP32C: in-plane basis as in Face32
+  double gt[3];                   // g / (2 pi): face origin phase in turns is Q . gt
+  float N[3];                     // 2 A n
+  float E1[3];                    // |N| e1 (e1 along the first non-degenerate edge)
+  float E2[3];                    // |N| e2, e2 = n x e1
+  float thr;                      // tau^2 |N|^2 / L^2 (-1 for an empty face)
+  float kap;                      // tau_rel^2 |N|^2
+  float invN;                     // 1 / |N|
+  int32_t v0;                     // first vertex record
+  int32_t nv;                     // vertex count
+  int32_t pad[2];
+};
+static_assert(sizeof(FaceP32) == 96, "FaceP32 layout");
+
+struct VtxP32 {
+  float ga, de;                   // half-vertex phase psi_k = Q.u_k / 2 in turns = s1 ga + s2 de
+  float al, be;                   // edge k -> k+1: P . d_k / (2 pi) = s2 al + s1 be
+  float x, y;                     // in-plane coordinates e1 . u_k, e2 . u_k (fan areas of the series)
+};
+static_assert(sizeof(VtxP32) == 24, "VtxP32 layout");
+
+struct PolyTile {                 // faces [f0, f1) with vertex records [v0, v1)
+  int32_t f0, f1, v0, v1;
+};
+
+struct PolyArgs {
+  const FaceP64* f64;
+  const VtxP64* v64;
+  const FaceP32* f32;
+  const VtxP32* v32;
+  const PolyTile* tiles;
+  int64_t ntiles;
+  int64_t tiles_per_split;
+};
+
+// prologue.hip: records of polygon faces (face_off: device CSR offsets into face_verts)
+hipError_t launch_poly_records(const void* verts, int vdtype, int64_t nv, const int64_t* face_off,
+                               const int32_t* face_verts, int64_t nf, const MeshInfo* info, double tau, FaceP64* f64,
+                               VtxP64* v64, hipStream_t s);
+// (the binary64 records must have been built with the FP32C threshold tau)
+hipError_t launch_poly_records32(const FaceP64* f64, const VtxP64* v64, int64_t nf, double tau_rel, FaceP32* f32,
+                                 VtxP32* v32, hipStream_t s);
+
 // fwd3d.hip
 struct FwdArgs {
   const Face64* f64;
@@ -173,6 +241,9 @@ struct FwdArgs {
 hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd3d_finish(const FwdArgs& a, int out_c128, hipStream_t s);
+// fwdpoly.hip: the forward over polygon faces (FwdArgs's face fields unused; splits over tiles)
+hipError_t launch_fwdpoly_fp64(const FwdArgs& a, const PolyArgs& p, hipStream_t s);
+hipError_t launch_fwdpoly_fp32c(const FwdArgs& a, const PolyArgs& p, hipStream_t s);
 
 // bwd3d.hip
 struct BwdArgs {

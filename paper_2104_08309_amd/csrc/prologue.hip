@@ -9,6 +9,9 @@
 namespace pft {
 namespace {
 
+constexpr double kInv2Pi = 0.15915494309189533577;
+constexpr double kInv4Pi = 0.07957747154594766788;
+
 __device__ inline void load_vertex(const void* verts, int vdtype, int dim, int64_t i, double* out) {
   if (vdtype == PFT_F64) {
     const double* v = static_cast<const double*>(verts) + i * dim;
@@ -127,6 +130,138 @@ __global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdty
   out[m] = f;
 }
 
+// One thread per polygon face: vertex mean g, area vector N = sum_k u_k x u_{k+1}
+// (u_k = r_k - g; exact for a planar face), longest edge, vertex offsets. A face
+// with an out-of-range index or zero area becomes empty (all-zero records).
+__global__ __launch_bounds__(256) void poly64_kernel(const void* verts, int vdtype, int64_t nv,
+                                                     const int64_t* face_off, const int32_t* face_verts, int64_t nf,
+                                                     const MeshInfo* info, double tau, FaceP64* fout,
+                                                     VtxP64* vout) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  const int64_t b = face_off[m], e = face_off[m + 1];
+  const int n = (int)(e - b);
+  bool ok = n >= 3;
+  for (int64_t k = b; k < e; ++k) ok = ok && face_verts[k] >= 0 && face_verts[k] < nv;
+  const MeshInfo mi = info[0];
+  FaceP64 f;
+  f.v0 = (int32_t)b;
+  f.nv = n;
+  f.pad[0] = f.pad[1] = 0;
+  double g[3] = {0.0, 0.0, 0.0};
+  if (ok) {
+    for (int64_t k = b; k < e; ++k) {
+      double r[3];
+      load_vertex(verts, vdtype, 3, face_verts[k], r);
+      for (int c = 0; c < 3; ++c) g[c] += r[c] - mi.t[c];
+    }
+    for (int c = 0; c < 3; ++c) g[c] /= (double)n;
+  }
+  double N[3] = {0.0, 0.0, 0.0}, L2 = 0.0;
+  double u0[3] = {0.0, 0.0, 0.0}, uprev[3] = {0.0, 0.0, 0.0};
+  for (int64_t k = b; k < e; ++k) {
+    double u[3] = {0.0, 0.0, 0.0};
+    if (ok) {
+      load_vertex(verts, vdtype, 3, face_verts[k], u);
+      for (int c = 0; c < 3; ++c) u[c] -= mi.t[c] + g[c];
+    }
+    VtxP64 r;
+    r.u[0] = u[0];
+    r.u[1] = u[1];
+    r.u[2] = u[2];
+    r.pad = 0.0;
+    vout[k] = r;
+    if (k == b) {
+      for (int c = 0; c < 3; ++c) u0[c] = u[c];
+    } else {
+      N[0] += uprev[1] * u[2] - uprev[2] * u[1];
+      N[1] += uprev[2] * u[0] - uprev[0] * u[2];
+      N[2] += uprev[0] * u[1] - uprev[1] * u[0];
+      double d2 = 0.0;
+      for (int c = 0; c < 3; ++c) d2 += (u[c] - uprev[c]) * (u[c] - uprev[c]);
+      L2 = fmax(L2, d2);
+    }
+    for (int c = 0; c < 3; ++c) uprev[c] = u[c];
+  }
+  if (n >= 1) {  // closing edge
+    N[0] += uprev[1] * u0[2] - uprev[2] * u0[1];
+    N[1] += uprev[2] * u0[0] - uprev[0] * u0[2];
+    N[2] += uprev[0] * u0[1] - uprev[1] * u0[0];
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) d2 += (u0[c] - uprev[c]) * (u0[c] - uprev[c]);
+    L2 = fmax(L2, d2);
+  }
+  const double N2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+  ok = ok && N2 > 0.0 && L2 > 0.0;
+  for (int c = 0; c < 3; ++c) {
+    f.g[c] = ok ? g[c] : 0.0;
+    f.N[c] = ok ? N[c] : 0.0;
+  }
+  f.thr = ok ? tau * tau * N2 / L2 : -1.0;
+  f.invN = ok ? 1.0 / sqrt(N2) : 0.0;
+  fout[m] = f;
+}
+
+// FP32C polygon records: orthonormal in-plane basis (e1 along the first edge of
+// non-zero length, e2 = n x e1) and the per-vertex coefficients.
+__global__ __launch_bounds__(256) void poly32_kernel(const FaceP64* fin, const VtxP64* vin, int64_t nf,
+                                                     double tau_rel, FaceP32* fout, VtxP32* vout) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nf) return;
+  const FaceP64 f = fin[m];
+  const bool ok = f.thr >= 0.0;
+  const double N2 = f.N[0] * f.N[0] + f.N[1] * f.N[1] + f.N[2] * f.N[2];
+  const double nN = sqrt(N2);
+  double e1[3] = {0.0, 0.0, 0.0}, e2[3] = {0.0, 0.0, 0.0};
+  if (ok) {
+    for (int k = 0; k < f.nv; ++k) {
+      const VtxP64 a = vin[f.v0 + k], b = vin[f.v0 + (k + 1) % f.nv];
+      double d[3] = {b.u[0] - a.u[0], b.u[1] - a.u[1], b.u[2] - a.u[2]};
+      const double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (dl > 0.0) {
+        for (int c = 0; c < 3; ++c) e1[c] = d[c] / dl;
+        break;
+      }
+    }
+    // e2 = n x e1
+    e2[0] = (f.N[1] * e1[2] - f.N[2] * e1[1]) / nN;
+    e2[1] = (f.N[2] * e1[0] - f.N[0] * e1[2]) / nN;
+    e2[2] = (f.N[0] * e1[1] - f.N[1] * e1[0]) / nN;
+  }
+  FaceP32 r;
+  for (int c = 0; c < 3; ++c) {
+    r.gt[c] = f.g[c] * kInv2Pi;
+    r.N[c] = (float)f.N[c];
+    r.E1[c] = (float)(nN * e1[c]);
+    r.E2[c] = (float)(nN * e2[c]);
+  }
+  r.thr = ok ? (float)f.thr : -1.0f;  // the binary64 records were built with this form's threshold
+  r.kap = ok ? (float)(tau_rel * tau_rel * N2) : -1.0f;
+  r.invN = (float)f.invN;
+  r.v0 = f.v0;
+  r.nv = f.nv;
+  r.pad[0] = r.pad[1] = 0;
+  fout[m] = r;
+  for (int k = 0; k < f.nv; ++k) {
+    const VtxP64 a = vin[f.v0 + k], b = vin[f.v0 + (k + 1) % f.nv];
+    VtxP32 v;
+    if (ok) {
+      const double d[3] = {b.u[0] - a.u[0], b.u[1] - a.u[1], b.u[2] - a.u[2]};
+      const double x = e1[0] * a.u[0] + e1[1] * a.u[1] + e1[2] * a.u[2];
+      const double y = e2[0] * a.u[0] + e2[1] * a.u[1] + e2[2] * a.u[2];
+      v.ga = (float)(x * kInv4Pi / nN);
+      v.de = (float)(y * kInv4Pi / nN);
+      v.al = (float)((e1[0] * d[0] + e1[1] * d[1] + e1[2] * d[2]) * kInv2Pi);
+      v.be = (float)(-(e2[0] * d[0] + e2[1] * d[1] + e2[2] * d[2]) * kInv2Pi);
+      v.x = (float)x;
+      v.y = (float)y;
+    } else {
+      v.ga = v.de = v.al = v.be = v.x = v.y = 0.0f;
+    }
+    vout[f.v0 + k] = v;
+  }
+}
+
 __global__ __launch_bounds__(256) void face_mesh_kernel(const int64_t* tri_off, int64_t n_meshes, int64_t nf_total,
                                                         int32_t* face_mesh) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -169,8 +304,6 @@ __global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, in
   out[m] = f;
 }
 
-constexpr double kInv2Pi = 0.15915494309189533577;
-constexpr double kInv4Pi = 0.07957747154594766788;
 
 __global__ __launch_bounds__(256) void iota_u32_kernel(uint32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -318,6 +451,21 @@ hipError_t launch_face64(const void* verts, int vdtype, int64_t nv, const int32_
                          const MeshInfo* info, double tau, Face64* out, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   face64_kernel<<<grid_for(nf), 256, 0, s>>>(verts, vdtype, nv, tris, nf, info, tau, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_poly_records(const void* verts, int vdtype, int64_t nv, const int64_t* face_off,
+                               const int32_t* face_verts, int64_t nf, const MeshInfo* info, double tau, FaceP64* f64,
+                               VtxP64* v64, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  poly64_kernel<<<grid_for(nf), 256, 0, s>>>(verts, vdtype, nv, face_off, face_verts, nf, info, tau, f64, v64);
+  return hipGetLastError();
+}
+
+hipError_t launch_poly_records32(const FaceP64* f64, const VtxP64* v64, int64_t nf, double tau_rel, FaceP32* f32,
+                                 VtxP32* v32, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  poly32_kernel<<<grid_for(nf), 256, 0, s>>>(f64, v64, nf, tau_rel, f32, v32);
   return hipGetLastError();
 }
 

@@ -94,6 +94,28 @@ def test_orientation_average_validation(lib):
     assert f(V(good), 1, 3, V(good), 1, None, 0, V(good), V(good), 4, 1, None, None) == _lib.PFT_OK
 
 
+def test_forward_3d_poly_validation(lib):
+    good = 0x10000
+    f = lib.pft_forward_3d_poly
+    P = ctypes.POINTER(ctypes.c_int64)
+    ok_off = (ctypes.c_int64 * 3)(0, 4, 8)
+    bad_off = (ctypes.c_int64 * 3)(0, 4, 3)    # decreasing
+    short = (ctypes.c_int64 * 3)(0, 2, 6)      # a 2-vertex face
+    big = (ctypes.c_int64 * 2)(0, 300)         # a 300-vertex face
+    cast = lambda a: ctypes.cast(a, P)
+    # verts, vdtype, nv, face_offsets, face_verts, nf, q, qdtype, nq, mode, out, intensity, stream
+    assert f(V(good), 1, 8, cast(bad_off), V(good), 2, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 8, cast(short), V(good), 2, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 8, cast(big), V(good), 1, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 8, None, V(good), 2, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 8, cast(ok_off), None, 2, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 8, cast(ok_off), V(good + 2), 2, V(good), 1, 4, 0, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 8, cast(ok_off), V(good), 2, V(good), 1, 4, 0, None, None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 8, cast(ok_off), V(good), 2, V(good), 1, 4, 7, V(good), None, None) == _lib.PFT_EUNSUPPORTED
+    # nq == 0 is a valid no-op
+    assert f(V(good), 1, 8, cast(ok_off), V(good), 2, None, 1, 0, 0, None, None, None) == _lib.PFT_OK
+
+
 def test_forward_2d_validation(lib):
     good = 0x10000
     f = lib.pft_forward_2d
