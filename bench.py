@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192, help="Q points of the oracle's timed sample")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU baseline")
     ap.add_argument("--no-orient", action="store_true", help="skip the orientation-average measurement")
+    ap.add_argument("--no-poly", action="store_true", help="skip the polygon-face measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -227,6 +228,30 @@ def main():
             orient["rel_err_fp32c_vs_oracle_sample"] = float(np.max(np.abs(I32[pick] - Io) / np.abs(Io)))
             orient["oracle_sample"] = f"|Q| = {qabs[pick[0]]:.5f}, all {dirs.shape[0]} directions"
 
+    # planar polygon faces: a lat-long sphere of radius 50 with 2496 quads and 128 pole triangles
+    # (5120 triangles when fan-triangulated, as config 2's mesh), on config 2's Q grid, native
+    # polygon kernel against the triangle kernel on the fan triangulation
+    poly = None
+    if not args.no_poly:
+        print("[bench] polygon faces", file=sys.stderr, flush=True)
+        pv, pf = mg.ellipsoid_quads([50.0, 50.0, 50.0], 42, 64)
+        ptri = np.array([[x[0], x[l], x[l + 1]] for x in pf for l in range(1, len(x) - 1)], dtype=np.int32)
+        PV = torch.tensor(pv, dtype=torch.float32, device=dev)
+        PT = torch.tensor(ptri, device=dev)
+        p_steps = max(3, args.steps // 4)
+        tp, Fp = timed(lambda: pft.forward_3d_poly(PV, pf, Q, mode="fp32c"), p_steps, 1)
+        n_p, ms_p = pft.profile_read("fwdpoly_fp32c")
+        tt, Ft = timed(lambda: pft.forward_3d(PV, PT, Q, mode="fp32c"), p_steps, 1)
+        n_t, ms_t = pft.profile_read("fwd3d_fp32c")
+        n_edges = sum(len(x) for x in pf)
+        Fp, Ft = Fp.cpu().numpy().astype(np.complex128), Ft.cpu().numpy().astype(np.complex128)
+        poly = {"workload": f"lat-long sphere R=50: {len(pf)} planar faces ({n_edges} edges; {ptri.shape[0]} "
+                            f"triangles when fan-triangulated) x config 2's {nq} Q, FP32C forward",
+                "poly_kernel_ms": ms_p / max(n_p, 1), "tri_kernel_ms": ms_t / max(n_t, 1),
+                "poly_ms_per_call": tp * 1e3, "tri_ms_per_call": tt * 1e3,
+                "poly_edge_q_per_s": n_edges * nq / (ms_p / max(n_p, 1) * 1e-3),
+                "rel_diff_poly_vs_triangles": float(np.linalg.norm(Fp - Ft) / np.linalg.norm(Ft))}
+
     # roofline of the dominant kernel (the longer of the forward and adjoint kernels)
     def roof(kernel, ms, flop):
         achieved = flop * nf * nq / (ms * 1e-3) / 1e12
@@ -282,6 +307,7 @@ def main():
         "roofline_other_kernel": other,
         "cpu_baseline": cpu,
         "orientation_average": orient,
+        "polygon_faces": poly,
     }
     print(json.dumps(line), flush=True)
 

@@ -531,7 +531,7 @@ pft_status pft_forward_3d_poly(const void* verts, pft_dtype vdtype, int64_t nv, 
   VtxP64* v64 = ar.get<VtxP64>(std::max<int64_t>(nref, 1));
   FaceP32* f32 = c128 ? nullptr : ar.get<FaceP32>(std::max<int64_t>(nf, 1));
   VtxP32* v32 = c128 ? nullptr : ar.get<VtxP32>(std::max<int64_t>(nref, 1));
-  const int64_t qblocks = cdiv(nq, (int64_t)kBlock * (c128 ? 1 : kQPT));
+  const int64_t qblocks = cdiv(nq, (int64_t)kBlock * (c128 ? 1 : kQPTPoly));
   const int64_t sp = std::max<int64_t>(1, std::min<int64_t>(cdiv(kTargetBlocks, qblocks), ntiles));
   const int64_t per = std::max<int64_t>(1, cdiv(ntiles, sp));
   const int splits = (int)std::max<int64_t>(1, cdiv(ntiles, per));

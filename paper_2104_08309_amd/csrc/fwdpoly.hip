@@ -245,14 +245,14 @@ __device__ __forceinline__ void poly_tile_fp32c(const FaceP32* fh, const VtxP32*
 __global__ __launch_bounds__(kBlock) void fwdpoly_fp32c_kernel(FwdArgs a, PolyArgs p) {
   __shared__ FaceP32 fh[kTileFP];
   __shared__ VtxP32 vr[kTileV];
-  const int64_t qbase = (int64_t)blockIdx.x * (kBlock * kQPT) + threadIdx.x;
+  const int64_t qbase = (int64_t)blockIdx.x * (kBlock * kQPTPoly) + threadIdx.x;
   const double R = a.info[0].R;
-  double Qd[kQPT][3];
-  float qx[kQPT], qy[kQPT], qz[kQPT], Q2[kQPT];
-  bool small[kQPT], active[kQPT];
+  double Qd[kQPTPoly][3];
+  float qx[kQPTPoly], qy[kQPTPoly], qz[kQPTPoly], Q2[kQPTPoly];
+  bool small[kQPTPoly], active[kQPTPoly];
   bool any_small = false;
 #pragma unroll
-  for (int k = 0; k < kQPT; ++k) {
+  for (int k = 0; k < kQPTPoly; ++k) {
     const int64_t qi = qbase + (int64_t)k * kBlock;
     active[k] = qi < a.nq;
     Qd[k][0] = Qd[k][1] = Qd[k][2] = 0.0;
@@ -267,27 +267,27 @@ __global__ __launch_bounds__(kBlock) void fwdpoly_fp32c_kernel(FwdArgs a, PolyAr
   }
   const int64_t t_begin = (int64_t)blockIdx.y * p.tiles_per_split;
   const int64_t t_end = min(p.ntiles, t_begin + p.tiles_per_split);
-  float sr[kQPT], si[kQPT], cr[kQPT], ci[kQPT];
-  double xr[kQPT], xi[kQPT];
+  float sr[kQPTPoly], si[kQPTPoly], cr[kQPTPoly], ci[kQPTPoly];
+  double xr[kQPTPoly], xi[kQPTPoly];
 #pragma unroll
-  for (int k = 0; k < kQPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
+  for (int k = 0; k < kQPTPoly; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
   for (int64_t t = t_begin; t < t_end; ++t) {
     const PolyTile tl = p.tiles[t];
     __syncthreads();
     stage_tile(tl, p.f32, p.v32, fh, vr);
     __syncthreads();
-    float tr[kQPT], ti[kQPT];
+    float tr[kQPTPoly], ti[kQPTPoly];
 #pragma unroll
-    for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
-    poly_tile_fp32c<kQPT>(fh, vr, tl.f1 - tl.f0, tl.v0, qx, qy, qz, Q2, Qd, small, tr, ti);
+    for (int k = 0; k < kQPTPoly; ++k) tr[k] = ti[k] = 0.0f;
+    poly_tile_fp32c<kQPTPoly>(fh, vr, tl.f1 - tl.f0, tl.v0, qx, qy, qz, Q2, Qd, small, tr, ti);
 #pragma unroll
-    for (int k = 0; k < kQPT; ++k) {
+    for (int k = 0; k < kQPTPoly; ++k) {
       kahan_add(sr[k], cr[k], tr[k]);
       kahan_add(si[k], ci[k], ti[k]);
     }
     if (any_small) {
 #pragma unroll
-      for (int k = 0; k < kQPT; ++k)
+      for (int k = 0; k < kQPTPoly; ++k)
         if (small[k])
           for (int f = tl.f0; f < tl.f1; ++f) {
             const FaceP64 F = p.f64[f];
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void fwdpoly_fp32c_kernel(FwdArgs a, PolyAr
     }
   }
 #pragma unroll
-  for (int k = 0; k < kQPT; ++k) {
+  for (int k = 0; k < kQPTPoly; ++k) {
     if (active[k]) {
       const double2 v = small[k] ? make_double2(xr[k], xi[k])
                                  : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
@@ -314,7 +314,7 @@ hipError_t launch_fwdpoly_fp64(const FwdArgs& a, const PolyArgs& p, hipStream_t 
 }
 
 hipError_t launch_fwdpoly_fp32c(const FwdArgs& a, const PolyArgs& p, hipStream_t s) {
-  dim3 grid((unsigned)((a.nq + kBlock * kQPT - 1) / (kBlock * kQPT)), (unsigned)a.splits);
+  dim3 grid((unsigned)((a.nq + kBlock * kQPTPoly - 1) / (kBlock * kQPTPoly)), (unsigned)a.splits);
   fwdpoly_fp32c_kernel<<<grid, kBlock, 0, s>>>(a, p);
   return hipGetLastError();
 }

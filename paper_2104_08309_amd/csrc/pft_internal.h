@@ -160,6 +160,10 @@ hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 // ---------------------------------------------------------------------------
 constexpr int kTileV = 256;       // vertex records per polygon tile (and the largest face)
 constexpr int kTileFP = 64;       // faces per polygon tile
+#ifndef PFT_QPT_POLY
+#define PFT_QPT_POLY 3
+#endif
+constexpr int kQPTPoly = PFT_QPT_POLY;  // Q per thread in the FP32C polygon forward
 
 struct alignas(16) FaceP64 {      // relative to the mesh centre t
   double g[3];                    // vertex mean of the polygon
