@@ -26,6 +26,8 @@ __all__ = [
     "icosphere", "subdivide", "perturb_radial", "orient_outward",
     "ellipsoid_uv", "convex_hull_mesh", "union_of_spheres",
     "union_of_spheres_config", "batch_config", "read_netgen_surfacemesh",
+    "box_quads", "prism_polygon", "ellipsoid_quads", "sphere_quadrature",
+    "stack_regions", "layered_sphere", "nested_boxes",
     "config1", "config2", "config3", "config4", "config5",
 ]
 
@@ -224,6 +226,49 @@ def box_quads(a: float = 1.0, b: float = 1.0, c: float = 1.0, origin=(0.0, 0.0, 
     v = np.array([[x, y, z] for z in (0.0, c) for y in (0.0, b) for x in (0.0, a)]) + o
     faces = [[0, 2, 3, 1], [4, 5, 7, 6], [0, 1, 5, 4], [2, 6, 7, 3], [0, 4, 6, 2], [1, 3, 7, 5]]
     return v, faces
+
+
+def stack_regions(surfaces, regions):
+    """One vertex / triangle list for several closed regions.
+
+    ``surfaces`` is a list of (verts, tris) closed outward surfaces; ``regions`` lists, per
+    region, the surfaces that bound it as (surface index, +1 outward or -1 reversed). A surface
+    shared by two regions keeps one copy of its vertices. Returns (verts, tris, region_offsets)
+    with region j's triangles at region_offsets[j] .. region_offsets[j+1].
+    """
+    base, verts = [], []
+    n = 0
+    for v, _ in surfaces:
+        base.append(n)
+        verts.append(np.asarray(v, dtype=np.float64))
+        n += len(v)
+    tris, offsets = [], [0]
+    for reg in regions:
+        for si, sign in reg:
+            t = np.asarray(surfaces[si][1], dtype=np.int64) + base[si]
+            tris.append(t if sign > 0 else t[:, ::-1])
+        offsets.append(offsets[-1] + sum(len(surfaces[si][1]) for si, _ in reg))
+    tv = np.concatenate(verts) if verts else np.zeros((0, 3))
+    tt = np.concatenate(tris).astype(np.int32) if tris else np.zeros((0, 3), dtype=np.int32)
+    return tv, tt, np.array(offsets, dtype=np.int64)
+
+
+def layered_sphere(level: int, radii, centre=(0.0, 0.0, 0.0)):
+    """Concentric icospheres of increasing radii as regions: a core (inside radii[0]) and shells
+    (between radii[j-1] and radii[j]), each bounded by its outer sphere and the reversed inner one."""
+    surfaces = []
+    for r in radii:
+        v, t = icosphere(level, r)
+        surfaces.append((v + np.asarray(centre, dtype=np.float64), t))
+    regions = [[(0, +1)]] + [[(j, +1), (j - 1, -1)] for j in range(1, len(radii))]
+    return stack_regions(surfaces, regions)
+
+
+def nested_boxes(outer, inner):
+    """A box inside a box as two regions (core = inner box, shell = outer minus inner).
+    ``outer`` and ``inner`` are ((a, b, c), origin)."""
+    surfaces = [box(*outer[0], origin=outer[1]), box(*inner[0], origin=inner[1])]
+    return stack_regions(surfaces, [[(1, +1)], [(0, +1), (1, -1)]])
 
 
 def prism_polygon(poly2d: np.ndarray, h: float, z0: float = 0.0):

@@ -20,6 +20,10 @@ Fourier transform of polygonal areas and volumes"):
   edges each (eq. sum_elements_3d in its general form).
 * ``grad3d`` -- dL/dvertices for a real loss L(F) given dL/dReF + i dL/dImF,
   from the derivative of the same volume integral (transport theorem).
+* ``ft3d_dq`` -- grad_Q F(Q) = i times the volume integral of r exp(i Q.r),
+  by the divergence theorem with the barycentric face moments of ``grad3d``.
+* ``ft3d_regions``, ``grad3d_regions`` -- a density constant on each of
+  several closed regions: F = sum_j rho_j F_j, and dL/dv, dL/drho, dL/dQ.
 * ``orientation_average`` -- sum_j w_j |F(q s_j)|^2 over a direction
   quadrature (the orientation-averaged scattering intensity).
 
@@ -34,4 +38,5 @@ from .pft_oracle import (  # noqa: F401
     area2d, volume3d, hsym, simplex_exp_series,
     ft2d, ft2d_edge_terms, ft3d, ft3d_face_terms, face_integrals, ft3d_poly, ft3d_poly_face_terms,
     face_vertex_moments, dft3d_dverts, grad3d, grad3d_vertices, orientation_average,
+    ft3d_dq, ft3d_regions, grad3d_regions,
 )

@@ -8,6 +8,9 @@ None of these share code or formulas with ``oracle/``:
 * ``quad_tet`` / ``quad_tri_fan`` -- tensor Gauss-Legendre quadrature on the
   collapsed (Duffy) cube mapped onto each simplex.
 * ``sphere_ft``     -- the paper's unit-sphere formula scaled to radius R.
+* ``tetfan_dF_dQ`` / ``quad_tet_moment`` -- grad_Q F = i * integral of r exp(iQ.r):
+  per tetrahedron the barycentric moments as divided differences with a
+  doubled node (expm), or Gauss-Legendre quadrature of r exp(iQ.r).
 """
 from __future__ import annotations
 
@@ -54,6 +57,23 @@ def tetfan_dF_dv(verts, tris, q) -> np.ndarray:
     return out
 
 
+def tetfan_dF_dQ(verts, tris, q, origin=None) -> np.ndarray:
+    """grad_Q F = i sum over tetrahedra (o, a, b, c) of sum_j r_j 6|T| exp[iQ.o, iQ.a, iQ.b, iQ.c, iQ.r_j]
+    (the integral of lambda_j exp(iQ.r) over T is 6|T| times the divided difference with node j
+    doubled). [nq, 3] complex."""
+    v = np.asarray(verts, dtype=np.float64)
+    o = v.mean(axis=0) if origin is None else np.asarray(origin, dtype=np.float64)
+    out = np.zeros((len(q), 3), dtype=np.complex128)
+    for qi, Q in enumerate(np.asarray(q, dtype=np.float64)):
+        for t in tris:
+            pts = [o, v[t[0]], v[t[1]], v[t[2]]]
+            six_vol = float(np.dot(pts[1] - o, np.cross(pts[2] - o, pts[3] - o)))
+            nodes = [1j * Q @ p for p in pts]
+            for j, p in enumerate(pts):
+                out[qi] += 1j * six_vol * dd_exp(nodes + [nodes[j]]) * p
+    return out
+
+
 def _gl01(n):
     x, w = np.polynomial.legendre.leggauss(n)
     return 0.5 * (x + 1.0), 0.5 * w
@@ -72,6 +92,21 @@ def quad_tet(a, b, c, d, Q, n=24) -> complex:
     six_vol = float(np.dot(b - a, np.cross(c - a, d - a)))
     f = np.exp(1j * (P @ Q))
     return complex(six_vol * np.sum(WU * WV * WW * jac * f))
+
+
+def quad_tet_moment(a, b, c, d, Q, n=24) -> np.ndarray:
+    """Integral of r exp(iQ.r) over the tetrahedron (a, b, c, d) by collapsed Gauss-Legendre (signed). [3]."""
+    x, w = _gl01(n)
+    U, V, W = np.meshgrid(x, x, x, indexing="ij")
+    WU, WV, WW = np.meshgrid(w, w, w, indexing="ij")
+    s1 = U
+    s2 = V * (1 - U)
+    s3 = W * (1 - U) * (1 - V)
+    jac = (1 - U) ** 2 * (1 - V)
+    P = (a[None, None, None, :] + s1[..., None] * (b - a) + s2[..., None] * (c - a) + s3[..., None] * (d - a))
+    six_vol = float(np.dot(b - a, np.cross(c - a, d - a)))
+    f = (WU * WV * WW * jac * np.exp(1j * (P @ Q)))[..., None] * P
+    return six_vol * np.sum(f.reshape(-1, 3), axis=0)
 
 
 def quad_tri_fan(verts2d, Q, n=30) -> complex:

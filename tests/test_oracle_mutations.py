@@ -19,7 +19,8 @@ import pytest
 
 import meshgen as mg
 from conftest import GOLDEN, ROOT
-from indep import dd_exp, quad_tet, quad_tri_fan, tetfan_ft3d
+from indep import dd_exp, quad_tet, quad_tet_moment, quad_tri_fan, tetfan_ft3d
+from test_oracle_dq import box_dq
 
 ORACLE_SRC = os.path.join(ROOT, "oracle", "pft_oracle.py")
 
@@ -133,9 +134,36 @@ def _pin_gradient(O):
     return _rel(O.grad3d(v, t, q, g), want)
 
 
+def _pin_dq_box(O):
+    # grad_Q F of a box: off-axis, along a face normal, and a small Q (tetrahedron-series branch)
+    a, b, c, o = 1.3, 0.7, 1.1, (0.2, -0.4, 0.3)
+    v, t = mg.box(a, b, c, origin=o)
+    q = np.array([[1.2, -0.7, 2.2], [0.0, 0.0, 2.5], [4.0, 3.0, -5.0], [0.05, 0.02, -0.03]])
+    return _rel(O.ft3d_dq(v, t, q), np.array([box_dq(a, b, c, o, Q) for Q in q]))
+
+
+def _pin_dq_tet_quadrature(O):
+    v, t = mg.tetrahedron()
+    v = v + np.array([0.3, -0.5, 0.2])
+    q = np.array([[1.2, -0.8, 2.0], [0.4, 3.1, -1.0], [0.05, -0.02, 0.03]])
+    want = np.array([1j * quad_tet_moment(v[0], v[1], v[2], v[3], Q) for Q in q])
+    return _rel(O.ft3d_dq(v, t, q), want)
+
+
+def _pin_regions_core_shell(O):
+    outer, inner = ((2.0, 1.6, 1.8), (-1.0, -0.7, -0.9)), ((0.9, 0.5, 0.7), (-0.3, -0.2, 0.1))
+    v, t, off = mg.nested_boxes(outer, inner)
+    q = np.array([[1.2, -0.7, 2.2], [0.0, 0.0, 2.5]])
+    F, _ = O.ft3d_regions(v, t, off, [3.0, -0.5], q)
+    want = np.array([-0.5 * _box_closed(*outer[0], outer[1], Q) + 3.5 * _box_closed(*inner[0], inner[1], Q)
+                     for Q in q])
+    return _rel(F, want)
+
+
 PINS = [_pin_rect_edges, _pin_rect_integral, _pin_polygon_quadrature, _pin_prism, _pin_box_axes_and_zero,
-        _pin_tet_quadrature, _pin_tetfan, _pin_gradient]
-TOL = {_pin_polygon_quadrature: 1e-9, _pin_tet_quadrature: 1e-9}
+        _pin_tet_quadrature, _pin_tetfan, _pin_gradient, _pin_dq_box, _pin_dq_tet_quadrature,
+        _pin_regions_core_shell]
+TOL = {_pin_polygon_quadrature: 1e-9, _pin_tet_quadrature: 1e-9, _pin_dq_tet_quadrature: 1e-9}
 
 
 def _failures(O):
@@ -194,6 +222,16 @@ MUTATIONS = [
      "- 0.0 * s[:, :, None] * 0.5 * u[(l + 2) % 3][None, :, :]))"),
     ("gradient conjugate dropped", 'Rw += np.real(np.einsum("q,qfk->fk", np.conj(go[s:e]), B))',
      'Rw += np.real(np.einsum("q,qfk->fk", go[s:e], B))'),
+    ("grad_Q: volume term dropped", "gF[idx[s:e]] = surf / q2[:, None] - qq * (Fc[idx[s:e]] / q2)[:, None]",
+     "gF[idx[s:e]] = surf / q2[:, None]"),
+    ("grad_Q: surface term sign", "surf += (qn * B[:, :, k]) @ vk", "surf -= (qn * B[:, :, k]) @ vk"),
+    ("grad_Q: tetrahedron moment factorial", "mom = vol6[None, :] * simplex_exp_series(ph + [ph[k + 1]], dim=4)",
+     "mom = vol6[None, :] * simplex_exp_series(ph + [ph[k + 1]], dim=3)"),
+    ("grad_Q: doubled node shifted", "mom = vol6[None, :] * simplex_exp_series(ph + [ph[k + 1]], dim=4)",
+     "mom = vol6[None, :] * simplex_exp_series(ph + [ph[k]], dim=4)"),
+    ("grad_Q: translation term sign", "return ph_t[:, None] * (gF + 1j * t[None, :] * Fc[:, None])",
+     "return ph_t[:, None] * (gF - 1j * t[None, :] * Fc[:, None])"),
+    ("regions: densities dropped", "return (rho[:, None] * Fj).sum(axis=0), Fj", "return Fj.sum(axis=0), Fj"),
 ]
 
 
