@@ -176,6 +176,58 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
                            void* grad_verts, void* stream);
 
 /*
+ * pft_forward_3d_regions -- F(Q) of a density that is constant on each of
+ * several closed regions: F = sum_j rho_j F_j, F_j the transform of region j
+ * (the "constant quantity over a volume" of the method, taken piecewise).
+ *
+ *  verts, vdtype, nv, q, qdtype, nq, mode, intensity as in pft_forward_3d.
+ *  tris            [nf][3] int32 (DEVICE): the outward boundaries of the
+ *                  regions, region j owning triangles region_offsets[j] ..
+ *                  region_offsets[j+1]). A surface shared by two regions is
+ *                  listed in both, with opposite orientations (it may reuse
+ *                  the same vertices). Each region must be closed.
+ *  region_offsets  HOST int64 [nreg + 1], non-decreasing from 0 to nf.
+ *  nreg            number of regions, 0 .. 4096 (nreg = 0 gives F = 0).
+ *  rho             [nreg] float64 densities (DEVICE).
+ *  out             [nq] complex (complex128 for PFT_FP64, complex64 for PFT_FP32C).
+ *  out_regions     NULL or [nreg][nq] complex of the same type: F_j, which is
+ *                  also dF/drho_j.
+ * Temporaries: about (nreg + 40) * nq * 16 bytes of partial sums.
+ * Errors: as pft_forward_3d; EINVAL also for bad offsets, offsets that do not
+ * end at nf, nreg outside 0 .. 4096, or rho NULL with nreg > 0.
+ */
+pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                  const int64_t* region_offsets, int64_t nreg, const double* rho, const void* q,
+                                  pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* out_regions,
+                                  void* intensity, void* stream);
+
+/*
+ * pft_backward_3d_regions -- gradients of a real loss L(F) with
+ * F = sum_j rho_j F_j (pft_forward_3d_regions), given
+ * grad_out = dL/dRe F + i dL/dIm F:
+ *     dL/dv_k    = sum_Q Re(conj(g) sum_j rho_j dF_j/dv_k)  (as pft_backward_3d, faces weighted by their density),
+ *     dL/drho_j  = sum_Q Re(conj(g) F_j),
+ *     dL/dQ      = Re(conj(g) grad_Q F),  grad_Q F = i * integral of rho r exp(iQ.r) dV.
+ * The paper gives none of these; grad_Q F follows from the divergence theorem
+ * with the field x_a (-iQ/|Q|^2) exp(iQ.r) and the barycentric moments of the
+ * faces (r is linear on a face), and from the tetrahedron fan for |Q| R < 0.5.
+ * With one region of density 1 this is the Q-gradient of pft_forward_3d.
+ *
+ *  Mesh, region, q and mode arguments as in pft_forward_3d_regions.
+ *  grad_out    [nq] complex (complex128 for PFT_FP64, complex64 for PFT_FP32C).
+ *  grad_verts  NULL or [nv][3] of vdtype, OVERWRITTEN.
+ *  grad_rho    NULL or [nreg] float64, OVERWRITTEN.
+ *  grad_q      NULL or [nq][3] of qdtype, OVERWRITTEN.
+ * Outputs that are NULL are not computed. Temporaries: as the adjoint for
+ * grad_verts; (nreg + 40) * nq * 64 bytes for grad_q.
+ * Errors: as pft_forward_3d_regions.
+ */
+pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                   const int64_t* region_offsets, int64_t nreg, const double* rho, const void* q,
+                                   pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
+                                   void* grad_verts, double* grad_rho, void* grad_q, void* stream);
+
+/*
  * A batch of independent closed meshes, each with its own Q list, stored as
  * concatenations. Offsets are HOST int64 arrays of length n_meshes + 1,
  * non-decreasing from 0; mesh i owns verts[vert_offsets[i] .. vert_offsets[i+1]),

@@ -18,7 +18,7 @@ from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
 
 __all__ = [
     "forward_2d", "forward_3d", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
-    "orientation_average",
+    "orientation_average", "forward_3d_regions", "backward_3d_regions",
     "validate_mesh",
     "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
 ]
@@ -199,6 +199,74 @@ def backward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, grad_o
                                           tris.shape[0], _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(g),
                                           _ptr(grad), _stream(verts.device)))
     return grad
+
+
+def _regions(region_offsets, nf: int, rho: torch.Tensor, device):
+    off = np.ascontiguousarray(np.asarray(region_offsets, dtype=np.int64).reshape(-1))
+    if off.size < 1 or off[0] != 0 or off[-1] != nf or np.any(np.diff(off) < 0):
+        raise ValueError("region_offsets must rise from 0 to the number of triangles")
+    rho = _on_gpu(rho, "rho").reshape(-1)
+    if rho.dtype != torch.float64:
+        raise TypeError(f"rho must be float64, got {rho.dtype}")
+    if rho.device != device:
+        raise ValueError("rho must be on the same device as the mesh")
+    if rho.shape[0] != off.size - 1:
+        raise ValueError("rho needs one density per region")
+    return off, rho.contiguous()
+
+
+def forward_3d_regions(verts: torch.Tensor, tris: torch.Tensor, region_offsets, rho: torch.Tensor, q: torch.Tensor,
+                       mode: str = "fp32c", per_region: bool = False, intensity: bool = False):
+    """F = sum_j rho_j F_j for a density rho_j constant on closed region j, whose outward boundary is
+    triangles region_offsets[j] .. region_offsets[j+1] (host offsets; rho float64 on the device).
+
+    Returns F, with F_j [nreg, nq] (= dF/drho) when ``per_region`` and |F|^2 when ``intensity``
+    appended in that order.
+    """
+    verts, tris = _mesh(verts, tris)
+    q = _qlist(q, verts.device)
+    off, rho = _regions(region_offsets, tris.shape[0], rho, verts.device)
+    m = mode_id(mode)
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    rdt = torch.float64 if m == PFT_FP64 else torch.float32
+    out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
+    regs = torch.empty((off.size - 1, q.shape[0]), dtype=cdt, device=verts.device) if per_region else None
+    inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_forward_3d_regions(
+            _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0],
+            off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), off.size - 1, _ptr(rho), _ptr(q),
+            _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(regs), _ptr(inten), _stream(verts.device)))
+    res = (out,) + ((regs,) if per_region else ()) + ((inten,) if intensity else ())
+    return res[0] if len(res) == 1 else res
+
+
+def backward_3d_regions(verts: torch.Tensor, tris: torch.Tensor, region_offsets, rho: torch.Tensor, q: torch.Tensor,
+                        grad_out: torch.Tensor, mode: str = "fp32c", need_verts: bool = True, need_rho: bool = True,
+                        need_q: bool = True):
+    """(dL/dverts, dL/drho, dL/dQ) for grad_out = dL/dReF + i dL/dImF, F = sum_j rho_j F_j.
+
+    Entries not asked for are None. dL/dverts has the dtype of verts, dL/drho float64, dL/dQ the
+    dtype of q.
+    """
+    verts, tris = _mesh(verts, tris)
+    q = _qlist(q, verts.device)
+    off, rho = _regions(region_offsets, tris.shape[0], rho, verts.device)
+    m = mode_id(mode)
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    g = _on_gpu(grad_out, "grad_out").reshape(-1)
+    if g.shape[0] != q.shape[0]:
+        raise ValueError("grad_out must have one entry per Q")
+    g = g.to(cdt).contiguous()
+    gv = torch.empty_like(verts) if need_verts else None
+    gr = torch.empty(off.size - 1, dtype=torch.float64, device=verts.device) if need_rho else None
+    gq = torch.empty_like(q) if need_q else None
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_backward_3d_regions(
+            _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0],
+            off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), off.size - 1, _ptr(rho), _ptr(q),
+            _real_dtype_id(q, "q"), q.shape[0], m, _ptr(g), _ptr(gv), _ptr(gr), _ptr(gq), _stream(verts.device)))
+    return gv, gr, gq
 
 
 def _batch_struct(verts, tris, q, vert_offsets, tri_offsets, q_offsets):

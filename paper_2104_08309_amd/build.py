@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpft.so")
 
-SOURCES = ["api.cpp", "prologue.hip", "fwd3d.hip", "bwd3d.hip", "fwd2d.hip", "batch.hip", "qorder.hip", "orient.hip", "fwdpoly.hip"]
+SOURCES = ["api.cpp", "prologue.hip", "fwd3d.hip", "bwd3d.hip", "fwd2d.hip", "batch.hip", "qorder.hip", "orient.hip",
+           "fwdpoly.hip", "dq3d.hip"]
 
 ARCH = os.environ.get("PFT_OFFLOAD_ARCH", "gfx950")
 

@@ -90,6 +90,75 @@ PFT_HD __forceinline__ void bary_moments(T d0, T d1, T m, T tol, T* yr, T* yi, T
   yr[1] = y1r; yi[1] = y1i;
 }
 
+// Edge form of the barycentric moments (|Q.(v - g)| beyond the series range):
+// the moment of corner k relative to exp(iQ.g), normalised by 2A, is
+// X_k * inv with inv = 1/|P|^2 (P = Q x N), and S is the face's edge sum, so
+// that X_0 + X_1 + X_2 = i S and the normalised face integral is i S inv. The
+// moments come from the closed-form Q-derivative of the edge sum.
+PFT_HD __forceinline__ void edge_moments_f64(const Face64& f, const double* G, const double* Q, double Px, double Py,
+                                             double Pz, double q0, double q1, double inv, double* Xr, double* Xi,
+                                             double& Sr, double& Si) {
+  const double q2 = -q0 - q1;
+  const double p0 = 0.5 * q0, p1 = 0.5 * q1, p2 = 0.5 * q2;
+  double s0, c0, s1, c1;
+  sincos(p0, &s0, &c0);
+  sincos(p1, &s1, &c1);
+  const double c2 = c0 * c1 - s0 * s1;
+  const double s2 = -(s0 * c1 + c0 * s1);
+  const double pi0 = Px * f.u0[0] + Py * f.u0[1] + Pz * f.u0[2];
+  const double pi1 = Px * f.u1[0] + Py * f.u1[1] + Pz * f.u1[2];
+  const double pi2 = -pi0 - pi1;
+  const double w[3] = {pi1 - pi0, pi2 - pi1, pi0 - pi2};
+  const double eta[3] = {p1 - p0, p2 - p1, p0 - p2};
+  const double sn[3] = {s1 * c0 - c1 * s0, s2 * c1 - c2 * s1, s0 * c2 - c0 * s2};
+  const double cs[3] = {c1 * c0 + s1 * s0, c2 * c1 + s2 * s1, c0 * c2 + s0 * s2};
+  // e_l = exp(-i psi_{l+2})
+  const double er[3] = {c2, c0, c1};
+  const double ei[3] = {-s2, -s0, -s1};
+  double ar[3], ai[3], br[3], bi[3], cr[3], ci[3];
+  Sr = 0.0;
+  Si = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const double x = eta[l];
+    double sg, dsg;
+    if (fabs(x) < 0.1) {
+      const double x2 = x * x;
+      sg = 1.0 + x2 * (-1.0 / 6.0 + x2 * (1.0 / 120.0 + x2 * (-1.0 / 5040.0 + x2 * (1.0 / 362880.0))));
+    } else {
+      sg = sn[l] / x;
+    }
+    dsg = fabs(x) < 0.5 ? dsinc_series(x) : (cs[l] - sg) / x;
+    cr[l] = sg * er[l];
+    ci[l] = sg * ei[l];
+    ar[l] = w[l] * cr[l];
+    ai[l] = w[l] * ci[l];
+    br[l] = w[l] * dsg * er[l];
+    bi[l] = w[l] * dsg * ei[l];
+    Sr += ar[l];
+    Si += ai[l];
+  }
+  // Gram matrix of the edges, G = {d0.d0, d1.d1, d2.d2, d0.d1, d1.d2, d2.d0}
+  const double Gm[3][3] = {{G[0], G[3], G[5]}, {G[3], G[1], G[4]}, {G[5], G[4], G[2]}};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int kp = (k + 1) % 3, km = (k + 2) % 3;
+    double xr = -0.5 * Si, xi = 0.5 * Sr;  // (i/2) S
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      xr += Gm[kp][l] * cr[l];
+      xi += Gm[kp][l] * ci[l];
+    }
+    xr += 0.5 * (br[km] - br[k]);
+    xi += 0.5 * (bi[km] - bi[k]);
+    xr += 0.5 * ai[kp];   // -(i/2) a_{k+1}
+    xi -= 0.5 * ar[kp];
+    const double s = 2.0 * w[kp] * inv;
+    Xr[k] = xr - s * Sr;
+    Xi[k] = xi - s * Si;
+  }
+}
+
 PFT_HD __forceinline__ void adj_term_f64(const Face64& f, const double* G, const double* Q, double gr,
                                              double gi, double* R) {
   const double Px = Q[1] * f.N[2] - Q[2] * f.N[1];
@@ -119,65 +188,11 @@ PFT_HD __forceinline__ void adj_term_f64(const Face64& f, const double* G, const
     R[2] = (zr * jr - zi * ji) - R[0] - R[1];
     return;
   }
-  const double p0 = 0.5 * q0, p1 = 0.5 * q1, p2 = 0.5 * q2;
-  double s0, c0, s1, c1;
-  sincos(p0, &s0, &c0);
-  sincos(p1, &s1, &c1);
-  const double c2 = c0 * c1 - s0 * s1;
-  const double s2 = -(s0 * c1 + c0 * s1);
-  const double pi0 = Px * f.u0[0] + Py * f.u0[1] + Pz * f.u0[2];
-  const double pi1 = Px * f.u1[0] + Py * f.u1[1] + Pz * f.u1[2];
-  const double pi2 = -pi0 - pi1;
-  const double w[3] = {pi1 - pi0, pi2 - pi1, pi0 - pi2};
-  const double eta[3] = {p1 - p0, p2 - p1, p0 - p2};
-  const double sn[3] = {s1 * c0 - c1 * s0, s2 * c1 - c2 * s1, s0 * c2 - c0 * s2};
-  const double cs[3] = {c1 * c0 + s1 * s0, c2 * c1 + s2 * s1, c0 * c2 + s0 * s2};
-  // e_l = exp(-i psi_{l+2})
-  const double er[3] = {c2, c0, c1};
-  const double ei[3] = {-s2, -s0, -s1};
-  double ar[3], ai[3], br[3], bi[3], cr[3], ci[3];
-  double Sr = 0.0, Si = 0.0;
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    const double x = eta[l];
-    double sg, dsg;
-    if (fabs(x) < 0.1) {
-      const double x2 = x * x;
-      sg = 1.0 + x2 * (-1.0 / 6.0 + x2 * (1.0 / 120.0 + x2 * (-1.0 / 5040.0 + x2 * (1.0 / 362880.0))));
-    } else {
-      sg = sn[l] / x;
-    }
-    dsg = fabs(x) < 0.5 ? dsinc_series(x) : (cs[l] - sg) / x;
-    cr[l] = sg * er[l];
-    ci[l] = sg * ei[l];
-    ar[l] = w[l] * cr[l];
-    ai[l] = w[l] * ci[l];
-    br[l] = w[l] * dsg * er[l];
-    bi[l] = w[l] * dsg * ei[l];
-    Sr += ar[l];
-    Si += ai[l];
-  }
-  // Gram matrix of the edges, G = {d0.d0, d1.d1, d2.d2, d0.d1, d1.d2, d2.d0}
-  const double Gm[3][3] = {{G[0], G[3], G[5]}, {G[3], G[1], G[4]}, {G[5], G[4], G[2]}};
   const double inv = 1.0 / P2;
+  double Xr[3], Xi[3], Sr, Si;
+  edge_moments_f64(f, G, Q, Px, Py, Pz, q0, q1, inv, Xr, Xi, Sr, Si);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int kp = (k + 1) % 3, km = (k + 2) % 3;
-    double Xr = -0.5 * Si, Xi = 0.5 * Sr;  // (i/2) S
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      Xr += Gm[kp][l] * cr[l];
-      Xi += Gm[kp][l] * ci[l];
-    }
-    Xr += 0.5 * (br[km] - br[k]);
-    Xi += 0.5 * (bi[km] - bi[k]);
-    Xr += 0.5 * ai[kp];   // -(i/2) a_{k+1}
-    Xi -= 0.5 * ar[kp];
-    const double s = 2.0 * w[kp] * inv;
-    Xr -= s * Sr;
-    Xi -= s * Si;
-    R[k] = (zr * Xr - zi * Xi) * inv;
-  }
+  for (int k = 0; k < 3; ++k) R[k] = (zr * Xr[k] - zi * Xi[k]) * inv;
 }
 
 // ---------------------------------------------------------------------------
@@ -195,6 +210,66 @@ __device__ __forceinline__ float dsinc_series_f(float x) {
   const float x2 = x * x;
   return x * (-1.0f / 3.0f + x2 * (1.0f / 30.0f + x2 * (-1.0f / 840.0f + x2 * (1.0f / 45360.0f +
              x2 * (-1.0f / 3991680.0f + x2 * (1.0f / 518918400.0f))))));
+}
+
+// Edge form of the barycentric moments in binary32, as edge_moments_f64:
+// moment k (normalised by 2A, relative to exp(iQ.g)) = X_k * inv, inv = 1/|P|^2,
+// and the face integral i S inv. Sinc and its derivative use their Taylor
+// series for |x| < 1 (the hardware sine loses relative accuracy at small
+// arguments) and quotients beyond.
+__device__ __forceinline__ void edge_moments_fp32c(const Face32B& f, float Px, float Py, float Pz, float q0, float q1,
+                                                   float inv, float* Xr, float* Xi, float& Sr, float& Si) {
+  const float w0 = Px * f.d0[0] + Py * f.d0[1] + Pz * f.d0[2];
+  const float w1 = Px * f.d1[0] + Py * f.d1[1] + Pz * f.d1[2];
+  const float w[3] = {w0, w1, -w0 - w1};
+  const float p0 = q0 * (0.5f * kInv2PiF), p1 = q1 * (0.5f * kInv2PiF), p2 = -p0 - p1;  // psi_k in turns
+  const float s0 = sin_turns(p0), c0 = cos_turns(p0);
+  const float s1 = sin_turns(p1), c1 = cos_turns(p1);
+  const float c2 = c0 * c1 - s0 * s1;
+  const float s2 = -(s0 * c1 + c0 * s1);
+  const float eta[3] = {p1 - p0, p2 - p1, p0 - p2};  // turns
+  const float cs[3] = {c1 * c0 + s1 * s0, c2 * c1 + s2 * s1, c0 * c2 + s0 * s2};
+  const float er[3] = {c2, c0, c1};
+  const float ei[3] = {-s2, -s0, -s1};
+  float ar[3], ai[3], br[3], bi[3], cr[3], ci[3];
+  Sr = 0.0f;
+  Si = 0.0f;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const float xt = eta[l];
+    const float x = kTwoPiF * xt;                  // radians
+    const float rx = rcp_f(xt) * kInv2PiF;         // 1/x
+    const bool near0 = fabsf(x) < 1.0f;
+    const float sg = near0 ? sinc_series_f(x) : sin_turns(xt) * rx;
+    const float dsg = near0 ? dsinc_series_f(x) : (cs[l] - sg) * rx;
+    cr[l] = sg * er[l];
+    ci[l] = sg * ei[l];
+    ar[l] = w[l] * cr[l];
+    ai[l] = w[l] * ci[l];
+    const float wd = w[l] * dsg;
+    br[l] = wd * er[l];
+    bi[l] = wd * ei[l];
+    Sr += ar[l];
+    Si += ai[l];
+  }
+  const float Gm[3][3] = {{f.G[0], f.G[3], f.G[5]}, {f.G[3], f.G[1], f.G[4]}, {f.G[5], f.G[4], f.G[2]}};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int kp = (k + 1) % 3, km = (k + 2) % 3;
+    float xr = -0.5f * Si, xi = 0.5f * Sr;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      xr += Gm[kp][l] * cr[l];
+      xi += Gm[kp][l] * ci[l];
+    }
+    xr += 0.5f * (br[km] - br[k]);
+    xi += 0.5f * (bi[km] - bi[k]);
+    xr += 0.5f * ai[kp];
+    xi -= 0.5f * ar[kp];
+    const float s = 2.0f * w[kp] * inv;
+    Xr[k] = xr - s * Sr;
+    Xi[k] = xi - s * Si;
+  }
 }
 
 __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float qy, float qz, float Q2,
@@ -224,60 +299,11 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
     R[2] = (zr * jr - zi * ji) - R[0] - R[1];
     return;
   }
-  const float w0 = Px * f.d0[0] + Py * f.d0[1] + Pz * f.d0[2];
-  const float w1 = Px * f.d1[0] + Py * f.d1[1] + Pz * f.d1[2];
-  const float w[3] = {w0, w1, -w0 - w1};
-  const float p0 = q0 * (0.5f * kInv2PiF), p1 = q1 * (0.5f * kInv2PiF), p2 = -p0 - p1;  // psi_k in turns
-  const float s0 = sin_turns(p0), c0 = cos_turns(p0);
-  const float s1 = sin_turns(p1), c1 = cos_turns(p1);
-  const float c2 = c0 * c1 - s0 * s1;
-  const float s2 = -(s0 * c1 + c0 * s1);
-  const float eta[3] = {p1 - p0, p2 - p1, p0 - p2};  // turns
-  const float cs[3] = {c1 * c0 + s1 * s0, c2 * c1 + s2 * s1, c0 * c2 + s0 * s2};
-  const float er[3] = {c2, c0, c1};
-  const float ei[3] = {-s2, -s0, -s1};
-  float ar[3], ai[3], br[3], bi[3], cr[3], ci[3];
-  float Sr = 0.0f, Si = 0.0f;
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    const float xt = eta[l];
-    const float x = kTwoPiF * xt;                  // radians
-    const float rx = rcp_f(xt) * kInv2PiF;         // 1/x
-    // sinc and its derivative: Taylor series for |x| < 1 (the hardware sine loses
-    // relative accuracy at small arguments), quotients beyond
-    const bool near0 = fabsf(x) < 1.0f;
-    const float sg = near0 ? sinc_series_f(x) : sin_turns(xt) * rx;
-    const float dsg = near0 ? dsinc_series_f(x) : (cs[l] - sg) * rx;
-    cr[l] = sg * er[l];
-    ci[l] = sg * ei[l];
-    ar[l] = w[l] * cr[l];
-    ai[l] = w[l] * ci[l];
-    const float wd = w[l] * dsg;
-    br[l] = wd * er[l];
-    bi[l] = wd * ei[l];
-    Sr += ar[l];
-    Si += ai[l];
-  }
-  const float Gm[3][3] = {{f.G[0], f.G[3], f.G[5]}, {f.G[3], f.G[1], f.G[4]}, {f.G[5], f.G[4], f.G[2]}};
   const float inv = rcp_f(fmaxf(P2, 1e-30f));
+  float Xr[3], Xi[3], Sr, Si;
+  edge_moments_fp32c(f, Px, Py, Pz, q0, q1, inv, Xr, Xi, Sr, Si);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int kp = (k + 1) % 3, km = (k + 2) % 3;
-    float Xr = -0.5f * Si, Xi = 0.5f * Sr;
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      Xr += Gm[kp][l] * cr[l];
-      Xi += Gm[kp][l] * ci[l];
-    }
-    Xr += 0.5f * (br[km] - br[k]);
-    Xi += 0.5f * (bi[km] - bi[k]);
-    Xr += 0.5f * ai[kp];
-    Xi -= 0.5f * ar[kp];
-    const float s = 2.0f * w[kp] * inv;
-    Xr -= s * Sr;
-    Xi -= s * Si;
-    R[k] = (zr * Xr - zi * Xi) * inv;
-  }
+  for (int k = 0; k < 3; ++k) R[k] = (zr * Xr[k] - zi * Xi[k]) * inv;
 }
 
 // ---------------------------------------------------------------------------

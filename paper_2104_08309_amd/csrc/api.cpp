@@ -455,6 +455,7 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   a.perm = perm;
   a.splits = splits;
   a.faces_per_split = per;
+  a.split_face = nullptr;
   a.partial = partial;
   a.out = out;
   a.intensity = intensity;
@@ -467,6 +468,54 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   e = launch_fwd3d_finish(a, c128 ? 1 : 0, s);
   if (e != hipSuccess) return hip_fail(e, "3D finish");
   return PFT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// closed regions of constant density
+// ---------------------------------------------------------------------------
+constexpr int64_t kMaxRegions = 4096;
+
+pft_status check_regions(const int64_t* off, int64_t nreg, int64_t nf, const double* rho) {
+  if (nreg < 0 || nreg > kMaxRegions) return fail(PFT_EINVAL, "nreg must be 0 .. 4096");
+  pft_status st = check_offsets(off, nreg, "region_offsets");
+  if (st != PFT_OK) return st;
+  if (off[nreg] != nf) return fail(PFT_EINVAL, "region_offsets must end at nf");
+  if (nreg > 0 && rho == nullptr) return fail(PFT_EINVAL, "rho is NULL");
+  if (rho && !aligned(rho, 8)) return fail(PFT_EINVAL, "rho misaligned");
+  return PFT_OK;
+}
+
+// Face splits that never cross a region boundary: each non-empty region gets
+// about nf_j / per splits (per as for one mesh), so every split's partial sum
+// belongs to one region and the finish kernels can weight and separate them.
+struct RegionPlan {
+  std::vector<int64_t> split_face;   // [splits + 1]
+  std::vector<int32_t> region_split; // [nreg + 1]
+  int splits = 0;
+  int64_t* d_split_face = nullptr;
+  int32_t* d_region_split = nullptr;
+};
+
+pft_status plan_regions(Arena& ar, const int64_t* off, int64_t nreg, int64_t nq, int qpt, RegionPlan& p,
+                        hipStream_t s) {
+  const int64_t nf = off[nreg];
+  int s0 = 0;
+  int64_t per = 0;
+  choose_face_splits(nq, nf, qpt, &s0, &per);
+  if (per <= 0) per = kTileF;
+  for (int64_t j = 0; j < nreg; ++j) {
+    p.region_split.push_back((int32_t)p.split_face.size());
+    const int64_t n = off[j + 1] - off[j];
+    if (n <= 0) continue;
+    const int64_t pj = cdiv(cdiv(n, cdiv(n, per)), (int64_t)kTileF) * kTileF;
+    for (int64_t f = off[j]; f < off[j + 1]; f += pj) p.split_face.push_back(f);
+  }
+  p.region_split.push_back((int32_t)p.split_face.size());
+  p.splits = (int)p.split_face.size();
+  p.split_face.push_back(nf);
+  pft_status st = upload(ar, p.split_face, &p.d_split_face, s);
+  if (st == PFT_OK) st = upload(ar, p.region_split, &p.d_region_split, s);
+  return st;
 }
 
 }  // namespace
@@ -558,6 +607,7 @@ pft_status pft_forward_3d_poly(const void* verts, pft_dtype vdtype, int64_t nv, 
   a.perm = perm;
   a.splits = splits;
   a.faces_per_split = 0;
+  a.split_face = nullptr;
   a.partial = partial;
   a.out = out;
   a.intensity = intensity;
@@ -670,9 +720,240 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   e = c128 ? launch_bwd3d_fp64(a, gram, s) : launch_bwd3d_fp32c(a, s);
   prof_end(nm, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint");
-  e = launch_bwd_face_contrib(partial, qs, f64, nf, contrib, s);
+  e = launch_bwd_face_contrib(partial, qs, f64, nullptr, nf, contrib, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint reduce");
   return gather_tail(ar, tris, nf, nullptr, nullptr, nv, contrib, grad_verts, vdtype, s);
+}
+
+pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                  const int64_t* region_offsets, int64_t nreg, const double* rho, const void* q,
+                                  pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* out_regions,
+                                  void* intensity, void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  if ((st = check_regions(region_offsets, nreg, nf, rho)) != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
+  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
+  if (out_regions && !aligned(out_regions, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out_regions misaligned");
+  if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
+  if (nq == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  Arena ar(s);
+  RegionPlan plan;
+  if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? 1 : kQPT, plan, s)) != PFT_OK) return st;
+  MeshInfo* info = ar.get<MeshInfo>(1);
+  Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
+  Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
+  double2* partial = ar.get<double2>((size_t)std::max(plan.splits, 1) * nq);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
+  if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, c128 ? kTauF64 : kTauF32, f64, s);
+  if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
+  if (e != hipSuccess) return hip_fail(e, "3D prologue");
+  uint32_t* perm = nullptr;
+  if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
+  FwdArgs a;
+  a.f64 = f64;
+  a.f32 = f32;
+  a.info = info;
+  a.nf = nf;
+  a.q = q;
+  a.qdtype = qdtype;
+  a.nq = nq;
+  a.perm = perm;
+  a.splits = plan.splits;
+  a.faces_per_split = 0;
+  a.split_face = plan.d_split_face;
+  a.partial = partial;
+  a.out = out;
+  a.intensity = intensity;
+  a.tau0 = c128 ? kTau0F64 : kTau0F32;
+  if (plan.splits > 0) {
+    const char* nm = main_name(true, mode);
+    prof_begin(nm, s);
+    e = c128 ? launch_fwd3d_fp64(a, s) : launch_fwd3d_fp32c(a, s);
+    prof_end(nm, s);
+    if (e != hipSuccess) return hip_fail(e, "3D transform");
+  }
+  RegionArgs r;
+  r.region_split = plan.d_region_split;
+  r.nreg = (int)nreg;
+  r.rho = rho;
+  r.out_regions = out_regions;
+  r.grad_out = nullptr;
+  r.rho_part = nullptr;
+  e = launch_regions_finish(a, r, c128 ? 1 : 0, s);
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "regions finish");
+}
+
+pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                   const int64_t* region_offsets, int64_t nreg, const double* rho, const void* q,
+                                   pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
+                                   void* grad_verts, double* grad_rho, void* grad_q, void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  if ((st = check_regions(region_offsets, nreg, nf, rho)) != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  if (nq > 0 && grad_out == nullptr) return fail(PFT_EINVAL, "grad_out is NULL");
+  if (grad_out && !aligned(grad_out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "grad_out misaligned");
+  if (grad_verts && !aligned(grad_verts, real_size(vdtype))) return fail(PFT_EINVAL, "grad_verts misaligned");
+  if (grad_rho && !aligned(grad_rho, 8)) return fail(PFT_EINVAL, "grad_rho misaligned");
+  if (grad_q && !aligned(grad_q, real_size(qdtype))) return fail(PFT_EINVAL, "grad_q misaligned");
+  const bool want_v = grad_verts != nullptr && nv > 0;
+  const bool want_r = grad_rho != nullptr && nreg > 0;
+  const bool want_q = grad_q != nullptr && nq > 0;
+  if (!want_v && !want_r && !want_q) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  hipError_t e = hipSuccess;
+  if (nq == 0 || nf == 0) {  // no Q or no faces: every gradient is zero
+    if (want_v) e = zero_bytes(grad_verts, (size_t)nv * 3 * real_size(vdtype), s);
+    if (e == hipSuccess && want_r) e = zero_bytes(grad_rho, (size_t)nreg * sizeof(double), s);
+    if (e == hipSuccess && want_q) e = zero_bytes(grad_q, (size_t)nq * 3 * real_size(qdtype), s);
+    return e == hipSuccess ? PFT_OK : hip_fail(e, "zero gradients");
+  }
+  Arena ar(s);
+  MeshInfo* info = ar.get<MeshInfo>(1);
+  Face64* f64 = ar.get<Face64>(nf);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
+  if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, kTauF64, f64, s);
+  if (e != hipSuccess) return hip_fail(e, "regions prologue");
+  Face32B* f32b = nullptr;
+  double* gram = nullptr;
+  if (want_v || want_q) {
+    f32b = c128 ? nullptr : ar.get<Face32B>(nf);
+    gram = c128 ? ar.get<double>((size_t)nf * 8) : nullptr;
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    e = c128 ? launch_gram64(f64, nf, gram, s) : launch_face32b(f64, nf, kTauB32, kTauRelB32, f32b, s);
+    if (e != hipSuccess) return hip_fail(e, "regions prologue");
+  }
+  // dL/dv: the vertex adjoint with each face's partial weighted by its region's density
+  if (want_v) {
+    int64_t* d_off = nullptr;
+    std::vector<int64_t> offv(region_offsets, region_offsets + nreg + 1);
+    if ((st = upload(ar, offv, &d_off, s)) != PFT_OK) return st;
+    double* face_w = ar.get<double>(nf);
+    int qs;
+    int64_t qper;
+    choose_q_splits(nq, nf, c128 ? kTileFB : kTileFB32, &qs, &qper);
+    double* partial = ar.get<double>((size_t)qs * nf * 3);
+    double* contrib = ar.get<double>((size_t)nf * 9);
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    e = launch_face_weights(d_off, (int)nreg, rho, nf, face_w, s);
+    if (e != hipSuccess) return hip_fail(e, "face weights");
+    QRec32* rec = nullptr;
+    QRec64* rec64 = nullptr;
+    if ((st = build_qrecs(ar, mode, q, qdtype, grad_out, nq, info, nullptr, 1, &rec, &rec64, s)) != PFT_OK) return st;
+    BwdArgs b;
+    b.info = info;
+    b.f64 = f64;
+    b.f32 = f32b;
+    b.nf = nf;
+    b.q = q;
+    b.qdtype = qdtype;
+    b.nq = nq;
+    b.grad_out = grad_out;
+    b.rec = rec;
+    b.rec64 = rec64;
+    b.qsplits = qs;
+    b.q_per_split = qper;
+    b.partial = partial;
+    const char* nm = main_name(false, mode);
+    prof_begin(nm, s);
+    e = c128 ? launch_bwd3d_fp64(b, gram, s) : launch_bwd3d_fp32c(b, s);
+    prof_end(nm, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint");
+    e = launch_bwd_face_contrib(partial, qs, f64, face_w, nf, contrib, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint reduce");
+    if ((st = gather_tail(ar, tris, nf, nullptr, nullptr, nv, contrib, grad_verts, vdtype, s)) != PFT_OK) return st;
+  }
+  if (!want_r && !want_q) return PFT_OK;
+  uint32_t* perm = nullptr;
+  if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
+  const int64_t nblocks = finish_blocks(nq);
+  double* rho_part = want_r ? ar.get<double>((size_t)nblocks * nreg) : nullptr;
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  RegionArgs r;
+  r.nreg = (int)nreg;
+  r.rho = rho;
+  r.out_regions = nullptr;
+  r.grad_out = grad_out;
+  r.rho_part = rho_part;
+  if (want_q) {
+    // dL/dQ (and dL/drho from the same partials): the grad_Q kernel
+    RegionPlan plan;
+    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? 1 : kQPTDQ, plan, s)) != PFT_OK) return st;
+    double2* partial = ar.get<double2>((size_t)std::max(plan.splits, 1) * 4 * nq);
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    DqArgs d;
+    d.info = info;
+    d.f64 = f64;
+    d.gram = gram;
+    d.f32 = f32b;
+    d.nf = nf;
+    d.q = q;
+    d.qdtype = qdtype;
+    d.nq = nq;
+    d.perm = perm;
+    d.splits = plan.splits;
+    d.faces_per_split = 0;
+    d.split_face = plan.d_split_face;
+    d.partial = partial;
+    d.tau = kTauDQ;
+    const char* nm = c128 ? "dq3d_fp64" : "dq3d_fp32c";
+    prof_begin(nm, s);
+    e = c128 ? launch_dq3d_fp64(d, s) : launch_dq3d_fp32c(d, s);
+    prof_end(nm, s);
+    if (e != hipSuccess) return hip_fail(e, "grad_Q transform");
+    r.region_split = plan.d_region_split;
+    e = launch_dq_finish(d, r, c128 ? 1 : 0, grad_q, qdtype, s);
+    if (e != hipSuccess) return hip_fail(e, "grad_Q finish");
+  } else {
+    // dL/drho only: the forward's partials per region
+    RegionPlan plan;
+    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? 1 : kQPT, plan, s)) != PFT_OK) return st;
+    Face32* f32 = c128 ? nullptr : ar.get<Face32>(nf);
+    double2* partial = ar.get<double2>((size_t)std::max(plan.splits, 1) * nq);
+    if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+    if (!c128) {
+      e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
+      if (e != hipSuccess) return hip_fail(e, "regions prologue");
+    }
+    FwdArgs a;
+    a.f64 = f64;
+    a.f32 = f32;
+    a.info = info;
+    a.nf = nf;
+    a.q = q;
+    a.qdtype = qdtype;
+    a.nq = nq;
+    a.perm = perm;
+    a.splits = plan.splits;
+    a.faces_per_split = 0;
+    a.split_face = plan.d_split_face;
+    a.partial = partial;
+    a.out = nullptr;
+    a.intensity = nullptr;
+    a.tau0 = c128 ? kTau0F64 : kTau0F32;
+    if (plan.splits > 0) {
+      const char* nm = main_name(true, mode);
+      prof_begin(nm, s);
+      e = c128 ? launch_fwd3d_fp64(a, s) : launch_fwd3d_fp32c(a, s);
+      prof_end(nm, s);
+      if (e != hipSuccess) return hip_fail(e, "3D transform");
+    }
+    r.region_split = plan.d_region_split;
+    e = launch_regions_finish(a, r, c128 ? 1 : 0, s);
+    if (e != hipSuccess) return hip_fail(e, "regions finish");
+  }
+  if (want_r) {
+    e = launch_rho_reduce(rho_part, nblocks, (int)nreg, grad_rho, s);
+    if (e != hipSuccess) return hip_fail(e, "rho reduce");
+  }
+  return PFT_OK;
 }
 
 }  // extern "C"

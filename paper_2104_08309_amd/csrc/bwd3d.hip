@@ -94,12 +94,13 @@ __global__ __launch_bounds__(256) void gram64_kernel(const Face64* f64, int64_t 
 // reduction over splits, per-corner vectors, vertex gather
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void face_contrib_kernel(const double* partial, int qsplits, const Face64* f64,
-                                                           int64_t nf, double* contrib) {
+                                                           const double* face_w, int64_t nf, double* contrib) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // corner slot 3m + k
   if (i >= nf * 3) return;
   const int64_t m = i / 3;
   double R = 0.0;
   for (int s = 0; s < qsplits; ++s) R += partial[(int64_t)s * nf * 3 + i];
+  if (face_w) R *= face_w[m];  // density of the face's region
   const Face64& f = f64[m];
   contrib[i * 3 + 0] = f.N[0] * R;
   contrib[i * 3 + 1] = f.N[1] * R;
@@ -174,10 +175,10 @@ hipError_t launch_bwd3d_fp32c(const BwdArgs& a, hipStream_t s) {
 }
 
 
-hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, int64_t nf,
-                                   double* contrib, hipStream_t s) {
+hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, const double* face_w,
+                                   int64_t nf, double* contrib, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
-  face_contrib_kernel<<<grid_for(nf * 3), 256, 0, s>>>(partial, qsplits, f64, nf, contrib);
+  face_contrib_kernel<<<grid_for(nf * 3), 256, 0, s>>>(partial, qsplits, f64, face_w, nf, contrib);
   return hipGetLastError();
 }
 

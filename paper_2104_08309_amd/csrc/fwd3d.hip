@@ -17,6 +17,18 @@
 namespace pft {
 namespace {
 
+// Face range of this block's split: from the split table when the splits
+// follow region boundaries, else equal ranges.
+__device__ __forceinline__ void split_faces(const FwdArgs& a, int64_t& b, int64_t& e) {
+  if (a.split_face) {
+    b = a.split_face[blockIdx.y];
+    e = a.split_face[blockIdx.y + 1];
+  } else {
+    b = (int64_t)blockIdx.y * a.faces_per_split;
+    e = min(a.nf, b + a.faces_per_split);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
   __shared__ Face64 tile[kTileF];
   const int64_t qi = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -25,8 +37,8 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
   if (active) load_q3(a.q, a.qdtype, a.perm ? (int64_t)a.perm[qi] : qi, Q);
   const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
   const bool small = sqrt(Q2) * a.info[0].R < a.tau0;
-  const int64_t f_begin = (int64_t)blockIdx.y * a.faces_per_split;
-  const int64_t f_end = min(a.nf, f_begin + a.faces_per_split);
+  int64_t f_begin, f_end;
+  split_faces(a, f_begin, f_end);
   double xr = 0.0, xi = 0.0;
   for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
     const int nt = (int)min((int64_t)kTileF, f_end - t0);
@@ -77,8 +89,8 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
     small[k] = sqrt(Q2d) * R < a.tau0;
     any_small |= small[k];
   }
-  const int64_t f_begin = (int64_t)blockIdx.y * a.faces_per_split;
-  const int64_t f_end = min(a.nf, f_begin + a.faces_per_split);
+  int64_t f_begin, f_end;
+  split_faces(a, f_begin, f_end);
   float sr[kQPT], si[kQPT], cr[kQPT], ci[kQPT];
   double xr[kQPT], xi[kQPT];
 #pragma unroll

@@ -32,6 +32,10 @@ constexpr int kQPTB = PFT_QPTB;    // Q per thread per pass in the adjoint
 #define PFT_TILEFB32 8
 #endif
 constexpr int kTileFB32 = PFT_TILEFB32;  // faces per block in the FP32C adjoint
+#ifndef PFT_QPT_DQ
+#define PFT_QPT_DQ 2
+#endif
+constexpr int kQPTDQ = PFT_QPT_DQ;  // Q per thread in the FP32C grad_Q kernel
 constexpr int kTileE = 64;         // 2D edges staged in LDS per tile
 
 // Series thresholds (dimensionless). A (Q, face) pair uses the face's simplex
@@ -49,6 +53,9 @@ constexpr double kTauRelB32 = 0.05;  // adjoint, FP32C mode, relative test
 // Whole-mesh series (fan of tetrahedra from the vertex mean) when |Q| R < tau0.
 constexpr double kTau0F64 = 0.01;
 constexpr double kTau0F32 = 0.2;
+// grad_Q F: the surface form cancels as (|Q| R)^-2 at small |Q| R; below this
+// the tetrahedron fan (binary64 series) is used in both forms.
+constexpr double kTauDQ = 0.5;
 // 2D fan series when |Q| R < tau0.
 constexpr double kTau02D = 0.01;
 
@@ -103,7 +110,7 @@ struct alignas(16) Face32B {
   float G[6];     // d0.d0, d1.d1, d2.d2, d0.d1, d1.d2, d2.d0
   float thr;      // tau_b^2 |N|^2 / L^2 (-1 for an empty face, whose record is otherwise all zero)
   float kap;      // tau_relb^2 |N|^2
-  float pad[2];
+  float c2[3];    // c - t (vertex c relative to the mesh centre; used by grad_Q F)
 };
 static_assert(sizeof(Face32B) == 128, "Face32B layout");
 
@@ -237,6 +244,7 @@ struct FwdArgs {
   int splits;
   int64_t faces_per_split;
   const uint32_t* perm;  // visiting order of Q (NULL: the caller's order); partials follow it
+  const int64_t* split_face;  // [splits + 1] face range of each split (NULL: faces_per_split each)
   double2* partial;   // [splits][nq] when splits > 1
   void* out;
   void* intensity;
@@ -245,6 +253,51 @@ struct FwdArgs {
 hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd3d_finish(const FwdArgs& a, int out_c128, hipStream_t s);
+
+// Closed regions of constant density (dq3d.hip): region j owns the splits
+// region_split[j] .. region_split[j+1] of the face-split partials.
+struct RegionArgs {
+  const int32_t* region_split;  // [nreg + 1] (device)
+  int nreg;
+  const double* rho;            // [nreg] densities (device)
+  void* out_regions;            // [nreg][nq] per-region F (NULL: not written)
+  const void* grad_out;         // [nq] cotangent for dL/drho and dL/dQ (NULL: forward only)
+  double* rho_part;             // [blocks][nreg] per-block sums of Re(conj(g) F_j) (NULL: not formed)
+};
+// F = sum_j rho_j F_j (and F_j, |F|^2, dL/drho partials) from forward partials.
+hipError_t launch_regions_finish(const FwdArgs& a, const RegionArgs& r, int out_c128, hipStream_t s);
+// dL/drho_j = sum over blocks of rho_part[.][j], fixed order.
+hipError_t launch_rho_reduce(const double* rho_part, int64_t nblocks, int nreg, double* grad_rho, hipStream_t s);
+int64_t finish_blocks(int64_t nq);
+// rho of the region owning each face (region offsets on the device).
+hipError_t launch_face_weights(const int64_t* d_region_off, int nreg, const double* rho, int64_t nf, double* w,
+                               hipStream_t s);
+
+// grad_Q F (dq3d.hip): per Q, the face sums A = sum_m (Q.N_m) e^{iQ.g_m} (sum over corners of
+// (v_k - t) times the normalised barycentric moments) and B = sum_m (Q.N_m) e^{iQ.g_m} J_m/2A,
+// or, for |Q| R < tau, the tetrahedron-fan grad F_c and F_c directly.
+struct DqArgs {
+  const MeshInfo* info;
+  const Face64* f64;
+  const double* gram;       // FP64: [nf][8] edge Gram matrices
+  const Face32B* f32;       // FP32C records
+  int64_t nf;
+  const void* q;
+  int qdtype;
+  int64_t nq;
+  const uint32_t* perm;
+  int splits;
+  int64_t faces_per_split;
+  const int64_t* split_face;
+  double2* partial;         // [splits][4][nq]: A_x, A_y, A_z, B
+  double tau;
+};
+hipError_t launch_dq3d_fp64(const DqArgs& a, hipStream_t s);
+hipError_t launch_dq3d_fp32c(const DqArgs& a, hipStream_t s);
+// dL/dQ = Re(conj(g) sum_j rho_j grad F_j) into grad_q ([nq][3] of gq_dtype, may be NULL), and
+// the dL/drho partials when r.rho_part is set.
+hipError_t launch_dq_finish(const DqArgs& a, const RegionArgs& r, int go_c128, void* grad_q, int gq_dtype,
+                            hipStream_t s);
 // fwdpoly.hip: the forward over polygon faces (FwdArgs's face fields unused; splits over tiles)
 hipError_t launch_fwdpoly_fp64(const FwdArgs& a, const PolyArgs& p, hipStream_t s);
 hipError_t launch_fwdpoly_fp32c(const FwdArgs& a, const PolyArgs& p, hipStream_t s);
@@ -296,7 +349,7 @@ hipError_t launch_qrec64_gather(const void* q, int qdtype, const void* grad_out,
                                 hipStream_t s);
 // Sum the per-split adjoint weights, form per-corner vectors N_m R_{m,k} and
 // gather them per vertex through the sorted incidence list.
-hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, int64_t nf,
+hipError_t launch_bwd_face_contrib(const double* partial, int qsplits, const Face64* f64, const double* face_w, int64_t nf,
                                    double* contrib /*[nf*3][3]*/, hipStream_t s);
 hipError_t launch_incidence_keys(const int32_t* tris, int64_t nf, const int64_t* d_vert_off,
                                  const int32_t* d_face_mesh, int64_t nv_total, uint32_t* keys, uint32_t* vals,

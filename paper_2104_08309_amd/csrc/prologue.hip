@@ -388,7 +388,7 @@ __global__ __launch_bounds__(256) void face32b_kernel(const Face64* in, int64_t 
   r.G[5] = ok ? (float)dot(d2, d0) : 0.0f;
   r.thr = ok ? (float)(tau * tau * N2 / L2) : -1.0f;
   r.kap = ok ? (float)(tau_rel * tau_rel * N2) : -1.0f;
-  r.pad[0] = r.pad[1] = 0.0f;
+  for (int k = 0; k < 3; ++k) r.c2[k] = ok ? (float)(f.g[k] - f.u0[k] - f.u1[k]) : 0.0f;
   out[m] = r;
 }
 

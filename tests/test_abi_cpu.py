@@ -116,6 +116,40 @@ def test_forward_3d_poly_validation(lib):
     assert f(V(good), 1, 8, cast(ok_off), V(good), 2, None, 1, 0, 0, None, None, None) == _lib.PFT_OK
 
 
+def test_regions_validation(lib):
+    good = 0x10000
+    f = lib.pft_forward_3d_regions
+    b = lib.pft_backward_3d_regions
+    P = ctypes.POINTER(ctypes.c_int64)
+    cast = lambda a: ctypes.cast(a, P)
+    ok = (ctypes.c_int64 * 3)(0, 4, 10)
+    short = (ctypes.c_int64 * 3)(0, 4, 9)      # does not end at nf = 10
+    down = (ctypes.c_int64 * 3)(0, 6, 4)
+    # verts, vdtype, nv, tris, nf, region_offsets, nreg, rho, q, qdtype, nq, mode, out, out_regions, intensity, stream
+    args = lambda off=ok, nreg=2, rho=V(good), out=V(good), oreg=None, nq=4: (
+        V(good), 1, 8, V(good), 10, cast(off), nreg, rho, V(good), 1, nq, 1, out, oreg, None, None)
+    assert f(*args(off=short)) == _lib.PFT_EINVAL
+    assert b"end at nf" in lib.pft_last_error()
+    assert f(*args(off=down)) == _lib.PFT_EINVAL
+    assert f(*args(nreg=5000)) == _lib.PFT_EINVAL
+    assert f(*args(nreg=-1)) == _lib.PFT_EINVAL
+    assert f(*args(rho=None)) == _lib.PFT_EINVAL
+    assert f(*args(rho=V(good + 4))) == _lib.PFT_EINVAL
+    assert f(*args(out=None)) == _lib.PFT_EINVAL
+    assert f(*args(oreg=V(good + 4))) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 8, V(good), 10, cast(ok), 2, V(good), V(good), 1, 4, 7, V(good), None, None, None) == \
+        _lib.PFT_EUNSUPPORTED
+    assert f(*args(nq=0)) == _lib.PFT_OK  # no Q: a valid no-op
+    # verts, vdtype, nv, tris, nf, offsets, nreg, rho, q, qdtype, nq, mode, grad_out, gv, grho, gq, stream
+    bargs = lambda go=V(good), gv=None, gr=None, gq=None, off=ok: (
+        V(good), 1, 8, V(good), 10, cast(off), 2, V(good), V(good), 1, 4, 1, go, gv, gr, gq, None)
+    assert b(*bargs(go=None, gq=V(good))) == _lib.PFT_EINVAL
+    assert b(*bargs(gq=V(good + 4))) == _lib.PFT_EINVAL
+    assert b(*bargs(gr=V(good + 4))) == _lib.PFT_EINVAL
+    assert b(*bargs(off=short, gv=V(good))) == _lib.PFT_EINVAL
+    assert b(*bargs()) == _lib.PFT_OK  # nothing asked for: no work
+
+
 def test_forward_2d_validation(lib):
     good = 0x10000
     f = lib.pft_forward_2d
