@@ -33,9 +33,15 @@ sys.path.insert(0, ROOT)
 #              the complex products and the accumulation);
 #   adjoint  = 200 flop: the same recomputed terms plus the derivative of the edge
 #              sum in Q that gives the three barycentric moments and their real
-#              weights against the cotangent.
+#              weights against the cotangent;
+#   grad_Q   = 246 flop: the adjoint's recomputed terms (66), edge derivatives (15)
+#              and edge products (25), two barycentric moments with their
+#              normalisation and the face integral (59), Q.N and its phase (7),
+#              the corner-weighted moment vector (42) and the accumulation of A
+#              and B (32).
 FLOP_FWD = 104.0
 FLOP_BWD = 200.0
+FLOP_DQ = 246.0
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (AMD published)
 PEAK_FP64_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
@@ -106,6 +112,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU baseline")
     ap.add_argument("--no-orient", action="store_true", help="skip the orientation-average measurement")
     ap.add_argument("--no-poly", action="store_true", help="skip the polygon-face measurement")
+    ap.add_argument("--no-regions", action="store_true",
+                    help="skip the grad_Q and multi-region (piecewise-constant density) measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -252,6 +260,65 @@ def main():
                 "poly_edge_q_per_s": n_edges * nq / (ms_p / max(n_p, 1) * 1e-3),
                 "rel_diff_poly_vs_triangles": float(np.linalg.norm(Fp - Ft) / np.linalg.norm(Ft))}
 
+    # grad_Q F on config 2 (the dL/dQ kernel, FP32C and FP64) and a three-region layered sphere
+    # (core R=30, shells to R=40 and R=50, level-4 icospheres: 25600 faces) on config 2's Q grid
+    gradq = regions = None
+    if not args.no_regions:
+        print("[bench] grad_Q and regions", file=sys.stderr, flush=True)
+        one = torch.ones(1, dtype=torch.float64, device=dev)
+        r_steps = max(3, args.steps // 4)
+        tq32, (_, _, GQ32) = timed(lambda: pft.backward_3d_regions(V, T, [0, nf], one, Q, G, mode="fp32c",
+                                                                    need_verts=False, need_rho=False), r_steps, 1)
+        n_q, ms_q = pft.profile_read("dq3d_fp32c")
+        tq64, (_, _, GQ64) = timed(lambda: pft.backward_3d_regions(V64, T, [0, nf], one, Q64, G64, mode="fp64",
+                                                                    need_verts=False, need_rho=False),
+                                   max(2, r_steps // 2), 1)
+        n_q6, ms_q6 = pft.profile_read("dq3d_fp64")
+        GQ32, GQ64 = GQ32.cpu().numpy().astype(np.float64), GQ64.cpu().numpy()
+        dq_ms, dq64_ms = ms_q / max(n_q, 1), ms_q6 / max(n_q6, 1)
+        achieved = FLOP_DQ * nf * nq / (dq_ms * 1e-3) / 1e12
+        gradq = {"workload": f"config 2 mesh x {nq} Q, dL/dQ = Re(conj(g) grad_Q F)",
+                 "kernel_ms_fp32c": dq_ms, "kernel_ms_fp64": dq64_ms, "ms_per_call_fp32c": tq32 * 1e3,
+                 "ms_per_call_fp64": tq64 * 1e3, "face_q_per_s_fp32c": nf * nq / (dq_ms * 1e-3),
+                 "speedup_fp32c_vs_fp64_kernel": dq64_ms / dq_ms,
+                 "alu": {"achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP32_TFLOPS, "flop_per_face_q": FLOP_DQ},
+                 "rel_err_fp32c_vs_fp64_gpu": float(np.linalg.norm(GQ32 - GQ64) / np.linalg.norm(GQ64))}
+        lv, lt, loff = mg.layered_sphere(4, [30.0, 40.0, 50.0])
+        LV = torch.tensor(lv, dtype=torch.float32, device=dev)
+        LT = torch.tensor(lt, dtype=torch.int32, device=dev)
+        rho_h = np.array([1.0, 0.6, 0.85])
+        RHO = torch.tensor(rho_h, device=dev)
+        tf, (FR, FRj) = timed(lambda: pft.forward_3d_regions(LV, LT, loff, RHO, Q, mode="fp32c", per_region=True),
+                              r_steps, 1)
+        n_rf, ms_rf = pft.profile_read("fwd3d_fp32c")
+        tb, _ = timed(lambda: pft.backward_3d_regions(LV, LT, loff, RHO, Q, G, mode="fp32c"), r_steps, 1)
+        n_rb, ms_rb = pft.profile_read("bwd3d_fp32c")
+        n_rq, ms_rq = pft.profile_read("dq3d_fp32c")
+        nfl = lt.shape[0]
+        regions = {"workload": f"layered sphere: core R=30 and shells to R=40, R=50 (level-4 icospheres, {nfl} "
+                               f"faces in 3 regions) x config 2's {nq} Q, FP32C",
+                   "forward_kernel_ms": ms_rf / max(n_rf, 1), "forward_ms_per_call": tf * 1e3,
+                   "forward_face_q_per_s": nfl * nq / (ms_rf / max(n_rf, 1) * 1e-3),
+                   "backward_ms_per_call": tb * 1e3, "adjoint_kernel_ms": ms_rb / max(n_rb, 1),
+                   "grad_q_kernel_ms": ms_rq / max(n_rq, 1),
+                   "backward_outputs": "dL/dverts, dL/drho, dL/dQ"}
+        if not args.no_cpu_baseline:
+            import oracle as O
+            srng = np.random.default_rng(13)
+            pick = np.concatenate([[int(np.argmin(np.linalg.norm(q, axis=1)))], srng.choice(nq, 255, replace=False)])
+            gq_o = np.real(np.conj(G.cpu().numpy().astype(np.complex128)[pick])[:, None]
+                           * O.ft3d_dq(v.astype(np.float32).astype(np.float64), t,
+                                       q[pick].astype(np.float32).astype(np.float64)))
+            gradq["rel_err_fp32c_vs_oracle_sample"] = float(np.linalg.norm(GQ32[pick] - gq_o) / np.linalg.norm(gq_o))
+            gradq["oracle_sample"] = "256 grid Q incl. Q = 0, all faces"
+            pr = pick[:64]
+            Fo, _ = O.ft3d_regions(lv.astype(np.float32).astype(np.float64), lt, loff, rho_h,
+                                   q[pr].astype(np.float32).astype(np.float64))
+            FRh = FR.cpu().numpy().astype(np.complex128)
+            regions["forward_rel_err_vs_oracle_sample"] = float(np.linalg.norm(FRh[pr] - Fo) / np.linalg.norm(Fo))
+            regions["oracle_sample"] = "64 grid Q incl. Q = 0, all faces"
+
     # roofline of the dominant kernel (the longer of the forward and adjoint kernels)
     def roof(kernel, ms, flop):
         achieved = flop * nf * nq / (ms * 1e-3) / 1e12
@@ -308,6 +375,8 @@ def main():
         "cpu_baseline": cpu,
         "orientation_average": orient,
         "polygon_faces": poly,
+        "grad_q": gradq,
+        "regions": regions,
     }
     print(json.dumps(line), flush=True)
 
