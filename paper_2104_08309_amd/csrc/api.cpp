@@ -98,8 +98,14 @@ constexpr int64_t kTargetBlocks = PFT_TARGET_BLOCKS;  // 64 blocks of 256 thread
 #define PFT_MIN_FACES_PER_SPLIT 128
 #endif
 constexpr int64_t kMinFacesPerSplit = PFT_MIN_FACES_PER_SPLIT;
-constexpr int64_t kBatchChunkF = 4096;    // faces per batched forward item
-constexpr int64_t kBatchChunkQ = 65536;   // Q per batched adjoint item
+#ifndef PFT_BATCH_CHUNK_F
+#define PFT_BATCH_CHUNK_F 4096
+#endif
+#ifndef PFT_BATCH_CHUNK_Q
+#define PFT_BATCH_CHUNK_Q 65536
+#endif
+constexpr int64_t kBatchChunkF = PFT_BATCH_CHUNK_F;  // faces per batched forward item
+constexpr int64_t kBatchChunkQ = PFT_BATCH_CHUNK_Q;  // Q per batched adjoint item
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
