@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU baseline")
     ap.add_argument("--no-orient", action="store_true", help="skip the orientation-average measurement")
     ap.add_argument("--no-poly", action="store_true", help="skip the polygon-face measurement")
+    ap.add_argument("--no-loss", action="store_true", help="skip the fused intensity-loss measurement (config 4)")
     ap.add_argument("--no-regions", action="store_true",
                     help="skip the grad_Q and multi-region (piecewise-constant density) measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -319,6 +320,47 @@ def main():
             regions["forward_rel_err_vs_oracle_sample"] = float(np.linalg.norm(FRh[pr] - Fo) / np.linalg.norm(Fo))
             regions["oracle_sample"] = "64 grid Q incl. Q = 0, all faces"
 
+    # the adjoint's workload (config 4: icosphere L6 with 2 % radial noise, 256^2 Q slice) as a fitting step:
+    # L = sum w (|F|^2 - I)^2 against the sphere's intensity and dL/dv, fused in one library call, against the
+    # same step through forward_3d, the loss in torch and backward_3d
+    lossf = None
+    if not args.no_loss:
+        print("[bench] fused intensity loss (config 4)", file=sys.stderr, flush=True)
+        c4 = mg.config4()
+        V4 = torch.tensor(c4["verts"], dtype=torch.float32, device=dev)
+        T4 = torch.tensor(c4["tris"], dtype=torch.int32, device=dev)
+        Q4 = torch.tensor(c4["q"], dtype=torch.float32, device=dev)
+        x = np.linalg.norm(c4["q"], axis=1) * c4["radius"]
+        vol = 4.0 / 3.0 * np.pi * c4["radius"] ** 3
+        with np.errstate(invalid="ignore", divide="ignore"):
+            form = np.where(x < 1e-3, 1.0 - x * x / 10.0, 3.0 * (np.sin(x) - x * np.cos(x)) / x ** 3)
+        I4 = torch.tensor((vol * form) ** 2, device=dev)
+        W4 = torch.full((len(x),), 1.0 / (len(x) * vol ** 4), dtype=torch.float64, device=dev)
+
+        def fused():
+            return pft.intensity_loss_3d(V4, T4, Q4, I4, W4, mode="fp32c")
+
+        def unfused():
+            F = pft.forward_3d(V4, T4, Q4, mode="fp32c").to(torch.complex128)
+            r = F.real ** 2 + F.imag ** 2 - I4
+            L = torch.sum(W4 * r * r)
+            return L, pft.backward_3d(V4, T4, Q4, (4.0 * W4 * r * F).to(torch.complex64), mode="fp32c")
+
+        l_steps = max(3, args.steps // 4)
+        tfu, (Lf, Gf) = timed(fused, l_steps, 1)
+        n_lf, ms_lf = pft.profile_read("fwd3d_fp32c")
+        n_lb, ms_lb = pft.profile_read("bwd3d_fp32c")
+        tun, (Lu, Gu) = timed(unfused, l_steps, 1)
+        Gf, Gu = Gf.cpu().numpy().astype(np.float64), Gu.cpu().numpy().astype(np.float64)
+        nf4, nq4 = c4["tris"].shape[0], len(x)
+        lossf = {"workload": f"config 4: icosphere L6 with 2% radial noise ({nf4} faces) x 256^2 Q slice, "
+                             f"L = sum w (|F|^2 - I_sphere)^2 and dL/dv, FP32C",
+                 "fused_ms_per_step": tfu * 1e3, "unfused_ms_per_step": tun * 1e3,
+                 "fused_face_q_per_s": nf4 * nq4 / tfu,
+                 "forward_kernel_ms": ms_lf / max(n_lf, 1), "adjoint_kernel_ms": ms_lb / max(n_lb, 1),
+                 "loss_rel_diff_fused_vs_unfused": abs(Lf.item() - Lu.item()) / abs(Lu.item()),
+                 "grad_rel_diff_fused_vs_unfused": float(np.linalg.norm(Gf - Gu) / np.linalg.norm(Gu))}
+
     # roofline of the dominant kernel (the longer of the forward and adjoint kernels)
     def roof(kernel, ms, flop):
         achieved = flop * nf * nq / (ms * 1e-3) / 1e12
@@ -377,6 +419,7 @@ def main():
         "polygon_faces": poly,
         "grad_q": gradq,
         "regions": regions,
+        "intensity_loss": lossf,
     }
     print(json.dumps(line), flush=True)
 

@@ -33,7 +33,10 @@
  *  - NaN / Inf in inputs propagate to the affected outputs.
  *  - Triangle indices outside [0, nv) never cause an out-of-bounds access: the
  *    face is treated as empty (contributes zero) and counted; use
- *    pft_validate_mesh to check a mesh.
+ *    pft_validate_mesh to check a mesh. With PFT_VALIDATE=1 in the environment
+ *    (read at each call), pft_forward_3d, pft_backward_3d, pft_intensity_loss_3d,
+ *    pft_orientation_average and the region entry points count such indices
+ *    on the device first (a synchronous check) and return PFT_EINVAL if any.
  *  - Results do not depend on the order of faces in the list except through
  *    floating-point rounding, and are bitwise reproducible for fixed inputs
  *    and sizes (fixed reduction order, no floating-point atomics).
@@ -174,6 +177,29 @@ pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t 
 pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                            const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
                            void* grad_verts, void* stream);
+
+/*
+ * pft_intensity_loss_3d -- the intensity loss
+ *     L = sum_Q w(Q) (|F(Q)|^2 - I(Q))^2
+ * and its vertex gradient in one call: the forward of pft_forward_3d, the
+ * cotangent dL/dRe F + i dL/dIm F = 4 w (|F|^2 - I) F formed on the device in
+ * binary64 as the partial sums are finished, and the adjoint of
+ * pft_backward_3d, sharing one set of face records and one Q order. For
+ * fitting a mesh to a measured intensity (the scattering use of the
+ * transform); the paper gives the forward only.
+ *
+ *  Mesh, q and mode arguments as in pft_forward_3d.
+ *  weight      NULL (w = 1) or [nq] float64 (DEVICE).
+ *  target      [nq] float64 I(Q) (DEVICE).
+ *  loss        DEVICE float64 scalar, overwritten with L (summed in binary64
+ *              in a fixed order).
+ *  out         NULL or [nq] complex F(Q) (complex128 for PFT_FP64, complex64 for PFT_FP32C).
+ *  grad_verts  NULL or [nv][3] of vdtype, OVERWRITTEN with dL/dv.
+ * Errors: as pft_forward_3d; EINVAL also for loss NULL, or target NULL with nq > 0.
+ */
+pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                 const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const double* weight,
+                                 const double* target, double* loss, void* out, void* grad_verts, void* stream);
 
 /*
  * pft_forward_3d_regions -- F(Q) of a density that is constant on each of

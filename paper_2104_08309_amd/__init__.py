@@ -8,9 +8,11 @@ declared in include/pft.h. This package is the thin Python binding.
 """
 from .api import (  # noqa: F401
     forward_2d, forward_3d, forward_3d_poly, backward_3d, batch_forward, batch_backward, orientation_average,
-    forward_3d_regions, backward_3d_regions, validate_mesh,
+    forward_3d_regions, backward_3d_regions, intensity_loss_3d, validate_mesh,
     profile_enable, profile_reset, profile_read, release_workspace, version,
 )
-from .autograd import PftFunction, PftRegionsFunction, ft3d, ft3d_regions, intensity_loss  # noqa: F401
+from .autograd import (  # noqa: F401
+    IntensityLossFunction, PftFunction, PftRegionsFunction, ft3d, ft3d_regions, fused_intensity_loss, intensity_loss,
+)
 
 __version__ = "0.1.0"

@@ -18,7 +18,7 @@ from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
 
 __all__ = [
     "forward_2d", "forward_3d", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
-    "orientation_average", "forward_3d_regions", "backward_3d_regions",
+    "orientation_average", "forward_3d_regions", "backward_3d_regions", "intensity_loss_3d",
     "validate_mesh",
     "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
 ]
@@ -199,6 +199,39 @@ def backward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, grad_o
                                           tris.shape[0], _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(g),
                                           _ptr(grad), _stream(verts.device)))
     return grad
+
+
+def intensity_loss_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, target: torch.Tensor,
+                      weight: Optional[torch.Tensor] = None, mode: str = "fp32c", need_grad: bool = True,
+                      return_F: bool = False):
+    """L = sum_Q w (|F|^2 - I)^2 and dL/dverts in one library call (forward, cotangent and adjoint
+    sharing the face records and the Q order). ``target`` and ``weight`` are float64 [nq] on the
+    device (weight None: w = 1). Returns (L as a 0-dim float64 tensor, dL/dverts or None[, F]).
+    """
+    verts, tris = _mesh(verts, tris)
+    q = _qlist(q, verts.device)
+    m = mode_id(mode)
+    nq = q.shape[0]
+
+    def f64vec(t, name):
+        t = _on_gpu(t, name).reshape(-1)
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64, got {t.dtype}")
+        if t.shape[0] != nq or t.device != verts.device:
+            raise ValueError(f"{name} must have one entry per Q on the mesh's device")
+        return t.contiguous()
+    target = f64vec(target, "target")
+    weight = None if weight is None else f64vec(weight, "weight")
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    loss = torch.empty((), dtype=torch.float64, device=verts.device)
+    F = torch.empty(nq, dtype=cdt, device=verts.device) if return_F else None
+    gv = torch.empty_like(verts) if need_grad else None
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_intensity_loss_3d(
+            _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(q),
+            _real_dtype_id(q, "q"), nq, m, _ptr(weight), _ptr(target), loss.data_ptr(), _ptr(F), _ptr(gv),
+            _stream(verts.device)))
+    return (loss, gv, F) if return_F else (loss, gv)
 
 
 def _regions(region_offsets, nf: int, rho: torch.Tensor, device):

@@ -62,6 +62,31 @@ def ft3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: str = "
     return PftFunction.apply(verts, tris, q, mode)
 
 
+class IntensityLossFunction(torch.autograd.Function):
+    """L = sum_Q w (|F|^2 - I)^2 as a function of the vertices, with dL/dverts computed by the fused
+    library call in the forward pass and scaled by the incoming gradient in the backward pass."""
+
+    @staticmethod
+    def forward(ctx, verts, tris, q, target, weight, mode="fp32c"):
+        loss, gv = api.intensity_loss_3d(verts, tris, q, target, weight, mode=mode,
+                                         need_grad=ctx.needs_input_grad[0])
+        ctx.save_for_backward(gv if gv is not None else torch.empty(0, device=verts.device))
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        (gv,) = ctx.saved_tensors
+        if gv.numel() == 0:
+            return None, None, None, None, None, None
+        return grad_loss.to(gv.dtype) * gv, None, None, None, None, None
+
+
+def fused_intensity_loss(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, target: torch.Tensor,
+                         weight=None, mode: str = "fp32c") -> torch.Tensor:
+    """Differentiable sum_Q w (|F|^2 - I)^2 of a closed mesh (one fused library call per evaluation)."""
+    return IntensityLossFunction.apply(verts, tris, q, target, weight, mode)
+
+
 def ft3d_regions(verts: torch.Tensor, tris: torch.Tensor, region_offsets, rho: torch.Tensor, q: torch.Tensor,
                  mode: str = "fp32c") -> torch.Tensor:
     """Differentiable F(Q) of a piecewise-constant density over closed regions."""

@@ -315,6 +315,21 @@ __device__ __forceinline__ double wave_total(double v) {
   return v;
 }
 
+// Sum over a block of NT threads in binary64 and a fixed order; every thread
+// must call it and every thread gets the total. lds holds NT / 64 doubles.
+template <int NT>
+__device__ __forceinline__ double block_total(double v, double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_total(v);
+  __syncthreads();
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) t += lds[w];
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // binary64 adjoint, one block's share: `nt` face records in LDS (with their
 // edge Gram matrices) against the reordered Q records [qb, qe), kQPTB Q per

@@ -5,6 +5,7 @@
 // enqueues the prologue / compute / finish kernels on that stream and returns.
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -140,6 +141,24 @@ int num_cus() {
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
+// With PFT_VALIDATE=1 in the environment, the single-mesh triangle entry points
+// also count out-of-range triangle indices on the device before any work (a
+// synchronous check) and return EINVAL if there are any; otherwise such faces
+// are empty.
+bool strict_validation() {
+  const char* e = std::getenv("PFT_VALIDATE");
+  return e != nullptr && e[0] == '1';
+}
+
+pft_status strict_tris(const int32_t* tris, int64_t nf, int64_t nv, void* stream) {
+  if (!strict_validation() || nf == 0) return PFT_OK;
+  int64_t bad = 0;
+  pft_status st = pft_validate_mesh(tris, nf, nv, &bad, nullptr, stream);
+  if (st != PFT_OK) return st;
+  if (bad > 0) return fail(PFT_EINVAL, std::to_string(bad) + " triangle indices out of range (PFT_VALIDATE=1)");
+  return PFT_OK;
+}
+
 pft_status check_mesh_args(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                            const void* q, int qdtype, int64_t nq, int mode) {
   if (mode != PFT_FP64 && mode != PFT_FP32C) return fail(PFT_EUNSUPPORTED, "unknown mode");
@@ -214,14 +233,12 @@ pft_status build_qorder(Arena& ar, const void* q, int qdtype, int64_t nq, const 
 
 // The adjoint's Q records: Q in visiting order with their centred cotangents
 // (binary32 records for FP32C, binary64 records for FP64; the other is NULL).
-pft_status build_qrecs(Arena& ar, int mode, const void* q, int qdtype, const void* grad_out, int64_t nq,
-                       const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, QRec32** rec,
-                       QRec64** rec64, hipStream_t s) {
+// The same records for a visiting order already built (perm NULL: the caller's order).
+pft_status qrecs_from_perm(Arena& ar, int mode, const void* q, int qdtype, const void* grad_out, int64_t nq,
+                           const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, uint32_t* perm,
+                           QRec32** rec, QRec64** rec64, hipStream_t s) {
   *rec = nullptr;
   *rec64 = nullptr;
-  uint32_t* perm = nullptr;
-  pft_status st = build_qorder(ar, q, qdtype, nq, d_q_off, n_meshes, &perm, s);
-  if (st != PFT_OK) return st;
   if (!perm) {  // identity order
     perm = ar.get<uint32_t>(nq);
     if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
@@ -239,6 +256,15 @@ pft_status build_qrecs(Arena& ar, int mode, const void* q, int qdtype, const voi
     e = launch_qrec32_gather(q, qdtype, grad_out, nq, perm, info, d_q_off, n_meshes, *rec, s);
   }
   return e == hipSuccess ? PFT_OK : hip_fail(e, "Q records");
+}
+
+pft_status build_qrecs(Arena& ar, int mode, const void* q, int qdtype, const void* grad_out, int64_t nq,
+                       const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, QRec32** rec,
+                       QRec64** rec64, hipStream_t s) {
+  uint32_t* perm = nullptr;
+  pft_status st = build_qorder(ar, q, qdtype, nq, d_q_off, n_meshes, &perm, s);
+  if (st != PFT_OK) return st;
+  return qrecs_from_perm(ar, mode, q, qdtype, grad_out, nq, info, d_q_off, n_meshes, perm, rec, rec64, s);
 }
 
 // Shared tail of the adjoint: per-corner vectors -> sorted incidence -> vertex gather.
@@ -538,6 +564,7 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
   if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
   if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
   if (nq == 0) return PFT_OK;
+  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   Arena ar(s);
@@ -649,6 +676,7 @@ pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t 
   if (ndir > 0 && nqa > INT64_MAX / 3 / ndir) return fail(PFT_EINVAL, "nqa * ndir too large");
   if (nqa > INT32_MAX) return fail(PFT_EINVAL, "too many magnitudes");
   if (nqa == 0) return PFT_OK;
+  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   if (ndir == 0) {  // empty quadrature: the sum is 0
@@ -682,6 +710,7 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   if (grad_out && !aligned(grad_out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "grad_out misaligned");
   if (grad_verts && !aligned(grad_verts, real_size(vdtype))) return fail(PFT_EINVAL, "grad_verts misaligned");
   if (nv == 0) return PFT_OK;
+  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   if (nq == 0 || nf == 0) {
@@ -731,6 +760,109 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   return gather_tail(ar, tris, nf, nullptr, nullptr, nv, contrib, grad_verts, vdtype, s);
 }
 
+pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                 const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const double* weight,
+                                 const double* target, double* loss, void* out, void* grad_verts, void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  if (loss == nullptr) return fail(PFT_EINVAL, "loss is NULL");
+  if (nq > 0 && target == nullptr) return fail(PFT_EINVAL, "target is NULL");
+  if (!aligned(loss, 8) || (target && !aligned(target, 8)) || (weight && !aligned(weight, 8)))
+    return fail(PFT_EINVAL, "loss, target or weight misaligned");
+  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
+  if (grad_verts && !aligned(grad_verts, real_size(vdtype))) return fail(PFT_EINVAL, "grad_verts misaligned");
+  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  hipError_t e = hipSuccess;
+  if (nq == 0) {  // no Q: L = 0 and no gradient
+    e = zero_bytes(loss, sizeof(double), s);
+    if (e == hipSuccess && grad_verts && nv > 0) e = zero_bytes(grad_verts, (size_t)nv * 3 * real_size(vdtype), s);
+    return e == hipSuccess ? PFT_OK : hip_fail(e, "zero outputs");
+  }
+  Arena ar(s);
+  // shared prologue: one set of face records and one Q order for the forward and the adjoint
+  MeshInfo* info = ar.get<MeshInfo>(1);
+  Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
+  Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
+  int splits;
+  int64_t per;
+  choose_face_splits(nq, nf, c128 ? 1 : kQPT, &splits, &per);
+  double2* partial = ar.get<double2>((size_t)splits * nq);
+  QRec32* rec = c128 ? nullptr : ar.get<QRec32>(nq);
+  QRec64* rec64 = c128 ? ar.get<QRec64>(nq) : nullptr;
+  double* loss_part = ar.get<double>(loss_blocks(nq));
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
+  // binary64 records with the binary64 series threshold (the FP32C forward takes its own from Face32)
+  if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, kTauF64, f64, s);
+  if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
+  if (e != hipSuccess) return hip_fail(e, "loss prologue");
+  uint32_t* perm = nullptr;
+  if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
+  FwdArgs a;
+  a.f64 = f64;
+  a.f32 = f32;
+  a.info = info;
+  a.nf = nf;
+  a.q = q;
+  a.qdtype = qdtype;
+  a.nq = nq;
+  a.perm = perm;
+  a.splits = splits;
+  a.faces_per_split = per;
+  a.split_face = nullptr;
+  a.partial = partial;
+  a.out = out;
+  a.intensity = nullptr;
+  a.tau0 = c128 ? kTau0F64 : kTau0F32;
+  const char* nm = main_name(true, mode);
+  prof_begin(nm, s);
+  e = c128 ? launch_fwd3d_fp64(a, s) : launch_fwd3d_fp32c(a, s);
+  prof_end(nm, s);
+  if (e != hipSuccess) return hip_fail(e, "3D transform");
+  e = launch_loss_finish(a, weight, target, c128 ? 1 : 0, rec, rec64, loss_part, loss, s);
+  if (e != hipSuccess) return hip_fail(e, "loss finish");
+  if (!grad_verts || nv == 0) return PFT_OK;
+  if (nf == 0) {
+    e = zero_bytes(grad_verts, (size_t)nv * 3 * real_size(vdtype), s);
+    return e == hipSuccess ? PFT_OK : hip_fail(e, "zero grad");
+  }
+  Face32B* f32b = c128 ? nullptr : ar.get<Face32B>(nf);
+  double* gram = c128 ? ar.get<double>((size_t)nf * 8) : nullptr;
+  int qs;
+  int64_t qper;
+  choose_q_splits(nq, nf, c128 ? kTileFB : kTileFB32, &qs, &qper);
+  double* bpart = ar.get<double>((size_t)qs * nf * 3);
+  double* contrib = ar.get<double>((size_t)nf * 9);
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  e = c128 ? launch_gram64(f64, nf, gram, s) : launch_face32b(f64, nf, kTauB32, kTauRelB32, f32b, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint prologue");
+  BwdArgs b;
+  b.info = info;
+  b.f64 = f64;
+  b.f32 = f32b;
+  b.nf = nf;
+  b.q = q;
+  b.qdtype = qdtype;
+  b.nq = nq;
+  b.grad_out = nullptr;
+  b.rec = rec;
+  b.rec64 = rec64;
+  b.qsplits = qs;
+  b.q_per_split = qper;
+  b.partial = bpart;
+  nm = main_name(false, mode);
+  prof_begin(nm, s);
+  e = c128 ? launch_bwd3d_fp64(b, gram, s) : launch_bwd3d_fp32c(b, s);
+  prof_end(nm, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint");
+  e = launch_bwd_face_contrib(bpart, qs, f64, nullptr, nf, contrib, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint reduce");
+  return gather_tail(ar, tris, nf, nullptr, nullptr, nv, contrib, grad_verts, vdtype, s);
+}
+
 pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                   const int64_t* region_offsets, int64_t nreg, const double* rho, const void* q,
                                   pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* out_regions,
@@ -744,6 +876,7 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   if (out_regions && !aligned(out_regions, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out_regions misaligned");
   if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
   if (nq == 0) return PFT_OK;
+  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   Arena ar(s);
@@ -811,6 +944,7 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
   const bool want_r = grad_rho != nullptr && nreg > 0;
   const bool want_q = grad_q != nullptr && nq > 0;
   if (!want_v && !want_r && !want_q) return PFT_OK;
+  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   hipError_t e = hipSuccess;
@@ -836,6 +970,9 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
     e = c128 ? launch_gram64(f64, nf, gram, s) : launch_face32b(f64, nf, kTauB32, kTauRelB32, f32b, s);
     if (e != hipSuccess) return hip_fail(e, "regions prologue");
   }
+  // one visiting order of Q for every part below
+  uint32_t* perm = nullptr;
+  if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
   // dL/dv: the vertex adjoint with each face's partial weighted by its region's density
   if (want_v) {
     int64_t* d_off = nullptr;
@@ -852,7 +989,8 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
     if (e != hipSuccess) return hip_fail(e, "face weights");
     QRec32* rec = nullptr;
     QRec64* rec64 = nullptr;
-    if ((st = build_qrecs(ar, mode, q, qdtype, grad_out, nq, info, nullptr, 1, &rec, &rec64, s)) != PFT_OK) return st;
+    if ((st = qrecs_from_perm(ar, mode, q, qdtype, grad_out, nq, info, nullptr, 1, perm, &rec, &rec64, s)) != PFT_OK)
+      return st;
     BwdArgs b;
     b.info = info;
     b.f64 = f64;
@@ -877,8 +1015,6 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
     if ((st = gather_tail(ar, tris, nf, nullptr, nullptr, nv, contrib, grad_verts, vdtype, s)) != PFT_OK) return st;
   }
   if (!want_r && !want_q) return PFT_OK;
-  uint32_t* perm = nullptr;
-  if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
   const int64_t nblocks = finish_blocks(nq);
   double* rho_part = want_r ? ar.get<double>((size_t)nblocks * nreg) : nullptr;
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");

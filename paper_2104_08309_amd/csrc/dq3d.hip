@@ -157,19 +157,6 @@ __global__ __launch_bounds__(kBlock) void dq3d_fp32c_kernel(DqArgs a) {
 // ---------------------------------------------------------------------------
 // finish kernels
 // ---------------------------------------------------------------------------
-// Sum over the block in binary64 and a fixed order (every thread must call it).
-__device__ __forceinline__ double block_total(double v, double* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v = wave_total(v);
-  __syncthreads();
-  if (lane == 0) lds[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < kFinishBlock / 64; ++w) t += lds[w];
-  return t;
-}
-
 __device__ __forceinline__ double2 load_cot(const void* g, int c128, int64_t i) {
   if (c128) return static_cast<const double2*>(g)[i];
   const float2 v = static_cast<const float2*>(g)[i];
@@ -215,7 +202,7 @@ __global__ __launch_bounds__(kFinishBlock) void regions_finish_kernel(FwdArgs a,
     Fr += rho * fr;
     Fi += rho * fi;
     if (r.rho_part) {
-      const double t = block_total(g.x * fr + g.y * fi, lds);  // Re(conj(g) F_j)
+      const double t = block_total<kFinishBlock>(g.x * fr + g.y * fi, lds);  // Re(conj(g) F_j)
       if (threadIdx.x == 0) r.rho_part[(int64_t)blockIdx.x * r.nreg + j] = t;
     }
   }
@@ -279,7 +266,7 @@ __global__ __launch_bounds__(kFinishBlock) void dq_finish_kernel(DqArgs a, Regio
     }
     if (r.rho_part) {
       const double fr = ct * fcr - st * fci, fi = ct * fci + st * fcr;
-      const double t = block_total(g.x * fr + g.y * fi, lds);
+      const double t = block_total<kFinishBlock>(g.x * fr + g.y * fi, lds);
       if (threadIdx.x == 0) r.rho_part[(int64_t)blockIdx.x * r.nreg + j] = t;
     }
   }
@@ -299,7 +286,7 @@ __global__ __launch_bounds__(kFinishBlock) void rho_reduce_kernel(const double* 
   const int j = blockIdx.x;
   double v = 0.0;
   for (int64_t b = threadIdx.x; b < nblocks; b += kFinishBlock) v += part[b * nreg + j];
-  v = block_total(v, lds);
+  v = block_total<kFinishBlock>(v, lds);
   if (threadIdx.x == 0) out[j] = v;
 }
 

@@ -48,7 +48,10 @@ constexpr double kTauB32 = 1.5;      // (record field of the FP32C adjoint; empt
 // The adjoint evaluates each face's barycentric moments by their series when the
 // largest centred vertex phase |Q.(v_k - g)| is at most this, by the
 // differentiated edge sums otherwise (there |Q_perp| L > 4.5).
-constexpr double kSeriesMaxPhase = 3.0;
+#ifndef PFT_SERIES_MAX_PHASE
+#define PFT_SERIES_MAX_PHASE 3.0
+#endif
+constexpr double kSeriesMaxPhase = PFT_SERIES_MAX_PHASE;
 constexpr double kTauRelB32 = 0.05;  // adjoint, FP32C mode, relative test
 // Whole-mesh series (fan of tetrahedra from the vertex mean) when |Q| R < tau0.
 constexpr double kTau0F64 = 0.01;
@@ -272,6 +275,13 @@ int64_t finish_blocks(int64_t nq);
 // rho of the region owning each face (region offsets on the device).
 hipError_t launch_face_weights(const int64_t* d_region_off, int nreg, const double* rho, int64_t nf, double* w,
                                hipStream_t s);
+
+// loss.hip: L = sum_Q w (|F|^2 - I)^2 from the forward's partials (a.out and a.intensity
+// optional), the adjoint's Q records with the cotangent 4 w (|F|^2 - I) F_c (rec for FP32C,
+// rec64 for FP64) in the visiting order, per-block loss sums and their fixed-order total.
+int64_t loss_blocks(int64_t nq);
+hipError_t launch_loss_finish(const FwdArgs& a, const double* weight, const double* target, int c128, QRec32* rec,
+                              QRec64* rec64, double* loss_part /*[loss_blocks(nq)]*/, double* loss, hipStream_t s);
 
 // grad_Q F (dq3d.hip): per Q, the face sums A = sum_m (Q.N_m) e^{iQ.g_m} (sum over corners of
 // (v_k - t) times the normalised barycentric moments) and B = sum_m (Q.N_m) e^{iQ.g_m} J_m/2A,

@@ -150,6 +150,22 @@ def test_regions_validation(lib):
     assert b(*bargs()) == _lib.PFT_OK  # nothing asked for: no work
 
 
+def test_intensity_loss_validation(lib):
+    good = 0x10000
+    f = lib.pft_intensity_loss_3d
+    # verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, weight, target, loss, out, grad_verts, stream
+    a = lambda w=None, tg=V(good), loss=V(good), out=None, gv=V(good), nq=4, mode=1: (
+        V(good), 1, 8, V(good), 12, V(good), 1, nq, mode, w, tg, loss, out, gv, None)
+    assert f(*a(loss=None)) == _lib.PFT_EINVAL
+    assert b"loss is NULL" in lib.pft_last_error()
+    assert f(*a(tg=None)) == _lib.PFT_EINVAL
+    assert f(*a(w=V(good + 4))) == _lib.PFT_EINVAL
+    assert f(*a(out=V(good + 8), mode=0)) == _lib.PFT_EINVAL  # complex128 (PFT_FP64) needs 16 bytes
+    assert f(*a(gv=V(good + 4))) == _lib.PFT_EINVAL
+    assert f(*a(mode=5)) == _lib.PFT_EUNSUPPORTED
+    assert f(*a(nq=-1)) == _lib.PFT_EINVAL
+
+
 def test_forward_2d_validation(lib):
     good = 0x10000
     f = lib.pft_forward_2d

@@ -6,6 +6,7 @@ import torch
 import meshgen as mg
 import oracle as O
 import paper_2104_08309_amd as pft
+from paper_2104_08309_amd import _lib
 from gpu_util import TOL_FP32C, TOL_FP64, dev, host, maxrel, nrel, special_q, step
 
 pytestmark = pytest.mark.gpu
@@ -88,6 +89,30 @@ def test_empty_and_degenerate_meshes(gpu):
     step("validate_mesh")
     bad, rep = pft.validate_mesh(dev(t2, torch.int32), v2.shape[0])
     assert bad == 1 and rep == 3
+
+
+def test_strict_index_validation(gpu, monkeypatch):
+    """With PFT_VALIDATE=1 an out-of-range triangle index is an argument error (checked on the
+    device before any work) in the forward, the adjoint and the region entry points."""
+    v, t = mg.box(1.0, 1.0, 1.0)
+    t2 = np.concatenate([t, [[0, 1, 99]]]).astype(np.int32)
+    q = mg.q_random_ball(50, 2.0, np.random.default_rng(5))
+    V, T2, Q = dev(v), dev(t2, torch.int32), dev(q)
+    g = torch.ones(len(q), dtype=torch.complex128, device="cuda:0")
+    one = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    monkeypatch.setenv("PFT_VALIDATE", "1")
+    step("PFT_VALIDATE=1 rejects a bad index")
+    for call in (lambda: pft.forward_3d(V, T2, Q, mode="fp64"),
+                 lambda: pft.backward_3d(V, T2, Q, g, mode="fp64"),
+                 lambda: pft.forward_3d_regions(V, T2, [0, len(t2)], one, Q, mode="fp64"),
+                 lambda: pft.backward_3d_regions(V, T2, [0, len(t2)], one, Q, g, mode="fp64")):
+        with pytest.raises(_lib.PftError, match="out of range"):
+            call()
+    step("PFT_VALIDATE=1 accepts a valid mesh")
+    assert nrel(host(pft.forward_3d(V, dev(t, torch.int32), Q, mode="fp64")), O.ft3d(v, t, q)) < TOL_FP64
+    monkeypatch.delenv("PFT_VALIDATE")
+    step("without PFT_VALIDATE the bad face is empty")
+    assert nrel(host(pft.forward_3d(V, T2, Q, mode="fp64")), O.ft3d(v, t, q)) < TOL_FP64
 
 
 def test_empty_q_list(gpu):
