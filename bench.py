@@ -119,8 +119,8 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the transform shards by Q across GPUs "
-              f"but this build runs and reports a single MI355X.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the transform would shard by Q across "
+              f"GPUs, but only the single-MI355X path is implemented and reported.", file=sys.stderr)
         sys.exit(2)
 
     import torch
