@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--no-orient", action="store_true", help="skip the orientation-average measurement")
     ap.add_argument("--no-poly", action="store_true", help="skip the polygon-face measurement")
     ap.add_argument("--no-loss", action="store_true", help="skip the fused intensity-loss measurement (config 4)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched (config 5) and 2D (config 1) measurements")
     ap.add_argument("--no-regions", action="store_true",
                     help="skip the grad_Q and multi-region (piecewise-constant density) measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -361,6 +362,67 @@ def main():
                  "loss_rel_diff_fused_vs_unfused": abs(Lf.item() - Lu.item()) / abs(Lu.item()),
                  "grad_rel_diff_fused_vs_unfused": float(np.linalg.norm(Gf - Gu) / np.linalg.norm(Gu))}
 
+    # config 5 (512 uneven meshes, one persistent launch each way) and config 1 (the 2D path, binary64)
+    batch = fwd2d = None
+    if not args.no_batch:
+        print("[bench] batch (config 5) and 2D (config 1)", file=sys.stderr, flush=True)
+        meshes = mg.config5()
+        vo, to, qo = [0], [0], [0]
+        for m in meshes:
+            vo.append(vo[-1] + len(m["verts"]))
+            to.append(to[-1] + len(m["tris"]))
+            qo.append(qo[-1] + len(m["q"]))
+        BV = torch.tensor(np.concatenate([m["verts"] for m in meshes]), dtype=torch.float32, device=dev)
+        BT = torch.tensor(np.concatenate([m["tris"] for m in meshes]), dtype=torch.int32, device=dev)
+        BQ = torch.tensor(np.concatenate([m["q"] for m in meshes]), dtype=torch.float32, device=dev)
+        brng = np.random.default_rng(5)
+        bg = (brng.normal(size=qo[-1]) + 1j * brng.normal(size=qo[-1])) / qo[-1]
+        BG = torch.tensor(bg.astype(np.complex64), device=dev)
+        pairs = sum(len(m["tris"]) * len(m["q"]) for m in meshes)
+
+        def bstep():
+            return (pft.batch_forward(BV, BT, BQ, vo, to, qo, mode="fp32c"),
+                    pft.batch_backward(BV, BT, BQ, vo, to, qo, BG, mode="fp32c"))
+
+        b_steps = max(2, args.steps // 8)
+        tb5, (BF, BD) = timed(bstep, b_steps, 1)
+        n_bf, ms_bf = pft.profile_read("batch_fwd")
+        n_bb, ms_bb = pft.profile_read("batch_bwd")
+        ms_bf, ms_bb = ms_bf / max(n_bf, 1), ms_bb / max(n_bb, 1)
+        batch = {"workload": f"config 5: {len(meshes)} meshes, {to[-1]} faces, {qo[-1]} Q, {pairs:.3e} face*Q "
+                             f"(each mesh its own Q list), FP32C forward + adjoint, one persistent launch each",
+                 "ms_per_step": tb5 * 1e3, "face_q_per_s": pairs / tb5,
+                 "forward_kernel_ms": ms_bf, "adjoint_kernel_ms": ms_bb,
+                 "forward_alu_frac": FLOP_FWD * pairs / (ms_bf * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                 "adjoint_alu_frac": FLOP_BWD * pairs / (ms_bb * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+        c1 = mg.config1()
+        P2 = torch.tensor(c1["verts"], device=dev)
+        Q2d = torch.tensor(c1["q"], device=dev)
+        t2, F2 = timed(lambda: pft.forward_2d(P2, Q2d), max(10, args.steps), 2)
+        n_2, ms_2 = pft.profile_read("fwd2d_fp64")
+        ne, nq2 = c1["verts"].shape[0], c1["q"].shape[0]
+        fwd2d = {"workload": f"config 1: star polygon, {ne} edges x {nq2} Q (128^2 grid over [-20,20)^2), binary64",
+                 "ms_per_call": t2 * 1e3, "kernel_ms": ms_2 / max(n_2, 1), "edge_q_per_s": ne * nq2 / t2}
+        if not args.no_cpu_baseline:
+            import oracle as O
+            F2o = O.ft2d(c1["verts"], c1["q"])
+            fwd2d["rel_err_vs_oracle"] = float(np.linalg.norm(F2.cpu().numpy() - F2o) / np.linalg.norm(F2o))
+            # the four meshes with the least work, every Q: forward and adjoint against the oracle
+            order = np.argsort([len(m["tris"]) * len(m["q"]) for m in meshes])[:4]
+            BFh = BF.cpu().numpy().astype(np.complex128)
+            BDh = BD.cpu().numpy().astype(np.float64)
+            ef, eb = [], []
+            for i in order:
+                m = meshes[i]
+                vm = m["verts"].astype(np.float32).astype(np.float64)
+                qm = m["q"].astype(np.float32).astype(np.float64)
+                Fo = O.ft3d(vm, m["tris"], qm)
+                ef.append(float(np.linalg.norm(BFh[qo[i]:qo[i + 1]] - Fo) / np.linalg.norm(Fo)))
+                Go = O.grad3d(vm, m["tris"], qm, bg.astype(np.complex64)[qo[i]:qo[i + 1]])
+                eb.append(float(np.linalg.norm(BDh[vo[i]:vo[i + 1]] - Go) / np.linalg.norm(Go)))
+            batch["forward_rel_err_vs_oracle_4_meshes"] = max(ef)
+            batch["adjoint_rel_err_vs_oracle_4_meshes"] = max(eb)
+
     # roofline of the dominant kernel (the longer of the forward and adjoint kernels)
     def roof(kernel, ms, flop):
         achieved = flop * nf * nq / (ms * 1e-3) / 1e12
@@ -420,6 +482,8 @@ def main():
         "grad_q": gradq,
         "regions": regions,
         "intensity_loss": lossf,
+        "batch": batch,
+        "forward_2d": fwd2d,
     }
     print(json.dumps(line), flush=True)
 
