@@ -293,7 +293,7 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
     // barycentric moments by their series in binary32 (terms decrease from the
     // start for |delta| <= 3; no cancellation with the face's size in Q)
     float yr[2], yi[2], jr, ji;
-    bary_moments<float, 29>(q0, q1, m, 1e-8f, yr, yi, jr, ji);
+    bary_moments<float, 29>(q0, q1, m, kSeriesTol32, yr, yi, jr, ji);
     R[0] = zr * yr[0] - zi * yi[0];
     R[1] = zr * yr[1] - zi * yi[1];
     R[2] = (zr * jr - zi * ji) - R[0] - R[1];

@@ -52,6 +52,13 @@ constexpr double kTauB32 = 1.5;      // (record field of the FP32C adjoint; empt
 #define PFT_SERIES_MAX_PHASE 3.0
 #endif
 constexpr double kSeriesMaxPhase = PFT_SERIES_MAX_PHASE;
+// Truncation bound of that binary32 series: terms stop once m^n / n! < tol, which
+// bounds the next term by tol / 6, about 1e-7 of sums of order 1/6 (binary32
+// resolution; a tighter bound only adds terms).
+#ifndef PFT_SERIES_TOL32
+#define PFT_SERIES_TOL32 1e-7f
+#endif
+constexpr float kSeriesTol32 = PFT_SERIES_TOL32;
 constexpr double kTauRelB32 = 0.05;  // adjoint, FP32C mode, relative test
 // Whole-mesh series (fan of tetrahedra from the vertex mean) when |Q| R < tau0.
 constexpr double kTau0F64 = 0.01;
