@@ -160,9 +160,32 @@ def _pin_regions_core_shell(O):
     return _rel(F, want)
 
 
+def _pin_poly_prism(O):
+    # a prism over a non-convex polygon whose first three vertices turn clockwise (a reflex vertex at
+    # index 1): polygon faces against the 2D transform times the axial integral, including Q along
+    # the axis (the caps' series branch) and in the plane
+    poly = np.array([[0.0, 0.0], [1.0, 0.4], [2.0, 0.0], [2.0, 2.0], [0.0, 2.0]]) + np.array([0.3, -0.2])
+    h, z0 = 1.3, -0.4
+    v, f = mg.prism_polygon(poly, h, z0)
+    q = np.array([[1.1, -0.7, 0.9], [0.0, 0.0, 1.7], [2.3, 0.4, 0.0], [-0.5, 1.9, -1.2]])
+    F2 = O.ft2d(poly, q[:, :2])
+    ax = np.array([h if Q == 0.0 else (np.exp(1j * Q * (z0 + h)) - np.exp(1j * Q * z0)) / (1j * Q) for Q in q[:, 2]])
+    return _rel(O.ft3d_poly(v, f, q), F2 * ax)
+
+
+def _pin_orient_box(O):
+    # the direction quadrature applied to the box's separable closed form
+    a, b, c, o = 1.3, 0.7, 1.1, (0.2, -0.4, 0.3)
+    v, t = mg.box(a, b, c, origin=o)
+    d, w = mg.sphere_quadrature(5, 10)
+    qabs = np.array([0.0, 0.9, 2.5])
+    want = [float(np.sum(w * np.abs([_box_closed(a, b, c, o, qa * s) for s in d]) ** 2)) for qa in qabs]
+    return _rel(O.orientation_average(v, t, qabs, d, w), want)
+
+
 PINS = [_pin_rect_edges, _pin_rect_integral, _pin_polygon_quadrature, _pin_prism, _pin_box_axes_and_zero,
         _pin_tet_quadrature, _pin_tetfan, _pin_gradient, _pin_dq_box, _pin_dq_tet_quadrature,
-        _pin_regions_core_shell]
+        _pin_regions_core_shell, _pin_poly_prism, _pin_orient_box]
 TOL = {_pin_polygon_quadrature: 1e-9, _pin_tet_quadrature: 1e-9, _pin_dq_tet_quadrature: 1e-9}
 
 
@@ -232,6 +255,18 @@ MUTATIONS = [
     ("grad_Q: translation term sign", "return ph_t[:, None] * (gF + 1j * t[None, :] * Fc[:, None])",
      "return ph_t[:, None] * (gF - 1j * t[None, :] * Fc[:, None])"),
     ("regions: densities dropped", "return (rho[:, None] * Fj).sum(axis=0), Fj", "return Fj.sum(axis=0), Fj"),
+    ("polygon: edges traversed backwards", "P1 = np.roll(P, -1, axis=1)", "P1 = np.roll(P, 1, axis=1)"),
+    ("polygon: closing edge dropped", "            for l in range(nu):\n                nxd = np.cross(nhat, d[:, l, :])",
+     "            for l in range(nu - 1):\n                nxd = np.cross(nhat, d[:, l, :])"),
+    ("polygon: unsigned fan-triangle areas",
+     'two_a = np.einsum("ij,ij->i", np.cross(b - a, c - a), nhat[fi])   # signed 2 A_t',
+     "two_a = np.linalg.norm(np.cross(b - a, c - a), axis=1)"),
+    ("polygon: edge phase at the start vertex", "m = 0.5 * (P + P1)                                       # m_l",
+     "m = P"),
+    ("orientation: quadrature weights dropped", "out[i] = float(np.sum(weights * np.abs(F) ** 2))",
+     "out[i] = float(np.mean(np.abs(F) ** 2))"),
+    ("orientation: modulus not squared", "out[i] = float(np.sum(weights * np.abs(F) ** 2))",
+     "out[i] = float(np.sum(weights * np.abs(F)))"),
 ]
 
 
