@@ -115,6 +115,44 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
                           void* stream);
 
 /*
+ * pft_strip_order -- an edge-sharing order of a triangle mesh's faces (HOST
+ * function, no GPU work): consecutive faces share an edge wherever the greedy
+ * chains over the edge adjacency allow, each face's vertex list rotated
+ * cyclically (which keeps its orientation) so that its edge 0 (v0 -> v1) is
+ * the edge it shares with the previous face. For pft_forward_3d_ordered; the
+ * order depends only on the connectivity, so it is computed once per mesh.
+ *
+ *  tris   [nf][3] int32 (HOST).
+ *  order  [nf] int32 (HOST), written: a permutation of 0 .. nf-1.
+ *  meta   [nf] uint8 (HOST), written: rotation r (0..2) | link << 2, link = 0
+ *         (no shared edge with the previous face) or k = 1, 2 (this face's
+ *         edge 0 is edge k of the previous face, after that face's rotation).
+ *  Faces with an out-of-range or repeated index are placed with link 0.
+ * Errors: EINVAL for negative counts or NULL pointers with nf > 0.
+ */
+pft_status pft_strip_order(const int32_t* tris, int64_t nf, int64_t nv, int32_t* order, uint8_t* meta);
+
+/*
+ * pft_forward_3d_ordered -- pft_forward_3d with the faces taken in an
+ * edge-sharing order (pft_strip_order, copied to the device). The sum over
+ * faces is unchanged (eq. sum_elements_3d; only the rounding order differs);
+ * in the FP32-compensated form the term sinc(Q.d/2) exp(iQ.m) of an edge
+ * shared with the previous face is reused, so a face costs two edge terms
+ * instead of three.
+ *
+ *  Arguments as pft_forward_3d, plus
+ *  face_order  [nf] int32 (DEVICE), a permutation of 0 .. nf-1 (an entry out
+ *              of range makes that position an empty face);
+ *  face_meta   [nf] uint8 (DEVICE), as written by pft_strip_order. A wrong
+ *              link gives a wrong result, never an out-of-bounds access.
+ * Errors: as pft_forward_3d; EINVAL also for face_order or face_meta NULL with nf > 0.
+ */
+pft_status pft_forward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                  const int32_t* face_order, const uint8_t* face_meta, const void* q,
+                                  pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* intensity,
+                                  void* stream);
+
+/*
  * pft_forward_3d_poly -- F(Q) of the volume enclosed by planar polygon faces
  * (3D section: eq. sum_elements_3d with nu_m edges per face, evaluated natively:
  * nu edge terms per face).

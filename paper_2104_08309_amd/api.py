@@ -8,6 +8,7 @@ library's HIP kernels; there is no CPU path.
 from __future__ import annotations
 
 import ctypes
+import weakref
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -18,7 +19,7 @@ from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
 
 __all__ = [
     "forward_2d", "forward_3d", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
-    "orientation_average", "forward_3d_regions", "backward_3d_regions", "intensity_loss_3d",
+    "orientation_average", "forward_3d_regions", "backward_3d_regions", "intensity_loss_3d", "strip_order",
     "validate_mesh",
     "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
 ]
@@ -103,12 +104,50 @@ def forward_2d(verts: torch.Tensor, q: torch.Tensor, contour_offsets: Optional[S
     return out
 
 
+def strip_order(tris, nv: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Edge-sharing face order of a triangle mesh (pft_strip_order, host code): (order int32 [nf],
+    meta uint8 [nf]) for forward_3d's ``order``. ``tris`` may be a tensor (copied to the host)."""
+    t = tris.detach().cpu().numpy() if isinstance(tris, torch.Tensor) else np.asarray(tris)
+    t = np.ascontiguousarray(t, dtype=np.int32).reshape(-1, 3)
+    if nv is None:
+        nv = int(t.max()) + 1 if t.size else 0
+    order = np.empty(t.shape[0], dtype=np.int32)
+    meta = np.empty(t.shape[0], dtype=np.uint8)
+    check(_lib.load().pft_strip_order(t.ctypes.data, t.shape[0], nv, order.ctypes.data, meta.ctypes.data))
+    return order, meta
+
+
+# Edge-sharing orders of triangle tensors seen by forward_3d (order="auto"), keyed by the tensor
+# object (its id, confirmed through a weak reference) and checked against its storage, shape and
+# in-place version counter on every use.
+_ORDER_CACHE: dict = {}
+_AUTO_ORDER_MIN_FACES = 256
+
+
+def _auto_order(tris_key: torch.Tensor, tris: torch.Tensor, nv: int):
+    stamp = (tris_key.data_ptr(), tuple(tris_key.shape), tris_key._version, nv)
+    hit = _ORDER_CACHE.get(id(tris_key))
+    if hit is not None and hit[0]() is tris_key and hit[1] == stamp:
+        return hit[2]
+    order, meta = strip_order(tris, nv)
+    dev_order = (torch.from_numpy(order).to(tris.device), torch.from_numpy(meta).to(tris.device))
+    if len(_ORDER_CACHE) >= 64:  # drop the entries whose tensors are gone
+        for k in [k for k, e in _ORDER_CACHE.items() if e[0]() is None]:
+            del _ORDER_CACHE[k]
+    _ORDER_CACHE[id(tris_key)] = (weakref.ref(tris_key), stamp, dev_order)
+    return dev_order
+
+
 def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: str = "fp32c",
-               intensity: bool = False):
+               intensity: bool = False, order="auto"):
     """F(Q) of the closed mesh; complex128 for mode 'fp64', complex64 for 'fp32c'.
 
-    Returns F, or (F, |F|^2) when ``intensity`` is True.
+    Returns F, or (F, |F|^2) when ``intensity`` is True. ``order``: "auto" (FP32C meshes of 256 faces
+    or more are evaluated in an edge-sharing face order, computed on the host at the first call for
+    a triangle tensor and reused while it is unchanged), None (the list order), or a pair of device
+    tensors (order int32, meta uint8) from ``strip_order``.
     """
+    tris_key = tris
     verts, tris = _mesh(verts, tris)
     q = _qlist(q, verts.device)
     m = mode_id(mode)
@@ -116,10 +155,25 @@ def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: s
     rdt = torch.float64 if m == PFT_FP64 else torch.float32
     out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
     inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
+    if isinstance(order, str):
+        if order != "auto":
+            raise ValueError(f"order must be 'auto', None or (order, meta), got {order!r}")
+        use = m == PFT_FP32C and tris.shape[0] >= _AUTO_ORDER_MIN_FACES and isinstance(tris_key, torch.Tensor)
+        order = _auto_order(tris_key, tris, verts.shape[0]) if use else None
     with torch.cuda.device(verts.device):
-        check(_lib.load().pft_forward_3d(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris),
-                                         tris.shape[0], _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out),
-                                         _ptr(inten), _stream(verts.device)))
+        if order is None:
+            check(_lib.load().pft_forward_3d(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0],
+                                             _ptr(tris), tris.shape[0], _ptr(q), _real_dtype_id(q, "q"),
+                                             q.shape[0], m, _ptr(out), _ptr(inten), _stream(verts.device)))
+        else:
+            fo, fm = (_on_gpu(x, name) for x, name in zip(order, ("order", "meta")))
+            if fo.dtype != torch.int32 or fm.dtype != torch.uint8 or fo.numel() != tris.shape[0] \
+                    or fm.numel() != tris.shape[0]:
+                raise ValueError("order must be (int32 [nf], uint8 [nf]) device tensors")
+            check(_lib.load().pft_forward_3d_ordered(
+                _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(fo),
+                _ptr(fm), _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(inten),
+                _stream(verts.device)))
     return (out, inten) if intensity else out
 
 

@@ -459,7 +459,7 @@ namespace {
 // `out` may be NULL when only |F|^2 is wanted.
 pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                           const void* q, int qdtype, int64_t nq, int mode, void* out, void* intensity,
-                          hipStream_t s) {
+                          hipStream_t s, const int32_t* order = nullptr, const uint8_t* meta = nullptr) {
   const bool c128 = mode == PFT_FP64;
   pft_status st = PFT_OK;
   MeshInfo* info = ar.get<MeshInfo>(1);
@@ -471,7 +471,8 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   double2* partial = ar.get<double2>((size_t)splits * nq);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
   hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
-  if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, c128 ? kTauF64 : kTauF32, f64, s);
+  if (e == hipSuccess)
+    e = launch_face64(verts, vdtype, nv, tris, nf, info, c128 ? kTauF64 : kTauF32, f64, s, order, meta);
   if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
   if (e != hipSuccess) return hip_fail(e, "3D prologue");
   uint32_t* perm = nullptr;
@@ -492,6 +493,7 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   a.out = out;
   a.intensity = intensity;
   a.tau0 = c128 ? kTau0F64 : kTau0F32;
+  a.share_edges = (order != nullptr && !c128) ? 1 : 0;
   const char* nm = main_name(true, mode);
   prof_begin(nm, s);
   e = c128 ? launch_fwd3d_fp64(a, s) : launch_fwd3d_fp32c(a, s);
@@ -569,6 +571,96 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
   ensure_pool();
   Arena ar(s);
   return forward3d_core(ar, verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, out, intensity, s);
+}
+
+pft_status pft_forward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                  const int32_t* face_order, const uint8_t* face_meta, const void* q,
+                                  pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* intensity,
+                                  void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  if (nf > 0 && (face_order == nullptr || face_meta == nullptr)) return fail(PFT_EINVAL, "face_order or face_meta is NULL");
+  if (face_order && !aligned(face_order, 4)) return fail(PFT_EINVAL, "face_order misaligned");
+  if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
+  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
+  if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
+  if (nq == 0) return PFT_OK;
+  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  Arena ar(s);
+  return forward3d_core(ar, verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, out, intensity, s,
+                        nf > 0 ? face_order : nullptr, nf > 0 ? face_meta : nullptr);
+}
+
+pft_status pft_strip_order(const int32_t* tris, int64_t nf, int64_t nv, int32_t* order, uint8_t* meta) {
+  if (nf < 0 || nv < 0) return fail(PFT_EINVAL, "negative count");
+  if (nf > INT32_MAX / 3 || nv > INT32_MAX) return fail(PFT_EINVAL, "mesh too large for 32-bit indices");
+  if (nf > 0 && (tris == nullptr || order == nullptr || meta == nullptr))
+    return fail(PFT_EINVAL, "tris, order or meta is NULL");
+  if (nf == 0) return PFT_OK;
+  // half-edges of the valid faces keyed by their unordered vertex pair; faces that list the same
+  // pair (in either direction) share that edge
+  auto valid = [&](int64_t f) {
+    const int32_t a = tris[3 * f], b = tris[3 * f + 1], c = tris[3 * f + 2];
+    return a >= 0 && b >= 0 && c >= 0 && a < nv && b < nv && c < nv && a != b && b != c && c != a;
+  };
+  std::vector<std::pair<uint64_t, int64_t>> he;
+  he.reserve((size_t)nf * 3);
+  for (int64_t f = 0; f < nf; ++f) {
+    if (!valid(f)) continue;
+    for (int e = 0; e < 3; ++e) {
+      const uint64_t x = (uint32_t)tris[3 * f + e], y = (uint32_t)tris[3 * f + (e + 1) % 3];
+      he.emplace_back(x < y ? (x << 32) | y : (y << 32) | x, 3 * f + e);
+    }
+  }
+  std::sort(he.begin(), he.end());
+  // each half-edge points at another half-edge of the same pair (the next one, cyclically)
+  std::vector<int64_t> nbr((size_t)nf * 3, -1);
+  for (size_t i = 0; i < he.size();) {
+    size_t j = i;
+    while (j < he.size() && he[j].first == he[i].first) ++j;
+    if (j - i > 1)
+      for (size_t k = i; k < j; ++k) nbr[he[k].second] = he[k + 1 < j ? k + 1 : i].second;
+    i = j;
+  }
+  // greedy chains: from the last face placed, continue across its edge 1 or 2 (after its rotation) to a
+  // face not yet placed, rotated so that the shared edge becomes its edge 0
+  std::vector<char> placed((size_t)nf, 0);
+  int64_t n = 0;
+  for (int64_t f0 = 0; f0 < nf; ++f0) {
+    if (placed[f0]) continue;
+    int64_t cur = f0;
+    int rot = 0;
+    placed[cur] = 1;
+    order[n] = (int32_t)cur;
+    meta[n] = 0;
+    ++n;
+    for (;;) {
+      int64_t next = -1;
+      int nrot = 0, link = 0;
+      for (int k = 1; k <= 2 && next < 0; ++k) {
+        const int64_t slot = 3 * cur + (rot + k) % 3;
+        for (int64_t p = nbr[slot]; p >= 0 && p != slot; p = nbr[p]) {
+          if (!placed[p / 3]) {
+            next = p / 3;
+            nrot = (int)(p % 3);
+            link = k;
+            break;
+          }
+        }
+      }
+      if (next < 0) break;
+      placed[next] = 1;
+      order[n] = (int32_t)next;
+      meta[n] = (uint8_t)(nrot | (link << 2));
+      ++n;
+      cur = next;
+      rot = nrot;
+    }
+  }
+  return PFT_OK;
 }
 
 pft_status pft_forward_3d_poly(const void* verts, pft_dtype vdtype, int64_t nv, const int64_t* face_offsets,

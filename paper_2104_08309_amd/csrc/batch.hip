@@ -99,7 +99,9 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         float tr[kQPTBatch], ti[kQPTBatch];
 #pragma unroll
         for (int k = 0; k < kQPTBatch; ++k) tr[k] = ti[k] = 0.0f;
-        fwd_tile_fp32c<kQPTBatch>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti);
+        float E[kQPTBatch][4];
+        bool prev_ok = false;
+        fwd_tile_fp32c<kQPTBatch, false>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, E, prev_ok);
 #pragma unroll
         for (int k = 0; k < kQPTBatch; ++k) {
           kahan_add(sr[k], cr[k], tr[k]);

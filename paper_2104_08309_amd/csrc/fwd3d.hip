@@ -66,7 +66,10 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
 // Each thread evaluates kQPT Q points (strided by the block size, so loads stay
 // coalesced) against every face record it reads from LDS: the record is loaded
 // once per kQPT terms and the kQPT evaluations are independent instruction
-// streams the scheduler can interleave.
+// streams the scheduler can interleave. SHARE: the records are in an
+// edge-sharing order and each face takes one edge term from its predecessor in
+// the split (two edge terms per face instead of three).
+template <bool SHARE>
 __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
   __shared__ Face32 tile[kTileF];
   const int64_t qbase = (int64_t)blockIdx.x * (kBlock * kQPT) + threadIdx.x;
@@ -95,6 +98,8 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
   double xr[kQPT], xi[kQPT];
 #pragma unroll
   for (int k = 0; k < kQPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
+  float E[kQPT][4];      // edge terms carried from the previous face (SHARE)
+  bool prev_ok = false;  // no previous face at the start of the split
   for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
     const int nt = (int)min((int64_t)kTileF, f_end - t0);
     __syncthreads();
@@ -107,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
     float tr[kQPT], ti[kQPT];
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
-    fwd_tile_fp32c<kQPT>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti);
+    fwd_tile_fp32c<kQPT, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, E, prev_ok);
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) {
       kahan_add(sr[k], cr[k], tr[k]);
@@ -174,7 +179,10 @@ hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s) {
 
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s) {
   dim3 grid((unsigned)((a.nq + kBlock * kQPT - 1) / (kBlock * kQPT)), (unsigned)a.splits);
-  fwd3d_fp32c_kernel<<<grid, kBlock, 0, s>>>(a);
+  if (a.share_edges)
+    fwd3d_fp32c_kernel<true><<<grid, kBlock, 0, s>>>(a);
+  else
+    fwd3d_fp32c_kernel<false><<<grid, kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 

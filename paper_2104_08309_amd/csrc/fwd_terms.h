@@ -130,22 +130,85 @@ __device__ __forceinline__ void face_series_fp32c(const SeriesInputs& sd, float&
   Ti = (float)(-QN * (cf * sr - sf * si));
 }
 
+// The same face term with one edge term taken from the previous face: in an
+// edge-sharing order (consecutive faces share an edge, Face32::link) the
+// shared edge's sinc(eta) exp(2 pi i t) is the same for both faces (the
+// midpoint is the same, and sinc is even in eta, whose sign flips with the
+// edge's direction); only its weight w = P.d belongs to each face. E holds
+// the previous face's terms of its edges 1 and 2 (re, im, re, im) and is
+// replaced by this face's; with reuse = 0 all three edge terms are computed.
+__device__ __forceinline__ void face_term_fp32c_shared(const Face32& f, float qx, float qy, float qz, float Q2,
+                                                       const double* Qd, bool reuse, float* E, float& Tr,
+                                                       float& Ti, bool& need_series, SeriesInputs& sd) {
+  const float QN = qx * f.N[0] + qy * f.N[1] + qz * f.N[2];
+  const float s1 = qx * f.E1[0] + qy * f.E1[1] + qz * f.E1[2];
+  const float s2 = qx * f.E2[0] + qy * f.E2[1] + qz * f.E2[2];
+  const float P2 = s1 * s1 + s2 * s2;
+  const float w0 = s2 * f.al[0] + s1 * f.be[0];
+  const float w1 = s2 * f.al[1] + s1 * f.be[1];
+  const float w2 = -w0 - w1;
+  const float p0 = s1 * f.ga[0] + s2 * f.de[0];
+  const float p1 = s1 * f.ga[1] + s2 * f.de[1];
+  const float p2 = -p0 - p1;
+  const double ph = Qd[0] * f.gt[0] + Qd[1] * f.gt[1] + Qd[2] * f.gt[2];
+  const float r = (float)(ph - rint(ph));
+  const float t0 = r - p2, t1 = r - p0, t2 = r - p1;
+  float e0r, e0i;
+  if (reuse) {
+    const bool one = f.link == 1u;
+    e0r = one ? E[0] : E[2];
+    e0i = one ? E[1] : E[3];
+  } else {
+    const float c0 = sinc2pi_turns(p1 - p0);
+    e0r = c0 * cos_turns(t0);
+    e0i = c0 * sin_turns(t0);
+  }
+  const float c1 = sinc2pi_turns(p2 - p1), c2 = sinc2pi_turns(p0 - p2);
+  E[0] = c1 * cos_turns(t1);
+  E[1] = c1 * sin_turns(t1);
+  E[2] = c2 * cos_turns(t2);
+  E[3] = c2 * sin_turns(t2);
+  const float Sr = w0 * e0r + w1 * E[0] + w2 * E[2];
+  const float Si = w0 * e0i + w1 * E[1] + w2 * E[3];
+  const float co = QN * rcp_f(fmaxf(P2, 1e-30f));
+  Tr = co * Sr;
+  Ti = co * Si;
+  need_series = P2 < fmaxf(f.thr, f.kap * Q2);
+  sd.p0 = p0;
+  sd.p1 = p1;
+  sd.QN = QN;
+  sd.r = r;
+}
+
 // One LDS tile of FP32C face records against the NQ Q points of a thread:
 // adds each face's term to tr[k], ti[k] (plain binary32 inside the tile). The
 // edge form is evaluated for every lane (no per-Q branch, so the NQ streams
 // interleave); pairs flagged near-degenerate are replaced by the series, and
 // lanes with small[k] set are left for the caller's small-|Q| path.
-template <int NQ>
+// SHARE: the records are in edge-sharing order; E[k] carries the previous
+// face's edge terms across faces and tiles, prev_ok says whether there is a
+// previous (non-empty) face of the same face range to take them from.
+template <int NQ, bool SHARE>
 __device__ __forceinline__ void fwd_tile_fp32c(const Face32* tile, int nt, const float* qx, const float* qy,
                                                const float* qz, const float* Q2, const double (*Qd)[3],
-                                               const bool* small, float* tr, float* ti) {
+                                               const bool* small, float* tr, float* ti, float (*E)[4],
+                                               bool& prev_ok) {
   for (int j = 0; j < nt; ++j) {
     float Tr[NQ], Ti[NQ];
     SeriesInputs sd[NQ];
     bool ser[NQ];
+    if (SHARE) {
+      const bool reuse = prev_ok && tile[j].link != 0u;
 #pragma unroll
-    for (int k = 0; k < NQ; ++k)
-      face_term_fp32c(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr[k], Ti[k], ser[k], sd[k]);
+      for (int k = 0; k < NQ; ++k)
+        face_term_fp32c_shared(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], reuse, E[k], Tr[k], Ti[k], ser[k],
+                               sd[k]);
+      prev_ok = tile[j].thr >= 0.0f;
+    } else {
+#pragma unroll
+      for (int k = 0; k < NQ; ++k)
+        face_term_fp32c(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr[k], Ti[k], ser[k], sd[k]);
+    }
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
       if (ser[k] && !small[k]) face_series_fp32c(sd[k], Tr[k], Ti[k]);

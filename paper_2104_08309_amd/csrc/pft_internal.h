@@ -105,7 +105,8 @@ struct alignas(16) Face32 {
   float de[2];    // (e2 . u_k) / (4 pi |N|)
   float thr;      // tau^2 |N|^2 / L^2
   float kap;      // tau_rel^2 |N|^2
-  float pad[3];
+  uint32_t link;  // 0, or k = 1, 2: edge 0 of this face is edge k of the previous face (edge-sharing order)
+  float pad[2];
 };
 static_assert(sizeof(Face32) == 112, "Face32 layout");
 
@@ -155,8 +156,11 @@ hipError_t launch_mesh_info(const void* verts, int vdtype, const int64_t* d_vert
                             MeshInfo* info, hipStream_t s);
 hipError_t launch_mesh_info_single(const void* verts, int vdtype, int dim, int64_t nv, MeshInfo* info,
                                    hipStream_t s);
+// With order / meta (device, [nf]; NULL: the list order), record m is face order[m] with its
+// vertex list rotated by meta[m] & 3, and pad[2] holds the link meta[m] >> 2 (0, 1 or 2).
 hipError_t launch_face64(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
-                         const MeshInfo* info, double tau, Face64* out, hipStream_t s);
+                         const MeshInfo* info, double tau, Face64* out, hipStream_t s,
+                         const int32_t* order = nullptr, const uint8_t* meta = nullptr);
 hipError_t launch_face32(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32* out, hipStream_t s);
 hipError_t launch_face32b(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32B* out, hipStream_t s);
 hipError_t launch_face64_batch(const void* verts, int vdtype, const int32_t* tris, const int64_t* d_vert_off,
@@ -259,6 +263,7 @@ struct FwdArgs {
   void* out;
   void* intensity;
   double tau0;
+  int share_edges = 0;  // FP32C: records are in edge-sharing order (Face32::link), reuse the shared edge's term
 };
 hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s);

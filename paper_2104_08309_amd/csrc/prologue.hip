@@ -107,11 +107,19 @@ __device__ inline void empty_face64(Face64& f) {
 }
 
 __global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdtype, int64_t nv, const int32_t* tris,
-                                                     int64_t nf, const MeshInfo* info, double tau, Face64* out) {
+                                                     int64_t nf, const MeshInfo* info, double tau, Face64* out,
+                                                     const int32_t* order, const uint8_t* meta) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= nf) return;
-  const int32_t ia = tris[3 * m], ib = tris[3 * m + 1], ic = tris[3 * m + 2];
+  // the face at this position of the (optional) edge-sharing order, its vertex list rotated
+  const int64_t src = order ? (int64_t)order[m] : m;
+  const int rot = meta ? (meta[m] & 3) : 0;
+  const int link = meta ? ((meta[m] >> 2) & 3) : 0;
   Face64 f;
+  const bool in_list = src >= 0 && src < nf && rot < 3;
+  const int32_t ia = in_list ? tris[3 * src + rot] : -1;
+  const int32_t ib = in_list ? tris[3 * src + (rot + 1) % 3] : -1;
+  const int32_t ic = in_list ? tris[3 * src + (rot + 2) % 3] : -1;
   if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) {
     empty_face64(f);
   } else {
@@ -126,6 +134,7 @@ __global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdty
       c[k] -= mi.t[k];
     }
     make_face64(a, b, c, tau, f);
+    f.pad[2] = (double)link;
   }
   out[m] = f;
 }
@@ -353,7 +362,8 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
     r.al[0] = r.al[1] = r.be[0] = r.be[1] = r.ga[0] = r.ga[1] = r.de[0] = r.de[1] = 0.0f;
     r.thr = r.kap = -1.0f;
   }
-  r.pad[0] = r.pad[1] = r.pad[2] = 0.0f;
+  r.link = ok ? (uint32_t)f.pad[2] : 0u;
+  r.pad[0] = r.pad[1] = 0.0f;
   out[m] = r;
 }
 
@@ -448,9 +458,10 @@ hipError_t launch_mesh_info_single(const void* verts, int vdtype, int dim, int64
 }
 
 hipError_t launch_face64(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
-                         const MeshInfo* info, double tau, Face64* out, hipStream_t s) {
+                         const MeshInfo* info, double tau, Face64* out, hipStream_t s, const int32_t* order,
+                         const uint8_t* meta) {
   if (nf <= 0) return hipSuccess;
-  face64_kernel<<<grid_for(nf), 256, 0, s>>>(verts, vdtype, nv, tris, nf, info, tau, out);
+  face64_kernel<<<grid_for(nf), 256, 0, s>>>(verts, vdtype, nv, tris, nf, info, tau, out, order, meta);
   return hipGetLastError();
 }
 

@@ -166,6 +166,18 @@ def test_intensity_loss_validation(lib):
     assert f(*a(nq=-1)) == _lib.PFT_EINVAL
 
 
+def test_forward_3d_ordered_validation(lib):
+    good = 0x10000
+    f = lib.pft_forward_3d_ordered
+    # verts, vdtype, nv, tris, nf, order, meta, q, qdtype, nq, mode, out, intensity, stream
+    assert f(V(good), 1, 3, V(good), 1, None, V(good), V(good), 1, 4, 1, V(good), None, None) == _lib.PFT_EINVAL
+    assert b"face_order" in lib.pft_last_error()
+    assert f(V(good), 1, 3, V(good), 1, V(good), None, V(good), 1, 4, 1, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good + 2), V(good), V(good), 1, 4, 1, V(good), None, None) == \
+        _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good), V(good), V(good), 1, 0, 1, None, None, None) == _lib.PFT_OK
+
+
 def test_forward_2d_validation(lib):
     good = 0x10000
     f = lib.pft_forward_2d

@@ -115,6 +115,42 @@ def test_strict_index_validation(gpu, monkeypatch):
     assert nrel(host(pft.forward_3d(V, T2, Q, mode="fp64")), O.ft3d(v, t, q)) < TOL_FP64
 
 
+def test_edge_sharing_order(gpu):
+    """forward_3d in an edge-sharing face order (automatic and explicit) against the oracle and the list
+    order; the cached order follows in-place changes of the triangle tensor; an out-of-range order
+    entry drops that position's face without faulting."""
+    rng = np.random.default_rng(71)
+    v, t = mg.ellipsoid_uv([3.0, 2.0, 1.5], 12, rot=np.linalg.qr(rng.normal(size=(3, 3)))[0], centre=(0.4, -0.2, 0.3))
+    q = np.concatenate([mg.q_random_ball(9000, 4.0, rng), special_q(3.0)])
+    want = O.ft3d(v, t, q)
+    V, Q = dev(v, torch.float32), dev(q, torch.float32)
+    T = dev(t, torch.int32)
+    step("edge-sharing order: automatic")
+    Fa = host(pft.forward_3d(V, T, Q, mode="fp32c"))
+    Fn = host(pft.forward_3d(V, T, Q, mode="fp32c", order=None))
+    want32 = O.ft3d(v.astype(np.float32).astype(np.float64), t, q.astype(np.float32).astype(np.float64))
+    assert nrel(Fa, want32) < TOL_FP32C and nrel(Fn, want32) < TOL_FP32C
+    assert nrel(Fa, Fn) < 2e-6
+    step("edge-sharing order: in-place change of the triangles")
+    perm = rng.permutation(len(t))
+    T.copy_(dev(t[perm][:, [1, 2, 0]], torch.int32))
+    assert nrel(host(pft.forward_3d(V, T, Q, mode="fp32c")), want32) < TOL_FP32C
+    step("edge-sharing order: explicit, with one position out of range")
+    order, meta = pft.strip_order(t)
+    drop = int(order[len(order) // 2])
+    order[len(order) // 2] = -1
+    keep = np.array([i for i in range(len(t)) if i != drop])
+    Fx = host(pft.forward_3d(V, dev(t, torch.int32), Q, mode="fp32c",
+                             order=(dev(order), dev(meta))))
+    # the surface is open without that face, where the small-|Q| branch (whose threshold differs
+    # between the forms) no longer agrees with the surface sum: compare with the list-order kernel
+    Fk = host(pft.forward_3d(V, dev(t[keep], torch.int32), Q, mode="fp32c", order=None))
+    assert nrel(Fx, Fk) < 2e-6
+    step("edge-sharing order: binary64 ignores it")
+    F64 = host(pft.forward_3d(dev(v), dev(t, torch.int32), dev(q), mode="fp64", order=(dev(order * 0 + np.arange(len(t), dtype=np.int32)), dev(meta))))
+    assert nrel(F64, want) < TOL_FP64
+
+
 def test_empty_q_list(gpu):
     v, t = mg.box()
     step("nq = 0")

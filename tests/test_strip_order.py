@@ -1,0 +1,59 @@
+"""The host edge-sharing face order (pft_strip_order): a permutation, cyclic rotations that keep each
+face's orientation, and links that name an edge the two consecutive faces really share."""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from paper_2104_08309_amd import _lib, api
+
+
+def rotated(tris, order, meta, i):
+    f = tris[order[i]]
+    r = int(meta[i]) & 3
+    assert r < 3
+    return [int(f[r]), int(f[(r + 1) % 3]), int(f[(r + 2) % 3])]
+
+
+def check_order(tris, order, meta, nv):
+    nf = len(tris)
+    assert sorted(order.tolist()) == list(range(nf))
+    for i in range(nf):
+        a = rotated(tris, order, meta, i)
+        f = [int(x) for x in tris[order[i]]]
+        # a cyclic rotation of the listed vertices: same orientation
+        assert any(a == f[k:] + f[:k] for k in range(3))
+        link = (int(meta[i]) >> 2) & 3
+        if link:
+            assert i > 0 and link in (1, 2)
+            b = rotated(tris, order, meta, i - 1)
+            assert {a[0], a[1]} == {b[link], b[(link + 1) % 3]}
+            assert all(0 <= x < nv for x in a + b) and len(set(a)) == 3 and len(set(b)) == 3
+    return float(np.mean(((meta >> 2) & 3) > 0))
+
+
+@pytest.mark.parametrize("level", [0, 2, 4])
+def test_icosphere_chains(level):
+    v, t = mg.icosphere(level, 1.0)
+    order, meta = api.strip_order(t)
+    frac = check_order(t, order, meta, len(v))
+    assert frac > (0.9 if level >= 2 else 0.6)
+
+
+def test_union_mesh_and_bad_faces():
+    """A marching-tetrahedra union mesh, plus faces with out-of-range and repeated indices (placed
+    unlinked) and a duplicated face listed backwards (three faces on an edge)."""
+    v, t = mg.union_of_spheres(np.array([[0.0, 0, 0], [1.2, 0.3, 0]]), np.array([1.0, 0.8]), h=0.25)
+    t2 = np.concatenate([t, [[0, 1, 10 ** 6], [3, 3, 4], t[7][::-1]]]).astype(np.int32)
+    order, meta = api.strip_order(t2, nv=len(v))
+    frac = check_order(t2, order, meta, len(v))
+    assert frac > 0.8
+    pos = {int(o): i for i, o in enumerate(order)}
+    for bad in (len(t), len(t) + 1):
+        assert (meta[pos[bad]] >> 2) & 3 == 0
+
+
+def test_validation():
+    lib = _lib.load()
+    assert lib.pft_strip_order(None, 4, 10, None, None) == _lib.PFT_EINVAL
+    assert lib.pft_strip_order(None, -1, 10, None, None) == _lib.PFT_EINVAL
+    assert lib.pft_strip_order(None, 0, 10, None, None) == _lib.PFT_OK
