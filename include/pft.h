@@ -189,13 +189,16 @@ pft_status pft_forward_3d_poly(const void* verts, pft_dtype vdtype, int64_t nv, 
  *  mode     PFT_FP64 or PFT_FP32C for the transform; the weighted sum is
  *           formed in binary64 in a fixed order either way.
  *  out      [nqa] float64 (DEVICE), overwritten; 0 when ndir == 0.
+ *  face_order, face_meta  NULL, or an edge-sharing face order as for
+ *           pft_forward_3d_ordered (DEVICE; both or neither).
  * Temporaries: nqa * ndir Q points (24 B each) and intensities.
- * Errors: as pft_forward_3d; EINVAL also for nqa > 2^31 - 1 or
- * nqa * ndir * 3 beyond int64.
+ * Errors: as pft_forward_3d; EINVAL also for nqa > 2^31 - 1,
+ * nqa * ndir * 3 beyond int64, or only one of face_order, face_meta given.
  */
 pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                    const double* qabs, int64_t nqa, const double* dirs, const double* weights,
-                                   int64_t ndir, pft_mode mode, double* out, void* stream);
+                                   int64_t ndir, pft_mode mode, double* out, const int32_t* face_order,
+                                   const uint8_t* face_meta, void* stream);
 
 /*
  * pft_backward_3d -- adjoint of pft_forward_3d with respect to the vertices.

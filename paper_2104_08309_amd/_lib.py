@@ -68,7 +68,7 @@ def load() -> ctypes.CDLL:
         "pft_backward_3d": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp],
         "pft_batch_forward": [P(PftMeshBatch), cint, vp, vp, vp],
         "pft_batch_backward": [P(PftMeshBatch), cint, vp, vp, vp],
-        "pft_orientation_average": [vp, cint, i64, vp, i64, vp, i64, vp, vp, i64, cint, vp, vp],
+        "pft_orientation_average": [vp, cint, i64, vp, i64, vp, i64, vp, vp, i64, cint, vp, vp, vp, vp],
         "pft_forward_3d_poly": [vp, cint, i64, P(i64), vp, i64, vp, cint, i64, cint, vp, vp, vp],
         "pft_strip_order": [vp, i64, i64, vp, vp],
         "pft_forward_3d_ordered": [vp, cint, i64, vp, i64, vp, vp, vp, cint, i64, cint, vp, vp, vp],

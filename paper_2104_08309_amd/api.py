@@ -138,6 +138,22 @@ def _auto_order(tris_key: torch.Tensor, tris: torch.Tensor, nv: int):
     return dev_order
 
 
+def _order_arg(order, tris_key, tris: torch.Tensor, nv: int, m: int):
+    """(order, meta) device tensors or (None, None) for an ``order`` argument ("auto", None or a pair)."""
+    if isinstance(order, str):
+        if order != "auto":
+            raise ValueError(f"order must be 'auto', None or (order, meta), got {order!r}")
+        use = m == PFT_FP32C and tris.shape[0] >= _AUTO_ORDER_MIN_FACES and isinstance(tris_key, torch.Tensor)
+        return _auto_order(tris_key, tris, nv) if use else (None, None)
+    if order is None:
+        return None, None
+    fo, fm = (_on_gpu(x, name) for x, name in zip(order, ("order", "meta")))
+    if fo.dtype != torch.int32 or fm.dtype != torch.uint8 or fo.numel() != tris.shape[0] \
+            or fm.numel() != tris.shape[0] or fo.device != tris.device or fm.device != tris.device:
+        raise ValueError("order must be (int32 [nf], uint8 [nf]) tensors on the mesh's device")
+    return fo, fm
+
+
 def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: str = "fp32c",
                intensity: bool = False, order="auto"):
     """F(Q) of the closed mesh; complex128 for mode 'fp64', complex64 for 'fp32c'.
@@ -155,21 +171,13 @@ def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: s
     rdt = torch.float64 if m == PFT_FP64 else torch.float32
     out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
     inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
-    if isinstance(order, str):
-        if order != "auto":
-            raise ValueError(f"order must be 'auto', None or (order, meta), got {order!r}")
-        use = m == PFT_FP32C and tris.shape[0] >= _AUTO_ORDER_MIN_FACES and isinstance(tris_key, torch.Tensor)
-        order = _auto_order(tris_key, tris, verts.shape[0]) if use else None
+    fo, fm = _order_arg(order, tris_key, tris, verts.shape[0], m)
     with torch.cuda.device(verts.device):
-        if order is None:
+        if fo is None:
             check(_lib.load().pft_forward_3d(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0],
                                              _ptr(tris), tris.shape[0], _ptr(q), _real_dtype_id(q, "q"),
                                              q.shape[0], m, _ptr(out), _ptr(inten), _stream(verts.device)))
         else:
-            fo, fm = (_on_gpu(x, name) for x, name in zip(order, ("order", "meta")))
-            if fo.dtype != torch.int32 or fm.dtype != torch.uint8 or fo.numel() != tris.shape[0] \
-                    or fm.numel() != tris.shape[0]:
-                raise ValueError("order must be (int32 [nf], uint8 [nf]) device tensors")
             check(_lib.load().pft_forward_3d_ordered(
                 _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(fo),
                 _ptr(fm), _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(inten),
@@ -206,12 +214,13 @@ def forward_3d_poly(verts: torch.Tensor, faces: Sequence[Sequence[int]], q: torc
 
 
 def orientation_average(verts: torch.Tensor, tris: torch.Tensor, qabs: torch.Tensor, dirs: torch.Tensor,
-                        weights: torch.Tensor, mode: str = "fp32c") -> torch.Tensor:
+                        weights: torch.Tensor, mode: str = "fp32c", order="auto") -> torch.Tensor:
     """I(|Q|) = sum_j w_j |F(|Q| s_j)|^2 for each magnitude in ``qabs`` (float64 result).
 
     ``dirs`` [ndir, 3] unit vectors and ``weights`` [ndir] form the direction
     quadrature (float64, on the mesh's device).
     """
+    tris_key = tris
     verts, tris = _mesh(verts, tris)
     qabs = _on_gpu(qabs, "qabs")
     dirs = _on_gpu(dirs, "dirs")
@@ -228,10 +237,11 @@ def orientation_average(verts: torch.Tensor, tris: torch.Tensor, qabs: torch.Ten
     if weights.dim() != 1 or weights.shape[0] != dirs.shape[0]:
         raise ValueError("weights must have shape [ndir] matching dirs")
     out = torch.empty(qabs.shape[0], dtype=torch.float64, device=verts.device)
+    fo, fm = _order_arg(order, tris_key, tris, verts.shape[0], mode_id(mode))
     with torch.cuda.device(verts.device):
         check(_lib.load().pft_orientation_average(
             _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(qabs),
-            qabs.shape[0], _ptr(dirs), _ptr(weights), dirs.shape[0], mode_id(mode), _ptr(out),
+            qabs.shape[0], _ptr(dirs), _ptr(weights), dirs.shape[0], mode_id(mode), _ptr(out), _ptr(fo), _ptr(fm),
             _stream(verts.device)))
     return out
 

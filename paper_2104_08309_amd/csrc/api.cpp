@@ -756,9 +756,12 @@ pft_status pft_forward_3d_poly(const void* verts, pft_dtype vdtype, int64_t nv, 
 
 pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                    const double* qabs, int64_t nqa, const double* dirs, const double* weights,
-                                   int64_t ndir, pft_mode mode, double* out, void* stream) {
+                                   int64_t ndir, pft_mode mode, double* out, const int32_t* face_order,
+                                   const uint8_t* face_meta, void* stream) {
   pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, nullptr, PFT_F64, 0, mode);
   if (st != PFT_OK) return st;
+  if ((face_order == nullptr) != (face_meta == nullptr)) return fail(PFT_EINVAL, "face_order and face_meta go together");
+  if (face_order && !aligned(face_order, 4)) return fail(PFT_EINVAL, "face_order misaligned");
   if (nqa < 0 || ndir < 0) return fail(PFT_EINVAL, "negative count");
   if (nqa > 0 && (qabs == nullptr || out == nullptr)) return fail(PFT_EINVAL, "qabs or out is NULL");
   if (ndir > 0 && (dirs == nullptr || weights == nullptr)) return fail(PFT_EINVAL, "dirs or weights is NULL");
@@ -783,7 +786,8 @@ pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t 
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
   hipError_t e = launch_qdirs(qabs, nqa, dirs, ndir, Q, s);
   if (e != hipSuccess) return hip_fail(e, "orientation Q list");
-  st = forward3d_core(ar, verts, vdtype, nv, tris, nf, Q, PFT_F64, nq, mode, nullptr, I, s);
+  st = forward3d_core(ar, verts, vdtype, nv, tris, nf, Q, PFT_F64, nq, mode, nullptr, I, s,
+                      nf > 0 ? face_order : nullptr, nf > 0 ? face_meta : nullptr);
   if (st != PFT_OK) return st;
   prof_begin("orient_sum", s);
   e = launch_dir_sum(I, c128 ? PFT_F64 : PFT_F32, weights, nqa, ndir, out, s);

@@ -79,19 +79,22 @@ def test_backward_3d_validation(lib):
 def test_orientation_average_validation(lib):
     good = 0x10000  # never dereferenced: validation fails first
     f = lib.pft_orientation_average
-    # verts, vdtype, nv, tris, nf, qabs, nqa, dirs, weights, ndir, mode, out, stream
-    assert f(V(good), 1, 3, V(good), 1, V(good), -1, V(good), V(good), 4, 1, V(good), None) == _lib.PFT_EINVAL
+    # verts, vdtype, nv, tris, nf, qabs, nqa, dirs, weights, ndir, mode, out, face_order, face_meta, stream
+    assert f(V(good), 1, 3, V(good), 1, V(good), -1, V(good), V(good), 4, 1, V(good), None, None, None) == _lib.PFT_EINVAL
     assert b"negative" in lib.pft_last_error()
-    assert f(V(good), 1, 3, V(good), 1, None, 2, V(good), V(good), 4, 1, V(good), None) == _lib.PFT_EINVAL
-    assert f(V(good), 1, 3, V(good), 1, V(good), 2, V(good), V(good), 4, 1, None, None) == _lib.PFT_EINVAL
-    assert f(V(good), 1, 3, V(good), 1, V(good), 2, None, V(good), 4, 1, V(good), None) == _lib.PFT_EINVAL
-    assert f(V(good), 1, 3, V(good), 1, V(good), 2, V(good), None, 4, 1, V(good), None) == _lib.PFT_EINVAL
-    assert f(V(good), 1, 3, V(good), 1, V(good + 4), 2, V(good), V(good), 4, 1, V(good), None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, None, 2, V(good), V(good), 4, 1, V(good), None, None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good), 2, V(good), V(good), 4, 1, None, None, None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good), 2, None, V(good), 4, 1, V(good), None, None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good), 2, V(good), None, 4, 1, V(good), None, None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good + 4), 2, V(good), V(good), 4, 1, V(good), None, None, None) == _lib.PFT_EINVAL
     assert b"misaligned" in lib.pft_last_error()
-    assert f(V(good), 1, 3, V(good), 1, V(good), 2, V(good), V(good), 4, 9, V(good), None) == _lib.PFT_EUNSUPPORTED
-    assert f(V(good), 1, 3, V(good), 1, V(good), 1 << 31, V(good), V(good), 4, 1, V(good), None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good), 2, V(good), V(good), 4, 9, V(good), None, None, None) == _lib.PFT_EUNSUPPORTED
+    assert f(V(good), 1, 3, V(good), 1, V(good), 1 << 31, V(good), V(good), 4, 1, V(good), None, None, None) == _lib.PFT_EINVAL
     # no magnitudes: a valid no-op
-    assert f(V(good), 1, 3, V(good), 1, None, 0, V(good), V(good), 4, 1, None, None) == _lib.PFT_OK
+    assert f(V(good), 1, 3, V(good), 1, None, 0, V(good), V(good), 4, 1, None, None, None, None) == _lib.PFT_OK
+    # an order without its meta
+    assert f(V(good), 1, 3, V(good), 1, V(good), 2, V(good), V(good), 4, 1, V(good), V(good), None, None) == \
+        _lib.PFT_EINVAL
 
 
 def test_forward_3d_poly_validation(lib):
