@@ -236,11 +236,15 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
  *              in a fixed order).
  *  out         NULL or [nq] complex F(Q) (complex128 for PFT_FP64, complex64 for PFT_FP32C).
  *  grad_verts  NULL or [nv][3] of vdtype, OVERWRITTEN with dL/dv.
- * Errors: as pft_forward_3d; EINVAL also for loss NULL, or target NULL with nq > 0.
+ *  face_order, face_meta  NULL, or an edge-sharing face order for the FP32C
+ *              forward as for pft_forward_3d_ordered (DEVICE; both or neither).
+ * Errors: as pft_forward_3d; EINVAL also for loss NULL, target NULL with
+ * nq > 0, or only one of face_order, face_meta given.
  */
 pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                  const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const double* weight,
-                                 const double* target, double* loss, void* out, void* grad_verts, void* stream);
+                                 const double* target, double* loss, void* out, void* grad_verts,
+                                 const int32_t* face_order, const uint8_t* face_meta, void* stream);
 
 /*
  * pft_forward_3d_regions -- F(Q) of a density that is constant on each of

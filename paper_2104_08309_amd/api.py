@@ -267,11 +267,13 @@ def backward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, grad_o
 
 def intensity_loss_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, target: torch.Tensor,
                       weight: Optional[torch.Tensor] = None, mode: str = "fp32c", need_grad: bool = True,
-                      return_F: bool = False):
+                      return_F: bool = False, order="auto"):
     """L = sum_Q w (|F|^2 - I)^2 and dL/dverts in one library call (forward, cotangent and adjoint
     sharing the face records and the Q order). ``target`` and ``weight`` are float64 [nq] on the
     device (weight None: w = 1). Returns (L as a 0-dim float64 tensor, dL/dverts or None[, F]).
+    ``order`` as for forward_3d (the FP32C forward part in an edge-sharing face order).
     """
+    tris_key = tris
     verts, tris = _mesh(verts, tris)
     q = _qlist(q, verts.device)
     m = mode_id(mode)
@@ -290,11 +292,12 @@ def intensity_loss_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, 
     loss = torch.empty((), dtype=torch.float64, device=verts.device)
     F = torch.empty(nq, dtype=cdt, device=verts.device) if return_F else None
     gv = torch.empty_like(verts) if need_grad else None
+    fo, fm = _order_arg(order, tris_key, tris, verts.shape[0], m)
     with torch.cuda.device(verts.device):
         check(_lib.load().pft_intensity_loss_3d(
             _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(q),
             _real_dtype_id(q, "q"), nq, m, _ptr(weight), _ptr(target), loss.data_ptr(), _ptr(F), _ptr(gv),
-            _stream(verts.device)))
+            _ptr(fo), _ptr(fm), _stream(verts.device)))
     return (loss, gv, F) if return_F else (loss, gv)
 
 

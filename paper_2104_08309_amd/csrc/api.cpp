@@ -858,11 +858,14 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
 
 pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                  const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const double* weight,
-                                 const double* target, double* loss, void* out, void* grad_verts, void* stream) {
+                                 const double* target, double* loss, void* out, void* grad_verts,
+                                 const int32_t* face_order, const uint8_t* face_meta, void* stream) {
   pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
   if (st != PFT_OK) return st;
   const bool c128 = mode == PFT_FP64;
   if (loss == nullptr) return fail(PFT_EINVAL, "loss is NULL");
+  if ((face_order == nullptr) != (face_meta == nullptr)) return fail(PFT_EINVAL, "face_order and face_meta go together");
+  if (face_order && !aligned(face_order, 4)) return fail(PFT_EINVAL, "face_order misaligned");
   if (nq > 0 && target == nullptr) return fail(PFT_EINVAL, "target is NULL");
   if (!aligned(loss, 8) || (target && !aligned(target, 8)) || (weight && !aligned(weight, 8)))
     return fail(PFT_EINVAL, "loss, target or weight misaligned");
@@ -878,9 +881,12 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
     return e == hipSuccess ? PFT_OK : hip_fail(e, "zero outputs");
   }
   Arena ar(s);
-  // shared prologue: one set of face records and one Q order for the forward and the adjoint
+  // shared prologue: one set of face records and one Q order for the forward and the adjoint (with an
+  // edge-sharing order the FP32C forward gets its own records in that order)
+  const bool ordered = face_order != nullptr && !c128 && nf > 0;
   MeshInfo* info = ar.get<MeshInfo>(1);
   Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
+  Face64* f64o = ordered ? ar.get<Face64>(nf) : f64;
   Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
   int splits;
   int64_t per;
@@ -893,12 +899,14 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
   e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
   // binary64 records with the binary64 series threshold (the FP32C forward takes its own from Face32)
   if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, kTauF64, f64, s);
-  if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
+  if (e == hipSuccess && ordered)
+    e = launch_face64(verts, vdtype, nv, tris, nf, info, kTauF64, f64o, s, face_order, face_meta);
+  if (e == hipSuccess && !c128) e = launch_face32(f64o, nf, kTauF32, kTauRel32, f32, s);
   if (e != hipSuccess) return hip_fail(e, "loss prologue");
   uint32_t* perm = nullptr;
   if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
   FwdArgs a;
-  a.f64 = f64;
+  a.f64 = f64o;
   a.f32 = f32;
   a.info = info;
   a.nf = nf;
@@ -913,6 +921,7 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
   a.out = out;
   a.intensity = nullptr;
   a.tau0 = c128 ? kTau0F64 : kTau0F32;
+  a.share_edges = ordered ? 1 : 0;
   const char* nm = main_name(true, mode);
   prof_begin(nm, s);
   e = c128 ? launch_fwd3d_fp64(a, s) : launch_fwd3d_fp32c(a, s);

@@ -156,9 +156,9 @@ def test_regions_validation(lib):
 def test_intensity_loss_validation(lib):
     good = 0x10000
     f = lib.pft_intensity_loss_3d
-    # verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, weight, target, loss, out, grad_verts, stream
-    a = lambda w=None, tg=V(good), loss=V(good), out=None, gv=V(good), nq=4, mode=1: (
-        V(good), 1, 8, V(good), 12, V(good), 1, nq, mode, w, tg, loss, out, gv, None)
+    # verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, weight, target, loss, out, grad_verts, order, meta, stream
+    a = lambda w=None, tg=V(good), loss=V(good), out=None, gv=V(good), nq=4, mode=1, fo=None, fm=None: (
+        V(good), 1, 8, V(good), 12, V(good), 1, nq, mode, w, tg, loss, out, gv, fo, fm, None)
     assert f(*a(loss=None)) == _lib.PFT_EINVAL
     assert b"loss is NULL" in lib.pft_last_error()
     assert f(*a(tg=None)) == _lib.PFT_EINVAL
@@ -167,6 +167,7 @@ def test_intensity_loss_validation(lib):
     assert f(*a(gv=V(good + 4))) == _lib.PFT_EINVAL
     assert f(*a(mode=5)) == _lib.PFT_EUNSUPPORTED
     assert f(*a(nq=-1)) == _lib.PFT_EINVAL
+    assert f(*a(fo=V(good))) == _lib.PFT_EINVAL  # an order without its meta
 
 
 def test_forward_3d_ordered_validation(lib):
