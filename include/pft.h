@@ -329,6 +329,20 @@ typedef struct {
 pft_status pft_batch_forward(const pft_mesh_batch* batch, pft_mode mode, void* out, void* intensity, void* stream);
 
 /*
+ * pft_batch_forward_ordered -- pft_batch_forward with each mesh's faces in an
+ * edge-sharing order (pft_strip_order of the mesh, offset by its first
+ * triangle), so that the FP32C forward reuses shared edge terms as
+ * pft_forward_3d_ordered does.
+ *  face_order  [total_nf] int32 (DEVICE): position m (in mesh i's triangle
+ *              range) holds a triangle of the same mesh; an entry out of
+ *              range makes that position an empty face.
+ *  face_meta   [total_nf] uint8 (DEVICE), as written by pft_strip_order.
+ * Errors: as pft_batch_forward; EINVAL also for face_order or face_meta NULL.
+ */
+pft_status pft_batch_forward_ordered(const pft_mesh_batch* b, const int32_t* face_order, const uint8_t* face_meta,
+                                     pft_mode mode, void* out, void* intensity, void* stream);
+
+/*
  * pft_batch_backward -- pft_backward_3d for every mesh of a batch.
  *  grad_out    [total_nq] complex (complex128 / complex64 by mode).
  *  grad_verts  [total_nv][3] of vdtype, overwritten.

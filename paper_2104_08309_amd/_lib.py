@@ -18,7 +18,7 @@ PFT_F32, PFT_F64 = 0, 1
 EXPORTS = [
     "pft_forward_2d", "pft_forward_3d", "pft_backward_3d", "pft_batch_forward", "pft_batch_backward",
     "pft_forward_3d_poly", "pft_orientation_average", "pft_forward_3d_regions", "pft_backward_3d_regions",
-    "pft_intensity_loss_3d", "pft_strip_order", "pft_forward_3d_ordered",
+    "pft_intensity_loss_3d", "pft_strip_order", "pft_forward_3d_ordered", "pft_batch_forward_ordered",
     "pft_validate_mesh", "pft_last_error", "pft_release_workspace", "pft_profile_enable",
     "pft_profile_reset", "pft_profile_read", "pft_version",
 ]
@@ -67,6 +67,7 @@ def load() -> ctypes.CDLL:
         "pft_forward_3d": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp],
         "pft_backward_3d": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp],
         "pft_batch_forward": [P(PftMeshBatch), cint, vp, vp, vp],
+        "pft_batch_forward_ordered": [P(PftMeshBatch), vp, vp, cint, vp, vp, vp],
         "pft_batch_backward": [P(PftMeshBatch), cint, vp, vp, vp],
         "pft_orientation_average": [vp, cint, i64, vp, i64, vp, i64, vp, vp, i64, cint, vp, vp, vp, vp],
         "pft_forward_3d_poly": [vp, cint, i64, P(i64), vp, i64, vp, cint, i64, cint, vp, vp, vp],

@@ -20,6 +20,7 @@ from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
 __all__ = [
     "forward_2d", "forward_3d", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
     "orientation_average", "forward_3d_regions", "backward_3d_regions", "intensity_loss_3d", "strip_order",
+    "batch_strip_order",
     "validate_mesh",
     "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
 ]
@@ -391,17 +392,71 @@ def _batch_struct(verts, tris, q, vert_offsets, tri_offsets, q_offsets):
     return b, offs, verts, tris, q
 
 
+def batch_strip_order(tris, vert_offsets, tri_offsets) -> Tuple[np.ndarray, np.ndarray]:
+    """Edge-sharing order of every mesh of a batch (indices local to each mesh): global (order, meta)
+    for batch_forward's ``order``, each mesh's order offset by its first triangle."""
+    t = tris.detach().cpu().numpy() if isinstance(tris, torch.Tensor) else np.asarray(tris)
+    t = np.ascontiguousarray(t, dtype=np.int32).reshape(-1, 3)
+    vo = np.asarray(vert_offsets, dtype=np.int64)
+    to = np.asarray(tri_offsets, dtype=np.int64)
+    order = np.empty(t.shape[0], dtype=np.int32)
+    meta = np.empty(t.shape[0], dtype=np.uint8)
+    for i in range(to.size - 1):
+        a, b = int(to[i]), int(to[i + 1])
+        if b > a:
+            o, mt = strip_order(t[a:b], int(vo[i + 1] - vo[i]))
+            order[a:b] = o + a
+            meta[a:b] = mt
+    return order, meta
+
+
+_BATCH_ORDER_CACHE: dict = {}
+
+
+def _batch_auto_order(tris_key: torch.Tensor, offs, device):
+    stamp = (tris_key.data_ptr(), tuple(tris_key.shape), tris_key._version, offs[0].tobytes(), offs[1].tobytes())
+    hit = _BATCH_ORDER_CACHE.get(id(tris_key))
+    if hit is not None and hit[0]() is tris_key and hit[1] == stamp:
+        return hit[2]
+    order, meta = batch_strip_order(tris_key, offs[0], offs[1])
+    dev_order = (torch.from_numpy(order).to(device), torch.from_numpy(meta).to(device))
+    if len(_BATCH_ORDER_CACHE) >= 16:
+        for k in [k for k, e in _BATCH_ORDER_CACHE.items() if e[0]() is None]:
+            del _BATCH_ORDER_CACHE[k]
+    _BATCH_ORDER_CACHE[id(tris_key)] = (weakref.ref(tris_key), stamp, dev_order)
+    return dev_order
+
+
 def batch_forward(verts, tris, q, vert_offsets, tri_offsets, q_offsets, mode: str = "fp32c",
-                  intensity: bool = False):
-    """Transform of every mesh of a concatenated batch (indices local to each mesh)."""
+                  intensity: bool = False, order="auto"):
+    """Transform of every mesh of a concatenated batch (indices local to each mesh).
+
+    ``order``: "auto" (FP32C: each mesh's faces in an edge-sharing order, computed on the host at the
+    first call for a triangle tensor and reused while it is unchanged), None, or device tensors
+    (order int32, meta uint8) from ``batch_strip_order``.
+    """
+    tris_key = tris
     b, offs, verts, tris, q = _batch_struct(verts, tris, q, vert_offsets, tri_offsets, q_offsets)
     m = mode_id(mode)
     cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
     rdt = torch.float64 if m == PFT_FP64 else torch.float32
     out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
     inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
+    if isinstance(order, str):
+        if order != "auto":
+            raise ValueError(f"order must be 'auto', None or (order, meta), got {order!r}")
+        use = m == PFT_FP32C and isinstance(tris_key, torch.Tensor) and tris.shape[0] >= _AUTO_ORDER_MIN_FACES
+        order = _batch_auto_order(tris_key, offs, verts.device) if use else None
     with torch.cuda.device(verts.device):
-        check(_lib.load().pft_batch_forward(ctypes.byref(b), m, _ptr(out), _ptr(inten), _stream(verts.device)))
+        if order is None:
+            check(_lib.load().pft_batch_forward(ctypes.byref(b), m, _ptr(out), _ptr(inten), _stream(verts.device)))
+        else:
+            fo, fm = (_on_gpu(x, name) for x, name in zip(order, ("order", "meta")))
+            if fo.dtype != torch.int32 or fm.dtype != torch.uint8 or fo.numel() != tris.shape[0] \
+                    or fm.numel() != tris.shape[0]:
+                raise ValueError("order must be (int32 [nf], uint8 [nf]) device tensors")
+            check(_lib.load().pft_batch_forward_ordered(ctypes.byref(b), _ptr(fo), _ptr(fm), m, _ptr(out),
+                                                        _ptr(inten), _stream(verts.device)))
     del offs  # host offsets are read synchronously by the call
     return (out, inten) if intensity else out
 

@@ -1233,7 +1233,8 @@ pft_status check_batch(const pft_mesh_batch* b, int mode) {
                          b->q_offsets[n], mode);
 }
 
-pft_status batch_prologue(Arena& ar, const pft_mesh_batch* b, double tau, BatchPrep& p, hipStream_t s) {
+pft_status batch_prologue(Arena& ar, const pft_mesh_batch* b, double tau, BatchPrep& p, hipStream_t s,
+                          const int32_t* order = nullptr, const uint8_t* meta = nullptr) {
   p.n = b->n_meshes;
   p.nv = b->vert_offsets[p.n];
   p.nf = b->tri_offsets[p.n];
@@ -1254,7 +1255,7 @@ pft_status batch_prologue(Arena& ar, const pft_mesh_batch* b, double tau, BatchP
   if (e == hipSuccess) e = launch_fill_face_mesh(p.d_tri_off, p.n, p.nf, p.d_face_mesh, s);
   if (e == hipSuccess)
     e = launch_face64_batch(b->verts, b->vdtype, b->tris, p.d_vert_off, p.d_tri_off, p.d_face_mesh, p.nf, p.info,
-                            tau, p.f64, s);
+                            tau, p.f64, s, order, meta);
   if (e != hipSuccess) return hip_fail(e, "batch prologue");
   return PFT_OK;
 }
@@ -1264,10 +1265,14 @@ pft_status batch_prologue(Arena& ar, const pft_mesh_batch* b, double tau, BatchP
 
 extern "C" {
 
-pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, void* intensity, void* stream) {
+static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, void* out, void* intensity,
+                                     const int32_t* face_order, const uint8_t* face_meta, void* stream) {
   pft_status st = check_batch(b, mode);
   if (st != PFT_OK) return st;
   const bool c128 = mode == PFT_FP64;
+  const bool share = face_order != nullptr && !c128;
+  if ((face_order == nullptr) != (face_meta == nullptr)) return fail(PFT_EINVAL, "face_order and face_meta go together");
+  if (face_order && !aligned(face_order, 4)) return fail(PFT_EINVAL, "face_order misaligned");
   const int64_t n = b->n_meshes, nq_total = b->q_offsets[n];
   if (nq_total > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
   if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
@@ -1277,7 +1282,8 @@ pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, 
   ensure_pool();
   Arena ar(s);
   BatchPrep p;
-  st = batch_prologue(ar, b, c128 ? kTauF64 : kTauF32, p, s);
+  st = batch_prologue(ar, b, c128 ? kTauF64 : kTauF32, p, s, share ? face_order : nullptr,
+                      share ? face_meta : nullptr);
   if (st != PFT_OK) return st;
   Face32* f32 = nullptr;
   if (!c128) {
@@ -1335,19 +1341,31 @@ pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, 
   if (e != hipSuccess) return hip_fail(e, "counter reset");
   const int64_t n_items = (int64_t)items.size();
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
-                                          (int64_t)num_cus() * batch_fwd_blocks_per_cu(mode));
+                                          (int64_t)num_cus() * batch_fwd_blocks_per_cu(mode, share));
   const double tau0 = c128 ? kTau0F64 : kTau0F32;
   prof_begin("batch_fwd", s);
   uint32_t* perm = nullptr;
   if ((st = build_qorder(ar, b->q, b->qdtype, nq_total, p.d_q_off, n, &perm, s)) != PFT_OK) return st;
   e = launch_batch_fwd(mode, d_items, n_items, counter, p.f64, f32, b->q, b->qdtype, perm, partial, p.info, tau0, grid,
-                       s);
+                       s, share);
   prof_end("batch_fwd", s);
   if (e != hipSuccess) return hip_fail(e, "batch forward");
   e = launch_batch_fwd_finish(partial, p.d_q_off, n, d_q_part, d_q_chunks, p.info, b->q, b->qdtype, perm, nq_total,
                               tau0, c128 ? 1 : 0, out, intensity, s);
   if (e != hipSuccess) return hip_fail(e, "batch finish");
   return PFT_OK;
+}
+
+pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, void* intensity, void* stream) {
+  return batch_forward_impl(b, mode, out, intensity, nullptr, nullptr, stream);
+}
+
+pft_status pft_batch_forward_ordered(const pft_mesh_batch* b, const int32_t* face_order, const uint8_t* face_meta,
+                                     pft_mode mode, void* out, void* intensity, void* stream) {
+  if (b && b->n_meshes > 0 && b->tri_offsets && b->tri_offsets[b->n_meshes] > 0 &&
+      (face_order == nullptr || face_meta == nullptr))
+    return fail(PFT_EINVAL, "face_order or face_meta is NULL");
+  return batch_forward_impl(b, mode, out, intensity, face_order, face_meta, stream);
 }
 
 pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void* grad_out, void* grad_verts,

@@ -23,7 +23,7 @@ __device__ __forceinline__ int64_t next_item(uint32_t* counter, int* slot) {
   return it;
 }
 
-template <int MODE>
+template <int MODE, bool SHARE = false>
 __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* __restrict__ items, int64_t n_items,
                                                           uint32_t* counter, const Face64* __restrict__ f64,
                                                           const Face32* __restrict__ f32, const void* q, int qdtype,
@@ -90,6 +90,8 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
       double xr[kQPTBatch], xi[kQPTBatch];
 #pragma unroll
       for (int k = 0; k < kQPTBatch; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
+      float E[kQPTBatch][4];  // edge terms carried from the previous face of the item (SHARE)
+      bool prev_ok = false;
       for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
         const int nt = (int)min((int64_t)kTileF, f_end - t0);
         __syncthreads();
@@ -99,9 +101,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         float tr[kQPTBatch], ti[kQPTBatch];
 #pragma unroll
         for (int k = 0; k < kQPTBatch; ++k) tr[k] = ti[k] = 0.0f;
-        float E[kQPTBatch][4];
-        bool prev_ok = false;
-        fwd_tile_fp32c<kQPTBatch, false>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, E, prev_ok);
+        fwd_tile_fp32c<kQPTBatch, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, E, prev_ok);
 #pragma unroll
         for (int k = 0; k < kQPTBatch; ++k) {
           kahan_add(sr[k], cr[k], tr[k]);
@@ -246,10 +246,12 @@ __global__ __launch_bounds__(256) void batch_bwd_reduce_kernel(const double* par
 
 }  // namespace
 
-int batch_fwd_blocks_per_cu(int mode) {
+int batch_fwd_blocks_per_cu(int mode, bool share) {
   int nb = 0;
   if (mode == PFT_FP64)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP64>, kBlock, 0);
+  else if (share)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP32C, true>, kBlock, 0);
   else
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP32C>, kBlock, 0);
   return nb > 0 ? nb : 1;
@@ -266,11 +268,15 @@ int batch_bwd_blocks_per_cu(int mode) {
 
 hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const Face32* f32, const void* q, int qdtype, const uint32_t* perm,
-                            double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s) {
+                            double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s,
+                            bool share) {
   if (n_items <= 0) return hipSuccess;
   if (mode == PFT_FP64)
     batch_fwd_kernel<PFT_FP64><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial,
                                                        info, tau0);
+  else if (share)
+    batch_fwd_kernel<PFT_FP32C, true><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm,
+                                                              partial, info, tau0);
   else
     batch_fwd_kernel<PFT_FP32C><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial,
                                                         info, tau0);

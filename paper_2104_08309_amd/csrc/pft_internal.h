@@ -165,7 +165,8 @@ hipError_t launch_face32(const Face64* f64, int64_t nf, double tau, double tau_r
 hipError_t launch_face32b(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32B* out, hipStream_t s);
 hipError_t launch_face64_batch(const void* verts, int vdtype, const int32_t* tris, const int64_t* d_vert_off,
                                const int64_t* d_tri_off, const int32_t* d_face_mesh, int64_t nf_total,
-                               const MeshInfo* info, double tau, Face64* out, hipStream_t s);
+                               const MeshInfo* info, double tau, Face64* out, hipStream_t s,
+                               const int32_t* order = nullptr, const uint8_t* meta = nullptr);
 hipError_t launch_fill_face_mesh(const int64_t* d_tri_off, int64_t n_meshes, int64_t nf_total, int32_t* face_mesh,
                                  hipStream_t s);
 hipError_t launch_edges2d(const double* verts, int64_t nv, const int64_t* d_off, int64_t ncont, MeshInfo* info,
@@ -406,11 +407,12 @@ struct BatchItemBwd {   // one (mesh, face-tile, Q-chunk) work item
   int64_t nq;           // Q in the chunk
   int64_t part;         // partial slot base (in units of face corners): partial[(part + j) * 3 + k]
 };
-int batch_fwd_blocks_per_cu(int mode);
+int batch_fwd_blocks_per_cu(int mode, bool share = false);
 int batch_bwd_blocks_per_cu(int mode);
 hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const Face32* f32, const void* q, int qdtype, const uint32_t* perm,
-                            double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s);
+                            double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s,
+                            bool share = false);
 hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_off, int64_t n_meshes,
                                    const int64_t* d_q_part, const int32_t* d_q_chunks, const MeshInfo* info,
                                    const void* q, int qdtype, const uint32_t* perm, int64_t nq_total, double tau0,

@@ -287,13 +287,21 @@ __global__ __launch_bounds__(256) void face_mesh_kernel(const int64_t* tri_off, 
 __global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, int vdtype, const int32_t* tris,
                                                            const int64_t* vert_off, const int64_t* tri_off,
                                                            const int32_t* face_mesh, int64_t nf_total,
-                                                           const MeshInfo* info, double tau, Face64* out) {
+                                                           const MeshInfo* info, double tau, Face64* out,
+                                                           const int32_t* order, const uint8_t* meta) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= nf_total) return;
   const int32_t mesh = face_mesh[m];
   const int64_t vb = vert_off[mesh];
   const int64_t nv = vert_off[mesh + 1] - vb;
-  const int32_t ia = tris[3 * m], ib = tris[3 * m + 1], ic = tris[3 * m + 2];
+  // the face at this position of the (optional) edge-sharing order (within its mesh), rotated
+  const int64_t src = order ? (int64_t)order[m] : m;
+  const int rot = meta ? (meta[m] & 3) : 0;
+  const int link = meta ? ((meta[m] >> 2) & 3) : 0;
+  const bool in_list = src >= 0 && src < nf_total && rot < 3;
+  const int32_t ia = in_list ? tris[3 * src + rot] : -1;
+  const int32_t ib = in_list ? tris[3 * src + (rot + 1) % 3] : -1;
+  const int32_t ic = in_list ? tris[3 * src + (rot + 2) % 3] : -1;
   Face64 f;
   if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) {
     empty_face64(f);
@@ -309,6 +317,7 @@ __global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, in
       c[k] -= mi.t[k];
     }
     make_face64(a, b, c, tau, f);
+    f.pad[2] = (double)link;
   }
   out[m] = f;
 }
@@ -501,10 +510,11 @@ hipError_t launch_fill_face_mesh(const int64_t* d_tri_off, int64_t n_meshes, int
 
 hipError_t launch_face64_batch(const void* verts, int vdtype, const int32_t* tris, const int64_t* d_vert_off,
                                const int64_t* d_tri_off, const int32_t* d_face_mesh, int64_t nf_total,
-                               const MeshInfo* info, double tau, Face64* out, hipStream_t s) {
+                               const MeshInfo* info, double tau, Face64* out, hipStream_t s,
+                               const int32_t* order, const uint8_t* meta) {
   if (nf_total <= 0) return hipSuccess;
   face64_batch_kernel<<<grid_for(nf_total), 256, 0, s>>>(verts, vdtype, tris, d_vert_off, d_tri_off, d_face_mesh,
-                                                         nf_total, info, tau, out);
+                                                         nf_total, info, tau, out, order, meta);
   return hipGetLastError();
 }
 

@@ -219,6 +219,9 @@ def test_batch_validation(lib):
     assert lib.pft_batch_forward(None, 0, V(0x10000), None, None) == _lib.PFT_EINVAL
     b, keep = _batch([0, 3, 6], [0, 1, 2], [0, 0, 0])  # no Q: no-op
     assert lib.pft_batch_forward(ctypes.byref(b), 0, None, None, None) == _lib.PFT_OK
+    # the ordered form needs both the order and its meta
+    assert lib.pft_batch_forward_ordered(ctypes.byref(b), None, V(0x10000), 1, None, None, None) == _lib.PFT_EINVAL
+    assert lib.pft_batch_forward_ordered(ctypes.byref(b), V(0x10000), None, 1, None, None, None) == _lib.PFT_EINVAL
 
 
 def test_validate_mesh_and_profile_host_paths(lib):

@@ -88,6 +88,32 @@ def test_batch_matches_single_mesh_calls(gpu):
         assert nrel(Fb[qo[i]:qo[i + 1]], Fs) < 1e-6
 
 
+def test_batch_edge_sharing_order(gpu):
+    """The batched forward with each mesh's faces in an edge-sharing order (automatic and explicit)
+    agrees with the list order; an out-of-range order entry empties that position without faulting."""
+    meshes = mg.batch_config(seed=9, n_meshes=7, max_faces=5000, min_q=800, max_q=3000)
+    V, T, Q, vo, to, qo = _concat(meshes)
+    Vd, Td, Qd = dev(V, torch.float32), dev(T, torch.int32), dev(Q, torch.float32)
+    step("batch edge-sharing order: automatic against the list order")
+    Fa = host(pft.batch_forward(Vd, Td, Qd, vo, to, qo, mode="fp32c"))
+    Fn = host(pft.batch_forward(Vd, Td, Qd, vo, to, qo, mode="fp32c", order=None))
+    for i in range(len(meshes)):
+        assert nrel(Fa[qo[i]:qo[i + 1]], Fn[qo[i]:qo[i + 1]]) < 2e-6, i
+    step("batch edge-sharing order: explicit, one entry out of range")
+    order, meta = pft.batch_strip_order(T, vo, to)
+    j = int(to[3]) + 5
+    drop = int(order[j])
+    order[j] = -1
+    keep = np.array([k for k in range(int(to[3]), int(to[4])) if k != drop]) - int(to[3])
+    Fx = host(pft.batch_forward(Vd, Td, Qd, vo, to, qo, mode="fp32c", order=(dev(order), dev(meta))))
+    m = meshes[3]
+    Fk = host(pft.forward_3d(dev(m["verts"], torch.float32), dev(m["tris"][keep], torch.int32),
+                             dev(m["q"], torch.float32), mode="fp32c", order=None))
+    assert nrel(Fx[qo[3]:qo[4]], Fk) < 2e-6
+    for i in (0, 1, 2, 4, 5, 6):
+        assert nrel(Fx[qo[i]:qo[i + 1]], Fn[qo[i]:qo[i + 1]]) < 2e-6, i
+
+
 def test_config5_full_size_sampled(gpu):
     """512 uneven meshes in one persistent launch (FP32C fwd + bwd); oracle on sampled meshes / Q / vertices."""
     meshes = mg.config5()
