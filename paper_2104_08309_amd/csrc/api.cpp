@@ -4,11 +4,14 @@
 // device memory from the stream-ordered allocator on the caller's stream,
 // enqueues the prologue / compute / finish kernels on that stream and returns.
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -52,14 +55,70 @@ void ensure_pool() {
   g_pool_ready.push_back(dev);
 }
 
+// Temporary device memory of one call. Each (device, stream) pair keeps a
+// workspace that calls on that stream reuse: stream order makes a call's kernels
+// finish before the next call's kernels touch the same bytes, and the workspace
+// mutex (held from construction to destruction, i.e. while the call enqueues its
+// work) keeps two host threads from interleaving their work on one stream. A
+// call that needs more than the workspace holds takes the rest from the
+// stream-ordered allocator and grows the workspace for the next call, so in a
+// steady loop no allocation or free is issued at all (freeing stream-ordered
+// memory was measured to block the host for about 0.17 ms per free here). An
+// Arena created while the same thread already holds the stream's workspace
+// (a nested call) uses the stream-ordered allocator only.
+struct Workspace {
+  std::mutex mu;
+  std::atomic<std::thread::id> owner{std::thread::id()};
+  char* base = nullptr;
+  size_t cap = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace* workspace_for(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  std::unique_ptr<Workspace>& w = g_ws[{dev, s}];
+  if (!w) w.reset(new Workspace);
+  return w.get();
+}
+
 struct Arena {
-  explicit Arena(hipStream_t s) : s_(s) {}
+  explicit Arena(hipStream_t s) : s_(s) {
+    Workspace* w = workspace_for(s);
+    if (w && w->owner.load() != std::this_thread::get_id()) {
+      w->mu.lock();
+      w->owner.store(std::this_thread::get_id());
+      ws_ = w;
+    }
+  }
   ~Arena() {
     for (void* p : ptrs_) (void)hipFreeAsync(p, s_);
+    if (!ws_) return;
+    if (need_ > ws_->cap) {  // grow for the next call (the old block is freed after this call's work)
+      if (ws_->base) (void)hipFreeAsync(ws_->base, s_);
+      ws_->base = nullptr;
+      ws_->cap = 0;
+      const size_t cap = need_ + need_ / 4;
+      void* b = nullptr;
+      if (hipMallocAsync(&b, cap, s_) == hipSuccess && b != nullptr) {
+        ws_->base = static_cast<char*>(b);
+        ws_->cap = cap;
+      }
+    }
+    ws_->owner.store(std::thread::id());
+    ws_->mu.unlock();
   }
   template <typename T>
   T* get(size_t count) {
-    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    const size_t bytes = (std::max<size_t>(count * sizeof(T), 256) + 255) / 256 * 256;
+    need_ += bytes;
+    if (ws_ && ws_->base && used_ + bytes <= ws_->cap) {
+      T* p = reinterpret_cast<T*>(ws_->base + used_);
+      used_ += bytes;
+      return p;
+    }
     void* p = nullptr;
     if (hipMallocAsync(&p, bytes, s_) != hipSuccess || p == nullptr) {
       failed = true;
@@ -72,6 +131,8 @@ struct Arena {
 
  private:
   hipStream_t s_;
+  Workspace* ws_ = nullptr;
+  size_t used_ = 0, need_ = 0;
   std::vector<void*> ptrs_;
 };
 
@@ -334,6 +395,16 @@ pft_status pft_release_workspace(void) {
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetDefaultMemPool");
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  {  // the per-stream workspaces of this device (none is in use: the calls that hold them are synchronous)
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto& kv : g_ws) {
+      if (kv.first.first != dev || !kv.second) continue;
+      std::lock_guard<std::mutex> wl(kv.second->mu);
+      if (kv.second->base) (void)hipFree(kv.second->base);
+      kv.second->base = nullptr;
+      kv.second->cap = 0;
+    }
+  }
   e = hipMemPoolTrimTo(pool, 0);
   if (e != hipSuccess) return hip_fail(e, "hipMemPoolTrimTo");
   return PFT_OK;
