@@ -21,8 +21,11 @@
  *    library never allocates or frees caller memory.
  *  - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
  *    legacy default stream) and is asynchronous; outputs are valid once the
- *    stream has reached that point. Temporary device memory is taken from the
- *    stream-ordered allocator on the same stream and released in stream order.
+ *    stream has reached that point. Temporary device memory comes from a
+ *    workspace the library keeps per (device, stream), reused by later calls on
+ *    that stream and grown through the stream-ordered allocator when needed;
+ *    pft_release_workspace frees it. Calls from several host threads on one
+ *    stream are serialised while they enqueue.
  *  - Return value: PFT_OK after synchronous argument validation and a
  *    successful launch, or an error code; the message is available from
  *    pft_last_error() on the calling thread. Device-side faults surface at the
@@ -361,7 +364,8 @@ pft_status pft_validate_mesh(const int32_t* tris, int64_t nf, int64_t nv, int64_
 /* Message for the last non-OK status returned on the calling thread ("" if none). */
 const char* pft_last_error(void);
 
-/* Return cached stream-ordered temporary memory of the current device to the system. */
+/* Free the per-stream workspaces of the current device and return cached
+ * stream-ordered memory to the system (synchronises the device). */
 pft_status pft_release_workspace(void);
 
 /*
