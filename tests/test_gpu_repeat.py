@@ -75,3 +75,37 @@ def test_regions_loss_poly_orientation_and_batch_repeat(gpu):
     a, b = twice(lambda: (pft.batch_forward(BV, BT, BQ, vo, to, qo, mode="fp32c"),
                           pft.batch_backward(BV, BT, BQ, vo, to, qo, BG, mode="fp32c")))
     assert same(a, b)
+
+
+def test_workspace_streams_threads_and_release(gpu):
+    """Temporaries live in a per-stream workspace: calls on two streams from two host threads at once,
+    and calls after pft_release_workspace, give the same bytes as a plain call."""
+    import threading
+    rng = np.random.default_rng(62)
+    v, t = mg.icosphere(3, 1.3)
+    V, T = dev(v, torch.float32), dev(t, torch.int32)
+    Qs = [dev(mg.q_random_ball(9000 + 1000 * i, 6.0, rng), torch.float32) for i in range(2)]
+    step("workspace: reference calls")
+    ref = [host(pft.forward_3d(V, T, Q, mode="fp32c")) for Q in Qs]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    got = [None, None]
+
+    def work(i):
+        with torch.cuda.stream(streams[i]):
+            for _ in range(3):
+                F = pft.forward_3d(V, T, Qs[i], mode="fp32c")
+            streams[i].synchronize()
+            got[i] = host(F)
+
+    step("workspace: two streams from two threads")
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    for i in range(2):
+        assert np.array_equal(got[i].view(np.uint8), ref[i].view(np.uint8))
+    step("workspace: release and call again")
+    pft.release_workspace()
+    again = host(pft.forward_3d(V, T, Qs[0], mode="fp32c"))
+    assert np.array_equal(again.view(np.uint8), ref[0].view(np.uint8))
