@@ -42,6 +42,7 @@ sys.path.insert(0, ROOT)
 FLOP_FWD = 104.0
 FLOP_BWD = 200.0
 FLOP_DQ = 246.0
+FLOP_2D = 21.0    # per edge-Q pair of the 2D edge sum (binary64)
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (AMD published)
 PEAK_FP64_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
@@ -87,6 +88,16 @@ def _oracle_chunk(args):
     return F, G, t1 - t0, t2 - t1
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(v, t, q_sample, g_sample, n_chunks):
     import multiprocessing as mp
 
@@ -114,6 +125,7 @@ def main():
     ap.add_argument("--no-poly", action="store_true", help="skip the polygon-face measurement")
     ap.add_argument("--no-loss", action="store_true", help="skip the fused intensity-loss measurement (config 4)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (config 5) and 2D (config 1) measurements")
+    ap.add_argument("--no-config3", action="store_true", help="skip the union-of-spheres forward (config 3)")
     ap.add_argument("--no-regions", action="store_true",
                     help="skip the grad_Q and multi-region (piecewise-constant density) measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -401,8 +413,10 @@ def main():
         t2, F2 = timed(lambda: pft.forward_2d(P2, Q2d), max(10, args.steps), 2)
         n_2, ms_2 = pft.profile_read("fwd2d_fp64")
         ne, nq2 = c1["verts"].shape[0], c1["q"].shape[0]
+        k2 = ms_2 / max(n_2, 1)
         fwd2d = {"workload": f"config 1: star polygon, {ne} edges x {nq2} Q (128^2 grid over [-20,20)^2), binary64",
-                 "ms_per_call": t2 * 1e3, "kernel_ms": ms_2 / max(n_2, 1), "edge_q_per_s": ne * nq2 / t2}
+                 "ms_per_call": t2 * 1e3, "kernel_ms": k2, "edge_q_per_s": ne * nq2 / t2,
+                 "fp64_alu_frac": FLOP_2D * ne * nq2 / (k2 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
         if not args.no_cpu_baseline:
             import oracle as O
             F2o = O.ft2d(c1["verts"], c1["q"])
@@ -422,6 +436,34 @@ def main():
                 eb.append(float(np.linalg.norm(BDh[vo[i]:vo[i + 1]] - Go) / np.linalg.norm(Go)))
             batch["forward_rel_err_vs_oracle_4_meshes"] = max(ef)
             batch["adjoint_rel_err_vs_oracle_4_meshes"] = max(eb)
+
+    # config 3: the union of 20 spheres (about 1e5 faces) x a 128^3 Q grid, FP32C forward with |F|^2
+    union = None
+    if not args.no_config3:
+        print("[bench] union of spheres (config 3)", file=sys.stderr, flush=True)
+        c3 = mg.config3()
+        V3 = torch.tensor(c3["verts"], dtype=torch.float32, device=dev)
+        T3 = torch.tensor(c3["tris"], dtype=torch.int32, device=dev)
+        Q3 = torch.tensor(c3["q"], dtype=torch.float32, device=dev)
+        t3, (F3, I3) = timed(lambda: pft.forward_3d(V3, T3, Q3, mode="fp32c", intensity=True), 2, 1)
+        n_3, ms_3 = pft.profile_read("fwd3d_fp32c")
+        ms_3 = ms_3 / max(n_3, 1)
+        nf3, nq3 = c3["tris"].shape[0], c3["q"].shape[0]
+        union = {"workload": f"config 3: union of 20 spheres ({nf3} faces) x 128^3 Q over [-0.3,0.3)^3, FP32C "
+                             f"forward with |F|^2 (edge-sharing order)",
+                 "ms_per_call": t3 * 1e3, "kernel_ms": ms_3, "face_q_per_s": nf3 * nq3 / t3,
+                 "alu_frac": FLOP_FWD * nf3 * nq3 / (ms_3 * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+        if not args.no_cpu_baseline:
+            import oracle as O
+            srng = np.random.default_rng(14)
+            pick = np.concatenate([[int(np.argmin(np.linalg.norm(c3["q"], axis=1)))], srng.choice(nq3, 63, replace=False)])
+            Fo3 = O.ft3d(c3["verts"].astype(np.float32).astype(np.float64), c3["tris"],
+                         c3["q"][pick].astype(np.float32).astype(np.float64))
+            F3h = F3.cpu().numpy().astype(np.complex128)[pick]
+            union["rel_err_vs_oracle_sample"] = float(np.linalg.norm(F3h - Fo3) / np.linalg.norm(Fo3))
+            union["max_err_over_max_F_sample"] = float(np.max(np.abs(F3h - Fo3)) / np.max(np.abs(Fo3)))
+            union["oracle_sample"] = "64 grid Q incl. Q = 0, all faces"
+        del V3, T3, Q3, F3, I3
 
     # roofline of the dominant kernel (the longer of the forward and adjoint kernels)
     def roof(kernel, ms, flop):
@@ -448,11 +490,22 @@ def main():
                "sample": f"{qs.shape[0]} of the {nq} grid Q (seeded, incl. Q=0, axes, diagonal), all {nf} faces, "
                          f"forward + vertex gradient, {wall:.1f} s wall"}
         acc["fwd_rel_err_vs_oracle_sample"] = float(np.linalg.norm(F32h[idx] - Fo) / np.linalg.norm(Fo))
+        acc["fwd_max_err_over_max_F_sample"] = float(np.max(np.abs(F32h[idx] - Fo)) / np.max(np.abs(Fo)))
         # the adjoint over the sample only: run the FP32C kernel on the same Q subset
         Gsub = pft.backward_3d(V, T, torch.tensor(qs, dtype=torch.float32, device=dev),
                                torch.tensor(gs.astype(np.complex64), device=dev), mode="fp32c").cpu().numpy()
         Go32 = Go  # oracle at float64 inputs; the kernel sees float32 Q and vertices
         acc["bwd_rel_err_vs_oracle_sample"] = float(np.linalg.norm(Gsub - Go32) / np.linalg.norm(Go32))
+        acc["bwd_max_err_over_max_grad_sample"] = float(np.max(np.abs(Gsub - Go32)) / np.max(np.abs(Go32)))
+        # one host core on a smaller sample of the same Q (the oracle as it stands, one process, one BLAS thread)
+        from threadpoolctl import threadpool_limits
+        sub = idx[: max(64, args.cpu_sample // 16)]
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            _oracle_chunk((v, t, q[sub], g[sub]))
+            cpu["single_core_value"] = nf * len(sub) / (time.perf_counter() - t1)
+        cpu["single_core_sample"] = f"{len(sub)} of the same Q, one process, one BLAS thread"
+        cpu["cpu_model"] = _cpu_model()
 
     line = {
         "metric": "face*Q evals/sec fwd+bwd, FP32-compensated vs FP64 GPU at <=1e-5 rel err",
@@ -484,6 +537,7 @@ def main():
         "intensity_loss": lossf,
         "batch": batch,
         "forward_2d": fwd2d,
+        "union_of_spheres": union,
     }
     print(json.dumps(line), flush=True)
 
