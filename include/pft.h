@@ -266,14 +266,19 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
  *  out             [nq] complex (complex128 for PFT_FP64, complex64 for PFT_FP32C).
  *  out_regions     NULL or [nreg][nq] complex of the same type: F_j, which is
  *                  also dF/drho_j.
+ *  face_order, face_meta  NULL, or an edge-sharing order as for
+ *                  pft_forward_3d_ordered that keeps every face within its
+ *                  region's range (DEVICE; both or neither; used by FP32C).
  * Temporaries: about (nreg + 40) * nq * 16 bytes of partial sums.
  * Errors: as pft_forward_3d; EINVAL also for bad offsets, offsets that do not
- * end at nf, nreg outside 0 .. 4096, or rho NULL with nreg > 0.
+ * end at nf, nreg outside 0 .. 4096, rho NULL with nreg > 0, or only one of
+ * face_order, face_meta given.
  */
 pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                   const int64_t* region_offsets, int64_t nreg, const double* rho, const void* q,
                                   pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* out_regions,
-                                  void* intensity, void* stream);
+                                  void* intensity, const int32_t* face_order, const uint8_t* face_meta,
+                                  void* stream);
 
 /*
  * pft_backward_3d_regions -- gradients of a real loss L(F) with

@@ -74,7 +74,8 @@ def load() -> ctypes.CDLL:
         "pft_strip_order": [vp, i64, i64, vp, vp],
         "pft_forward_3d_ordered": [vp, cint, i64, vp, i64, vp, vp, vp, cint, i64, cint, vp, vp, vp],
         "pft_intensity_loss_3d": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp, vp, vp, vp, vp, vp],
-        "pft_forward_3d_regions": [vp, cint, i64, vp, i64, P(i64), i64, vp, vp, cint, i64, cint, vp, vp, vp, vp],
+        "pft_forward_3d_regions": [vp, cint, i64, vp, i64, P(i64), i64, vp, vp, cint, i64, cint, vp, vp, vp, vp, vp,
+                                   vp],
         "pft_backward_3d_regions": [vp, cint, i64, vp, i64, P(i64), i64, vp, vp, cint, i64, cint, vp, vp, vp, vp,
                                     vp],
         "pft_validate_mesh": [vp, i64, i64, P(i64), P(i64), vp],

@@ -317,13 +317,16 @@ def _regions(region_offsets, nf: int, rho: torch.Tensor, device):
 
 
 def forward_3d_regions(verts: torch.Tensor, tris: torch.Tensor, region_offsets, rho: torch.Tensor, q: torch.Tensor,
-                       mode: str = "fp32c", per_region: bool = False, intensity: bool = False):
+                       mode: str = "fp32c", per_region: bool = False, intensity: bool = False, order="auto"):
     """F = sum_j rho_j F_j for a density rho_j constant on closed region j, whose outward boundary is
     triangles region_offsets[j] .. region_offsets[j+1] (host offsets; rho float64 on the device).
 
     Returns F, with F_j [nreg, nq] (= dF/drho) when ``per_region`` and |F|^2 when ``intensity``
-    appended in that order.
+    appended in that order. ``order``: "auto" (FP32C: each region's faces in an edge-sharing order,
+    cached per triangle tensor and offsets), None, or (order, meta) device tensors that keep every face
+    within its region.
     """
+    tris_key = tris
     verts, tris = _mesh(verts, tris)
     q = _qlist(q, verts.device)
     off, rho = _regions(region_offsets, tris.shape[0], rho, verts.device)
@@ -333,11 +336,21 @@ def forward_3d_regions(verts: torch.Tensor, tris: torch.Tensor, region_offsets, 
     out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
     regs = torch.empty((off.size - 1, q.shape[0]), dtype=cdt, device=verts.device) if per_region else None
     inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
+    if isinstance(order, str):
+        if order != "auto":
+            raise ValueError(f"order must be 'auto', None or (order, meta), got {order!r}")
+        use = m == PFT_FP32C and isinstance(tris_key, torch.Tensor) and tris.shape[0] >= _AUTO_ORDER_MIN_FACES
+        # regions are ranges of one triangle list over shared vertices: order each range on its own
+        nvs = np.full(off.size, verts.shape[0], dtype=np.int64)
+        nvs[0] = 0
+        order = _batch_auto_order(tris_key, (np.cumsum(nvs), off), verts.device) if use else None
+    fo, fm = _order_arg(order, None, tris, verts.shape[0], m) if order is not None else (None, None)
     with torch.cuda.device(verts.device):
         check(_lib.load().pft_forward_3d_regions(
             _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0],
             off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), off.size - 1, _ptr(rho), _ptr(q),
-            _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(regs), _ptr(inten), _stream(verts.device)))
+            _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(regs), _ptr(inten), _ptr(fo), _ptr(fm),
+            _stream(verts.device)))
     res = (out,) + ((regs,) if per_region else ()) + ((inten,) if intensity else ())
     return res[0] if len(res) == 1 else res
 

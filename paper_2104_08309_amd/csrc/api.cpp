@@ -1042,10 +1042,13 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
 pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                   const int64_t* region_offsets, int64_t nreg, const double* rho, const void* q,
                                   pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* out_regions,
-                                  void* intensity, void* stream) {
+                                  void* intensity, const int32_t* face_order, const uint8_t* face_meta,
+                                  void* stream) {
   pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
   if (st != PFT_OK) return st;
   if ((st = check_regions(region_offsets, nreg, nf, rho)) != PFT_OK) return st;
+  if ((face_order == nullptr) != (face_meta == nullptr)) return fail(PFT_EINVAL, "face_order and face_meta go together");
+  if (face_order && !aligned(face_order, 4)) return fail(PFT_EINVAL, "face_order misaligned");
   const bool c128 = mode == PFT_FP64;
   if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
   if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
@@ -1064,7 +1067,10 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   double2* partial = ar.get<double2>((size_t)std::max(plan.splits, 1) * nq);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
   hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
-  if (e == hipSuccess) e = launch_face64(verts, vdtype, nv, tris, nf, info, c128 ? kTauF64 : kTauF32, f64, s);
+  const bool ordered = face_order != nullptr && !c128 && nf > 0;
+  if (e == hipSuccess)
+    e = launch_face64(verts, vdtype, nv, tris, nf, info, c128 ? kTauF64 : kTauF32, f64, s,
+                      ordered ? face_order : nullptr, ordered ? face_meta : nullptr);
   if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
   if (e != hipSuccess) return hip_fail(e, "3D prologue");
   uint32_t* perm = nullptr;
@@ -1085,6 +1091,7 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   a.out = out;
   a.intensity = intensity;
   a.tau0 = c128 ? kTau0F64 : kTau0F32;
+  a.share_edges = ordered ? 1 : 0;
   if (plan.splits > 0) {
     const char* nm = main_name(true, mode);
     prof_begin(nm, s);

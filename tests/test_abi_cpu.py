@@ -128,9 +128,10 @@ def test_regions_validation(lib):
     ok = (ctypes.c_int64 * 3)(0, 4, 10)
     short = (ctypes.c_int64 * 3)(0, 4, 9)      # does not end at nf = 10
     down = (ctypes.c_int64 * 3)(0, 6, 4)
-    # verts, vdtype, nv, tris, nf, region_offsets, nreg, rho, q, qdtype, nq, mode, out, out_regions, intensity, stream
-    args = lambda off=ok, nreg=2, rho=V(good), out=V(good), oreg=None, nq=4: (
-        V(good), 1, 8, V(good), 10, cast(off), nreg, rho, V(good), 1, nq, 1, out, oreg, None, None)
+    # verts, vdtype, nv, tris, nf, region_offsets, nreg, rho, q, qdtype, nq, mode, out, out_regions, intensity,
+    # face_order, face_meta, stream
+    args = lambda off=ok, nreg=2, rho=V(good), out=V(good), oreg=None, nq=4, fo=None: (
+        V(good), 1, 8, V(good), 10, cast(off), nreg, rho, V(good), 1, nq, 1, out, oreg, None, fo, None, None)
     assert f(*args(off=short)) == _lib.PFT_EINVAL
     assert b"end at nf" in lib.pft_last_error()
     assert f(*args(off=down)) == _lib.PFT_EINVAL
@@ -140,8 +141,9 @@ def test_regions_validation(lib):
     assert f(*args(rho=V(good + 4))) == _lib.PFT_EINVAL
     assert f(*args(out=None)) == _lib.PFT_EINVAL
     assert f(*args(oreg=V(good + 4))) == _lib.PFT_EINVAL
-    assert f(V(good), 1, 8, V(good), 10, cast(ok), 2, V(good), V(good), 1, 4, 7, V(good), None, None, None) == \
-        _lib.PFT_EUNSUPPORTED
+    assert f(V(good), 1, 8, V(good), 10, cast(ok), 2, V(good), V(good), 1, 4, 7, V(good), None, None, None, None,
+             None) == _lib.PFT_EUNSUPPORTED
+    assert f(*args(fo=V(good))) == _lib.PFT_EINVAL  # an order without its meta
     assert f(*args(nq=0)) == _lib.PFT_OK  # no Q: a valid no-op
     # verts, vdtype, nv, tris, nf, offsets, nreg, rho, q, qdtype, nq, mode, grad_out, gv, grho, gq, stream
     bargs = lambda go=V(good), gv=None, gr=None, gq=None, off=ok: (
