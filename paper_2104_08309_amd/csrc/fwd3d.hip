@@ -12,6 +12,8 @@
 //    coordinates, the face origin phase Q.g reduced in binary64 and
 //    evaluated in turns, the near-degenerate series branch in binary64, the
 //    sum over faces blocked per LDS tile and compensated (Kahan) across tiles.
+//    With the records in an edge-sharing order (Face32::link) a face takes
+//    the term of the edge it shares with its predecessor from registers.
 #include "fwd_terms.h"
 
 namespace pft {
