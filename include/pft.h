@@ -136,24 +136,41 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
 pft_status pft_strip_order(const int32_t* tris, int64_t nf, int64_t nv, int32_t* order, uint8_t* meta);
 
 /*
+ * pft_q_order -- the order in which the kernels visit a Q list: sorted by the
+ * Morton code of Q (nearby Q share wavefronts; below 8192 Q, the list order).
+ * Each Q's F does not depend on the order; the adjoint's sums over Q follow it.
+ * Computing it once and passing it to pft_forward_3d_ordered and
+ * pft_backward_3d_ordered saves the sort in every call on the same Q.
+ *  q      [nq][3] of qdtype (DEVICE).
+ *  order  [nq] uint32 (DEVICE), written: a permutation of 0 .. nq-1.
+ * Errors: EINVAL for NULL pointers with nq > 0, misalignment or nq > 2^32 - 1.
+ */
+pft_status pft_q_order(const void* q, pft_dtype qdtype, int64_t nq, uint32_t* order, void* stream);
+
+/*
  * pft_forward_3d_ordered -- pft_forward_3d with the faces taken in an
- * edge-sharing order (pft_strip_order, copied to the device). The sum over
- * faces is unchanged (eq. sum_elements_3d; only the rounding order differs);
- * in the FP32-compensated form the term sinc(Q.d/2) exp(iQ.m) of an edge
- * shared with the previous face is reused, so a face costs two edge terms
- * instead of three.
+ * edge-sharing order (pft_strip_order, copied to the device) and/or the Q
+ * visited in a given order (pft_q_order). The sum over faces is unchanged
+ * (eq. sum_elements_3d; only the rounding order differs); in the
+ * FP32-compensated form the term sinc(Q.d/2) exp(iQ.m) of an edge shared with
+ * the previous face is reused, so a face costs two edge terms instead of three.
  *
  *  Arguments as pft_forward_3d, plus
- *  face_order  [nf] int32 (DEVICE), a permutation of 0 .. nf-1 (an entry out
- *              of range makes that position an empty face);
- *  face_meta   [nf] uint8 (DEVICE), as written by pft_strip_order. A wrong
- *              link gives a wrong result, never an out-of-bounds access.
- * Errors: as pft_forward_3d; EINVAL also for face_order or face_meta NULL with nf > 0.
+ *  face_order  NULL (the list order) or [nf] int32 (DEVICE), a permutation
+ *              of 0 .. nf-1 (an entry out of range makes that position an
+ *              empty face);
+ *  face_meta   NULL with face_order, else [nf] uint8 (DEVICE), as written by
+ *              pft_strip_order. A wrong link gives a wrong result, never an
+ *              out-of-bounds access.
+ *  q_order     NULL (sorted here) or [nq] uint32 (DEVICE), a permutation of
+ *              0 .. nq-1 (an entry out of range is replaced by its position).
+ * Errors: as pft_forward_3d; EINVAL also for only one of face_order,
+ * face_meta given.
  */
 pft_status pft_forward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                   const int32_t* face_order, const uint8_t* face_meta, const void* q,
                                   pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* intensity,
-                                  void* stream);
+                                  const uint32_t* q_order, void* stream);
 
 /*
  * pft_forward_3d_poly -- F(Q) of the volume enclosed by planar polygon faces
@@ -221,6 +238,17 @@ pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t 
 pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                            const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
                            void* grad_verts, void* stream);
+
+/*
+ * pft_backward_3d_ordered -- pft_backward_3d visiting the Q in a given order
+ * (pft_q_order) instead of sorting them in the call.
+ *  q_order  NULL (sorted here) or [nq] uint32 (DEVICE), a permutation of
+ *           0 .. nq-1 (an entry out of range is replaced by its position).
+ * Errors: as pft_backward_3d.
+ */
+pft_status pft_backward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                   const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
+                                   void* grad_verts, const uint32_t* q_order, void* stream);
 
 /*
  * pft_intensity_loss_3d -- the intensity loss

@@ -19,6 +19,7 @@ EXPORTS = [
     "pft_forward_2d", "pft_forward_3d", "pft_backward_3d", "pft_batch_forward", "pft_batch_backward",
     "pft_forward_3d_poly", "pft_orientation_average", "pft_forward_3d_regions", "pft_backward_3d_regions",
     "pft_intensity_loss_3d", "pft_strip_order", "pft_forward_3d_ordered", "pft_batch_forward_ordered",
+    "pft_q_order", "pft_backward_3d_ordered",
     "pft_validate_mesh", "pft_last_error", "pft_release_workspace", "pft_profile_enable",
     "pft_profile_reset", "pft_profile_read", "pft_version",
 ]
@@ -72,7 +73,9 @@ def load() -> ctypes.CDLL:
         "pft_orientation_average": [vp, cint, i64, vp, i64, vp, i64, vp, vp, i64, cint, vp, vp, vp, vp],
         "pft_forward_3d_poly": [vp, cint, i64, P(i64), vp, i64, vp, cint, i64, cint, vp, vp, vp],
         "pft_strip_order": [vp, i64, i64, vp, vp],
-        "pft_forward_3d_ordered": [vp, cint, i64, vp, i64, vp, vp, vp, cint, i64, cint, vp, vp, vp],
+        "pft_forward_3d_ordered": [vp, cint, i64, vp, i64, vp, vp, vp, cint, i64, cint, vp, vp, vp, vp],
+        "pft_q_order": [vp, cint, i64, vp, vp],
+        "pft_backward_3d_ordered": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp, vp],
         "pft_intensity_loss_3d": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp, vp, vp, vp, vp, vp],
         "pft_forward_3d_regions": [vp, cint, i64, vp, i64, P(i64), i64, vp, vp, cint, i64, cint, vp, vp, vp, vp, vp,
                                    vp],

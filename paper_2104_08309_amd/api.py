@@ -20,7 +20,7 @@ from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
 __all__ = [
     "forward_2d", "forward_3d", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
     "orientation_average", "forward_3d_regions", "backward_3d_regions", "intensity_loss_3d", "strip_order",
-    "batch_strip_order",
+    "batch_strip_order", "q_order",
     "validate_mesh",
     "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
 ]
@@ -155,16 +155,62 @@ def _order_arg(order, tris_key, tris: torch.Tensor, nv: int, m: int):
     return fo, fm
 
 
+def q_order(q: torch.Tensor) -> torch.Tensor:
+    """The kernels' visiting order of a Q list (pft_q_order): uint32 [nq] on the device, computed there."""
+    q = _on_gpu(q, "q")
+    if q.dim() != 2 or q.shape[1] != 3:
+        raise ValueError(f"q must have shape [nq, 3], got {tuple(q.shape)}")
+    out = torch.empty(q.shape[0], dtype=torch.uint32, device=q.device)
+    with torch.cuda.device(q.device):
+        check(_lib.load().pft_q_order(_ptr(q), _real_dtype_id(q, "q"), q.shape[0], _ptr(out), _stream(q.device)))
+    return out
+
+
+# Visiting orders of Q tensors seen by forward_3d / backward_3d (q_order="auto"), keyed and checked
+# like the face orders; below the sorting size the kernels keep the list order and nothing is cached.
+_Q_ORDER_CACHE: dict = {}
+_Q_ORDER_MIN = 8192
+
+
+def _q_order_arg(q_order, q_key, q: torch.Tensor):
+    if isinstance(q_order, str):
+        if q_order != "auto":
+            raise ValueError(f"q_order must be 'auto', None or a uint32 tensor, got {q_order!r}")
+        if not isinstance(q_key, torch.Tensor) or q.shape[0] < _Q_ORDER_MIN:
+            return None
+        stamp = (q_key.data_ptr(), tuple(q_key.shape), q_key._version, q_key.dtype)
+        hit = _Q_ORDER_CACHE.get(id(q_key))
+        if hit is not None and hit[0]() is q_key and hit[1] == stamp:
+            return hit[2]
+        perm = q_order_fn(q)
+        if len(_Q_ORDER_CACHE) >= 64:
+            for k in [k for k, e in _Q_ORDER_CACHE.items() if e[0]() is None]:
+                del _Q_ORDER_CACHE[k]
+        _Q_ORDER_CACHE[id(q_key)] = (weakref.ref(q_key), stamp, perm)
+        return perm
+    if q_order is None:
+        return None
+    qo = _on_gpu(q_order, "q_order")
+    if qo.dtype != torch.uint32 or qo.numel() != q.shape[0] or qo.device != q.device:
+        raise ValueError("q_order must be a uint32 [nq] tensor on the device of q")
+    return qo
+
+
+q_order_fn = q_order
+
+
 def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: str = "fp32c",
-               intensity: bool = False, order="auto"):
+               intensity: bool = False, order="auto", q_order="auto"):
     """F(Q) of the closed mesh; complex128 for mode 'fp64', complex64 for 'fp32c'.
 
     Returns F, or (F, |F|^2) when ``intensity`` is True. ``order``: "auto" (FP32C meshes of 256 faces
     or more are evaluated in an edge-sharing face order, computed on the host at the first call for
     a triangle tensor and reused while it is unchanged), None (the list order), or a pair of device
-    tensors (order int32, meta uint8) from ``strip_order``.
+    tensors (order int32, meta uint8) from ``strip_order``. ``q_order``: "auto" (the visiting order of
+    Q, computed on the device once per Q tensor and reused while it is unchanged), None (sorted in
+    the call), or a uint32 tensor from ``q_order``.
     """
-    tris_key = tris
+    tris_key, q_key = tris, q
     verts, tris = _mesh(verts, tris)
     q = _qlist(q, verts.device)
     m = mode_id(mode)
@@ -173,15 +219,16 @@ def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: s
     out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
     inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
     fo, fm = _order_arg(order, tris_key, tris, verts.shape[0], m)
+    qo = _q_order_arg(q_order, q_key, q)
     with torch.cuda.device(verts.device):
-        if fo is None:
+        if fo is None and qo is None:
             check(_lib.load().pft_forward_3d(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0],
                                              _ptr(tris), tris.shape[0], _ptr(q), _real_dtype_id(q, "q"),
                                              q.shape[0], m, _ptr(out), _ptr(inten), _stream(verts.device)))
         else:
             check(_lib.load().pft_forward_3d_ordered(
                 _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(fo),
-                _ptr(fm), _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(inten),
+                _ptr(fm), _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(inten), _ptr(qo),
                 _stream(verts.device)))
     return (out, inten) if intensity else out
 
@@ -248,8 +295,10 @@ def orientation_average(verts: torch.Tensor, tris: torch.Tensor, qabs: torch.Ten
 
 
 def backward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, grad_out: torch.Tensor,
-                mode: str = "fp32c") -> torch.Tensor:
-    """dL/dverts for grad_out = dL/dReF + i dL/dImF; same dtype and shape as verts."""
+                mode: str = "fp32c", q_order="auto") -> torch.Tensor:
+    """dL/dverts for grad_out = dL/dReF + i dL/dImF; same dtype and shape as verts. ``q_order`` as for
+    forward_3d."""
+    q_key = q
     verts, tris = _mesh(verts, tris)
     q = _qlist(q, verts.device)
     m = mode_id(mode)
@@ -259,10 +308,11 @@ def backward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, grad_o
         raise ValueError("grad_out must have one entry per Q")
     g = g.to(cdt).contiguous()
     grad = torch.empty_like(verts)
+    qo = _q_order_arg(q_order, q_key, q)
     with torch.cuda.device(verts.device):
-        check(_lib.load().pft_backward_3d(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris),
-                                          tris.shape[0], _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(g),
-                                          _ptr(grad), _stream(verts.device)))
+        check(_lib.load().pft_backward_3d_ordered(
+            _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(q),
+            _real_dtype_id(q, "q"), q.shape[0], m, _ptr(g), _ptr(grad), _ptr(qo), _stream(verts.device)))
     return grad
 
 

@@ -294,6 +294,14 @@ pft_status build_qorder(Arena& ar, const void* q, int qdtype, int64_t nq, const 
 
 // The adjoint's Q records: Q in visiting order with their centred cotangents
 // (binary32 records for FP32C, binary64 records for FP64; the other is NULL).
+// A caller's Q visiting order (a permutation of 0 .. nq-1), clamped into range on the device.
+pft_status caller_qorder(Arena& ar, const uint32_t* q_order, int64_t nq, uint32_t** perm, hipStream_t s) {
+  *perm = ar.get<uint32_t>(std::max<int64_t>(nq, 1));
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_clamp_perm(q_order, nq, *perm, s);
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "Q order");
+}
+
 // The same records for a visiting order already built (perm NULL: the caller's order).
 pft_status qrecs_from_perm(Arena& ar, int mode, const void* q, int qdtype, const void* grad_out, int64_t nq,
                            const MeshInfo* info, const int64_t* d_q_off, int64_t n_meshes, uint32_t* perm,
@@ -530,7 +538,8 @@ namespace {
 // `out` may be NULL when only |F|^2 is wanted.
 pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                           const void* q, int qdtype, int64_t nq, int mode, void* out, void* intensity,
-                          hipStream_t s, const int32_t* order = nullptr, const uint8_t* meta = nullptr) {
+                          hipStream_t s, const int32_t* order = nullptr, const uint8_t* meta = nullptr,
+                          const uint32_t* q_order = nullptr) {
   const bool c128 = mode == PFT_FP64;
   pft_status st = PFT_OK;
   MeshInfo* info = ar.get<MeshInfo>(1);
@@ -547,7 +556,8 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
   if (e != hipSuccess) return hip_fail(e, "3D prologue");
   uint32_t* perm = nullptr;
-  if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
+  st = q_order ? caller_qorder(ar, q_order, nq, &perm, s) : build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s);
+  if (st != PFT_OK) return st;
   FwdArgs a;
   a.f64 = f64;
   a.f32 = f32;
@@ -647,12 +657,13 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
 pft_status pft_forward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                                   const int32_t* face_order, const uint8_t* face_meta, const void* q,
                                   pft_dtype qdtype, int64_t nq, pft_mode mode, void* out, void* intensity,
-                                  void* stream) {
+                                  const uint32_t* q_order, void* stream) {
   pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
   if (st != PFT_OK) return st;
   const bool c128 = mode == PFT_FP64;
-  if (nf > 0 && (face_order == nullptr || face_meta == nullptr)) return fail(PFT_EINVAL, "face_order or face_meta is NULL");
+  if ((face_order == nullptr) != (face_meta == nullptr)) return fail(PFT_EINVAL, "face_order and face_meta go together");
   if (face_order && !aligned(face_order, 4)) return fail(PFT_EINVAL, "face_order misaligned");
+  if (q_order && !aligned(q_order, 4)) return fail(PFT_EINVAL, "q_order misaligned");
   if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
   if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
   if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
@@ -662,7 +673,25 @@ pft_status pft_forward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t n
   ensure_pool();
   Arena ar(s);
   return forward3d_core(ar, verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, out, intensity, s,
-                        nf > 0 ? face_order : nullptr, nf > 0 ? face_meta : nullptr);
+                        nf > 0 ? face_order : nullptr, nf > 0 ? face_meta : nullptr, q_order);
+}
+
+pft_status pft_q_order(const void* q, pft_dtype qdtype, int64_t nq, uint32_t* order, void* stream) {
+  if (qdtype != PFT_F32 && qdtype != PFT_F64) return fail(PFT_EUNSUPPORTED, "unknown q dtype");
+  if (nq < 0) return fail(PFT_EINVAL, "negative count");
+  if (nq > UINT32_MAX) return fail(PFT_EINVAL, "too many Q for 32-bit order entries");
+  if (nq > 0 && (q == nullptr || order == nullptr)) return fail(PFT_EINVAL, "q or order is NULL");
+  if ((q && !aligned(q, real_size(qdtype))) || (order && !aligned(order, 4))) return fail(PFT_EINVAL, "argument misaligned");
+  if (nq == 0) return PFT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ensure_pool();
+  Arena ar(s);
+  uint32_t* perm = nullptr;
+  pft_status st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s);
+  if (st != PFT_OK) return st;
+  hipError_t e = perm ? hipMemcpyAsync(order, perm, sizeof(uint32_t) * nq, hipMemcpyDeviceToDevice, s)
+                      : launch_iota_u32(order, nq, s);  // below the sorting size: the list order
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "Q order");
 }
 
 pft_status pft_strip_order(const int32_t* tris, int64_t nf, int64_t nv, int32_t* order, uint8_t* meta) {
@@ -866,11 +895,12 @@ pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t 
   return e == hipSuccess ? PFT_OK : hip_fail(e, "orientation sum");
 }
 
-pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
-                           const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
-                           void* grad_verts, void* stream) {
+static pft_status backward3d_impl(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                  const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
+                                  void* grad_verts, const uint32_t* q_order, void* stream) {
   pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
   if (st != PFT_OK) return st;
+  if (q_order && !aligned(q_order, 4)) return fail(PFT_EINVAL, "q_order misaligned");
   const bool c128 = mode == PFT_FP64;
   if (nq > 0 && grad_out == nullptr) return fail(PFT_EINVAL, "grad_out is NULL");
   if (nv > 0 && grad_verts == nullptr) return fail(PFT_EINVAL, "grad_verts is NULL");
@@ -902,7 +932,14 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   if (e != hipSuccess) return hip_fail(e, "adjoint prologue");
   QRec32* rec = nullptr;
   QRec64* rec64 = nullptr;
-  if ((st = build_qrecs(ar, mode, q, qdtype, grad_out, nq, info, nullptr, 1, &rec, &rec64, s)) != PFT_OK) return st;
+  if (q_order) {
+    uint32_t* perm = nullptr;
+    if ((st = caller_qorder(ar, q_order, nq, &perm, s)) != PFT_OK) return st;
+    st = qrecs_from_perm(ar, mode, q, qdtype, grad_out, nq, info, nullptr, 1, perm, &rec, &rec64, s);
+  } else {
+    st = build_qrecs(ar, mode, q, qdtype, grad_out, nq, info, nullptr, 1, &rec, &rec64, s);
+  }
+  if (st != PFT_OK) return st;
   BwdArgs a;
   a.info = info;
   a.f64 = f64;
@@ -925,6 +962,18 @@ pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, cons
   e = launch_bwd_face_contrib(partial, qs, f64, nullptr, nf, contrib, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint reduce");
   return gather_tail(ar, tris, nf, nullptr, nullptr, nv, contrib, grad_verts, vdtype, s);
+}
+
+pft_status pft_backward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                           const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
+                           void* grad_verts, void* stream) {
+  return backward3d_impl(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, grad_out, grad_verts, nullptr, stream);
+}
+
+pft_status pft_backward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                   const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, const void* grad_out,
+                                   void* grad_verts, const uint32_t* q_order, void* stream) {
+  return backward3d_impl(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, grad_out, grad_verts, q_order, stream);
 }
 
 pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,

@@ -174,6 +174,8 @@ hipError_t launch_edges2d(const double* verts, int64_t nv, const int64_t* d_off,
 hipError_t launch_validate(const int32_t* tris, int64_t nf, int64_t nv, unsigned long long* counts, hipStream_t s);
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_iota_u32(uint32_t* p, int64_t n, hipStream_t s);
+// out[i] = in[i] if in[i] < n, else i (a caller's Q order made safe to index with).
+hipError_t launch_clamp_perm(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Planar polygon faces (fwdpoly.hip): a face header plus one record per vertex

@@ -323,6 +323,16 @@ __global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, in
 }
 
 
+// A caller's Q visiting order made safe to index with: entries out of range
+// become the position itself (a wrong order then gives wrong values, never an
+// out-of-bounds access).
+__global__ __launch_bounds__(256) void clamp_perm_kernel(const uint32_t* in, int64_t n, uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t v = in[i];
+  out[i] = (int64_t)v < n ? v : (uint32_t)i;
+}
+
 __global__ __launch_bounds__(256) void iota_u32_kernel(uint32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = (uint32_t)i;
@@ -530,6 +540,12 @@ hipError_t launch_edges2d(const double* verts, int64_t nv, const int64_t* d_off,
 hipError_t launch_validate(const int32_t* tris, int64_t nf, int64_t nv, unsigned long long* counts, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   validate_kernel<<<grid_for(nf), 256, 0, s>>>(tris, nf, nv, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_clamp_perm(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  clamp_perm_kernel<<<grid_for(n), 256, 0, s>>>(in, n, out);
   return hipGetLastError();
 }
 

@@ -175,13 +175,32 @@ def test_intensity_loss_validation(lib):
 def test_forward_3d_ordered_validation(lib):
     good = 0x10000
     f = lib.pft_forward_3d_ordered
-    # verts, vdtype, nv, tris, nf, order, meta, q, qdtype, nq, mode, out, intensity, stream
-    assert f(V(good), 1, 3, V(good), 1, None, V(good), V(good), 1, 4, 1, V(good), None, None) == _lib.PFT_EINVAL
+    # verts, vdtype, nv, tris, nf, order, meta, q, qdtype, nq, mode, out, intensity, q_order, stream
+    a = lambda fo=V(good), fm=V(good), nq=4, out=V(good), qo=None: (
+        V(good), 1, 3, V(good), 1, fo, fm, V(good), 1, nq, 1, out, None, qo, None)
+    assert f(*a(fo=None)) == _lib.PFT_EINVAL  # meta without its order
     assert b"face_order" in lib.pft_last_error()
-    assert f(V(good), 1, 3, V(good), 1, V(good), None, V(good), 1, 4, 1, V(good), None, None) == _lib.PFT_EINVAL
-    assert f(V(good), 1, 3, V(good), 1, V(good + 2), V(good), V(good), 1, 4, 1, V(good), None, None) == \
-        _lib.PFT_EINVAL
-    assert f(V(good), 1, 3, V(good), 1, V(good), V(good), V(good), 1, 0, 1, None, None, None) == _lib.PFT_OK
+    assert f(*a(fm=None)) == _lib.PFT_EINVAL
+    assert f(*a(fo=V(good + 2))) == _lib.PFT_EINVAL
+    assert f(*a(qo=V(good + 2))) == _lib.PFT_EINVAL
+    assert f(*a(out=None)) == _lib.PFT_EINVAL
+    assert f(*a(nq=0, out=None)) == _lib.PFT_OK
+    assert f(*a(fo=None, fm=None, nq=0, out=None)) == _lib.PFT_OK
+
+
+def test_q_order_and_backward_ordered_validation(lib):
+    good = 0x10000
+    g = lib.pft_q_order
+    assert g(V(good), 1, -1, V(good), None) == _lib.PFT_EINVAL
+    assert g(None, 1, 5, V(good), None) == _lib.PFT_EINVAL
+    assert g(V(good), 1, 5, None, None) == _lib.PFT_EINVAL
+    assert g(V(good), 7, 5, V(good), None) == _lib.PFT_EUNSUPPORTED
+    assert g(V(good), 1, 0, None, None) == _lib.PFT_OK
+    b = lib.pft_backward_3d_ordered
+    # verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, grad_out, grad_verts, q_order, stream
+    assert b(V(good), 1, 3, V(good), 1, V(good), 1, 4, 1, None, V(good), None, None) == _lib.PFT_EINVAL
+    assert b(V(good), 1, 3, V(good), 1, V(good), 1, 4, 1, V(good), V(good), V(good + 2), None) == _lib.PFT_EINVAL
+    assert b(V(good), 1, 0, V(good), 1, V(good), 1, 4, 1, V(good), None, None, None) == _lib.PFT_OK  # nv == 0
 
 
 def test_forward_2d_validation(lib):

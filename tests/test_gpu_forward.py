@@ -151,6 +151,35 @@ def test_edge_sharing_order(gpu):
     assert nrel(F64, want) < TOL_FP64
 
 
+def test_q_order_reuse(gpu):
+    """Q visiting orders computed once (q_order) and passed in: the forward gives bitwise the values of
+    an in-call sort for any permutation (each Q is evaluated on its own), the adjoint bitwise the same
+    for the same order and within rounding for another; the cache follows in-place changes of Q."""
+    rng = np.random.default_rng(72)
+    v, t = mg.icosphere(3, 1.5)
+    V, T = dev(v, torch.float32), dev(t, torch.int32)
+    Q = dev(mg.q_random_ball(20000, 5.0, rng), torch.float32)
+    g = dev(rng.normal(size=20000) + 1j * rng.normal(size=20000), torch.complex64)
+    step("q order: forward with the cached order, an in-call sort and a reversed order")
+    Fa = host(pft.forward_3d(V, T, Q, mode="fp32c"))
+    Fn = host(pft.forward_3d(V, T, Q, mode="fp32c", q_order=None))
+    rev = torch.arange(Q.shape[0] - 1, -1, -1, dtype=torch.int64, device=Q.device).to(torch.uint32)
+    Fr = host(pft.forward_3d(V, T, Q, mode="fp32c", q_order=rev))
+    assert np.array_equal(Fa.view(np.uint8), Fn.view(np.uint8))
+    assert np.array_equal(Fr.view(np.uint8), Fn.view(np.uint8))
+    step("q order: adjoint")
+    Ga = host(pft.backward_3d(V, T, Q, g, mode="fp32c"))
+    Gn = host(pft.backward_3d(V, T, Q, g, mode="fp32c", q_order=None))
+    Gr = host(pft.backward_3d(V, T, Q, g, mode="fp32c", q_order=rev))
+    assert np.array_equal(Ga.view(np.uint8), Gn.view(np.uint8))
+    assert nrel(Gr, Gn) < 1e-6
+    step("q order: in-place change of Q")
+    Q.mul_(0.5)
+    F2 = host(pft.forward_3d(V, T, Q, mode="fp32c"))
+    F2n = host(pft.forward_3d(V, T, Q, mode="fp32c", q_order=None))
+    assert np.array_equal(F2.view(np.uint8), F2n.view(np.uint8))
+
+
 def test_empty_q_list(gpu):
     v, t = mg.box()
     step("nq = 0")
