@@ -611,6 +611,23 @@ struct RegionPlan {
   int32_t* d_region_split = nullptr;
 };
 
+// Each region's own radius about its centre (region_R) and, per split, its region's centre and radius
+// (split_geo): the small-|Q| tests and the tetrahedron fan's apex use them, so that a region much smaller than the whole set is not summed by its
+// surface form where that form cancels (|Q| times the region's size small).
+pft_status region_radii(Arena& ar, const int64_t* off, int64_t nreg, const Face64* f64, const int32_t* d_region_split,
+                        int splits, double** region_R, double4** split_geo, hipStream_t s) {
+  *region_R = ar.get<double>(std::max<int64_t>(nreg, 1));
+  double4* region_geo = ar.get<double4>(std::max<int64_t>(nreg, 1));
+  *split_geo = ar.get<double4>(std::max(splits, 1));
+  int64_t* d_off = nullptr;
+  std::vector<int64_t> offv(off, off + nreg + 1);
+  pft_status st = upload(ar, offv, &d_off, s);
+  if (st != PFT_OK) return st;
+  if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
+  hipError_t e = launch_region_radii(f64, d_off, (int)nreg, d_region_split, *region_R, region_geo, *split_geo, s);
+  return e == hipSuccess ? PFT_OK : hip_fail(e, "region radii");
+}
+
 pft_status plan_regions(Arena& ar, const int64_t* off, int64_t nreg, int64_t nq, int qpt, RegionPlan& p,
                         hipStream_t s) {
   const int64_t nf = off[nreg];
@@ -1122,6 +1139,11 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
                       ordered ? face_order : nullptr, ordered ? face_meta : nullptr);
   if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
   if (e != hipSuccess) return hip_fail(e, "3D prologue");
+  double* region_R = nullptr;
+  double4* split_geo = nullptr;
+  if ((st = region_radii(ar, region_offsets, nreg, f64, plan.d_region_split, plan.splits, &region_R, &split_geo, s)) !=
+      PFT_OK)
+    return st;
   uint32_t* perm = nullptr;
   if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
   FwdArgs a;
@@ -1139,8 +1161,9 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   a.partial = partial;
   a.out = out;
   a.intensity = intensity;
-  a.tau0 = c128 ? kTau0F64 : kTau0F32;
+  a.tau0 = c128 ? kTau0F64 : kTauRegion32;
   a.share_edges = ordered ? 1 : 0;
+  a.split_geo = split_geo;
   if (plan.splits > 0) {
     const char* nm = main_name(true, mode);
     prof_begin(nm, s);
@@ -1155,6 +1178,7 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   r.out_regions = out_regions;
   r.grad_out = nullptr;
   r.rho_part = nullptr;
+  r.region_R = region_R;
   e = launch_regions_finish(a, r, c128 ? 1 : 0, s);
   return e == hipSuccess ? PFT_OK : hip_fail(e, "regions finish");
 }
@@ -1251,6 +1275,7 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
   double* rho_part = want_r ? ar.get<double>((size_t)nblocks * nreg) : nullptr;
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
   RegionArgs r;
+  r.region_R = nullptr;
   r.nreg = (int)nreg;
   r.rho = rho;
   r.out_regions = nullptr;
@@ -1276,7 +1301,14 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
     d.faces_per_split = 0;
     d.split_face = plan.d_split_face;
     d.partial = partial;
-    d.tau = kTauDQ;
+    d.tau = c128 ? kTauDQ : kTauRegion32;
+    double* region_R = nullptr;
+    double4* split_geo = nullptr;
+    if ((st = region_radii(ar, region_offsets, nreg, f64, plan.d_region_split, plan.splits, &region_R, &split_geo, s)) !=
+        PFT_OK)
+      return st;
+    d.split_geo = split_geo;
+    r.region_R = region_R;
     const char* nm = c128 ? "dq3d_fp64" : "dq3d_fp32c";
     prof_begin(nm, s);
     e = c128 ? launch_dq3d_fp64(d, s) : launch_dq3d_fp32c(d, s);
@@ -1311,7 +1343,14 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
     a.partial = partial;
     a.out = nullptr;
     a.intensity = nullptr;
-    a.tau0 = c128 ? kTau0F64 : kTau0F32;
+    a.tau0 = c128 ? kTau0F64 : kTauRegion32;
+    double* region_R = nullptr;
+    double4* split_geo = nullptr;
+    if ((st = region_radii(ar, region_offsets, nreg, f64, plan.d_region_split, plan.splits, &region_R, &split_geo, s)) !=
+        PFT_OK)
+      return st;
+    a.split_geo = split_geo;
+    r.region_R = region_R;
     if (plan.splits > 0) {
       const char* nm = main_name(true, mode);
       prof_begin(nm, s);

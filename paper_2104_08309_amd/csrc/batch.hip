@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
             xi += Ti;
           }
         } else {
-          for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Qd, xr, xi);
+          for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Qd, xr, xi, kZeroOrigin);
         }
       }
       if (active) store_stream(partial + it.part + lane, make_double2(xr, xi));
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
 #pragma unroll
           for (int k = 0; k < kQPTBatch; ++k)
             if (small[k])
-              for (int j = 0; j < nt; ++j) tet_term_f64(f64[t0 + j], Qd[k], xr[k], xi[k]);
+              for (int j = 0; j < nt; ++j) tet_term_f64(f64[t0 + j], Qd[k], xr[k], xi[k], kZeroOrigin);
         }
       }
 #pragma unroll

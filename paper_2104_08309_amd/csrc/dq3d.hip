@@ -44,7 +44,9 @@ __global__ __launch_bounds__(kBlock) void dq3d_fp64_kernel(DqArgs a) {
   const bool active = qi < a.nq;
   double Q[3] = {0.0, 0.0, 0.0};
   if (active) load_q3(a.q, a.qdtype, a.perm ? (int64_t)a.perm[qi] : qi, Q);
-  const bool small = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]) * a.info[0].R < a.tau;
+  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
+  const double o[3] = {geo.x, geo.y, geo.z};
+  const bool small = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]) * geo.w < a.tau;
   int64_t f_begin, f_end;
   split_range(a, f_begin, f_end);
   double Ar[3] = {0.0, 0.0, 0.0}, Ai[3] = {0.0, 0.0, 0.0}, Br = 0.0, Bi = 0.0;
@@ -62,9 +64,10 @@ __global__ __launch_bounds__(kBlock) void dq3d_fp64_kernel(DqArgs a) {
     if (!small) {
       for (int j = 0; j < nt; ++j) dq_term_f64(tile[j], gtile[j], Q, Ar, Ai, Br, Bi);
     } else {
-      for (int j = 0; j < nt; ++j) dq_tet_f64(tile[j], Q, Ar, Ai, Br, Bi);
+      for (int j = 0; j < nt; ++j) dq_tet_f64(tile[j], Q, Ar, Ai, Br, Bi, o);
     }
   }
+  if (small && a.split_geo) dq_apex(Q, o, Ar, Ai, Br, Bi);
   if (active) {
     for (int c = 0; c < 3; ++c) store_stream(dq_slot(a, c, qi), make_double2(Ar[c], Ai[c]));
     store_stream(dq_slot(a, 3, qi), make_double2(Br, Bi));
@@ -80,7 +83,9 @@ __global__ __launch_bounds__(kBlock) void dq3d_fp32c_kernel(DqArgs a) {
   constexpr int P = kQPTDQ;
   __shared__ Face32B tile[kTileF];
   const int64_t qbase = (int64_t)blockIdx.x * (kBlock * P) + threadIdx.x;
-  const double R = a.info[0].R;
+  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
+  const double R = geo.w;
+  const double o[3] = {geo.x, geo.y, geo.z};
   double Qd[P][3];
   float qx[P], qy[P], qz[P];
   bool small[P], active[P];
@@ -144,7 +149,8 @@ __global__ __launch_bounds__(kBlock) void dq3d_fp32c_kernel(DqArgs a) {
     for (int c = 0; c < 8; ++c) v[c] = (double)sum[k][c] - (double)cmp[k][c];
     if (any_small && small[k]) {
       double Gr[3] = {0.0, 0.0, 0.0}, Gi[3] = {0.0, 0.0, 0.0}, Fr = 0.0, Fi = 0.0;
-      for (int64_t f = f_begin; f < f_end; ++f) dq_tet_f64(a.f64[f], Qd[k], Gr, Gi, Fr, Fi);
+      for (int64_t f = f_begin; f < f_end; ++f) dq_tet_f64(a.f64[f], Qd[k], Gr, Gi, Fr, Fi, o);
+      if (a.split_geo) dq_apex(Qd[k], o, Gr, Gi, Fr, Fi);
       for (int c = 0; c < 3; ++c) v[2 * c] = Gr[c], v[2 * c + 1] = Gi[c];
       v[6] = Fr;
       v[7] = Fi;
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(kFinishBlock) void regions_finish_kernel(FwdArgs a,
   if (valid) load_q3(a.q, a.qdtype, dst, Q);
   const MeshInfo mi = a.info[0];
   const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
-  const bool small = sqrt(Q2) * mi.R < a.tau0;
+  const double qabs = sqrt(Q2);
   double st, ct;
   sincos(Q[0] * mi.t[0] + Q[1] * mi.t[1] + Q[2] * mi.t[2], &st, &ct);
   const double2 g = (valid && r.grad_out) ? load_cot(r.grad_out, out_c128, dst) : make_double2(0.0, 0.0);
@@ -192,7 +198,7 @@ __global__ __launch_bounds__(kFinishBlock) void regions_finish_kernel(FwdArgs a,
         xr += v.x;
         xi += v.y;
       }
-    if (!small) {
+    if (!(qabs * (r.region_R ? r.region_R[j] : mi.R) < a.tau0)) {  // this region's small-|Q| test
       xr /= Q2;
       xi /= Q2;
     }
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(kFinishBlock) void dq_finish_kernel(DqArgs a, Regio
   if (valid) load_q3(a.q, a.qdtype, dst, Q);
   const MeshInfo mi = a.info[0];
   const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
-  const bool small = sqrt(Q2) * mi.R < a.tau;
+  const double qabs = sqrt(Q2);
   double st, ct;
   sincos(Q[0] * mi.t[0] + Q[1] * mi.t[1] + Q[2] * mi.t[2], &st, &ct);
   const double2 g = valid ? load_cot(r.grad_out, go_c128, dst) : make_double2(0.0, 0.0);
@@ -243,7 +249,7 @@ __global__ __launch_bounds__(kFinishBlock) void dq_finish_kernel(DqArgs a, Regio
         }
     // centred F_c and grad F_c
     double fcr, fci, gcr[3], gci[3];
-    if (small) {
+    if (qabs * (r.region_R ? r.region_R[j] : mi.R) < a.tau) {  // this region's small-|Q| test
       fcr = v[6];
       fci = v[7];
       for (int c = 0; c < 3; ++c) gcr[c] = v[2 * c], gci[c] = v[2 * c + 1];
@@ -288,6 +294,52 @@ __global__ __launch_bounds__(kFinishBlock) void rho_reduce_kernel(const double* 
   for (int64_t b = threadIdx.x; b < nblocks; b += kFinishBlock) v += part[b * nreg + j];
   v = block_total<kFinishBlock>(v, lds);
   if (threadIdx.x == 0) out[j] = v;
+}
+
+// One block per region: the mean of its face centroids, then the largest corner distance from it.
+__global__ __launch_bounds__(kFinishBlock) void region_radii_kernel(const Face64* f64, const int64_t* off,
+                                                                    double* region_R, double4* region_geo) {
+  __shared__ double lds[kFinishBlock / 64];
+  const int j = blockIdx.x;
+  const int64_t b = off[j], e = off[j + 1];
+  double c[3];
+  for (int k = 0; k < 3; ++k) {
+    double v = 0.0;
+    for (int64_t m = b + threadIdx.x; m < e; m += kFinishBlock) v += f64[m].g[k];
+    c[k] = block_total<kFinishBlock>(v, lds) / (double)max<int64_t>(e - b, 1);
+  }
+  double r2 = 0.0;
+  for (int64_t m = b + threadIdx.x; m < e; m += kFinishBlock) {
+    const Face64& f = f64[m];
+    for (int q = 0; q < 3; ++q) {
+      double d2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        const double u = q == 0 ? f.u0[k] : (q == 1 ? f.u1[k] : -f.u0[k] - f.u1[k]);
+        const double x = f.g[k] + u - c[k];
+        d2 += x * x;
+      }
+      r2 = fmax(r2, d2);
+    }
+  }
+  // block maximum (fixed order)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o, 64));
+  __syncthreads();
+  if (lane == 0) lds[wave] = r2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int w = 0; w < kFinishBlock / 64; ++w) mx = fmax(mx, lds[w]);
+    region_R[j] = sqrt(mx);
+    region_geo[j] = make_double4(c[0], c[1], c[2], sqrt(mx));
+  }
+}
+
+__global__ __launch_bounds__(256) void split_radii_kernel(const int32_t* region_split, int nreg,
+                                                          const double4* region_geo, double4* split_geo) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nreg) return;
+  for (int sp = region_split[j]; sp < region_split[j + 1]; ++sp) split_geo[sp] = region_geo[j];
 }
 
 __global__ __launch_bounds__(256) void face_weights_kernel(const int64_t* off, int nreg, const double* rho,
@@ -342,6 +394,17 @@ hipError_t launch_dq_finish(const DqArgs& a, const RegionArgs& r, int go_c128, v
 hipError_t launch_rho_reduce(const double* rho_part, int64_t nblocks, int nreg, double* grad_rho, hipStream_t s) {
   if (nreg <= 0) return hipSuccess;
   rho_reduce_kernel<<<(unsigned)nreg, kFinishBlock, 0, s>>>(rho_part, nblocks, nreg, grad_rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_region_radii(const Face64* f64, const int64_t* d_region_off, int nreg,
+                               const int32_t* d_region_split, double* region_R, double4* region_geo,
+                               double4* split_geo, hipStream_t s) {
+  if (nreg <= 0) return hipSuccess;
+  region_radii_kernel<<<(unsigned)nreg, kFinishBlock, 0, s>>>(f64, d_region_off, region_R, region_geo);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  split_radii_kernel<<<(unsigned)((nreg + 255) / 256), 256, 0, s>>>(d_region_split, nreg, region_geo, split_geo);
   return hipGetLastError();
 }
 

@@ -69,15 +69,15 @@ PFT_HD inline void tet_moments_f64(const double* x, double& sr, double& si, doub
   }
 }
 
-// Small |Q| R: the tetrahedron (t, a, b, c) of face F adds 6|T| S to F_c and
-// i sum_k v_k 6|T| T_k to grad F_c (coordinates relative to t).
+// Small |Q| R: the tetrahedron (o, a, b, c) of face F (o an apex relative to t) adds 6|T| S to F and
+// i sum_k v_k 6|T| T_k to grad F, both about o (dq_apex moves them to t).
 PFT_HD __forceinline__ void dq_tet_f64(const Face64& F, const double* Q, double* Gr, double* Gi, double& Fr,
-                                       double& Fi) {
+                                       double& Fi, const double* o) {
   double v[3][3];
   for (int c = 0; c < 3; ++c) {
-    v[0][c] = F.g[c] + F.u0[c];
-    v[1][c] = F.g[c] + F.u1[c];
-    v[2][c] = F.g[c] - F.u0[c] - F.u1[c];
+    v[0][c] = F.g[c] + F.u0[c] - o[c];
+    v[1][c] = F.g[c] + F.u1[c] - o[c];
+    v[2][c] = F.g[c] - F.u0[c] - F.u1[c] - o[c];
   }
   const double six_v = F.N[0] * v[0][0] + F.N[1] * v[0][1] + F.N[2] * v[0][2];
   double x[3];
@@ -92,6 +92,22 @@ PFT_HD __forceinline__ void dq_tet_f64(const Face64& F, const double* Q, double*
     Gr[c] -= six_v * mi;  // i (mr + i mi)
     Gi[c] += six_v * mr;
   }
+}
+
+// The fan sums about an apex o, moved to coordinates about t: F = exp(iQ.o) F_o and
+// grad F = exp(iQ.o) (grad F_o + i o F_o).
+PFT_HD __forceinline__ void dq_apex(const double* Q, const double* o, double* Gr, double* Gi, double& Fr,
+                                    double& Fi) {
+  double so, co;
+  sincos(Q[0] * o[0] + Q[1] * o[1] + Q[2] * o[2], &so, &co);
+  for (int c = 0; c < 3; ++c) {
+    const double ur = Gr[c] - o[c] * Fi, ui = Gi[c] + o[c] * Fr;
+    Gr[c] = co * ur - so * ui;
+    Gi[c] = co * ui + so * ur;
+  }
+  const double fr = co * Fr - so * Fi;
+  Fi = co * Fi + so * Fr;
+  Fr = fr;
 }
 
 // binary64 surface term of face f: A += c sum_k (v_k - t) Y_k, B += c J.

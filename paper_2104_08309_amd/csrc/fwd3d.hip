@@ -19,6 +19,16 @@
 namespace pft {
 namespace {
 
+// The tetrahedron fan about an apex o (relative to t) gives the integral of exp(iQ.(r - o)); times
+// exp(iQ.o) it is relative to t like the surface sums.
+__device__ __forceinline__ void apex_phase(const double* Q, const double* o, double& xr, double& xi) {
+  double so, co;
+  sincos(Q[0] * o[0] + Q[1] * o[1] + Q[2] * o[2], &so, &co);
+  const double r = co * xr - so * xi;
+  xi = co * xi + so * xr;
+  xr = r;
+}
+
 // Face range of this block's split: from the split table when the splits
 // follow region boundaries, else equal ranges.
 __device__ __forceinline__ void split_faces(const FwdArgs& a, int64_t& b, int64_t& e) {
@@ -38,7 +48,10 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
   double Q[3] = {0.0, 0.0, 0.0};
   if (active) load_q3(a.q, a.qdtype, a.perm ? (int64_t)a.perm[qi] : qi, Q);
   const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
-  const bool small = sqrt(Q2) * a.info[0].R < a.tau0;
+  // the split's region (centre o relative to t, radius) when the splits follow regions, else the mesh
+  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
+  const double o[3] = {geo.x, geo.y, geo.z};
+  const bool small = sqrt(Q2) * geo.w < a.tau0;
   int64_t f_begin, f_end;
   split_faces(a, f_begin, f_end);
   double xr = 0.0, xi = 0.0;
@@ -59,9 +72,10 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
         xi += Ti;
       }
     } else {
-      for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Q, xr, xi);
+      for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Q, xr, xi, o);
     }
   }
+  if (small && a.split_geo) apex_phase(Q, o, xr, xi);
   if (active) store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qi, make_double2(xr, xi));
 }
 
@@ -75,7 +89,9 @@ template <bool SHARE>
 __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
   __shared__ Face32 tile[kTileF];
   const int64_t qbase = (int64_t)blockIdx.x * (kBlock * kQPT) + threadIdx.x;
-  const double R = a.info[0].R;
+  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
+  const double R = geo.w;
+  const double o[3] = {geo.x, geo.y, geo.z};
   double Qd[kQPT][3];
   float qx[kQPT], qy[kQPT], qz[kQPT], Q2[kQPT];
   bool small[kQPT], active[kQPT];
@@ -124,12 +140,13 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
 #pragma unroll
       for (int k = 0; k < kQPT; ++k)
         if (small[k])
-          for (int j = 0; j < nt; ++j) tet_term_f64(a.f64[t0 + j], Qd[k], xr[k], xi[k]);
+          for (int j = 0; j < nt; ++j) tet_term_f64(a.f64[t0 + j], Qd[k], xr[k], xi[k], o);
     }
   }
 #pragma unroll
   for (int k = 0; k < kQPT; ++k) {
     if (active[k]) {
+      if (small[k] && a.split_geo) apex_phase(Qd[k], o, xr[k], xi[k]);
       const double2 v = small[k] ? make_double2(xr[k], xi[k])
                                  : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
       store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qbase + (int64_t)k * kBlock, v);

@@ -180,13 +180,17 @@ PFT_HD inline void tet_series_f64(double xa, double xb, double xc, double& sr, d
   }
 }
 
-// Contribution N.a * series of the tetrahedron (t, a, b, c) for a small-|Q| lane.
-PFT_HD __forceinline__ void tet_term_f64(const Face64& F, const double* Q, double& xr, double& xi) {
+__device__ constexpr double kZeroOrigin[3] = {0.0, 0.0, 0.0};
+
+// Contribution N.a * series of the tetrahedron (o, a, b, c) for a small-|Q| lane, o an apex given relative
+// to the mesh centre t (the sum over a closed surface is then the volume integral of exp(iQ.(r - o))).
+PFT_HD __forceinline__ void tet_term_f64(const Face64& F, const double* Q, double& xr, double& xi,
+                                         const double* o) {
   double a[3], b[3], c[3];
   for (int k = 0; k < 3; ++k) {
-    a[k] = F.g[k] + F.u0[k];
-    b[k] = F.g[k] + F.u1[k];
-    c[k] = F.g[k] - F.u0[k] - F.u1[k];
+    a[k] = F.g[k] + F.u0[k] - o[k];
+    b[k] = F.g[k] + F.u1[k] - o[k];
+    c[k] = F.g[k] - F.u0[k] - F.u1[k] - o[k];
   }
   const double six_v = F.N[0] * a[0] + F.N[1] * a[1] + F.N[2] * a[2];
   const double xa = Q[0] * a[0] + Q[1] * a[1] + Q[2] * a[2];

@@ -66,6 +66,11 @@ constexpr double kTau0F32 = 0.2;
 // grad_Q F: the surface form cancels as (|Q| R)^-2 at small |Q| R; below this
 // the tetrahedron fan (binary64 series) is used in both forms.
 constexpr double kTauDQ = 0.5;
+// Closed regions in FP32C: the surface sum of a small region cancels by a factor of about 45 / (|Q| R_j)
+// for a tetrahedron (R_j the region's own radius), so below |Q| R_j = 2 its binary64 tetrahedron fan about
+// the region's centre is used (the forward and grad_Q alike); for regions of the size of the whole set
+// this covers a negligible share of a Q grid.
+constexpr double kTauRegion32 = 2.0;
 // 2D fan series when |Q| R < tau0.
 constexpr double kTau02D = 0.01;
 
@@ -267,6 +272,9 @@ struct FwdArgs {
   void* intensity;
   double tau0;
   int share_edges = 0;  // FP32C: records are in edge-sharing order (Face32::link), reuse the shared edge's term
+  // [splits] (x, y, z) the centre of the split's region relative to t, w its radius: the small-|Q| test of
+  // a split uses that radius and its tetrahedron fan that apex (NULL: the mesh's R, apex t)
+  const double4* split_geo = nullptr;
 };
 hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s);
@@ -281,6 +289,7 @@ struct RegionArgs {
   void* out_regions;            // [nreg][nq] per-region F (NULL: not written)
   const void* grad_out;         // [nq] cotangent for dL/drho and dL/dQ (NULL: forward only)
   double* rho_part;             // [blocks][nreg] per-block sums of Re(conj(g) F_j) (NULL: not formed)
+  const double* region_R;       // [nreg] each region's own radius for the small-|Q| test (NULL: the mesh's R)
 };
 // F = sum_j rho_j F_j (and F_j, |F|^2, dL/drho partials) from forward partials.
 hipError_t launch_regions_finish(const FwdArgs& a, const RegionArgs& r, int out_c128, hipStream_t s);
@@ -288,6 +297,11 @@ hipError_t launch_regions_finish(const FwdArgs& a, const RegionArgs& r, int out_
 hipError_t launch_rho_reduce(const double* rho_part, int64_t nblocks, int nreg, double* grad_rho, hipStream_t s);
 int64_t finish_blocks(int64_t nq);
 // rho of the region owning each face (region offsets on the device).
+// Radius of each region about its own centre (the mean of its face centroids), from the binary64
+// records: region_R[j]; and split_geo[s] = (centre relative to t, radius) of the region owning split s.
+hipError_t launch_region_radii(const Face64* f64, const int64_t* d_region_off, int nreg,
+                               const int32_t* d_region_split, double* region_R, double4* region_geo,
+                               double4* split_geo, hipStream_t s);
 hipError_t launch_face_weights(const int64_t* d_region_off, int nreg, const double* rho, int64_t nf, double* w,
                                hipStream_t s);
 
@@ -316,6 +330,7 @@ struct DqArgs {
   const int64_t* split_face;
   double2* partial;         // [splits][4][nq]: A_x, A_y, A_z, B
   double tau;
+  const double4* split_geo = nullptr;  // as FwdArgs::split_geo
 };
 hipError_t launch_dq3d_fp64(const DqArgs& a, hipStream_t s);
 hipError_t launch_dq3d_fp32c(const DqArgs& a, hipStream_t s);

@@ -173,3 +173,30 @@ def test_config2_mesh_grad_q_full_size(gpu):
     want = np.real(np.conj(g[idx])[:, None] * O.ft3d_dq(v, t, q[idx]))
     assert nrel(g64[idx], want) < TOL_GRAD64
     assert nrel(g32[idx], want) < TOL_FP32C
+
+
+def test_many_regions(gpu):
+    """500 regions (small tetrahedra with random densities and positions): one face split per region
+    at least, the per-region finish and the dL/drho reduction over many regions."""
+    rng = np.random.default_rng(58)
+    surfaces, regions = [], []
+    for i in range(500):
+        v, t = mg.tetrahedron(rng.normal(size=(4, 3)) * 0.4 + rng.uniform(-3, 3, size=3))
+        t = mg.orient_outward(v, t)
+        surfaces.append((v, t))
+        regions.append([(i, +1)])
+    v, t, off = mg.stack_regions(surfaces, regions)
+    rho = rng.uniform(-1.0, 2.0, size=500)
+    q = mg.q_random_ball(9000, 3.0, rng)
+    g = rng.normal(size=len(q)) + 1j * rng.normal(size=len(q))
+    want, want_j = O.ft3d_regions(v, t, off, rho, q)
+    for mode, tol in (("fp64", TOL_FP64), ("fp32c", TOL_FP32C)):
+        step(f"500 regions forward {mode}")
+        F, Fj, _ = fwd(v, t, off, rho, q, mode)
+        assert nrel(F, want) < tol, mode
+        assert nrel(Fj, want_j) < tol, mode
+        step(f"500 regions dL/drho {mode}")
+        gg = g if mode == "fp64" else g.astype(np.complex64).astype(np.complex128)
+        _, gr, _ = bwd(v, t, off, rho, q, gg, mode, need_verts=False, need_q=False)
+        wr = np.array([np.sum(np.real(np.conj(gg) * want_j[j])) for j in range(500)])
+        assert nrel(gr, wr) < (1e-10 if mode == "fp64" else TOL_FP32C), mode
