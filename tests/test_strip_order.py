@@ -57,3 +57,18 @@ def test_validation():
     assert lib.pft_strip_order(None, 4, 10, None, None) == _lib.PFT_EINVAL
     assert lib.pft_strip_order(None, -1, 10, None, None) == _lib.PFT_EINVAL
     assert lib.pft_strip_order(None, 0, 10, None, None) == _lib.PFT_OK
+
+
+def test_batch_order_stays_within_each_mesh():
+    """batch_strip_order: each mesh's range holds a permutation of its own triangles, offset by its first
+    triangle, with valid links inside the range and none across a range boundary."""
+    meshes = [mg.icosphere(2, 1.0), mg.box(), mg.icosphere(1, 2.0)]
+    tris = np.concatenate([t for _, t in meshes]).astype(np.int32)
+    to = np.cumsum([0] + [len(t) for _, t in meshes])
+    vo = np.cumsum([0] + [len(v) for v, _ in meshes])
+    order, meta = api.batch_strip_order(tris, vo, to)
+    for i, (v, t) in enumerate(meshes):
+        a, b = int(to[i]), int(to[i + 1])
+        local_order = order[a:b] - a
+        assert (meta[a] >> 2) & 3 == 0
+        check_order(t, local_order, meta[a:b], len(v))
