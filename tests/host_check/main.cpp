@@ -1,0 +1,90 @@
+// Host-side checks of libpft under AddressSanitizer and UndefinedBehaviorSanitizer (host code only):
+// the edge-sharing face order on random and broken meshes, and every entry point's synchronous
+// argument validation (each call below returns before any GPU work). Exits non-zero on a failed check.
+#include <cstdint>
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "pft.h"
+
+static int failures = 0;
+#define CHECK(c)                                                           \
+  do {                                                                     \
+    if (!(c)) {                                                            \
+      std::fprintf(stderr, "check failed (line %d): %s\n", __LINE__, #c); \
+      ++failures;                                                          \
+    }                                                                      \
+  } while (0)
+
+static void check_order(const std::vector<int32_t>& tris, int64_t nf, int64_t nv) {
+  std::vector<int32_t> order(nf > 0 ? nf : 1);
+  std::vector<uint8_t> meta(nf > 0 ? nf : 1);
+  CHECK(pft_strip_order(tris.data(), nf, nv, order.data(), meta.data()) == PFT_OK);
+  std::vector<int> seen(nf, 0);
+  for (int64_t i = 0; i < nf; ++i) {
+    CHECK(order[i] >= 0 && order[i] < nf);
+    if (order[i] >= 0 && order[i] < nf) ++seen[order[i]];
+    const int rot = meta[i] & 3, link = (meta[i] >> 2) & 3;
+    CHECK(rot < 3 && link < 3);
+    if (link && i > 0) {
+      const int32_t* a = &tris[3 * (int64_t)order[i]];
+      const int32_t* b = &tris[3 * (int64_t)order[i - 1]];
+      const int rb = meta[i - 1] & 3;
+      const int32_t a0 = a[rot], a1 = a[(rot + 1) % 3];
+      const int32_t b0 = b[(rb + link) % 3], b1 = b[(rb + link + 1) % 3];
+      CHECK((a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0));
+    }
+  }
+  for (int64_t f = 0; f < nf; ++f) CHECK(seen[f] == 1);
+}
+
+int main() {
+  std::mt19937 rng(7);
+  // a closed strip of a cylinder: a grid of quads split into triangles
+  for (int n : {1, 3, 17, 200}) {
+    std::vector<int32_t> t;
+    const int m = 12;
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < m; ++c) {
+        const int a = r * m + c, b = r * m + (c + 1) % m, d = (r + 1) * m + c, e = (r + 1) * m + (c + 1) % m;
+        t.insert(t.end(), {a, b, e, a, e, d});
+      }
+    check_order(t, (int64_t)t.size() / 3, (int64_t)(n + 1) * m);
+  }
+  // random indices, out-of-range and repeated ones, and faces repeated many times (non-manifold edges)
+  for (int trial = 0; trial < 20; ++trial) {
+    const int nv = 1 + (int)(rng() % 50), nf = (int)(rng() % 300);
+    std::vector<int32_t> t(3 * (size_t)nf);
+    for (auto& x : t) x = (int32_t)(rng() % (nv + 3)) - 1;
+    check_order(t, nf, nv);
+  }
+  check_order({}, 0, 0);
+  CHECK(pft_strip_order(nullptr, 3, 3, nullptr, nullptr) == PFT_EINVAL);
+  CHECK(pft_strip_order(nullptr, -1, 3, nullptr, nullptr) == PFT_EINVAL);
+
+  // synchronous validation paths (no GPU work is reached)
+  void* g = reinterpret_cast<void*>(0x10000);
+  CHECK(pft_forward_3d(g, PFT_F64, -1, (const int32_t*)g, 1, g, PFT_F64, 4, PFT_FP64, g, nullptr, nullptr) ==
+        PFT_EINVAL);
+  CHECK(pft_forward_3d(g, PFT_F64, 3, (const int32_t*)g, 1, g, PFT_F64, 0, PFT_FP64, nullptr, nullptr, nullptr) ==
+        PFT_OK);
+  CHECK(pft_backward_3d(g, PFT_F64, 3, (const int32_t*)g, 1, g, PFT_F64, 4, PFT_FP64, nullptr, g, nullptr) ==
+        PFT_EINVAL);
+  const int64_t off_bad[3] = {0, 5, 3};
+  CHECK(pft_forward_3d_poly(g, PFT_F64, 8, off_bad, (const int32_t*)g, 2, g, PFT_F64, 4, PFT_FP64, g, nullptr,
+                            nullptr) == PFT_EINVAL);
+  const int64_t reg_short[3] = {0, 4, 9};
+  CHECK(pft_forward_3d_regions(g, PFT_F64, 8, (const int32_t*)g, 10, reg_short, 2, (const double*)g, g, PFT_F64, 4,
+                               PFT_FP32C, g, nullptr, nullptr, nullptr, nullptr, nullptr) == PFT_EINVAL);
+  CHECK(pft_q_order(g, PFT_F64, -1, (uint32_t*)g, nullptr) == PFT_EINVAL);
+  CHECK(pft_intensity_loss_3d(g, PFT_F64, 8, (const int32_t*)g, 12, g, PFT_F64, 4, PFT_FP32C, nullptr,
+                              (const double*)g, nullptr, nullptr, g, nullptr, nullptr, nullptr) == PFT_EINVAL);
+  CHECK(pft_batch_forward(nullptr, PFT_FP64, g, nullptr, nullptr) == PFT_EINVAL);
+  int64_t bad = 7, rep = 7;
+  CHECK(pft_validate_mesh(nullptr, -1, 3, &bad, &rep, nullptr) == PFT_EINVAL);
+  CHECK(pft_last_error() != nullptr && pft_version() != nullptr);
+  if (failures) std::fprintf(stderr, "%d checks failed\n", failures);
+  else std::printf("host checks passed\n");
+  return failures ? 1 : 0;
+}
