@@ -545,6 +545,8 @@ def main():
         "grad_q": gradq,
         "regions": regions,
         "intensity_loss": lossf,
+        "kernel_source_digest": kernel_source_digest(),
+        "host_cpu": _cpu_model(),
         "batch": batch,
         "forward_2d": fwd2d,
         "union_of_spheres": union,
