@@ -208,7 +208,10 @@ def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: s
     a triangle tensor and reused while it is unchanged), None (the list order), or a pair of device
     tensors (order int32, meta uint8) from ``strip_order``. ``q_order``: "auto" (the visiting order of
     Q, computed on the device once per Q tensor and reused while it is unchanged), None (sorted in
-    the call), or a uint32 tensor from ``q_order``.
+    the call), or a uint32 tensor from ``q_order``. "Unchanged" is judged by the tensor's storage,
+    shape and version counter, which torch advances on every in-place write through the tensor or
+    its views; memory rewritten behind torch's back (another library writing the same device buffer)
+    is not seen, and such callers pass None. A stale order gives wrong values, never a fault.
     """
     tris_key, q_key = tris, q
     verts, tris = _mesh(verts, tris)
