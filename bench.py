@@ -528,7 +528,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (compensated; f64 branches)",
+        "dtype": "f32",
+        "dtype_note": "FP32-compensated: edge arithmetic in binary32, face phases, series branches and the "
+                      "sums across tiles and splits in binary64",
         "data": "synthetic",
         "config": {"workload": "icosphere L4 (5120 tri, R=50), Q 64^3 grid over [-0.5,0.5)^3, fwd+bwd FP32C",
                    "faces": nf, "vertices": nv, "n_q": nq},
