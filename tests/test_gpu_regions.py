@@ -200,3 +200,27 @@ def test_many_regions(gpu):
         _, gr, _ = bwd(v, t, off, rho, q, gg, mode, need_verts=False, need_q=False)
         wr = np.array([np.sum(np.real(np.conj(gg) * want_j[j])) for j in range(500)])
         assert nrel(gr, wr) < (1e-10 if mode == "fp64" else TOL_FP32C), mode
+
+
+def test_f32_inputs(gpu):
+    """float32 vertices and Q through the region forward and backward: gradients come back as float32 and
+    agree with the oracle at the rounded inputs."""
+    v, t, off = mg.layered_sphere(1, [0.7, 1.0, 1.3], centre=(0.1, 0.2, -0.3))
+    rho = np.array([1.5, -0.7, 2.2])
+    rng = np.random.default_rng(59)
+    q = mg.q_random_ball(900, 5.0, rng)
+    g = (rng.normal(size=len(q)) + 1j * rng.normal(size=len(q))).astype(np.complex64)
+    v32, q32 = v.astype(np.float32), q.astype(np.float32)
+    V, T, Q, R = dev(v32), dev(t, torch.int32), dev(q32), dev(rho)
+    step("regions f32 inputs")
+    F = host(pft.forward_3d_regions(V, T, off, R, Q, mode="fp32c"))
+    gv, gr, gq = pft.backward_3d_regions(V, T, off, R, Q, dev(g), mode="fp32c")
+    torch.cuda.synchronize()
+    assert gv.dtype == torch.float32 and gq.dtype == torch.float32 and gr.dtype == torch.float64
+    vd, qd = v32.astype(np.float64), q32.astype(np.float64)
+    want, _ = O.ft3d_regions(vd, t, off, rho, qd)
+    wv, wr, wq = O.grad3d_regions(vd, t, off, rho, qd, g.astype(np.complex128))
+    assert nrel(F, want) < TOL_FP32C
+    assert nrel(host(gv).astype(np.float64), wv) < TOL_FP32C
+    assert nrel(host(gr), wr) < TOL_FP32C
+    assert nrel(host(gq).astype(np.float64), wq) < TOL_FP32C
