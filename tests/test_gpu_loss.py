@@ -126,3 +126,19 @@ def test_config4_full_size(gpu):
     G64 = host(G64)
     for G, tol in ((G64, 1e-8), (G32, 1e-4)):
         assert np.max(np.abs(G.sum(axis=0))) < tol * np.max(np.abs(G)) * np.sqrt(len(v))
+
+
+def test_f32_inputs(gpu):
+    """float32 vertices and Q: the fused loss's gradient is float32 and matches the unfused path."""
+    v, t, q, target, w = loss_case(level=2, n=24, seed=5)
+    V, T, Q = dev(v, torch.float32), dev(t, torch.int32), dev(q, torch.float32)
+    step("fused loss f32 inputs")
+    loss, gv = pft.intensity_loss_3d(V, T, Q, dev(target), dev(w), mode="fp32c")
+    F = pft.forward_3d(V, T, Q, mode="fp32c").to(torch.complex128)
+    r = F.real ** 2 + F.imag ** 2 - dev(target)
+    G_ref = host(pft.backward_3d(V, T, Q, (4 * dev(w) * r * F).to(torch.complex64), mode="fp32c"))
+    torch.cuda.synchronize()
+    assert gv.dtype == torch.float32
+    L_ref = torch.sum(dev(w) * r * r).item()
+    assert abs(loss.item() - L_ref) <= 1e-4 * abs(L_ref)
+    assert nrel(host(gv), G_ref) < 1e-4
