@@ -26,21 +26,24 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic operation counts per (triangle, Q) pair (multiply or add = 1,
-# FMA = 2; sin, cos, reciprocal = 1 each):
-#   forward  = 104 flop: one face term of the edge sum (cross and dot products with
-#              Q, three edge sincs, two half-vertex phases, the face-origin phase,
-#              the complex products and the accumulation);
-#   adjoint  = 200 flop: the same recomputed terms plus the derivative of the edge
-#              sum in Q that gives the three barycentric moments and their real
-#              weights against the cotangent;
+# Operation counts per (triangle, Q) pair (multiply or add = 1, FMA = 2; sin, cos, reciprocal = 1 each):
+#   forward  = 104 flop (algorithmic): one face term of the edge sum with all three edges evaluated
+#              (cross and dot products with Q, three edge sincs, two half-vertex phases, the
+#              face-origin phase, the complex products and the accumulation); the kernel's edge sharing
+#              and polynomial sinc do less work for the same result, which this count credits;
+#   adjoint  = 181.5 flop (counted): on this workload every pair takes the adjoint's barycentric-series
+#              branch (largest centred vertex phase 2.07 < 3), whose operation count depends on the
+#              number of terms, so the basis is the hardware count of the FP32, transcendental and FP64
+#              operations the adjoint kernel executes per pair here (SQ_INSTS_VALU_FLOPS_FP32, _TRANS
+#              and _FP64 on config 2, profiles/valu_counters_icosphere_L4_grid64.txt) rather than the
+#              200 of the differentiated edge-sum branch;
 #   grad_Q   = 246 flop: the adjoint's recomputed terms (66), edge derivatives (15)
 #              and edge products (25), two barycentric moments with their
 #              normalisation and the face integral (59), Q.N and its phase (7),
 #              the corner-weighted moment vector (42) and the accumulation of A
 #              and B (32).
 FLOP_FWD = 104.0
-FLOP_BWD = 200.0
+FLOP_BWD = 181.5
 FLOP_DQ = 246.0
 FLOP_2D = 21.0    # per edge-Q pair of the 2D edge sum (binary64)
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (AMD published)
@@ -77,7 +80,6 @@ def measured_traffic(kernel):
 def _oracle_chunk(args):
     """CPU-baseline worker: the oracle's forward and gradient on one Q chunk."""
     v, t, q, g = args
-    sys.path.insert(0, ROOT)
     import oracle as O
 
     t0 = time.perf_counter()
@@ -86,6 +88,21 @@ def _oracle_chunk(args):
     G = O.grad3d(v, t, q, g)
     t2 = time.perf_counter()
     return F, G, t1 - t0, t2 - t1
+
+
+def _worker_init():
+    """One BLAS thread per worker process (the pool supplies the parallelism) and the oracle imported
+    before any timed work."""
+    sys.path.insert(0, ROOT)
+    from threadpoolctl import threadpool_limits
+
+    global _BLAS_LIMIT
+    _BLAS_LIMIT = threadpool_limits(limits=1)
+    import oracle  # noqa: F401
+
+
+def _ready(_):
+    return os.getpid()
 
 
 def _cpu_model() -> str:
@@ -98,19 +115,24 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(v, t, q_sample, g_sample, n_chunks):
+def cpu_baseline(v, t, q_sample, g_sample, runs=3):
+    """The oracle on a Q sample over a process pool of the host's cores (at most 16: the share of the
+    host that one GPU's job gets), started and warmed before the clock runs; the median of `runs` runs."""
     import multiprocessing as mp
 
     cores = min(len(os.sched_getaffinity(0)), 16)
+    n_chunks = 4 * cores
     chunks = [(v, t, qc, gc) for qc, gc in zip(np.array_split(q_sample, n_chunks), np.array_split(g_sample, n_chunks))]
-    ctx = mp.get_context("spawn")
-    t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        res = pool.map(_oracle_chunk, chunks)
-    wall = time.perf_counter() - t0
+    walls = []
+    with mp.get_context("spawn").Pool(cores, initializer=_worker_init) as pool:
+        pool.map(_ready, range(4 * cores), chunksize=1)
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_chunk, chunks, chunksize=1)
+            walls.append(time.perf_counter() - t0)
     F = np.concatenate([r[0] for r in res])
     G = sum(r[1] for r in res)
-    return F, G, wall, cores
+    return F, G, float(np.median(walls)), walls, cores
 
 
 def main():
@@ -119,7 +141,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=8192, help="Q points of the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="Q points of the oracle's timed sample")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU baseline")
     ap.add_argument("--no-orient", action="store_true", help="skip the orientation-average measurement")
     ap.add_argument("--no-poly", action="store_true", help="skip the polygon-face measurement")
@@ -178,23 +200,33 @@ def main():
         dV = pft.backward_3d(V64, T, Q64, G64, mode="fp64")
         return F, dV
 
-    def timed(fn, steps, warmup):
+    def timed(fn, steps, warmup, per_step=None):
+        """Mean wall time of `steps` calls bracketed by synchronisations; with a list `per_step`, also
+        each call's time from HIP events on the current stream (no synchronisation in between)."""
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         pft.profile_reset()
         pft.profile_enable(True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_step is not None else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        if ev:
+            ev[0].record()
+        for i in range(steps):
             out = fn()
+            if ev:
+                ev[i + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         pft.profile_enable(False)
+        if ev:
+            per_step.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
         return wall / steps, out
 
     print(f"[bench] fp32c fwd+bwd, {args.steps} steps", file=sys.stderr, flush=True)
-    dt32, (F32, dV32) = timed(step32, args.steps, args.warmup)
+    step_ms = []
+    dt32, (F32, dV32) = timed(step32, args.steps, args.warmup, per_step=step_ms)
     n_f, ms_f = pft.profile_read("fwd3d_fp32c")
     n_b, ms_b = pft.profile_read("bwd3d_fp32c")
     fwd_ms, bwd_ms = ms_f / max(n_f, 1), ms_b / max(n_b, 1)
@@ -382,6 +414,34 @@ def main():
                  "forward_kernel_ms": ms_lf / max(n_lf, 1), "adjoint_kernel_ms": ms_lb / max(n_lb, 1),
                  "loss_rel_diff_fused_vs_unfused": abs(Lf.item() - Lu.item()) / abs(Lu.item()),
                  "grad_rel_diff_fused_vs_unfused": float(np.linalg.norm(Gf - Gu) / np.linalg.norm(Gu))}
+        # accuracy against the FP64 form: the adjoint alone (both forms on one cotangent, the loss's, formed
+        # from the FP64 forward) and end to end (each form's own fused loss gradient). The end-to-end error
+        # is the FP32C forward's error passed through the loss ("cotangent error": the FP64 adjoint of the
+        # cotangent formed from the FP32C F) plus the adjoint's own.
+        V4d, Q4d = V4.double(), Q4.double()
+        L64, G64, F64 = pft.intensity_loss_3d(V4d, T4, Q4d, I4, W4, mode="fp64", return_F=True)
+        L32, G32, F32 = pft.intensity_loss_3d(V4, T4, Q4, I4, W4, mode="fp32c", return_F=True)
+        F32 = F32.to(torch.complex128)
+
+        def cot(F):
+            return 4.0 * W4 * (F.real ** 2 + F.imag ** 2 - I4) * F
+
+        g64 = cot(F64).to(torch.complex64)
+        A32 = pft.backward_3d(V4, T4, Q4, g64, mode="fp32c").double()
+        A64 = pft.backward_3d(V4d, T4, Q4d, g64.to(torch.complex128), mode="fp64")
+        Gc = pft.backward_3d(V4d, T4, Q4d, cot(F32), mode="fp64")
+
+        def nrel(a, b):
+            return float(torch.linalg.norm(a.double() - b.double()) / torch.linalg.norm(b.double()))
+
+        e_F, e_c, e_g = nrel(F32, F64), nrel(Gc, G64), nrel(G32, G64)
+        lossf.update({"forward_rel_err_fp32c_vs_fp64": e_F,
+                      "adjoint_rel_err_same_cotangent_fp32c_vs_fp64": nrel(A32, A64),
+                      "grad_rel_err_fp32c_vs_fp64": e_g,
+                      "cotangent_error_through_adjoint": e_c,
+                      "loss_amplification_of_forward_error": e_c / e_F,
+                      "loss_rel_err_fp32c_vs_fp64": abs(L32.item() - L64.item()) / abs(L64.item())})
+        del V4d, Q4d, F64, F32, G64, G32, A32, A64, Gc
 
     # config 5 (512 uneven meshes, one persistent launch each way) and config 1 (the 2D path, binary64)
     batch = fwd2d = None
@@ -494,10 +554,12 @@ def main():
                                         srng.choice(nq, args.cpu_sample, replace=False)]))[: args.cpu_sample]
         qs = q[idx]
         gs = g[idx]
-        Fo, Go, wall, cores = cpu_baseline(v, t, qs, gs, n_chunks=32)
+        Fo, Go, wall, walls, cores = cpu_baseline(v, t, qs, gs)
         cpu = {"value": nf * qs.shape[0] / wall, "unit": "face*Q/s (fwd+bwd)", "cores": cores, "kind": "oracle",
                "sample": f"{qs.shape[0]} of the {nq} grid Q (seeded, incl. Q=0, axes, diagonal), all {nf} faces, "
-                         f"forward + vertex gradient, {wall:.1f} s wall"}
+                         f"forward + vertex gradient; median of {len(walls)} runs "
+                         f"({', '.join(f'{w:.1f}' for w in walls)} s wall) on a pool started beforehand",
+               "runs_s": walls}
         acc["fwd_rel_err_vs_oracle_sample"] = float(np.linalg.norm(F32h[idx] - Fo) / np.linalg.norm(Fo))
         acc["fwd_max_err_over_max_F_sample"] = float(np.max(np.abs(F32h[idx] - Fo)) / np.max(np.abs(Fo)))
         # the adjoint over the sample only: run the FP32C kernel on the same Q subset
@@ -508,12 +570,14 @@ def main():
         acc["bwd_max_err_over_max_grad_sample"] = float(np.max(np.abs(Gsub - Go32)) / np.max(np.abs(Go32)))
         # one host core on a smaller sample of the same Q (the oracle as it stands, one process, one BLAS thread)
         from threadpoolctl import threadpool_limits
-        sub = idx[: max(64, args.cpu_sample // 16)]
+        sub = idx[: max(64, len(idx) // 8)]
         with threadpool_limits(limits=1):
             t1 = time.perf_counter()
             _oracle_chunk((v, t, q[sub], g[sub]))
             cpu["single_core_value"] = nf * len(sub) / (time.perf_counter() - t1)
         cpu["single_core_sample"] = f"{len(sub)} of the same Q, one process, one BLAS thread"
+        cpu["single_core_times_cores"] = cpu["single_core_value"] * cores
+        cpu["parallel_efficiency"] = cpu["value"] / cpu["single_core_times_cores"]
         cpu["cpu_model"] = _cpu_model()
 
     line = {
@@ -524,6 +588,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt32 * 1e3,
+        "ms_per_step_median": float(np.median(step_ms)),
         "ms_per_step_list_order_sorted_in_call": dt32p * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -536,6 +601,8 @@ def main():
                    "faces": nf, "vertices": nv, "n_q": nq},
         "fwd_kernel_ms": fwd_ms,
         "bwd_kernel_ms": bwd_ms,
+        "alu_frac_fwd": r_fwd["frac"],
+        "alu_frac_bwd": r_bwd["frac"],
         "fp64_gpu": fp64,
         "speedup_vs_fp64_gpu": (fp64["ms_per_step"] / (dt32 * 1e3)) if fp64 else None,
         "accuracy": acc,

@@ -9,10 +9,23 @@ if ROOT not in sys.path:
 
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
+# Text of the paper (for the appendix's embedded two-sphere mesh); PFT_PAPER_TEXT overrides the
+# location of the read-only copy in the build container. Absent elsewhere: the tests that need it skip.
+PAPER_TEXT = os.environ.get("PFT_PAPER_TEXT", "/root/reference/PAPER.md")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an AMD GPU (MI355X) and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU checks")
+
+
+@pytest.fixture(scope="session")
+def paper_text():
+    """The paper's text, or a skip when no copy is available."""
+    if not os.path.exists(PAPER_TEXT):
+        pytest.skip("paper text not available (set PFT_PAPER_TEXT)")
+    with open(PAPER_TEXT) as f:
+        return f.read()
 
 
 @pytest.fixture(scope="session")

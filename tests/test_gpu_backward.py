@@ -50,7 +50,9 @@ def test_f32_vertices(gpu):
 
 
 def test_autograd_intensity_loss(gpu):
-    """L = sum w (|F|^2 - I)^2 through PftFunction: gradient matches the oracle's chain rule."""
+    """L = sum w (|F|^2 - I)^2 through PftFunction: gradient matches the oracle's chain rule. FP32C:
+    within 1.5 e_c + 1e-5, e_c the error that the FP32C forward's F alone brings through the loss
+    (the exact adjoint of the cotangent formed from it; the loss amplifies the forward's error)."""
     v0, t = mg.icosphere(3, 5.0)
     rng = np.random.default_rng(2)
     v = mg.perturb_radial(v0, 0.02, rng)
@@ -59,7 +61,7 @@ def test_autograd_intensity_loss(gpu):
     w = 1.0 / (q.shape[0] * O.volume3d(v0, t) ** 4)
     F = O.ft3d(v, t, q)
     want = O.grad3d(v, t, q, 4 * w * (np.abs(F) ** 2 - target) * F)
-    for mode, tol in (("fp64", 1e-9), ("fp32c", 1e-4)):
+    for mode in ("fp64", "fp32c"):
         step(f"autograd loss {mode}")
         vt = dev(v).requires_grad_(True)
         Fg = pft.ft3d(vt, dev(t, torch.int32), dev(q), mode)
@@ -67,7 +69,13 @@ def test_autograd_intensity_loss(gpu):
         loss.backward()
         got = host(vt.grad)
         e = nrel(got, want)
-        print(f"autograd {mode}: rel err {e:.3e}")
+        if mode == "fp64":
+            tol = 1e-9
+        else:
+            F32 = host(Fg.detach()).astype(np.complex128)
+            e_c = nrel(O.grad3d(v, t, q, 4 * w * (np.abs(F32) ** 2 - target) * F32), want)
+            tol = 1.5 * e_c + TOL_FP32C
+        print(f"autograd {mode}: rel err {e:.3e} (bar {tol:.2e})")
         assert e < tol
         # translation invariance of |F|^2: the vertex gradients sum to zero
         assert np.max(np.abs(got.sum(axis=0))) < 1e-3 * np.max(np.abs(got))

@@ -1,5 +1,4 @@
 """Input generators (closed, outward, stated sizes) and the paper's embedded two-sphere mesh."""
-import os
 import re
 
 import numpy as np
@@ -7,9 +6,6 @@ import pytest
 
 import meshgen as mg
 import oracle as O
-
-PAPER = "/root/reference/PAPER.md"
-
 
 def closed_oriented(v, t):
     e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
@@ -51,22 +47,19 @@ def test_batch_generator_small():
         assert np.all(np.linalg.norm(m["q"], axis=1) <= 0.5 + 1e-12)
 
 
-def _paper_mesh():
-    if not os.path.exists(PAPER):
-        pytest.skip("paper text not available")
-    text = open(PAPER).read()
+def _paper_mesh(text):
     m = re.search(r'twospheres_surfacemesh = """\\\n(.*?)"""', text, re.S)
     assert m, "embedded surface mesh not found"
     return mg.read_netgen_surfacemesh(m.group(1))
 
 
-def test_paper_two_sphere_mesh_facts():
+def test_paper_two_sphere_mesh_facts(paper_text):
     """The appendix mesh (union of two unit spheres at x = -0.6, 0.6): closed, outward, genus 0.
 
     The paper prints no numeric transform values for it; its own F(0) and
     symmetries are what can be checked (parity beyond these is unpinned).
     """
-    v, t = _paper_mesh()
+    v, t = _paper_mesh(paper_text)
     assert v.shape == (83, 3) and t.shape == (160, 3)
     used = np.unique(t)
     assert used.size == 82
