@@ -173,6 +173,31 @@ pft_status pft_forward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t n
                                   const uint32_t* q_order, void* stream);
 
 /*
+ * pft_forward_3d_noalloc -- pft_forward_3d for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the call allocates and frees nothing. Its
+ * temporaries (mesh centre, per-face records, per-split partial sums) live in
+ * a device array of fixed size, 64 MiB on each GPU the library runs on, held
+ * until the process ends. The Q are visited in the list order, the face splits
+ * are as many as fit beside the records, and the PFT_VALIDATE check (which
+ * synchronises) is not run. The caller still passes inputs and outputs.
+ *
+ *  Arguments, outputs and results as pft_forward_3d (equal up to the rounding
+ *  order of the face sum).
+ *  Limits: the records take 240 bytes per face in PFT_FP32C (128 in PFT_FP64)
+ *  and each Q at least 16 bytes, within 64 MiB (e.g. 99 460 faces with
+ *  2 097 152 Q in PFT_FP32C).
+ *  Concurrency: every call on one GPU uses that GPU's one array, so calls that
+ *  overlap on a GPU (other streams or host threads) race; calls on one stream
+ *  are ordered.
+ * Errors: as pft_forward_3d; EINVAL also for a mesh or Q list too large for
+ * the array (the message gives the sizes).
+ */
+pft_status pft_forward_3d_noalloc(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                                  const void* q, pft_dtype qdtype, int64_t nq, pft_mode mode, void* out,
+                                  void* intensity, void* stream);
+
+/*
  * pft_forward_3d_poly -- F(Q) of the volume enclosed by planar polygon faces
  * (3D section: eq. sum_elements_3d with nu_m edges per face, evaluated natively:
  * nu edge terms per face).

@@ -19,7 +19,7 @@ EXPORTS = [
     "pft_forward_2d", "pft_forward_3d", "pft_backward_3d", "pft_batch_forward", "pft_batch_backward",
     "pft_forward_3d_poly", "pft_orientation_average", "pft_forward_3d_regions", "pft_backward_3d_regions",
     "pft_intensity_loss_3d", "pft_strip_order", "pft_forward_3d_ordered", "pft_batch_forward_ordered",
-    "pft_q_order", "pft_backward_3d_ordered",
+    "pft_q_order", "pft_backward_3d_ordered", "pft_forward_3d_noalloc",
     "pft_validate_mesh", "pft_last_error", "pft_release_workspace", "pft_profile_enable",
     "pft_profile_reset", "pft_profile_read", "pft_version",
 ]
@@ -66,6 +66,7 @@ def load() -> ctypes.CDLL:
     sig = {
         "pft_forward_2d": [vp, i64, P(i64), i64, vp, i64, vp, vp],
         "pft_forward_3d": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp],
+        "pft_forward_3d_noalloc": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp],
         "pft_backward_3d": [vp, cint, i64, vp, i64, vp, cint, i64, cint, vp, vp, vp],
         "pft_batch_forward": [P(PftMeshBatch), cint, vp, vp, vp],
         "pft_batch_forward_ordered": [P(PftMeshBatch), vp, vp, cint, vp, vp, vp],

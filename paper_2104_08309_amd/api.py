@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import PFT_F32, PFT_F64, PFT_FP32C, PFT_FP64, PftMeshBatch, check
 
 __all__ = [
-    "forward_2d", "forward_3d", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
+    "forward_2d", "forward_3d", "forward_3d_noalloc", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
     "orientation_average", "forward_3d_regions", "backward_3d_regions", "intensity_loss_3d", "strip_order",
     "batch_strip_order", "q_order",
     "validate_mesh",
@@ -233,6 +233,25 @@ def forward_3d(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: s
                 _ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0], _ptr(tris), tris.shape[0], _ptr(fo),
                 _ptr(fm), _ptr(q), _real_dtype_id(q, "q"), q.shape[0], m, _ptr(out), _ptr(inten), _ptr(qo),
                 _stream(verts.device)))
+    return (out, inten) if intensity else out
+
+
+def forward_3d_noalloc(verts: torch.Tensor, tris: torch.Tensor, q: torch.Tensor, mode: str = "fp32c",
+                       intensity: bool = False):
+    """forward_3d through pft_forward_3d_noalloc: the library allocates nothing in the call (its
+    temporaries are in a fixed 64 MiB device array per GPU); Q in the list order, faces in the list
+    order. The outputs are allocated here by torch, as for every wrapper."""
+    verts, tris = _mesh(verts, tris)
+    q = _qlist(q, verts.device)
+    m = mode_id(mode)
+    cdt = torch.complex128 if m == PFT_FP64 else torch.complex64
+    rdt = torch.float64 if m == PFT_FP64 else torch.float32
+    out = torch.empty(q.shape[0], dtype=cdt, device=verts.device)
+    inten = torch.empty(q.shape[0], dtype=rdt, device=verts.device) if intensity else None
+    with torch.cuda.device(verts.device):
+        check(_lib.load().pft_forward_3d_noalloc(_ptr(verts), _real_dtype_id(verts, "verts"), verts.shape[0],
+                                                 _ptr(tris), tris.shape[0], _ptr(q), _real_dtype_id(q, "q"),
+                                                 q.shape[0], m, _ptr(out), _ptr(inten), _stream(verts.device)))
     return (out, inten) if intensity else out
 
 

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpft.so")
 
 SOURCES = ["api.cpp", "prologue.hip", "fwd3d.hip", "bwd3d.hip", "fwd2d.hip", "batch.hip", "qorder.hip", "orient.hip",
-           "fwdpoly.hip", "dq3d.hip", "loss.hip"]
+           "fwdpoly.hip", "dq3d.hip", "loss.hip", "noalloc.hip"]
 
 ARCH = os.environ.get("PFT_OFFLOAD_ARCH", "gfx950")
 

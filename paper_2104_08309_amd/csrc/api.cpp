@@ -93,7 +93,11 @@ struct Arena {
       ws_ = w;
     }
   }
+  // A fixed buffer of `cap` device bytes that the caller owns: get() carves from it and fails
+  // (failed = true) past its end; nothing is ever allocated or freed.
+  Arena(hipStream_t s, char* base, size_t cap) : s_(s), fixed_(base), fixed_cap_(cap) {}
   ~Arena() {
+    if (fixed_) return;
     for (void* p : ptrs_) (void)hipFreeAsync(p, s_);
     if (!ws_) return;
     if (need_ > ws_->cap) {  // grow for the next call (the old block is freed after this call's work)
@@ -110,10 +114,24 @@ struct Arena {
     ws_->owner.store(std::thread::id());
     ws_->mu.unlock();
   }
+  // bytes that get<T>(count) takes
+  template <typename T>
+  static size_t take(size_t count) {
+    return (std::max<size_t>(count * sizeof(T), 256) + 255) / 256 * 256;
+  }
   template <typename T>
   T* get(size_t count) {
-    const size_t bytes = (std::max<size_t>(count * sizeof(T), 256) + 255) / 256 * 256;
+    const size_t bytes = take<T>(count);
     need_ += bytes;
+    if (fixed_) {
+      if (used_ + bytes > fixed_cap_) {
+        failed = true;
+        return nullptr;
+      }
+      T* p = reinterpret_cast<T*>(fixed_ + used_);
+      used_ += bytes;
+      return p;
+    }
     if (ws_ && ws_->base && used_ + bytes <= ws_->cap) {
       T* p = reinterpret_cast<T*>(ws_->base + used_);
       used_ += bytes;
@@ -132,6 +150,8 @@ struct Arena {
  private:
   hipStream_t s_;
   Workspace* ws_ = nullptr;
+  char* fixed_ = nullptr;
+  size_t fixed_cap_ = 0;
   size_t used_ = 0, need_ = 0;
   std::vector<void*> ptrs_;
 };
@@ -536,10 +556,13 @@ namespace {
 
 // The 3D forward after validation: prologue, Q order, transform, finish.
 // `out` may be NULL when only |F|^2 is wanted.
+// sort_q = false with no q_order visits Q in the list order (no sort temporaries); max_partials > 0 caps
+// splits * nq (a fixed scratch); profile = false records no timing events.
 pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
                           const void* q, int qdtype, int64_t nq, int mode, void* out, void* intensity,
                           hipStream_t s, const int32_t* order = nullptr, const uint8_t* meta = nullptr,
-                          const uint32_t* q_order = nullptr) {
+                          const uint32_t* q_order = nullptr, bool sort_q = true, int64_t max_partials = -1,
+                          bool profile = true) {
   const bool c128 = mode == PFT_FP64;
   pft_status st = PFT_OK;
   MeshInfo* info = ar.get<MeshInfo>(1);
@@ -548,6 +571,11 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   int splits;
   int64_t per;
   choose_face_splits(nq, nf, c128 ? 1 : kQPT, &splits, &per);
+  if (max_partials > 0 && (int64_t)splits * nq > max_partials && nf > 0) {
+    const int64_t cap = std::max<int64_t>(1, max_partials / nq);
+    per = cdiv(cdiv(nf, cap), kTileF) * kTileF;
+    splits = (int)cdiv(nf, per);
+  }
   double2* partial = ar.get<double2>((size_t)splits * nq);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
   hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
@@ -556,7 +584,10 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   if (e == hipSuccess && !c128) e = launch_face32(f64, nf, kTauF32, kTauRel32, f32, s);
   if (e != hipSuccess) return hip_fail(e, "3D prologue");
   uint32_t* perm = nullptr;
-  st = q_order ? caller_qorder(ar, q_order, nq, &perm, s) : build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s);
+  if (q_order)
+    st = caller_qorder(ar, q_order, nq, &perm, s);
+  else if (sort_q)
+    st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s);
   if (st != PFT_OK) return st;
   FwdArgs a;
   a.f64 = f64;
@@ -576,9 +607,9 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   a.tau0 = c128 ? kTau0F64 : kTau0F32;
   a.share_edges = (order != nullptr && !c128) ? 1 : 0;
   const char* nm = main_name(true, mode);
-  prof_begin(nm, s);
+  if (profile) prof_begin(nm, s);
   e = c128 ? launch_fwd3d_fp64(a, s) : launch_fwd3d_fp32c(a, s);
-  prof_end(nm, s);
+  if (profile) prof_end(nm, s);
   if (e != hipSuccess) return hip_fail(e, "3D transform");
   e = launch_fwd3d_finish(a, c128 ? 1 : 0, s);
   if (e != hipSuccess) return hip_fail(e, "3D finish");
@@ -692,6 +723,53 @@ pft_status pft_forward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t n
   return forward3d_core(ar, verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, out, intensity, s,
                         nf > 0 ? face_order : nullptr, nf > 0 ? face_meta : nullptr, q_order);
 }
+
+}  // extern "C"
+
+namespace pft {
+
+pft_status set_error(pft_status st, const char* msg) { return fail(st, msg); }
+
+// pft_forward_3d with every temporary carved from `scratch` (cap bytes of device memory the caller
+// keeps): the Q are visited in the list order (no sort), the face splits are capped so that the
+// partial sums fit, and the PFT_VALIDATE check (synchronous) and timing events are not used.
+// `scratch_fn` supplies the buffer once the arguments have been checked.
+pft_status forward3d_noalloc(pft_status (*scratch_fn)(void**), size_t cap, const void* verts, int vdtype,
+                             int64_t nv, const int32_t* tris, int64_t nf, const void* q, int qdtype, int64_t nq,
+                             int mode, void* out, void* intensity, void* stream) {
+  pft_status st = check_mesh_args(verts, vdtype, nv, tris, nf, q, qdtype, nq, mode);
+  if (st != PFT_OK) return st;
+  const bool c128 = mode == PFT_FP64;
+  if (nq > 0 && out == nullptr) return fail(PFT_EINVAL, "out is NULL");
+  if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
+  if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
+  if (nq == 0) return PFT_OK;
+  const size_t fixed = Arena::take<MeshInfo>(1) + Arena::take<Face64>(std::max<int64_t>(nf, 1)) +
+                       (c128 ? 0 : Arena::take<Face32>(std::max<int64_t>(nf, 1)));
+  const size_t per_face = sizeof(Face64) + (c128 ? 0 : sizeof(Face32));
+  if (fixed + Arena::take<double2>((size_t)nq) > cap) {
+    if (fixed + Arena::take<double2>(1) > cap)
+      return fail(PFT_EINVAL, "mesh too large for the no-allocation scratch: " + std::to_string(nf) +
+                                  " faces need " + std::to_string(fixed) + " of its " + std::to_string(cap) +
+                                  " bytes (" + std::to_string(per_face) + " bytes per face)");
+    return fail(PFT_EINVAL, "too many Q for the no-allocation scratch with this mesh: at most " +
+                                std::to_string((cap - fixed) / sizeof(double2) - 16) + " Q (16 bytes per Q " +
+                                "beside the face records)");
+  }
+  void* base = nullptr;
+  if ((st = scratch_fn(&base)) != PFT_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Arena ar(s, static_cast<char*>(base), cap);
+  const int64_t max_partials = (int64_t)((cap - fixed) / sizeof(double2)) - 16;
+  st = forward3d_core(ar, verts, vdtype, nv, tris, nf, q, qdtype, nq, mode, out, intensity, s, nullptr, nullptr,
+                      nullptr, false, max_partials, false);
+  if (st == PFT_OK && ar.failed) return fail(PFT_EINVAL, "no-allocation scratch exhausted");
+  return st;
+}
+
+}  // namespace pft
+
+extern "C" {
 
 pft_status pft_q_order(const void* q, pft_dtype qdtype, int64_t nq, uint32_t* order, void* stream) {
   if (qdtype != PFT_F32 && qdtype != PFT_F64) return fail(PFT_EUNSUPPORTED, "unknown q dtype");

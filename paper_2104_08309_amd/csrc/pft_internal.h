@@ -451,3 +451,16 @@ void prof_begin(const char* name, hipStream_t s);
 void prof_end(const char* name, hipStream_t s);
 
 }  // namespace pft
+
+// ---------------------------------------------------------------------------
+// Allocation-free forward (api.cpp, noalloc.hip)
+// ---------------------------------------------------------------------------
+namespace pft {
+// Record `msg` as the calling thread's last error and return `st`.
+pft_status set_error(pft_status st, const char* msg);
+// pft_forward_3d with its temporaries carved from a fixed device buffer of `cap` bytes that
+// scratch_fn supplies after the arguments have been checked (sizes beyond the buffer give EINVAL).
+pft_status forward3d_noalloc(pft_status (*scratch_fn)(void**), size_t cap, const void* verts, int vdtype,
+                             int64_t nv, const int32_t* tris, int64_t nf, const void* q, int qdtype, int64_t nq,
+                             int mode, void* out, void* intensity, void* stream);
+}  // namespace pft

@@ -67,6 +67,23 @@ def test_forward_3d_validation(lib):
     assert f(V(good), 1, 3, V(good), 1, None, 1, 0, 0, None, None, None) == _lib.PFT_OK
 
 
+def test_forward_3d_noalloc_validation(lib):
+    """The allocation-free forward checks its arguments and the size of its fixed array on the host,
+    before it looks up the array or touches the GPU."""
+    good = 0x10000
+    f = lib.pft_forward_3d_noalloc
+    assert f(V(good), 1, -1, V(good), 1, V(good), 1, 1, 1, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good + 4), 1, 3, V(good), 1, V(good), 1, 4, 1, V(good), None, None) == _lib.PFT_EINVAL
+    assert f(V(good), 1, 3, V(good), 1, V(good), 1, 4, 9, V(good), None, None) == _lib.PFT_EUNSUPPORTED
+    assert f(V(good), 1, 3, V(good), 1, None, 1, 0, 1, None, None, None) == _lib.PFT_OK
+    # FP32C records take 240 bytes per face: 300 000 faces exceed the 64 MiB array
+    assert f(V(good), 1, 3, V(good), 300_000, V(good), 0, 4, 1, V(good), None, None) == _lib.PFT_EINVAL
+    assert b"mesh too large" in lib.pft_last_error()
+    # 5 120 faces leave room for about 4.1M Q in FP32C, not 5M
+    assert f(V(good), 1, 3, V(good), 5120, V(good), 0, 5_000_000, 1, V(good), None, None) == _lib.PFT_EINVAL
+    assert b"too many Q" in lib.pft_last_error()
+
+
 def test_backward_3d_validation(lib):
     good = 0x10000
     f = lib.pft_backward_3d
