@@ -120,17 +120,22 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
 /*
  * pft_strip_order -- an edge-sharing order of a triangle mesh's faces (HOST
  * function, no GPU work): consecutive faces share an edge wherever the greedy
- * chains over the edge adjacency allow, each face's vertex list rotated
- * cyclically (which keeps its orientation) so that its edge 0 (v0 -> v1) is
- * the edge it shares with the previous face. For pft_forward_3d_ordered; the
- * order depends only on the connectivity, so it is computed once per mesh.
+ * chains over the edge adjacency allow. Each face is traversed from a cyclic
+ * rotation of its vertex list, reversed where needed, so that its edge 0
+ * (v0 -> v1) is the edge it shares with the previous face and its edge 1
+ * (v1 -> v2) the edge it shares with the next one; the face term of a triangle
+ * is the same for both traversals (3D section: each edge's term keeps its
+ * value when the normal and the edge both flip), and the library keeps the
+ * outward normal for Q.N. For pft_forward_3d_ordered; the order depends only on
+ * the connectivity, so it is computed once per mesh.
  *
  *  tris   [nf][3] int32 (HOST).
  *  order  [nf] int32 (HOST), written: a permutation of 0 .. nf-1.
- *  meta   [nf] uint8 (HOST), written: rotation r (0..2) | link << 2, link = 0
- *         (no shared edge with the previous face) or k = 1, 2 (this face's
- *         edge 0 is edge k of the previous face, after that face's rotation).
- *  Faces with an out-of-range or repeated index are placed with link 0.
+ *  meta   [nf] uint8 (HOST), written: rotation r (0..2) in bits 0-1, bit 2
+ *         set if edge 0 (after the rotation) is edge 1 of the previous face
+ *         (after its own rotation and reversal), bit 3 set if the traversal is
+ *         reversed: (v_r, v_r+1, v_r+2) becomes (v_r+1, v_r, v_r+2).
+ *  Faces with an out-of-range or repeated index are placed without a link.
  * Errors: EINVAL for negative counts or NULL pointers with nf > 0.
  */
 pft_status pft_strip_order(const int32_t* tris, int64_t nf, int64_t nv, int32_t* order, uint8_t* meta);
@@ -160,8 +165,8 @@ pft_status pft_q_order(const void* q, pft_dtype qdtype, int64_t nq, uint32_t* or
  *              of 0 .. nf-1 (an entry out of range makes that position an
  *              empty face);
  *  face_meta   NULL with face_order, else [nf] uint8 (DEVICE), as written by
- *              pft_strip_order. A wrong link gives a wrong result, never an
- *              out-of-bounds access.
+ *              pft_strip_order. A wrong link or reversal gives a wrong result,
+ *              never an out-of-bounds access.
  *  q_order     NULL (sorted here) or [nq] uint32 (DEVICE), a permutation of
  *              0 .. nq-1 (an entry out of range is replaced by its position).
  * Errors: as pft_forward_3d; EINVAL also for only one of face_order,

@@ -27,6 +27,10 @@ COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     # packed FP32 instructions stay disabled: the compiler would otherwise form them from scalar float code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiplies and adds fuse only within one source expression: with free fusion across statements the
+    # unrolled copies of a loop over a thread's Q points can round differently, and a Q's value would
+    # depend on which slot of which thread evaluates it
+    "-ffp-contract=on",
     "-I", INCLUDE, "-I", CSRC,
     "-Wno-unused-command-line-argument",
 ]

@@ -821,7 +821,9 @@ pft_status pft_strip_order(const int32_t* tris, int64_t nf, int64_t nv, int32_t*
     i = j;
   }
   // greedy chains: from the last face placed, continue across its edge 1 or 2 (after its rotation) to a
-  // face not yet placed, rotated so that the shared edge becomes its edge 0
+  // face not yet placed, rotated so that the shared edge becomes its edge 0. Leaving through edge 2, the
+  // face placed last is marked reflected: its traversal (b, a, c) keeps edge 0 and makes the old edge 2
+  // its edge 1, so that the edge a face passes on is always its edge 1.
   std::vector<char> placed((size_t)nf, 0);
   int64_t n = 0;
   for (int64_t f0 = 0; f0 < nf; ++f0) {
@@ -834,22 +836,23 @@ pft_status pft_strip_order(const int32_t* tris, int64_t nf, int64_t nv, int32_t*
     ++n;
     for (;;) {
       int64_t next = -1;
-      int nrot = 0, link = 0;
+      int nrot = 0, via = 0;
       for (int k = 1; k <= 2 && next < 0; ++k) {
         const int64_t slot = 3 * cur + (rot + k) % 3;
         for (int64_t p = nbr[slot]; p >= 0 && p != slot; p = nbr[p]) {
           if (!placed[p / 3]) {
             next = p / 3;
             nrot = (int)(p % 3);
-            link = k;
+            via = k;
             break;
           }
         }
       }
       if (next < 0) break;
+      if (via == 2) meta[n - 1] = (uint8_t)(meta[n - 1] | kMetaReflect);
       placed[next] = 1;
       order[n] = (int32_t)next;
-      meta[n] = (uint8_t)(nrot | (link << 2));
+      meta[n] = (uint8_t)(nrot | kMetaLink);
       ++n;
       cur = next;
       rot = nrot;

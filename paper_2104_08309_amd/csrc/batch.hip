@@ -90,8 +90,8 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
       double xr[kQPTBatch], xi[kQPTBatch];
 #pragma unroll
       for (int k = 0; k < kQPTBatch; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
-      float E[kQPTBatch][4];  // edge terms carried from the previous face of the item (SHARE)
-      bool prev_ok = false;
+      FwdCarry<kQPTBatch> carry;  // shared edge term from the previous face of the item
+      carry.reset();
       for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
         const int nt = (int)min((int64_t)kTileF, f_end - t0);
         __syncthreads();
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         float tr[kQPTBatch], ti[kQPTBatch];
 #pragma unroll
         for (int k = 0; k < kQPTBatch; ++k) tr[k] = ti[k] = 0.0f;
-        fwd_tile_fp32c<kQPTBatch, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, E, prev_ok);
+        fwd_tile_fp32c<kQPTBatch, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, carry);
 #pragma unroll
         for (int k = 0; k < kQPTBatch; ++k) {
           kahan_add(sr[k], cr[k], tr[k]);

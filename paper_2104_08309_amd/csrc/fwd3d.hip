@@ -12,7 +12,7 @@
 //    coordinates, the face origin phase Q.g reduced in binary64 and
 //    evaluated in turns, the near-degenerate series branch in binary64, the
 //    sum over faces blocked per LDS tile and compensated (Kahan) across tiles.
-//    With the records in an edge-sharing order (Face32::link) a face takes
+//    With the records in an edge-sharing order (Face32::flags) a face takes
 //    the term of the edge it shares with its predecessor from registers.
 #include "fwd_terms.h"
 
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
 // edge-sharing order and each face takes one edge term from its predecessor in
 // the split (two edge terms per face instead of three).
 template <bool SHARE>
-__global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
+__global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs a) {
   __shared__ Face32 tile[kTileF];
   const int64_t qbase = (int64_t)blockIdx.x * (kBlock * kQPT) + threadIdx.x;
   const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
@@ -116,8 +116,8 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
   double xr[kQPT], xi[kQPT];
 #pragma unroll
   for (int k = 0; k < kQPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
-  float E[kQPT][4];      // edge terms carried from the previous face (SHARE)
-  bool prev_ok = false;  // no previous face at the start of the split
+  FwdCarry<kQPT> carry;  // shared edge term from the previous face (SHARE)
+  carry.reset();         // no previous face at the start of the split
   for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
     const int nt = (int)min((int64_t)kTileF, f_end - t0);
     __syncthreads();
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp32c_kernel(FwdArgs a) {
     float tr[kQPT], ti[kQPT];
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
-    fwd_tile_fp32c<kQPT, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, E, prev_ok);
+    fwd_tile_fp32c<kQPT, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, carry);
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) {
       kahan_add(sr[k], cr[k], tr[k]);

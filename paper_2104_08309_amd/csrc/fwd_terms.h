@@ -65,54 +65,28 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 // ---------------------------------------------------------------------------
 // FP32-compensated per-(Q, face) term
 // ---------------------------------------------------------------------------
-// Edge-sum form of the FP32-compensated face term. Sets `need_series` when the
-// pair is near-degenerate (Q close to the face normal) so that the caller
-// replaces the result with face_series_fp32c; keeping the branch out of this
-// function leaves straight-line code that the compiler can interleave across
-// the several Q a thread evaluates. The quantities the series needs (the
-// half-vertex phases, Q.N and the reduced face phase) are returned in `sd`.
+// Per (Q, face), in binary32 on the record's face-local quantities:
+//   QN = Q.N, s_j = Q.(|N| e_j), |P|^2 = s1^2 + s2^2, w_l = P.d_l (w_2 = -w_0 - w_1),
+//   half-vertex phases p_k = Q.u_k / (4 pi) in turns (p_2 = -p_0 - p_1),
+//   eta_l = p_{l+1} - p_l, edge midpoint phase t_l = r - p_{l+2} with r = Q.g / (2 pi),
+//   E_l = 2 pi sinc(2 pi eta_l) exp(2 pi i t_l),  T = (QN / |P|^2) sum_l w_l E_l,
+// the face term (Q.N)/|P|^2 exp(iQ.g) S of the 3D section written in turns. The
+// 2 pi sinc comes from sinc2pi_poly (no transcendental instruction) and the
+// midpoint exponentials from the hardware sine and cosine of turns.
+//
+// The origin phase r is formed in binary64 and reduced to [-1/2, 1/2] before it
+// is rounded to binary32. In an edge-sharing order (Face32::flags) edge 0 is the
+// previous record's edge 1, whose E is carried in registers: it depends only on
+// the edge (its midpoint, and |eta| since the sinc is even). Near-degenerate
+// pairs (Q nearly along the face normal, and empty faces) are replaced by the
+// face's simplex series in binary64.
+
+// Inputs of the binary64 series fix-up for one pair.
 struct SeriesInputs {
   float p0, p1;  // half-vertex phases psi_0, psi_1 in turns
   float QN;      // Q . N
-  float r;       // face origin phase Q.g in turns, reduced to [-1/2, 1/2]
+  float r;       // face origin phase Q.g in turns (any integer offset)
 };
-
-__device__ __forceinline__ void face_term_fp32c(const Face32& f, float qx, float qy, float qz, float Q2,
-                                                const double* Qd, float& Tr, float& Ti, bool& need_series,
-                                                SeriesInputs& sd) {
-  const float QN = qx * f.N[0] + qy * f.N[1] + qz * f.N[2];
-  // in-plane components of Q (times |N|); P = Q x N = s2 e1 - s1 e2
-  const float s1 = qx * f.E1[0] + qy * f.E1[1] + qz * f.E1[2];
-  const float s2 = qx * f.E2[0] + qy * f.E2[1] + qz * f.E2[2];
-  const float P2 = s1 * s1 + s2 * s2;
-  // edge weights w_l = P . d_l (over 2 pi)
-  const float w0 = s2 * f.al[0] + s1 * f.be[0];
-  const float w1 = s2 * f.al[1] + s1 * f.be[1];
-  const float w2 = -w0 - w1;
-  // half-vertex phases psi_k in turns
-  const float p0 = s1 * f.ga[0] + s2 * f.de[0];
-  const float p1 = s1 * f.ga[1] + s2 * f.de[1];
-  const float p2 = -p0 - p1;
-  // 2 pi sinc(eta_l), eta_l = psi_{l+1} - psi_l (turns)
-  const float a0 = w0 * sinc2pi_turns(p1 - p0);
-  const float a1 = w1 * sinc2pi_turns(p2 - p1);
-  const float a2 = w2 * sinc2pi_turns(p0 - p2);
-  // face origin phase Q.g in turns, reduced to [-1/2, 1/2] in binary64; the edge
-  // midpoint phases are Q.m_l = Q.g - psi_{l+2}
-  const double ph = Qd[0] * f.gt[0] + Qd[1] * f.gt[1] + Qd[2] * f.gt[2];
-  const float r = (float)(ph - rint(ph));
-  const float t0 = r - p2, t1 = r - p0, t2 = r - p1;
-  const float Sr = a0 * cos_turns(t0) + a1 * cos_turns(t1) + a2 * cos_turns(t2);
-  const float Si = a0 * sin_turns(t0) + a1 * sin_turns(t1) + a2 * sin_turns(t2);
-  const float co = QN * rcp_f(fmaxf(P2, 1e-30f));
-  Tr = co * Sr;
-  Ti = co * Si;
-  need_series = P2 < fmaxf(f.thr, f.kap * Q2);
-  sd.p0 = p0;
-  sd.p1 = p1;
-  sd.QN = QN;
-  sd.r = r;
-}
 
 // Q nearly along the face normal: simplex series of the face in binary64,
 // T = -i (Q.N) exp(i Q.g) sum_n i^n h_n(delta) / (n+2)!, delta_k = 4 pi psi_k,
@@ -130,92 +104,115 @@ __device__ __forceinline__ void face_series_fp32c(const SeriesInputs& sd, float&
   Ti = (float)(-QN * (cf * sr - sf * si));
 }
 
-// The same face term with one edge term taken from the previous face: in an
-// edge-sharing order (consecutive faces share an edge, Face32::link) the
-// shared edge's sinc(eta) exp(2 pi i t) is the same for both faces (the
-// midpoint is the same, and sinc is even in eta, whose sign flips with the
-// edge's direction); only its weight w = P.d belongs to each face. E holds
-// the previous face's terms of its edges 1 and 2 (re, im, re, im) and is
-// replaced by this face's; with reuse = 0 all three edge terms are computed.
-__device__ __forceinline__ void face_term_fp32c_shared(const Face32& f, float qx, float qy, float qz, float Q2,
-                                                       const double* Qd, bool reuse, float* E, float& Tr,
-                                                       float& Ti, bool& need_series, SeriesInputs& sd) {
-  const float QN = qx * f.N[0] + qy * f.N[1] + qz * f.N[2];
-  const float s1 = qx * f.E1[0] + qy * f.E1[1] + qz * f.E1[2];
-  const float s2 = qx * f.E2[0] + qy * f.E2[1] + qz * f.E2[2];
-  const float P2 = s1 * s1 + s2 * s2;
-  const float w0 = s2 * f.al[0] + s1 * f.be[0];
-  const float w1 = s2 * f.al[1] + s1 * f.be[1];
-  const float w2 = -w0 - w1;
-  const float p0 = s1 * f.ga[0] + s2 * f.de[0];
-  const float p1 = s1 * f.ga[1] + s2 * f.de[1];
-  const float p2 = -p0 - p1;
-  const double ph = Qd[0] * f.gt[0] + Qd[1] * f.gt[1] + Qd[2] * f.gt[2];
-  const float r = (float)(ph - rint(ph));
-  const float t0 = r - p2, t1 = r - p0, t2 = r - p1;
-  float e0r, e0i;
-  if (reuse) {
-    const bool one = f.link == 1u;
-    e0r = one ? E[0] : E[2];
-    e0i = one ? E[1] : E[3];
-  } else {
-    const float c0 = sinc2pi_turns(p1 - p0);
-    e0r = c0 * cos_turns(t0);
-    e0i = c0 * sin_turns(t0);
-  }
-  const float c1 = sinc2pi_turns(p2 - p1), c2 = sinc2pi_turns(p0 - p2);
-  E[0] = c1 * cos_turns(t1);
-  E[1] = c1 * sin_turns(t1);
-  E[2] = c2 * cos_turns(t2);
-  E[3] = c2 * sin_turns(t2);
-  const float Sr = w0 * e0r + w1 * E[0] + w2 * E[2];
-  const float Si = w0 * e0i + w1 * E[1] + w2 * E[3];
-  const float co = QN * rcp_f(fmaxf(P2, 1e-30f));
-  Tr = co * Sr;
-  Ti = co * Si;
-  need_series = P2 < fmaxf(f.thr, f.kap * Q2);
-  sd.p0 = p0;
-  sd.p1 = p1;
-  sd.QN = QN;
-  sd.r = r;
-}
+// What one thread carries from face to face within a face range.
+template <int NQ>
+struct FwdCarry {
+  float er[NQ], ei[NQ];  // E of the previous record's edge 1
+  bool prev;             // there is a previous record in this range (uniform)
+  __device__ __forceinline__ void reset() { prev = false; }
+};
 
-// One LDS tile of FP32C face records against the NQ Q points of a thread:
-// adds each face's term to tr[k], ti[k] (plain binary32 inside the tile). The
-// edge form is evaluated for every lane (no per-Q branch, so the NQ streams
-// interleave); pairs flagged near-degenerate are replaced by the series, and
-// lanes with small[k] set are left for the caller's small-|Q| path.
-// SHARE: the records are in edge-sharing order; E[k] carries the previous
-// face's edge terms across faces and tiles, prev_ok says whether there is a
-// previous (non-empty) face of the same face range to take them from.
+// One face record against a thread's NQ Q points: adds each term to tr[k], ti[k]
+// (lanes with small[k] set are left for the caller's small-|Q| path).
 template <int NQ, bool SHARE>
-__device__ __forceinline__ void fwd_tile_fp32c(const Face32* tile, int nt, const float* qx, const float* qy,
-                                               const float* qz, const float* Q2, const double (*Qd)[3],
-                                               const bool* small, float* tr, float* ti, float (*E)[4],
-                                               bool& prev_ok) {
-  for (int j = 0; j < nt; ++j) {
-    float Tr[NQ], Ti[NQ];
-    SeriesInputs sd[NQ];
-    bool ser[NQ];
-    if (SHARE) {
-      const bool reuse = prev_ok && tile[j].link != 0u;
+__device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx, const float* qy, const float* qz,
+                                               const float* Q2, const double (*Qd)[3], const bool* small, float* tr,
+                                               float* ti, FwdCarry<NQ>& c) {
+  const uint32_t flags = __builtin_amdgcn_readfirstlane(f.flags);
+  const bool linked = SHARE && c.prev && (flags & kFaceLinked) != 0u;
+  float QN[NQ], P2[NQ], w0[NQ], w1[NQ], p0[NQ], p1[NQ], r[NQ], c1[NQ], c2[NQ];
+  float m = 0.0f;
 #pragma unroll
-      for (int k = 0; k < NQ; ++k)
-        face_term_fp32c_shared(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], reuse, E[k], Tr[k], Ti[k], ser[k],
-                               sd[k]);
-      prev_ok = tile[j].thr >= 0.0f;
-    } else {
+  for (int k = 0; k < NQ; ++k) {
+    QN[k] = qx[k] * f.N[0] + qy[k] * f.N[1] + qz[k] * f.N[2];
+    const float s1 = qx[k] * f.E1[0] + qy[k] * f.E1[1] + qz[k] * f.E1[2];
+    const float s2 = qx[k] * f.E2[0] + qy[k] * f.E2[1] + qz[k] * f.E2[2];
+    P2[k] = s1 * s1 + s2 * s2;
+    w0[k] = s2 * f.al[0] + s1 * f.be[0];
+    w1[k] = s2 * f.al[1] + s1 * f.be[1];
+    p0[k] = s1 * f.ga[0] + s2 * f.de[0];
+    p1[k] = s1 * f.ga[1] + s2 * f.de[1];
+    // eta_1 = p_2 - p_1 and eta_2 = p_0 - p_2 with p_2 = -p_0 - p_1
+    const float x1 = fmaf(-2.0f, p1[k], -p0[k]), x2 = fmaf(2.0f, p0[k], p1[k]);
+    c1[k] = sinc2pi_poly(x1);
+    c2[k] = sinc2pi_poly(x2);
+    m = fmaxf(m, fmaxf(fabsf(x1), fabsf(x2)));
+  }
+  if (__builtin_expect(m > kSincPolyMax, 0)) {  // long edges at large |Q|: the sine quotient
 #pragma unroll
-      for (int k = 0; k < NQ; ++k)
-        face_term_fp32c(tile[j], qx[k], qy[k], qz[k], Q2[k], Qd[k], Tr[k], Ti[k], ser[k], sd[k]);
+    for (int k = 0; k < NQ; ++k) {
+      c1[k] = sinc2pi_wide(fmaf(-2.0f, p1[k], -p0[k]), c1[k]);
+      c2[k] = sinc2pi_wide(fmaf(2.0f, p0[k], p1[k]), c2[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const double ph = Qd[k][0] * f.gt[0] + Qd[k][1] * f.gt[1] + Qd[k][2] * f.gt[2];
+    r[k] = (float)(ph - rint(ph));
+  }
+  float e0r[NQ], e0i[NQ];
+  if (linked) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      e0r[k] = c.er[k];
+      e0i[k] = c.ei[k];
+    }
+  } else {  // edge 0 too (first face of a chain, or the list order)
+    float c0[NQ];
+    float m0 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const float x0 = p1[k] - p0[k];
+      c0[k] = sinc2pi_poly(x0);
+      m0 = fmaxf(m0, fabsf(x0));
+    }
+    if (__builtin_expect(m0 > kSincPolyMax, 0)) {
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) c0[k] = sinc2pi_wide(p1[k] - p0[k], c0[k]);
     }
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-      if (ser[k] && !small[k]) face_series_fp32c(sd[k], Tr[k], Ti[k]);
-      tr[k] += Tr[k];
-      ti[k] += Ti[k];
+      const float t0 = r[k] + p0[k] + p1[k];
+      e0r[k] = c0[k] * cos_turns(t0);
+      e0i[k] = c0[k] * sin_turns(t0);
     }
   }
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const float t1 = r[k] - p0[k], t2 = r[k] - p1[k];
+    const float e1r = c1[k] * cos_turns(t1), e1i = c1[k] * sin_turns(t1);
+    const float e2r = c2[k] * cos_turns(t2), e2i = c2[k] * sin_turns(t2);
+    const float w2 = -(w0[k] + w1[k]);
+    const float Sr = w0[k] * e0r[k] + w1[k] * e1r + w2 * e2r;
+    const float Si = w0[k] * e0i[k] + w1[k] * e1i + w2 * e2i;
+    const float co = QN[k] * rcp_f(P2[k]);
+    float Tr = co * Sr, Ti = co * Si;
+    // |Q_perp| L < tau or |Q_perp| < tau_rel |Q| (and every pair of an empty face): the series
+    if (P2[k] < fmaf(f.kap, Q2[k], f.thr) && !small[k]) {
+      SeriesInputs sd;
+      sd.p0 = p0[k];
+      sd.p1 = p1[k];
+      sd.QN = QN[k];
+      sd.r = r[k];
+      face_series_fp32c(sd, Tr, Ti);
+    }
+    tr[k] += Tr;
+    ti[k] += Ti;
+    c.er[k] = e1r;
+    c.ei[k] = e1i;
+  }
+  c.prev = true;
+}
+
+// One LDS tile of FP32C face records against the NQ Q points of a thread
+// (plain binary32 sums inside the tile). SHARE: the records are in an
+// edge-sharing order; `c` carries the shared edge's term and the origin phase
+// across faces and tiles of one face range (reset it at the range's start).
+template <int NQ, bool SHARE>
+__device__ __forceinline__ void fwd_tile_fp32c(const Face32* tile, int nt, const float* qx, const float* qy,
+                                               const float* qz, const float* Q2, const double (*Qd)[3],
+                                               const bool* small, float* tr, float* ti, FwdCarry<NQ>& c) {
+  for (int j = 0; j < nt; ++j) fwd_face_fp32c<NQ, SHARE>(tile[j], qx, qy, qz, Q2, Qd, small, tr, ti, c);
 }
 
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {

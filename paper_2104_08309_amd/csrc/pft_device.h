@@ -79,6 +79,25 @@ __device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x
 // at most 2 pi, so the minimum leaves it unchanged.
 __device__ __forceinline__ float sinc2pi_turns(float x) { return fminf(sin_turns(x) * rcp_f(x), kTwoPiF); }
 
+// The same function as a polynomial in y = x^2 for |x| <= kSincPolyMax = 1/2 turn: the minimax fit of
+// degree 5 in y (Remez exchange on the absolute error over y in [0, 1/4]; fit error 3.9e-7), with the
+// coefficients rounded to binary32. Evaluated by Horner's rule in binary32 the error stays below 1e-6,
+// i.e. 1.6e-7 of the value 2 pi at x = 0 -- the size of the hardware sine's own error divided by x -- with
+// no transcendental instruction and no removable point. Beyond 1/2 turn the caller uses sinc2pi_turns.
+constexpr float kSincPolyMax = 0.5f;
+__device__ __forceinline__ float sinc2pi_poly(float x) {
+  const float y = x * x;
+  float p = fmaf(-12.473669052124023f, y, 41.344398498535156f);
+  p = fmaf(p, y, -76.61480712890625f);
+  p = fmaf(p, y, 81.5999755859375f);
+  p = fmaf(p, y, -41.341590881347656f);
+  return fmaf(p, y, 6.283185005187988f);
+}
+// sinc2pi_poly's value `c` at x where it applies, the sine-quotient form beyond.
+__device__ __forceinline__ float sinc2pi_wide(float x, float c) {
+  return fabsf(x) > kSincPolyMax ? sin_turns(x) * rcp_f(x) : c;
+}
+
 // 1/n! for n = 0..95, correctly rounded binary64 (device constant memory; a
 // host copy for host builds of the binary64 math).
 #define PFT_INV_FACT_VALUES \

@@ -14,12 +14,19 @@ namespace pft {
 // Tuning constants
 // ---------------------------------------------------------------------------
 constexpr int kBlock = 256;        // threads per block for the Q-parallel kernels
-constexpr int kTileF = 64;         // faces staged in LDS per tile (forward)
+#ifndef PFT_TILEF
+#define PFT_TILEF 64
+#endif
+constexpr int kTileF = PFT_TILEF;  // faces staged in LDS per tile (forward)
 constexpr int kTileFB = 8;         // faces per block in the binary64 adjoint
 #ifndef PFT_QPT
 #define PFT_QPT 3
 #endif
 constexpr int kQPT = PFT_QPT;      // Q per thread in the FP32C forward
+#ifndef PFT_FWD_WAVES
+#define PFT_FWD_WAVES 4
+#endif
+constexpr int kFwdWaves = PFT_FWD_WAVES;  // waves per SIMD the FP32C forward's registers must allow
 #ifndef PFT_QPT_BATCH
 #define PFT_QPT_BATCH 1
 #endif
@@ -95,25 +102,37 @@ struct alignas(16) Face64 {
 static_assert(sizeof(Face64) == 128, "Face64 layout");
 
 // FP32C forward face record (staged in LDS). The in-plane geometry is held in
-// an orthonormal basis e1, e2 of the face plane (e1 along b - a, e2 = n x e1):
-// with s_j = Q . (|N| e_j), the in-plane part of Q, P = Q x N = s2 e1 - s1 e2,
-// so |P|^2 = s1^2 + s2^2, P . d_l = s2 (e1 . d_l) - s1 (e2 . d_l) and the
-// vertex phases Q . u_k = s1 (e1 . u_k)/|N| + s2 (e2 . u_k)/|N|.
+// an orthonormal basis e1, e2 of the face plane (e1 along b - a, e2 = n x e1,
+// with a, b, c the vertices in the record's traversal order and n that order's
+// unit normal): with s_j = Q . (|N| e_j), the in-plane part of Q,
+// P = Q x N = s2 e1 - s1 e2, so |P|^2 = s1^2 + s2^2, P . d_l = s2 (e1 . d_l) - s1 (e2 . d_l)
+// and the half-vertex phases Q . u_k / 2 = s1 (e1 . u_k)/(2|N|) + s2 (e2 . u_k)/(2|N|).
+// In an edge-sharing order the traversal may be the reverse of the outward
+// (counter-clockwise) one, so that the edge shared with the next face is edge
+// 1: the edge sum S is the same for both traversals (each edge's P . d and
+// sinc are unchanged when both the normal and the edge flip), and N below
+// stays the outward normal, so the face term (Q.N)/|P|^2 S is unchanged.
 struct alignas(16) Face32 {
   double gt[3];   // centroid / (2 pi), binary64: face origin phase in turns is Q . gt
-  float N[3];     // (b - a) x (c - a)
+  float N[3];     // outward (b - a) x (c - a) of the counter-clockwise traversal, for Q.N
   float E1[3];    // |N| e1
   float E2[3];    // |N| e2
   float al[2];    // (e1 . d_l) / (2 pi), l = 0, 1 (d_0 = b - a, d_1 = c - b)
   float be[2];    // -(e2 . d_l) / (2 pi)
   float ga[2];    // (e1 . u_k) / (4 pi |N|), k = 0, 1 (u_0 = a - g, u_1 = b - g)
   float de[2];    // (e2 . u_k) / (4 pi |N|)
-  float thr;      // tau^2 |N|^2 / L^2
+  float thr;      // tau^2 |N|^2 / L^2 (1 for an empty face: its series term is Q.N = 0 times a sum)
   float kap;      // tau_rel^2 |N|^2
-  uint32_t link;  // 0, or k = 1, 2: edge 0 of this face is edge k of the previous face (edge-sharing order)
+  uint32_t flags; // kFaceLinked: edge 0 is the previous record's edge 1 (edge-sharing order)
   float pad[2];
 };
 static_assert(sizeof(Face32) == 112, "Face32 layout");
+constexpr uint32_t kFaceLinked = 1u;
+// Edge-sharing order metadata (pft_strip_order, one byte per position): the face's
+// vertex list rotated by (meta & 3), edge 0 shared with the previous position's
+// edge 1 if (meta & kMetaLink), and the traversal reversed (b, a, c) if (meta & kMetaReflect).
+constexpr unsigned kMetaLink = 4u;
+constexpr unsigned kMetaReflect = 8u;
 
 // FP32C adjoint face record.
 struct alignas(16) Face32B {

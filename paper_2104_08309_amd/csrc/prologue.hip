@@ -106,6 +106,14 @@ __device__ inline void empty_face64(Face64& f) {
   f.pad[0] = f.pad[1] = f.pad[2] = 0.0;
 }
 
+// The edge-sharing flags of position m kept in Face64::pad[2] for the FP32C record
+// builder: 1 = linked to the previous position, 2 = traversal reversed. The Face64
+// record itself keeps the outward (rotated) vertex order.
+__device__ __forceinline__ int order_code(const uint8_t* meta, int64_t m) {
+  if (!meta) return 0;
+  return ((meta[m] & kMetaLink) ? 1 : 0) | ((meta[m] & kMetaReflect) ? 2 : 0);
+}
+
 __global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdtype, int64_t nv, const int32_t* tris,
                                                      int64_t nf, const MeshInfo* info, double tau, Face64* out,
                                                      const int32_t* order, const uint8_t* meta) {
@@ -114,7 +122,7 @@ __global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdty
   // the face at this position of the (optional) edge-sharing order, its vertex list rotated
   const int64_t src = order ? (int64_t)order[m] : m;
   const int rot = meta ? (meta[m] & 3) : 0;
-  const int link = meta ? ((meta[m] >> 2) & 3) : 0;
+  const int code = order_code(meta, m);
   Face64 f;
   const bool in_list = src >= 0 && src < nf && rot < 3;
   const int32_t ia = in_list ? tris[3 * src + rot] : -1;
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdty
       c[k] -= mi.t[k];
     }
     make_face64(a, b, c, tau, f);
-    f.pad[2] = (double)link;
+    f.pad[2] = (double)code;
   }
   out[m] = f;
 }
@@ -297,7 +305,7 @@ __global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, in
   // the face at this position of the (optional) edge-sharing order (within its mesh), rotated
   const int64_t src = order ? (int64_t)order[m] : m;
   const int rot = meta ? (meta[m] & 3) : 0;
-  const int link = meta ? ((meta[m] >> 2) & 3) : 0;
+  const int code = order_code(meta, m);
   const bool in_list = src >= 0 && src < nf_total && rot < 3;
   const int32_t ia = in_list ? tris[3 * src + rot] : -1;
   const int32_t ib = in_list ? tris[3 * src + (rot + 1) % 3] : -1;
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, in
       c[k] -= mi.t[k];
     }
     make_face64(a, b, c, tau, f);
-    f.pad[2] = (double)link;
+    f.pad[2] = (double)code;
   }
   out[m] = f;
 }
@@ -346,21 +354,31 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
   Face32 r;
   const double L2 = f.pad[0], N2 = f.pad[1];
   const bool ok = f.thr >= 0.0;
-  double d0[3], d1[3], e1[3], e2[3];
+  const int code = (int)f.pad[2];
+  // linked only to a non-empty predecessor (an empty record carries no edge term)
+  const bool link = ok && (code & 1) && m > 0 && in[m - 1].thr >= 0.0;
+  const bool refl = (code & 2) != 0;
+  // traversal order (a, b, c), or (b, a, c) reversed; the normal of the traversal
+  double u0[3], u1[3], Nt[3], d0[3], d1[3], e1[3], e2[3];
+  for (int k = 0; k < 3; ++k) {
+    u0[k] = refl ? f.u1[k] : f.u0[k];
+    u1[k] = refl ? f.u0[k] : f.u1[k];
+    Nt[k] = refl ? -f.N[k] : f.N[k];
+    d0[k] = u1[k] - u0[k];
+    d1[k] = -u0[k] - 2.0 * u1[k];
+  }
   for (int k = 0; k < 3; ++k) {
     r.gt[k] = f.g[k] * kInv2Pi;
     r.N[k] = (float)f.N[k];
-    d0[k] = f.u1[k] - f.u0[k];
-    d1[k] = -f.u0[k] - 2.0 * f.u1[k];
   }
   auto dot = [](const double* x, const double* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
   const double nN = sqrt(N2), nd0 = sqrt(dot(d0, d0));
   if (ok && nd0 > 0.0) {
     for (int k = 0; k < 3; ++k) e1[k] = d0[k] / nd0;
-    // e2 = n x e1 = (N x d0) / (|N| |d0|)
-    e2[0] = (f.N[1] * d0[2] - f.N[2] * d0[1]) / (nN * nd0);
-    e2[1] = (f.N[2] * d0[0] - f.N[0] * d0[2]) / (nN * nd0);
-    e2[2] = (f.N[0] * d0[1] - f.N[1] * d0[0]) / (nN * nd0);
+    // e2 = n x e1 = (N x d0) / (|N| |d0|), with the traversal's normal
+    e2[0] = (Nt[1] * d0[2] - Nt[2] * d0[1]) / (nN * nd0);
+    e2[1] = (Nt[2] * d0[0] - Nt[0] * d0[2]) / (nN * nd0);
+    e2[2] = (Nt[0] * d0[1] - Nt[1] * d0[0]) / (nN * nd0);
     for (int k = 0; k < 3; ++k) {
       r.E1[k] = (float)(nN * e1[k]);
       r.E2[k] = (float)(nN * e2[k]);
@@ -369,19 +387,22 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
     r.al[1] = (float)(dot(e1, d1) * kInv2Pi);
     r.be[0] = (float)(-dot(e2, d0) * kInv2Pi);
     r.be[1] = (float)(-dot(e2, d1) * kInv2Pi);
-    r.ga[0] = (float)(dot(e1, f.u0) * kInv4Pi / nN);
-    r.ga[1] = (float)(dot(e1, f.u1) * kInv4Pi / nN);
-    r.de[0] = (float)(dot(e2, f.u0) * kInv4Pi / nN);
-    r.de[1] = (float)(dot(e2, f.u1) * kInv4Pi / nN);
+    r.ga[0] = (float)(dot(e1, u0) * kInv4Pi / nN);
+    r.ga[1] = (float)(dot(e1, u1) * kInv4Pi / nN);
+    r.de[0] = (float)(dot(e2, u0) * kInv4Pi / nN);
+    r.de[1] = (float)(dot(e2, u1) * kInv4Pi / nN);
     r.thr = (float)(tau * tau * N2 / L2);
     r.kap = (float)(tau_rel * tau_rel * N2);
+    r.flags = link ? kFaceLinked : 0u;
   } else {
-    // empty face: every weight is zero, so its term is exactly zero
+    // empty face: every weight is zero; thr > 0 sends every pair to the series, whose term is
+    // Q.N = 0 times a finite sum, so its contribution is exactly zero (the edge form would be 0/0)
     for (int k = 0; k < 3; ++k) r.N[k] = r.E1[k] = r.E2[k] = 0.0f;
     r.al[0] = r.al[1] = r.be[0] = r.be[1] = r.ga[0] = r.ga[1] = r.de[0] = r.de[1] = 0.0f;
-    r.thr = r.kap = -1.0f;
+    r.thr = 1.0f;
+    r.kap = 0.0f;
+    r.flags = 0u;
   }
-  r.link = ok ? (uint32_t)f.pad[2] : 0u;
   r.pad[0] = r.pad[1] = 0.0f;
   out[m] = r;
 }

@@ -21,19 +21,25 @@ static void check_order(const std::vector<int32_t>& tris, int64_t nf, int64_t nv
   std::vector<int32_t> order(nf > 0 ? nf : 1);
   std::vector<uint8_t> meta(nf > 0 ? nf : 1);
   CHECK(pft_strip_order(tris.data(), nf, nv, order.data(), meta.data()) == PFT_OK);
+  // traversal of position i: rotation r, then (b, a, c) when reversed (bit 3)
+  auto trav = [&](int64_t i, int32_t* v) {
+    const int32_t* f = &tris[3 * (int64_t)order[i]];
+    const int r = meta[i] & 3;
+    const bool rev = (meta[i] & 8) != 0;
+    v[0] = f[(r + (rev ? 1 : 0)) % 3];
+    v[1] = f[(r + (rev ? 0 : 1)) % 3];
+    v[2] = f[(r + 2) % 3];
+  };
   std::vector<int> seen(nf, 0);
   for (int64_t i = 0; i < nf; ++i) {
     CHECK(order[i] >= 0 && order[i] < nf);
     if (order[i] >= 0 && order[i] < nf) ++seen[order[i]];
-    const int rot = meta[i] & 3, link = (meta[i] >> 2) & 3;
-    CHECK(rot < 3 && link < 3);
-    if (link && i > 0) {
-      const int32_t* a = &tris[3 * (int64_t)order[i]];
-      const int32_t* b = &tris[3 * (int64_t)order[i - 1]];
-      const int rb = meta[i - 1] & 3;
-      const int32_t a0 = a[rot], a1 = a[(rot + 1) % 3];
-      const int32_t b0 = b[(rb + link) % 3], b1 = b[(rb + link + 1) % 3];
-      CHECK((a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0));
+    CHECK((meta[i] & 3) < 3 && (meta[i] & ~15) == 0);
+    if ((meta[i] & 4) && i > 0) {  // edge 0 of this face is edge 1 of the previous face
+      int32_t a[3], b[3];
+      trav(i, a);
+      trav(i - 1, b);
+      CHECK((a[0] == b[1] && a[1] == b[2]) || (a[0] == b[2] && a[1] == b[1]));
     }
   }
   for (int64_t f = 0; f < nf; ++f) CHECK(seen[f] == 1);

@@ -1,34 +1,41 @@
-"""The host edge-sharing face order (pft_strip_order): a permutation, cyclic rotations that keep each
-face's orientation, and links that name an edge the two consecutive faces really share."""
+"""The host edge-sharing face order (pft_strip_order): a permutation; per position a cyclic rotation of the
+face's vertex list, optionally traversed in reverse (b, a, c); and links that name an edge the two
+consecutive faces really share: edge 0 of the face is edge 1 of its predecessor."""
 import numpy as np
 import pytest
 
 import meshgen as mg
 from paper_2104_08309_amd import _lib, api
 
+LINK, REFLECT = 4, 8
 
-def rotated(tris, order, meta, i):
+
+def traversal(tris, order, meta, i):
     f = tris[order[i]]
     r = int(meta[i]) & 3
     assert r < 3
-    return [int(f[r]), int(f[(r + 1) % 3]), int(f[(r + 2) % 3])]
+    a = [int(f[r]), int(f[(r + 1) % 3]), int(f[(r + 2) % 3])]
+    return [a[1], a[0], a[2]] if int(meta[i]) & REFLECT else a
 
 
 def check_order(tris, order, meta, nv):
     nf = len(tris)
     assert sorted(order.tolist()) == list(range(nf))
+    assert np.all((meta & ~np.uint8(3 | LINK | REFLECT)) == 0)
     for i in range(nf):
-        a = rotated(tris, order, meta, i)
+        a = traversal(tris, order, meta, i)
         f = [int(x) for x in tris[order[i]]]
-        # a cyclic rotation of the listed vertices: same orientation
-        assert any(a == f[k:] + f[:k] for k in range(3))
-        link = (int(meta[i]) >> 2) & 3
-        if link:
-            assert i > 0 and link in (1, 2)
-            b = rotated(tris, order, meta, i - 1)
-            assert {a[0], a[1]} == {b[link], b[(link + 1) % 3]}
+        rev = f[::-1]
+        if int(meta[i]) & REFLECT:  # the reversed orientation
+            assert any(a == rev[k:] + rev[:k] for k in range(3))
+        else:  # a cyclic rotation of the listed vertices: same orientation
+            assert any(a == f[k:] + f[:k] for k in range(3))
+        if int(meta[i]) & LINK:
+            assert i > 0
+            b = traversal(tris, order, meta, i - 1)
+            assert {a[0], a[1]} == {b[1], b[2]}
             assert all(0 <= x < nv for x in a + b) and len(set(a)) == 3 and len(set(b)) == 3
-    return float(np.mean(((meta >> 2) & 3) > 0))
+    return float(np.mean((meta & LINK) > 0))
 
 
 @pytest.mark.parametrize("level", [0, 2, 4])
@@ -49,7 +56,7 @@ def test_union_mesh_and_bad_faces():
     assert frac > 0.8
     pos = {int(o): i for i, o in enumerate(order)}
     for bad in (len(t), len(t) + 1):
-        assert (meta[pos[bad]] >> 2) & 3 == 0
+        assert meta[pos[bad]] & LINK == 0
 
 
 def test_validation():
@@ -70,5 +77,5 @@ def test_batch_order_stays_within_each_mesh():
     for i, (v, t) in enumerate(meshes):
         a, b = int(to[i]), int(to[i + 1])
         local_order = order[a:b] - a
-        assert (meta[a] >> 2) & 3 == 0
+        assert meta[a] & LINK == 0
         check_order(t, local_order, meta[a:b], len(v))
