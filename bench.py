@@ -466,16 +466,27 @@ def main():
                     pft.batch_backward(BV, BT, BQ, vo, to, qo, BG, mode="fp32c"))
 
         b_steps = max(2, args.steps // 8)
+        # the first (warmup) call tunes the tile sizes for this input's size bucket; then the same step
+        # with the compiled default tile sizes
         tb5, (BF, BD) = timed(bstep, b_steps, 1)
         n_bf, ms_bf = pft.profile_read("batch_fwd")
         n_bb, ms_bb = pft.profile_read("batch_bwd")
         ms_bf, ms_bb = ms_bf / max(n_bf, 1), ms_bb / max(n_bb, 1)
+        os.environ["PFT_AUTOTUNE"] = "0"
+        tb5d, _ = timed(bstep, b_steps, 1)
+        n_df, ms_df = pft.profile_read("batch_fwd")
+        n_db, ms_db = pft.profile_read("batch_bwd")
+        del os.environ["PFT_AUTOTUNE"]
         batch = {"workload": f"config 5: {len(meshes)} meshes, {to[-1]} faces, {qo[-1]} Q, {pairs:.3e} face*Q "
                              f"(each mesh its own Q list), FP32C forward + adjoint, one persistent launch each",
                  "ms_per_step": tb5 * 1e3, "face_q_per_s": pairs / tb5,
                  "forward_kernel_ms": ms_bf, "adjoint_kernel_ms": ms_bb,
                  "forward_alu_frac": FLOP_FWD * pairs / (ms_bf * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
-                 "adjoint_alu_frac": FLOP_BWD * pairs / (ms_bb * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+                 "adjoint_alu_frac": FLOP_BWD * pairs / (ms_bb * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                 "tuned_tiles": pft.tuning_info().strip().split("\n"),
+                 "default_tiles_ms_per_step": tb5d * 1e3,
+                 "default_tiles_forward_kernel_ms": ms_df / max(n_df, 1),
+                 "default_tiles_adjoint_kernel_ms": ms_db / max(n_db, 1)}
         c1 = mg.config1()
         P2 = torch.tensor(c1["verts"], device=dev)
         Q2d = torch.tensor(c1["q"], device=dev)

@@ -35,11 +35,13 @@
  *  - Complex outputs are interleaved (re, im) pairs.
  *  - NaN / Inf in inputs propagate to the affected outputs.
  *  - Triangle indices outside [0, nv) never cause an out-of-bounds access: the
- *    face is treated as empty (contributes zero) and counted; use
- *    pft_validate_mesh to check a mesh. With PFT_VALIDATE=1 in the environment
- *    (read at each call), pft_forward_3d, pft_backward_3d, pft_intensity_loss_3d,
- *    pft_orientation_average and the region entry points count such indices
- *    on the device first (a synchronous check) and return PFT_EINVAL if any.
+ *    face is treated as empty (contributes zero); pft_validate_mesh counts them
+ *    on the device and pft_check_mesh checks a mesh on the host (indices, closed,
+ *    consistently oriented). With PFT_VALIDATE=1 in the environment (read at
+ *    each call), pft_forward_3d, pft_backward_3d, pft_intensity_loss_3d,
+ *    pft_orientation_average and the region entry points run that check on
+ *    their mesh first (synchronously; each region on its own), also require a
+ *    non-negative enclosed volume, and return PFT_EINVAL if the mesh fails.
  *  - Results do not depend on the order of faces in the list except through
  *    floating-point rounding, and are bitwise reproducible for fixed inputs
  *    and sizes (fixed reduction order, no floating-point atomics).
@@ -417,6 +419,30 @@ pft_status pft_batch_backward(const pft_mesh_batch* batch, pft_mode mode, const 
                               void* stream);
 
 /*
+ * pft_check_mesh -- what the method requires of a triangle mesh, checked on the
+ * host (3D section: the boundary is a closed polygonal surface whose faces run
+ * counter-clockwise seen from outside). An open surface makes the sum over
+ * faces depend on the origin, and faces of inconsistent orientation subtract
+ * where they should add. HOST function, no GPU work.
+ *
+ *  tris    [nf][3] int32 (HOST).
+ *  report  HOST, written: the counts below; a mesh passes when all are zero.
+ * The enclosed volume's sign (negative for an inward mesh, which gives -F) needs
+ * the vertices: F(0) is that volume. With PFT_VALIDATE=1 in the environment the
+ * 3D entry points run this check on their (device) mesh, each region on its
+ * own, and also reject a negative volume, returning EINVAL with the counts.
+ * Errors: EINVAL for negative counts or NULL pointers.
+ */
+typedef struct {
+  int64_t bad_index;          /* faces with an index outside [0, nv) */
+  int64_t repeated_vertex;    /* faces listing a vertex twice */
+  int64_t open_edges;         /* edges of exactly one face: the surface has a boundary */
+  int64_t nonmanifold_edges;  /* edges of more than two faces */
+  int64_t misoriented_edges;  /* edges that both of their faces run in the same direction */
+} pft_mesh_check;
+pft_status pft_check_mesh(const int32_t* tris, int64_t nf, int64_t nv, pft_mesh_check* report);
+
+/*
  * pft_validate_mesh -- count triangle indices outside [0, nv) and faces with a
  * repeated vertex. Synchronous: blocks until the check has run on `stream`.
  * Both outputs are HOST pointers (either may be NULL).
@@ -442,6 +468,20 @@ pft_status pft_release_workspace(void);
 pft_status pft_profile_enable(int enable);
 pft_status pft_profile_reset(void);
 pft_status pft_profile_read(const char* name, int64_t* launches, double* total_ms);
+
+/*
+ * Tile sizes of the batched launches (the batched forward's Q per thread and
+ * faces per work item, the batched adjoint's Q per work item) are chosen at run
+ * time per (GPU, form, size bucket of meshes, faces and face*Q pairs): the
+ * first pft_batch_forward / pft_batch_backward call with a new key runs each
+ * candidate once on its input, times it (that call synchronises), keeps the
+ * fastest and produces its output with it; later calls with the key reuse the
+ * choice. PFT_AUTOTUNE=0 in the environment selects the compiled defaults.
+ * pft_tuning_info returns one line per choice made in this process (key,
+ * choice and each candidate's time); the text is valid until the next call on
+ * the same thread.
+ */
+const char* pft_tuning_info(void);
 
 /* Library version string. */
 const char* pft_version(void);

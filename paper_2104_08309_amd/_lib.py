@@ -19,7 +19,7 @@ EXPORTS = [
     "pft_forward_2d", "pft_forward_3d", "pft_backward_3d", "pft_batch_forward", "pft_batch_backward",
     "pft_forward_3d_poly", "pft_orientation_average", "pft_forward_3d_regions", "pft_backward_3d_regions",
     "pft_intensity_loss_3d", "pft_strip_order", "pft_forward_3d_ordered", "pft_batch_forward_ordered",
-    "pft_q_order", "pft_backward_3d_ordered", "pft_forward_3d_noalloc",
+    "pft_q_order", "pft_backward_3d_ordered", "pft_forward_3d_noalloc", "pft_check_mesh", "pft_tuning_info",
     "pft_validate_mesh", "pft_last_error", "pft_release_workspace", "pft_profile_enable",
     "pft_profile_reset", "pft_profile_read", "pft_version",
 ]
@@ -39,6 +39,13 @@ class PftMeshBatch(ctypes.Structure):
         ("q", ctypes.c_void_p),
         ("qdtype", ctypes.c_int),
     ]
+
+
+class PftMeshCheck(ctypes.Structure):
+    """Mirror of ``pft_mesh_check``."""
+
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("bad_index", "repeated_vertex", "open_edges", "nonmanifold_edges", "misoriented_edges")]
 
 
 class PftError(RuntimeError):
@@ -83,17 +90,19 @@ def load() -> ctypes.CDLL:
         "pft_backward_3d_regions": [vp, cint, i64, vp, i64, P(i64), i64, vp, vp, cint, i64, cint, vp, vp, vp, vp,
                                     vp],
         "pft_validate_mesh": [vp, i64, i64, P(i64), P(i64), vp],
+        "pft_check_mesh": [vp, i64, i64, P(PftMeshCheck)],
         "pft_last_error": [],
         "pft_release_workspace": [],
         "pft_profile_enable": [cint],
         "pft_profile_reset": [],
         "pft_profile_read": [ctypes.c_char_p, P(i64), P(ctypes.c_double)],
         "pft_version": [],
+        "pft_tuning_info": [],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = ctypes.c_char_p if name in ("pft_last_error", "pft_version") else cint
+        fn.restype = ctypes.c_char_p if name in ("pft_last_error", "pft_version", "pft_tuning_info") else cint
     _lib = lib
     return lib
 

@@ -21,8 +21,8 @@ __all__ = [
     "forward_2d", "forward_3d", "forward_3d_noalloc", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
     "orientation_average", "forward_3d_regions", "backward_3d_regions", "intensity_loss_3d", "strip_order",
     "batch_strip_order", "q_order",
-    "validate_mesh",
-    "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id",
+    "validate_mesh", "check_mesh",
+    "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id", "tuning_info",
 ]
 
 _MODES = {"fp64": PFT_FP64, "fp32c": PFT_FP32C}
@@ -561,6 +561,19 @@ def batch_backward(verts, tris, q, vert_offsets, tri_offsets, q_offsets, grad_ou
     return grad
 
 
+def check_mesh(tris, nv: Optional[int] = None) -> dict:
+    """pft_check_mesh on the host: counts of out-of-range indices, faces with a repeated vertex, open
+    edges, edges of more than two faces and edges both faces run the same way (all zero for a closed,
+    consistently oriented triangle mesh). ``tris`` may be a tensor (copied to the host)."""
+    t = tris.detach().cpu().numpy() if isinstance(tris, torch.Tensor) else np.asarray(tris)
+    t = np.ascontiguousarray(t, dtype=np.int32).reshape(-1, 3)
+    if nv is None:
+        nv = int(t.max()) + 1 if t.size else 0
+    rep = _lib.PftMeshCheck()
+    check(_lib.load().pft_check_mesh(t.ctypes.data, t.shape[0], nv, ctypes.byref(rep)))
+    return {name: int(getattr(rep, name)) for name, _ in rep._fields_}
+
+
 def validate_mesh(tris: torch.Tensor, nv: int) -> Tuple[int, int]:
     """(number of out-of-range indices, number of faces with a repeated vertex)."""
     tris = _on_gpu(tris, "tris").to(torch.int32)
@@ -588,6 +601,12 @@ def profile_read(name: str) -> Tuple[int, float]:
 
 def release_workspace() -> None:
     check(_lib.load().pft_release_workspace())
+
+
+def tuning_info() -> str:
+    """The batched launches' tile sizes chosen at run time in this process (pft_tuning_info), one line
+    per (GPU, form, size bucket): the choice and each candidate's time in ms."""
+    return _lib.load().pft_tuning_info().decode()
 
 
 def version() -> str:

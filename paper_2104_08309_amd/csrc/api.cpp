@@ -4,6 +4,7 @@
 // device memory from the stream-ordered allocator on the caller's stream,
 // enqueues the prologue / compute / finish kernels on that stream and returns.
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdint>
 #include <cstdlib>
@@ -191,6 +192,82 @@ constexpr int64_t kBatchChunkQ = PFT_BATCH_CHUNK_Q;  // Q per batched adjoint it
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ---------------------------------------------------------------------------
+// tile sizes of the batched launches, tuned at run time
+// ---------------------------------------------------------------------------
+// The batched forward's Q per thread and faces per work item, and the batched
+// adjoint's Q per work item, are chosen per (GPU, form, size bucket): the
+// first call whose key is new runs every candidate once on its own input, times
+// each with events (a synchronous call), keeps the fastest, and produces its
+// output with it; later calls with that key use the kept choice. With
+// PFT_AUTOTUNE=0 in the environment the compiled defaults are used.
+struct BatchTiles {
+  int qpt = kQPTBatch;
+  int64_t chunk_f = kBatchChunkF;
+  int64_t chunk_q = kBatchChunkQ;
+};
+std::mutex g_tune_mu;
+std::map<std::string, BatchTiles> g_tuned;
+std::vector<std::string> g_tune_log;
+thread_local std::string g_tune_text;
+
+bool autotune_enabled() {
+  const char* e = std::getenv("PFT_AUTOTUNE");
+  return e == nullptr || e[0] != '0';
+}
+
+int log2_bucket(double x) { return x > 1.0 ? (int)std::floor(std::log2(x)) : 0; }
+
+std::string tune_key(const char* what, int mode, bool share, int64_t n_meshes, double pairs, int64_t nf) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  return std::string(what) + "[" + arch + (mode == PFT_FP64 ? ",fp64" : ",fp32c") + (share ? ",edge-sharing" : "") +
+         ",meshes~2^" + std::to_string(log2_bucket((double)n_meshes)) + ",faces~2^" +
+         std::to_string(log2_bucket((double)nf)) + ",pairs~2^" + std::to_string(log2_bucket(pairs)) + "]";
+}
+
+bool tuned_tiles(const std::string& key, BatchTiles* t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(key);
+  if (it == g_tuned.end()) return false;
+  *t = it->second;
+  return true;
+}
+
+void keep_tiles(const std::string& key, const BatchTiles& t, const std::string& log) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = t;
+  g_tune_log.push_back(log);
+}
+
+// Time each candidate (enqueued by run(candidate)) on stream s; returns the index of the fastest, or
+// -1 if timing failed (the caller then uses its first candidate).
+template <typename F>
+int time_candidates(int n, F run, hipStream_t s, std::vector<float>& ms) {
+  std::vector<hipEvent_t> ev(2 * n, nullptr);
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+  int best = -1;
+  bool ok = true;
+  for (int i = 0; i < n && ok; ++i) {
+    ok = ev[2 * i] && ev[2 * i + 1] && hipEventRecord(ev[2 * i], s) == hipSuccess;
+    ok = ok && run(i) == PFT_OK && hipEventRecord(ev[2 * i + 1], s) == hipSuccess;
+  }
+  ms.assign(n, 0.0f);
+  if (ok && hipEventSynchronize(ev[2 * n - 1]) == hipSuccess) {
+    for (int i = 0; i < n; ++i) {
+      if (hipEventElapsedTime(&ms[i], ev[2 * i], ev[2 * i + 1]) != hipSuccess) ms[i] = 1e30f;
+      if (best < 0 || ms[i] < ms[best]) best = i;
+    }
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return best;
+}
+
 void choose_face_splits(int64_t nq, int64_t nf, int qpt, int* splits, int64_t* per) {
   if (nf <= 0) {
     *splits = 1;
@@ -223,20 +300,105 @@ int num_cus() {
 // validation
 // ---------------------------------------------------------------------------
 // With PFT_VALIDATE=1 in the environment, the single-mesh triangle entry points
-// also count out-of-range triangle indices on the device before any work (a
-// synchronous check) and return EINVAL if there are any; otherwise such faces
-// are empty.
+// first check the mesh on the host (a synchronous copy of the triangles and
+// vertices): indices in range, no repeated vertex, closed (every edge used by
+// exactly two faces) and consistently oriented (the two faces of an edge run it
+// in opposite directions), and a non-negative enclosed volume (outward); each
+// region is checked on its own. They return EINVAL if the mesh fails.
 bool strict_validation() {
   const char* e = std::getenv("PFT_VALIDATE");
   return e != nullptr && e[0] == '1';
 }
 
-pft_status strict_tris(const int32_t* tris, int64_t nf, int64_t nv, void* stream) {
+// Edge counts of faces [f0, f1) of a host triangle list (the checks of pft_check_mesh).
+void count_mesh(const int32_t* tris, int64_t f0, int64_t f1, int64_t nv, pft_mesh_check* c) {
+  *c = pft_mesh_check{0, 0, 0, 0, 0};
+  std::vector<std::pair<uint64_t, int>> he;  // (unordered vertex pair, direction)
+  he.reserve((size_t)(f1 - f0) * 3);
+  for (int64_t f = f0; f < f1; ++f) {
+    const int32_t v[3] = {tris[3 * f], tris[3 * f + 1], tris[3 * f + 2]};
+    bool ok = true;
+    for (int k = 0; k < 3; ++k)
+      if (v[k] < 0 || v[k] >= nv) {
+        ++c->bad_index;
+        ok = false;
+      }
+    if (!ok) continue;
+    if (v[0] == v[1] || v[1] == v[2] || v[2] == v[0]) {
+      ++c->repeated_vertex;
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) {
+      const uint64_t a = (uint32_t)v[k], b = (uint32_t)v[(k + 1) % 3];
+      he.emplace_back(a < b ? (a << 32) | b : (b << 32) | a, a < b ? 1 : -1);
+    }
+  }
+  std::sort(he.begin(), he.end());
+  for (size_t i = 0; i < he.size();) {
+    size_t j = i;
+    int dir = 0;
+    while (j < he.size() && he[j].first == he[i].first) dir += he[j++].second;
+    const size_t n = j - i;
+    if (n == 1) ++c->open_edges;
+    else if (n > 2) ++c->nonmanifold_edges;
+    else if (dir != 0) ++c->misoriented_edges;
+    i = j;
+  }
+}
+
+// Signed volume of faces [f0, f1) (host arrays, coordinates relative to the vertex mean).
+double signed_volume(const std::vector<double>& v, const int32_t* tris, int64_t f0, int64_t f1) {
+  const int64_t nv = (int64_t)v.size() / 3;
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) t[k] += v[3 * i + k] / (double)nv;
+  double vol = 0.0;
+  for (int64_t f = f0; f < f1; ++f) {
+    double p[3][3];
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) p[j][k] = v[3 * (int64_t)tris[3 * f + j] + k] - t[k];
+    vol += (p[0][0] * (p[1][1] * p[2][2] - p[1][2] * p[2][1]) - p[0][1] * (p[1][0] * p[2][2] - p[1][2] * p[2][0]) +
+            p[0][2] * (p[1][0] * p[2][1] - p[1][1] * p[2][0])) / 6.0;
+  }
+  return vol;
+}
+
+// The PFT_VALIDATE=1 check of a device mesh; region_offsets NULL: one region of all faces.
+pft_status strict_mesh(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                       const int64_t* region_offsets, int64_t nreg, void* stream) {
   if (!strict_validation() || nf == 0) return PFT_OK;
-  int64_t bad = 0;
-  pft_status st = pft_validate_mesh(tris, nf, nv, &bad, nullptr, stream);
-  if (st != PFT_OK) return st;
-  if (bad > 0) return fail(PFT_EINVAL, std::to_string(bad) + " triangle indices out of range (PFT_VALIDATE=1)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(s);
+  std::vector<int32_t> t((size_t)nf * 3);
+  std::vector<double> v((size_t)nv * 3);
+  if (e == hipSuccess) e = hipMemcpy(t.data(), tris, t.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && nv > 0) {
+    if (vdtype == PFT_F64) {
+      e = hipMemcpy(v.data(), verts, v.size() * sizeof(double), hipMemcpyDeviceToHost);
+    } else {
+      std::vector<float> vf(v.size());
+      e = hipMemcpy(vf.data(), verts, vf.size() * sizeof(float), hipMemcpyDeviceToHost);
+      for (size_t i = 0; i < vf.size(); ++i) v[i] = vf[i];
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "mesh check copy (PFT_VALIDATE=1)");
+  const int64_t nr = region_offsets ? nreg : 1;
+  for (int64_t r = 0; r < nr; ++r) {
+    const int64_t f0 = region_offsets ? region_offsets[r] : 0, f1 = region_offsets ? region_offsets[r + 1] : nf;
+    if (f1 <= f0) continue;
+    pft_mesh_check c;
+    count_mesh(t.data(), f0, f1, nv, &c);
+    const std::string where = region_offsets ? " in region " + std::to_string(r) : std::string();
+    if (c.bad_index || c.repeated_vertex || c.open_edges || c.nonmanifold_edges || c.misoriented_edges)
+      return fail(PFT_EINVAL, "mesh not closed and consistently oriented" + where + " (PFT_VALIDATE=1): " +
+                                  std::to_string(c.bad_index) + " indices out of range, " +
+                                  std::to_string(c.repeated_vertex) + " faces with a repeated vertex, " +
+                                  std::to_string(c.open_edges) + " open edges, " +
+                                  std::to_string(c.nonmanifold_edges) + " edges of more than two faces, " +
+                                  std::to_string(c.misoriented_edges) + " edges run the same way by both faces");
+    if (signed_volume(v, t.data(), f0, f1) < 0.0)
+      return fail(PFT_EINVAL, "mesh oriented inward (negative enclosed volume)" + where + " (PFT_VALIDATE=1)");
+  }
   return PFT_OK;
 }
 
@@ -436,6 +598,13 @@ pft_status pft_release_workspace(void) {
   e = hipMemPoolTrimTo(pool, 0);
   if (e != hipSuccess) return hip_fail(e, "hipMemPoolTrimTo");
   return PFT_OK;
+}
+
+const char* pft_tuning_info(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_text.clear();
+  for (const std::string& l : g_tune_log) g_tune_text += l + "\n";
+  return g_tune_text.c_str();
 }
 
 pft_status pft_profile_enable(int enable) {
@@ -695,7 +864,7 @@ pft_status pft_forward_3d(const void* verts, pft_dtype vdtype, int64_t nv, const
   if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
   if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
   if (nq == 0) return PFT_OK;
-  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  if ((st = strict_mesh(verts, vdtype, nv, tris, nf, nullptr, 0, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   Arena ar(s);
@@ -716,7 +885,7 @@ pft_status pft_forward_3d_ordered(const void* verts, pft_dtype vdtype, int64_t n
   if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
   if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
   if (nq == 0) return PFT_OK;
-  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  if ((st = strict_mesh(verts, vdtype, nv, tris, nf, nullptr, 0, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   Arena ar(s);
@@ -787,6 +956,14 @@ pft_status pft_q_order(const void* q, pft_dtype qdtype, int64_t nq, uint32_t* or
   hipError_t e = perm ? hipMemcpyAsync(order, perm, sizeof(uint32_t) * nq, hipMemcpyDeviceToDevice, s)
                       : launch_iota_u32(order, nq, s);  // below the sorting size: the list order
   return e == hipSuccess ? PFT_OK : hip_fail(e, "Q order");
+}
+
+pft_status pft_check_mesh(const int32_t* tris, int64_t nf, int64_t nv, pft_mesh_check* report) {
+  if (nf < 0 || nv < 0) return fail(PFT_EINVAL, "negative count");
+  if (nf > INT32_MAX / 3 || nv > INT32_MAX) return fail(PFT_EINVAL, "mesh too large for 32-bit indices");
+  if (report == nullptr || (nf > 0 && tris == nullptr)) return fail(PFT_EINVAL, "tris or report is NULL");
+  count_mesh(tris, 0, nf, nv, report);
+  return PFT_OK;
 }
 
 pft_status pft_strip_order(const int32_t* tris, int64_t nf, int64_t nv, int32_t* order, uint8_t* meta) {
@@ -969,7 +1146,7 @@ pft_status pft_orientation_average(const void* verts, pft_dtype vdtype, int64_t 
   if (ndir > 0 && nqa > INT64_MAX / 3 / ndir) return fail(PFT_EINVAL, "nqa * ndir too large");
   if (nqa > INT32_MAX) return fail(PFT_EINVAL, "too many magnitudes");
   if (nqa == 0) return PFT_OK;
-  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  if ((st = strict_mesh(verts, vdtype, nv, tris, nf, nullptr, 0, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   if (ndir == 0) {  // empty quadrature: the sum is 0
@@ -1005,7 +1182,7 @@ static pft_status backward3d_impl(const void* verts, pft_dtype vdtype, int64_t n
   if (grad_out && !aligned(grad_out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "grad_out misaligned");
   if (grad_verts && !aligned(grad_verts, real_size(vdtype))) return fail(PFT_EINVAL, "grad_verts misaligned");
   if (nv == 0) return PFT_OK;
-  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  if ((st = strict_mesh(verts, vdtype, nv, tris, nf, nullptr, 0, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   if (nq == 0 || nf == 0) {
@@ -1089,7 +1266,7 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
     return fail(PFT_EINVAL, "loss, target or weight misaligned");
   if (out && !aligned(out, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out misaligned");
   if (grad_verts && !aligned(grad_verts, real_size(vdtype))) return fail(PFT_EINVAL, "grad_verts misaligned");
-  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  if ((st = strict_mesh(verts, vdtype, nv, tris, nf, nullptr, 0, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   hipError_t e = hipSuccess;
@@ -1202,7 +1379,7 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   if (out_regions && !aligned(out_regions, c128 ? 16 : 8)) return fail(PFT_EINVAL, "out_regions misaligned");
   if (intensity && !aligned(intensity, c128 ? 8 : 4)) return fail(PFT_EINVAL, "intensity misaligned");
   if (nq == 0) return PFT_OK;
-  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  if ((st = strict_mesh(verts, vdtype, nv, tris, nf, region_offsets, nreg, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   Arena ar(s);
@@ -1281,7 +1458,7 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
   const bool want_r = grad_rho != nullptr && nreg > 0;
   const bool want_q = grad_q != nullptr && nq > 0;
   if (!want_v && !want_r && !want_q) return PFT_OK;
-  if ((st = strict_tris(tris, nf, nv, stream)) != PFT_OK) return st;
+  if ((st = strict_mesh(verts, vdtype, nv, tris, nf, region_offsets, nreg, stream)) != PFT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   ensure_pool();
   hipError_t e = hipSuccess;
@@ -1539,68 +1716,110 @@ static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, voi
     hipError_t e = launch_face32(p.f64, p.nf, kTauF32, kTauRel32, f32, s);
     if (e != hipSuccess) return hip_fail(e, "batch prologue");
   }
-  // work items: (mesh, Q-tile, face chunk), longest first
-  std::vector<BatchItemFwd> items;
-  std::vector<int64_t> q_part(n);
-  std::vector<int32_t> q_chunks(n);
-  int64_t P = 0;
-  const int64_t qtile = c128 ? kBlock : (int64_t)kBlock * kQPTBatch;  // Q per item (one block)
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t nqi = b->q_offsets[i + 1] - b->q_offsets[i];
-    const int64_t nfi = b->tri_offsets[i + 1] - b->tri_offsets[i];
-    int64_t C = 1, cf = nfi;
-    if (nfi > 0) {
-      C = cdiv(nfi, kBatchChunkF);
-      cf = cdiv(cdiv(nfi, C), kTileF) * kTileF;
-      C = cdiv(nfi, cf);
-    }
-    q_part[i] = P;
-    q_chunks[i] = (int32_t)C;
-    for (int64_t c = 0; c < C; ++c) {
-      for (int64_t t = 0; t < nqi; t += qtile) {
-        BatchItemFwd it;
-        it.mesh = (int32_t)i;
-        it.chunk = (int32_t)c;
-        it.q0 = b->q_offsets[i] + t;
-        it.nq = (int32_t)std::min<int64_t>(qtile, nqi - t);
-        it.pad = 0;
-        it.f0 = b->tri_offsets[i] + c * cf;
-        it.nf = nfi > 0 ? std::min<int64_t>(cf, nfi - c * cf) : 0;
-        it.part = P + c * nqi + t;
-        items.push_back(it);
+  // work items: (mesh, Q-tile, face chunk), longest first, for given tile sizes; returns the number of
+  // partial slots they need
+  auto make_items = [&](const BatchTiles& t, std::vector<BatchItemFwd>& items, std::vector<int64_t>& q_part,
+                        std::vector<int32_t>& q_chunks) {
+    items.clear();
+    q_part.assign(n, 0);
+    q_chunks.assign(n, 1);
+    int64_t P = 0;
+    const int64_t qtile = c128 ? kBlock : (int64_t)kBlock * t.qpt;  // Q per item (one block)
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t nqi = b->q_offsets[i + 1] - b->q_offsets[i];
+      const int64_t nfi = b->tri_offsets[i + 1] - b->tri_offsets[i];
+      int64_t C = 1, cf = nfi;
+      if (nfi > 0) {
+        C = cdiv(nfi, t.chunk_f);
+        cf = cdiv(cdiv(nfi, C), kTileF) * kTileF;
+        C = cdiv(nfi, cf);
       }
+      q_part[i] = P;
+      q_chunks[i] = (int32_t)C;
+      for (int64_t c = 0; c < C; ++c) {
+        for (int64_t t0 = 0; t0 < nqi; t0 += qtile) {
+          BatchItemFwd it;
+          it.mesh = (int32_t)i;
+          it.chunk = (int32_t)c;
+          it.q0 = b->q_offsets[i] + t0;
+          it.nq = (int32_t)std::min<int64_t>(qtile, nqi - t0);
+          it.pad = 0;
+          it.f0 = b->tri_offsets[i] + c * cf;
+          it.nf = nfi > 0 ? std::min<int64_t>(cf, nfi - c * cf) : 0;
+          it.part = P + c * nqi + t0;
+          items.push_back(it);
+        }
+      }
+      P += C * nqi;
     }
-    P += C * nqi;
+    std::stable_sort(items.begin(), items.end(), [](const BatchItemFwd& x, const BatchItemFwd& y) {
+      return x.nf * (int64_t)x.nq > y.nf * (int64_t)y.nq;
+    });
+    return P;
+  };
+  BatchTiles chosen;
+  std::vector<BatchTiles> cands;
+  std::string key;
+  if (!c128 && autotune_enabled()) {
+    double pairs = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+      pairs += (double)(b->tri_offsets[i + 1] - b->tri_offsets[i]) * (double)(b->q_offsets[i + 1] - b->q_offsets[i]);
+    key = tune_key("batch_forward", mode, share, n, pairs, p.nf);
+    if (!tuned_tiles(key, &chosen))
+      for (int qpt : {1, 2})
+        for (int64_t cf : {2048, 4096, 8192}) {
+          BatchTiles t;
+          t.qpt = qpt;
+          t.chunk_f = cf;
+          cands.push_back(t);
+        }
   }
-  std::stable_sort(items.begin(), items.end(), [](const BatchItemFwd& x, const BatchItemFwd& y) {
-    return x.nf * (int64_t)x.nq > y.nf * (int64_t)y.nq;
-  });
-  BatchItemFwd* d_items;
-  int64_t* d_q_part;
-  int32_t* d_q_chunks;
-  if ((st = upload(ar, items, &d_items, s)) != PFT_OK) return st;
-  if ((st = upload(ar, q_part, &d_q_part, s)) != PFT_OK) return st;
-  if ((st = upload(ar, q_chunks, &d_q_chunks, s)) != PFT_OK) return st;
-  double2* partial = ar.get<double2>(std::max<int64_t>(P, 1));
+  std::vector<BatchItemFwd> items;
+  std::vector<int64_t> q_part;
+  std::vector<int32_t> q_chunks;
+  int64_t Pmax = make_items(chosen, items, q_part, q_chunks);
+  for (const BatchTiles& t : cands) Pmax = std::max(Pmax, make_items(t, items, q_part, q_chunks));
+  double2* partial = ar.get<double2>(std::max<int64_t>(Pmax, 1));
   uint32_t* counter = ar.get<uint32_t>(1);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
-  hipError_t e = launch_zero_u32(counter, 1, s);
-  if (e != hipSuccess) return hip_fail(e, "counter reset");
-  const int64_t n_items = (int64_t)items.size();
-  const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
-                                          (int64_t)num_cus() * batch_fwd_blocks_per_cu(mode, share));
-  const double tau0 = c128 ? kTau0F64 : kTau0F32;
-  prof_begin("batch_fwd", s);
   uint32_t* perm = nullptr;
   if ((st = build_qorder(ar, b->q, b->qdtype, nq_total, p.d_q_off, n, &perm, s)) != PFT_OK) return st;
-  e = launch_batch_fwd(mode, d_items, n_items, counter, p.f64, f32, b->q, b->qdtype, perm, partial, p.info, tau0, grid,
-                       s, share);
-  prof_end("batch_fwd", s);
-  if (e != hipSuccess) return hip_fail(e, "batch forward");
-  e = launch_batch_fwd_finish(partial, p.d_q_off, n, d_q_part, d_q_chunks, p.info, b->q, b->qdtype, perm, nq_total,
-                              tau0, c128 ? 1 : 0, out, intensity, s);
-  if (e != hipSuccess) return hip_fail(e, "batch finish");
-  return PFT_OK;
+  const double tau0 = c128 ? kTau0F64 : kTau0F32;
+  auto run = [&](const BatchTiles& t, bool profile) -> pft_status {
+    make_items(t, items, q_part, q_chunks);
+    BatchItemFwd* d_items;
+    int64_t* d_q_part;
+    int32_t* d_q_chunks;
+    pft_status rs;
+    if ((rs = upload(ar, items, &d_items, s)) != PFT_OK) return rs;
+    if ((rs = upload(ar, q_part, &d_q_part, s)) != PFT_OK) return rs;
+    if ((rs = upload(ar, q_chunks, &d_q_chunks, s)) != PFT_OK) return rs;
+    hipError_t e = launch_zero_u32(counter, 1, s);
+    if (e != hipSuccess) return hip_fail(e, "counter reset");
+    const int64_t n_items = (int64_t)items.size();
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
+                                            (int64_t)num_cus() * batch_fwd_blocks_per_cu(mode, share, t.qpt));
+    if (profile) prof_begin("batch_fwd", s);
+    e = launch_batch_fwd(mode, d_items, n_items, counter, p.f64, f32, b->q, b->qdtype, perm, partial, p.info, tau0,
+                         grid, s, share, t.qpt);
+    if (profile) prof_end("batch_fwd", s);
+    if (e != hipSuccess) return hip_fail(e, "batch forward");
+    e = launch_batch_fwd_finish(partial, p.d_q_off, n, d_q_part, d_q_chunks, p.info, b->q, b->qdtype, perm, nq_total,
+                                tau0, c128 ? 1 : 0, out, intensity, s);
+    return e == hipSuccess ? PFT_OK : hip_fail(e, "batch finish");
+  };
+  if (!cands.empty()) {
+    std::vector<float> ms;
+    const int best = time_candidates((int)cands.size(), [&](int i) { return run(cands[i], false); }, s, ms);
+    chosen = cands[best >= 0 ? best : 0];
+    std::string log = key + ": qpt=" + std::to_string(chosen.qpt) + " faces/item=" + std::to_string(chosen.chunk_f) +
+                      " (candidates qpt x faces/item, ms:";
+    for (size_t i = 0; i < cands.size(); ++i)
+      log += " " + std::to_string(cands[i].qpt) + "x" + std::to_string(cands[i].chunk_f) + "=" +
+             std::to_string(ms[i]).substr(0, 7);
+    keep_tiles(key, chosen, log + ")");
+  }
+  return run(chosen, true);
 }
 
 pft_status pft_batch_forward(const pft_mesh_batch* b, pft_mode mode, void* out, void* intensity, void* stream) {
@@ -1655,56 +1874,89 @@ pft_status pft_batch_backward(const pft_mesh_batch* b, pft_mode mode, const void
   if ((st = build_qrecs(ar, mode, b->q, b->qdtype, grad_out, nq_total, p.info, p.d_q_off, n, &rec, &rec64, s)) !=
       PFT_OK)
     return st;
-  std::vector<BatchItemBwd> items;
   const int64_t ftile = c128 ? kTileFB : kTileFB32;  // faces per item (one block)
-  std::vector<int64_t> face_base(n);
-  std::vector<int32_t> face_nchunks(n);
-  int64_t B = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t nqi = b->q_offsets[i + 1] - b->q_offsets[i];
-    const int64_t nfi = b->tri_offsets[i + 1] - b->tri_offsets[i];
-    const int64_t S = std::max<int64_t>(1, cdiv(nqi, kBatchChunkQ));
-    const int64_t cq = std::max<int64_t>(1, cdiv(nqi, S));
-    face_base[i] = B;
-    face_nchunks[i] = (int32_t)S;
-    for (int64_t sc = 0; sc < S; ++sc) {
-      for (int64_t ft = 0; ft < nfi; ft += ftile) {
-        BatchItemBwd it;
-        it.mesh = (int32_t)i;
-        it.qchunk = (int32_t)sc;
-        it.f0 = b->tri_offsets[i] + ft;
-        it.nf = (int32_t)std::min<int64_t>(ftile, nfi - ft);
-        it.pad = 0;
-        it.q0 = b->q_offsets[i] + std::min(nqi, sc * cq);
-        it.nq = std::max<int64_t>(0, std::min(cq, nqi - sc * cq));
-        it.part = B + sc * nfi + ft;
-        items.push_back(it);
+  // work items: (mesh, face tile, Q chunk), longest first, for a given Q chunk; returns the partial slots
+  std::vector<BatchItemBwd> items;
+  std::vector<int64_t> face_base;
+  std::vector<int32_t> face_nchunks;
+  auto make_items = [&](int64_t chunk_q) {
+    items.clear();
+    face_base.assign(n, 0);
+    face_nchunks.assign(n, 1);
+    int64_t B = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t nqi = b->q_offsets[i + 1] - b->q_offsets[i];
+      const int64_t nfi = b->tri_offsets[i + 1] - b->tri_offsets[i];
+      const int64_t S = std::max<int64_t>(1, cdiv(nqi, chunk_q));
+      const int64_t cq = std::max<int64_t>(1, cdiv(nqi, S));
+      face_base[i] = B;
+      face_nchunks[i] = (int32_t)S;
+      for (int64_t sc = 0; sc < S; ++sc) {
+        for (int64_t ft = 0; ft < nfi; ft += ftile) {
+          BatchItemBwd it;
+          it.mesh = (int32_t)i;
+          it.qchunk = (int32_t)sc;
+          it.f0 = b->tri_offsets[i] + ft;
+          it.nf = (int32_t)std::min<int64_t>(ftile, nfi - ft);
+          it.pad = 0;
+          it.q0 = b->q_offsets[i] + std::min(nqi, sc * cq);
+          it.nq = std::max<int64_t>(0, std::min(cq, nqi - sc * cq));
+          it.part = B + sc * nfi + ft;
+          items.push_back(it);
+        }
       }
+      B += S * nfi;
     }
-    B += S * nfi;
+    std::stable_sort(items.begin(), items.end(), [](const BatchItemBwd& x, const BatchItemBwd& y) {
+      return (int64_t)x.nf * x.nq > (int64_t)y.nf * y.nq;
+    });
+    return B;
+  };
+  BatchTiles chosen;
+  std::vector<int64_t> cands;
+  std::string key;
+  if (!c128 && autotune_enabled()) {
+    double pairs = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+      pairs += (double)(b->tri_offsets[i + 1] - b->tri_offsets[i]) * (double)(b->q_offsets[i + 1] - b->q_offsets[i]);
+    key = tune_key("batch_backward", mode, false, n, pairs, p.nf);
+    if (!tuned_tiles(key, &chosen)) cands = {32768, 65536, 131072};
   }
-  std::stable_sort(items.begin(), items.end(), [](const BatchItemBwd& x, const BatchItemBwd& y) {
-    return (int64_t)x.nf * x.nq > (int64_t)y.nf * y.nq;
-  });
-  BatchItemBwd* d_items;
-  int64_t* d_face_base;
-  int32_t* d_face_nchunks;
-  if ((st = upload(ar, items, &d_items, s)) != PFT_OK) return st;
-  if ((st = upload(ar, face_base, &d_face_base, s)) != PFT_OK) return st;
-  if ((st = upload(ar, face_nchunks, &d_face_nchunks, s)) != PFT_OK) return st;
-  double* partial = ar.get<double>((size_t)std::max<int64_t>(B, 1) * 3);
+  int64_t Bmax = make_items(chosen.chunk_q);
+  for (int64_t cq : cands) Bmax = std::max(Bmax, make_items(cq));
+  double* partial = ar.get<double>((size_t)std::max<int64_t>(Bmax, 1) * 3);
   double* contrib = ar.get<double>((size_t)p.nf * 9);
   uint32_t* counter = ar.get<uint32_t>(1);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
-  e = launch_zero_u32(counter, 1, s);
-  if (e != hipSuccess) return hip_fail(e, "counter reset");
-  const int64_t n_items = (int64_t)items.size();
-  const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
-                                          (int64_t)num_cus() * batch_bwd_blocks_per_cu(mode));
-  prof_begin("batch_bwd", s);
-  e = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, rec, rec64, partial, grid, s);
-  prof_end("batch_bwd", s);
-  if (e != hipSuccess) return hip_fail(e, "batch adjoint");
+  int32_t* d_face_nchunks = nullptr;
+  int64_t* d_face_base = nullptr;
+  auto run = [&](int64_t chunk_q, bool profile) -> pft_status {
+    make_items(chunk_q);
+    BatchItemBwd* d_items;
+    pft_status rs;
+    if ((rs = upload(ar, items, &d_items, s)) != PFT_OK) return rs;
+    if ((rs = upload(ar, face_base, &d_face_base, s)) != PFT_OK) return rs;
+    if ((rs = upload(ar, face_nchunks, &d_face_nchunks, s)) != PFT_OK) return rs;
+    hipError_t re = launch_zero_u32(counter, 1, s);
+    if (re != hipSuccess) return hip_fail(re, "counter reset");
+    const int64_t n_items = (int64_t)items.size();
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
+                                            (int64_t)num_cus() * batch_bwd_blocks_per_cu(mode));
+    if (profile) prof_begin("batch_bwd", s);
+    re = launch_batch_bwd(mode, d_items, n_items, counter, p.f64, gram, f32b, rec, rec64, partial, grid, s);
+    if (profile) prof_end("batch_bwd", s);
+    return re == hipSuccess ? PFT_OK : hip_fail(re, "batch adjoint");
+  };
+  if (!cands.empty()) {
+    std::vector<float> ms;
+    const int best = time_candidates((int)cands.size(), [&](int i) { return run(cands[i], false); }, s, ms);
+    chosen.chunk_q = cands[best >= 0 ? best : 0];
+    std::string log = key + ": Q/item=" + std::to_string(chosen.chunk_q) + " (candidates Q/item, ms:";
+    for (size_t i = 0; i < cands.size(); ++i)
+      log += " " + std::to_string(cands[i]) + "=" + std::to_string(ms[i]).substr(0, 7);
+    keep_tiles(key, chosen, log + ")");
+  }
+  if ((st = run(chosen.chunk_q, true)) != PFT_OK) return st;
   e = launch_batch_bwd_reduce(partial, d_face_base, d_face_nchunks, p.d_tri_off, p.d_face_mesh, p.f64, p.nf, contrib,
                               s);
   if (e != hipSuccess) return hip_fail(e, "batch adjoint reduce");

@@ -23,7 +23,7 @@ __device__ __forceinline__ int64_t next_item(uint32_t* counter, int* slot) {
   return it;
 }
 
-template <int MODE, bool SHARE = false>
+template <int MODE, bool SHARE = false, int QPT = 1>
 __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* __restrict__ items, int64_t n_items,
                                                           uint32_t* counter, const Face64* __restrict__ f64,
                                                           const Face32* __restrict__ f32, const void* q, int qdtype,
@@ -66,14 +66,14 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
       }
       if (active) store_stream(partial + it.part + lane, make_double2(xr, xi));
     } else {
-      // kQPTBatch Q per thread, strided by the block size
+      // QPT Q per thread, strided by the block size
       Face32* tile = reinterpret_cast<Face32*>(smem);
-      double Qd[kQPTBatch][3];
-      float qx[kQPTBatch], qy[kQPTBatch], qz[kQPTBatch], Q2[kQPTBatch];
-      bool small[kQPTBatch], active[kQPTBatch];
+      double Qd[QPT][3];
+      float qx[QPT], qy[QPT], qz[QPT], Q2[QPT];
+      bool small[QPT], active[QPT];
       bool any_small = false;
 #pragma unroll
-      for (int k = 0; k < kQPTBatch; ++k) {
+      for (int k = 0; k < QPT; ++k) {
         const int qo = lane + k * kBlock;
         active[k] = qo < it.nq;
         Qd[k][0] = Qd[k][1] = Qd[k][2] = 0.0;
@@ -86,11 +86,11 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         small[k] = sqrt(Q2d) * R < tau0;
         any_small |= small[k];
       }
-      float sr[kQPTBatch], si[kQPTBatch], cr[kQPTBatch], ci[kQPTBatch];
-      double xr[kQPTBatch], xi[kQPTBatch];
+      float sr[QPT], si[QPT], cr[QPT], ci[QPT];
+      double xr[QPT], xi[QPT];
 #pragma unroll
-      for (int k = 0; k < kQPTBatch; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
-      FwdCarry<kQPTBatch> carry;  // shared edge term from the previous face of the item
+      for (int k = 0; k < QPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
+      FwdCarry<QPT> carry;  // shared edge term from the previous face of the item
       carry.reset();
       for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
         const int nt = (int)min((int64_t)kTileF, f_end - t0);
@@ -98,24 +98,24 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         for (int i = lane; i < nt * (int)(sizeof(Face32) / 16); i += kBlock)
           reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f32 + t0)[i];
         __syncthreads();
-        float tr[kQPTBatch], ti[kQPTBatch];
+        float tr[QPT], ti[QPT];
 #pragma unroll
-        for (int k = 0; k < kQPTBatch; ++k) tr[k] = ti[k] = 0.0f;
-        fwd_tile_fp32c<kQPTBatch, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, carry);
+        for (int k = 0; k < QPT; ++k) tr[k] = ti[k] = 0.0f;
+        fwd_tile_fp32c<QPT, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, carry);
 #pragma unroll
-        for (int k = 0; k < kQPTBatch; ++k) {
+        for (int k = 0; k < QPT; ++k) {
           kahan_add(sr[k], cr[k], tr[k]);
           kahan_add(si[k], ci[k], ti[k]);
         }
         if (any_small) {
 #pragma unroll
-          for (int k = 0; k < kQPTBatch; ++k)
+          for (int k = 0; k < QPT; ++k)
             if (small[k])
               for (int j = 0; j < nt; ++j) tet_term_f64(f64[t0 + j], Qd[k], xr[k], xi[k], kZeroOrigin);
         }
       }
 #pragma unroll
-      for (int k = 0; k < kQPTBatch; ++k) {
+      for (int k = 0; k < QPT; ++k) {
         if (active[k]) {
           const double2 v = small[k] ? make_double2(xr[k], xi[k])
                                      : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
@@ -246,14 +246,20 @@ __global__ __launch_bounds__(256) void batch_bwd_reduce_kernel(const double* par
 
 }  // namespace
 
-int batch_fwd_blocks_per_cu(int mode, bool share) {
+int batch_fwd_blocks_per_cu(int mode, bool share, int qpt) {
   int nb = 0;
   if (mode == PFT_FP64)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP64>, kBlock, 0);
   else if (share)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP32C, true>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, qpt >= 3 ? batch_fwd_kernel<PFT_FP32C, true, 3> : qpt == 2 ? batch_fwd_kernel<PFT_FP32C, true, 2>
+                                                                        : batch_fwd_kernel<PFT_FP32C, true, 1>,
+        kBlock, 0);
   else
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP32C>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, qpt >= 3 ? batch_fwd_kernel<PFT_FP32C, false, 3> : qpt == 2 ? batch_fwd_kernel<PFT_FP32C, false, 2>
+                                                                         : batch_fwd_kernel<PFT_FP32C, false, 1>,
+        kBlock, 0);
   return nb > 0 ? nb : 1;
 }
 
@@ -269,17 +275,19 @@ int batch_bwd_blocks_per_cu(int mode) {
 hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const Face32* f32, const void* q, int qdtype, const uint32_t* perm,
                             double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s,
-                            bool share) {
+                            bool share, int qpt) {
   if (n_items <= 0) return hipSuccess;
+#define PFT_BATCH_FWD(M, SH, QP) \
+  batch_fwd_kernel<M, SH, QP><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial, info, tau0)
   if (mode == PFT_FP64)
-    batch_fwd_kernel<PFT_FP64><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial,
-                                                       info, tau0);
+    PFT_BATCH_FWD(PFT_FP64, false, 1);
   else if (share)
-    batch_fwd_kernel<PFT_FP32C, true><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm,
-                                                              partial, info, tau0);
+    qpt >= 3 ? PFT_BATCH_FWD(PFT_FP32C, true, 3) : qpt == 2 ? PFT_BATCH_FWD(PFT_FP32C, true, 2)
+                                                            : PFT_BATCH_FWD(PFT_FP32C, true, 1);
   else
-    batch_fwd_kernel<PFT_FP32C><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial,
-                                                        info, tau0);
+    qpt >= 3 ? PFT_BATCH_FWD(PFT_FP32C, false, 3) : qpt == 2 ? PFT_BATCH_FWD(PFT_FP32C, false, 2)
+                                                             : PFT_BATCH_FWD(PFT_FP32C, false, 1);
+#undef PFT_BATCH_FWD
   return hipGetLastError();
 }
 

@@ -427,7 +427,7 @@ struct BatchItemFwd {   // one (mesh, Q-tile, face-chunk) work item
   int32_t mesh;
   int32_t chunk;        // face-chunk index within the mesh
   int64_t q0;           // first global Q index of the tile
-  int32_t nq;           // Q in the tile (<= kBlock for FP64, <= kBlock * kQPTBatch for FP32C)
+  int32_t nq;           // Q in the tile (<= kBlock for FP64, <= kBlock * (Q per thread) for FP32C)
   int32_t pad;
   int64_t f0;           // first global face index of the chunk
   int64_t nf;           // faces in the chunk
@@ -443,12 +443,12 @@ struct BatchItemBwd {   // one (mesh, face-tile, Q-chunk) work item
   int64_t nq;           // Q in the chunk
   int64_t part;         // partial slot base (in units of face corners): partial[(part + j) * 3 + k]
 };
-int batch_fwd_blocks_per_cu(int mode, bool share = false);
+int batch_fwd_blocks_per_cu(int mode, bool share = false, int qpt = 1);
 int batch_bwd_blocks_per_cu(int mode);
 hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const Face32* f32, const void* q, int qdtype, const uint32_t* perm,
                             double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s,
-                            bool share = false);
+                            bool share = false, int qpt = 1);
 hipError_t launch_batch_fwd_finish(const double2* partial, const int64_t* d_q_off, int64_t n_meshes,
                                    const int64_t* d_q_part, const int32_t* d_q_chunks, const MeshInfo* info,
                                    const void* q, int qdtype, const uint32_t* perm, int64_t nq_total, double tau0,

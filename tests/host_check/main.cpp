@@ -66,6 +66,23 @@ int main() {
     check_order(t, nf, nv);
   }
   check_order({}, 0, 0);
+  // the closed-mesh check on the same kinds of input (random, broken, empty)
+  for (int trial = 0; trial < 10; ++trial) {
+    const int nv = 1 + (int)(rng() % 40), nf = (int)(rng() % 200);
+    std::vector<int32_t> t(3 * (size_t)nf);
+    for (auto& x : t) x = (int32_t)(rng() % (nv + 3)) - 1;
+    pft_mesh_check c;
+    CHECK(pft_check_mesh(t.data(), nf, nv, &c) == PFT_OK);
+    CHECK(c.bad_index >= 0 && c.open_edges >= 0 && c.nonmanifold_edges >= 0 && c.misoriented_edges >= 0);
+  }
+  {
+    pft_mesh_check c;
+    const int32_t tet[12] = {0, 2, 1, 0, 1, 3, 0, 3, 2, 1, 2, 3};
+    CHECK(pft_check_mesh(tet, 4, 4, &c) == PFT_OK);
+    CHECK(c.bad_index == 0 && c.open_edges == 0 && c.nonmanifold_edges == 0 && c.misoriented_edges == 0);
+    CHECK(pft_check_mesh(tet, 3, 4, &c) == PFT_OK && c.open_edges == 3);
+    CHECK(pft_check_mesh(nullptr, 2, 4, &c) == PFT_EINVAL);
+  }
   CHECK(pft_strip_order(nullptr, 3, 3, nullptr, nullptr) == PFT_EINVAL);
   CHECK(pft_strip_order(nullptr, -1, 3, nullptr, nullptr) == PFT_EINVAL);
 

@@ -135,3 +135,35 @@ def test_config5_full_size_sampled(gpu):
         ids = rng.choice(m["verts"].shape[0], 3, replace=False)
         wg = O.grad3d_vertices(m["verts"], m["tris"], q32, G[qo[i]:qo[i + 1]], ids)
         assert nrel(Gv[vo[i]:vo[i + 1]][ids], wg) < TOL_FP32C, i
+
+
+def test_batch_tile_tuning(gpu):
+    """The batched launches tune their tile sizes at the first call of a size bucket: the choice is
+    reported, the tuning call's output is the chosen configuration's (a second call repeats it bitwise),
+    and the compiled defaults (PFT_AUTOTUNE=0) agree with it to rounding."""
+    import os
+
+    meshes = mg.batch_config(seed=11, n_meshes=24, max_faces=6000, min_q=500, max_q=3000)
+    V, T, Q, vo, to, qo = _concat(meshes)
+    rng = np.random.default_rng(5)
+    G = dev((rng.normal(size=Q.shape[0]) + 1j * rng.normal(size=Q.shape[0])).astype(np.complex64))
+    Vd, Td, Qd = dev(V), dev(T, torch.int32), dev(Q)
+    step("batch tuning: first calls (tune) and repeats")
+    F1 = host(pft.batch_forward(Vd, Td, Qd, vo, to, qo, mode="fp32c"))
+    G1 = host(pft.batch_backward(Vd, Td, Qd, vo, to, qo, G, mode="fp32c"))
+    F2 = host(pft.batch_forward(Vd, Td, Qd, vo, to, qo, mode="fp32c"))
+    G2 = host(pft.batch_backward(Vd, Td, Qd, vo, to, qo, G, mode="fp32c"))
+    info = pft.tuning_info()
+    assert "batch_forward[" in info and "batch_backward[" in info, info
+    assert np.array_equal(F1.view(np.uint8), F2.view(np.uint8))
+    assert np.array_equal(G1.view(np.uint8), G2.view(np.uint8))
+    step("batch tuning: compiled defaults")
+    os.environ["PFT_AUTOTUNE"] = "0"
+    try:
+        F0 = host(pft.batch_forward(Vd, Td, Qd, vo, to, qo, mode="fp32c"))
+        G0 = host(pft.batch_backward(Vd, Td, Qd, vo, to, qo, G, mode="fp32c"))
+    finally:
+        del os.environ["PFT_AUTOTUNE"]
+    assert nrel(F0, F1) < 1e-6 and nrel(G0, G1) < 1e-6
+    want = O.ft3d(meshes[0]["verts"], meshes[0]["tris"], meshes[0]["q"])
+    assert nrel(F1[qo[0]:qo[1]], want) < TOL_FP32C
