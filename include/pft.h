@@ -74,6 +74,21 @@ typedef enum {
  *             faces accumulated with compensation; complex64 outputs. */
 typedef enum { PFT_FP64 = 0, PFT_FP32C = 1 } pft_mode;
 
+/* FP32C phase range (radians). The binary32 form takes every phase it
+ * evaluates relative to a face origin, so its accuracy depends on |Q| rho, rho
+ * being the largest distance from a face's centroid to one of its vertices
+ * (over the mesh; for a batch, over each mesh). For |Q| rho <= PFT_FP32C_PHASE_MAX
+ * every binary32 phase is under 21 turns and rounded to within 6e-6 rad; at
+ * each Q beyond it the FP32C entry points write NaN instead of a value of
+ * unknown accuracy: F and |F|^2 of the forward calls (each region's F and the
+ * dL/drho sums of the region calls, dL/dQ of pft_backward_3d_regions), the loss
+ * term of pft_intensity_loss_3d (so the loss and every gradient entry are NaN),
+ * and that Q's cotangent in the adjoints (every vertex gradient is NaN).
+ * PFT_FP64 has no such bound. pft_fp32c_q_limit gives the bound on |Q| for a
+ * host mesh; the device check computes rho in binary64 from the centred mesh,
+ * so a Q within rounding of the bound may fall on either side. */
+#define PFT_FP32C_PHASE_MAX 128.0
+
 /* Real element type of an input array. */
 typedef enum { PFT_F32 = 0, PFT_F64 = 1 } pft_dtype;
 
@@ -441,6 +456,19 @@ typedef struct {
   int64_t misoriented_edges;  /* edges that both of their faces run in the same direction */
 } pft_mesh_check;
 pft_status pft_check_mesh(const int32_t* tris, int64_t nf, int64_t nv, pft_mesh_check* report);
+
+/*
+ * pft_fp32c_q_limit -- the largest |Q| at which the FP32C form evaluates a
+ * triangle mesh: PFT_FP32C_PHASE_MAX / rho, rho the largest distance from a
+ * face's centroid to one of its vertices (faces with an index outside [0, nv)
+ * are skipped, as the transform skips them); +infinity when no face has extent.
+ * HOST function, no GPU work: verts [nv][3] of vdtype, tris [nf][3] int32 and
+ * q_limit are host pointers.
+ * Errors: EINVAL for negative counts or NULL pointers (verts may be NULL when
+ * nv is 0, tris when nf is 0), EUNSUPPORTED for an unknown vertex dtype.
+ */
+pft_status pft_fp32c_q_limit(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                             double* q_limit);
 
 /*
  * pft_validate_mesh -- count triangle indices outside [0, nv) and faces with a

@@ -8,7 +8,7 @@ declared in include/pft.h. This package is the thin Python binding.
 """
 from .api import (  # noqa: F401
     forward_2d, forward_3d, forward_3d_noalloc, forward_3d_poly, backward_3d, batch_forward, batch_backward, orientation_average,
-    forward_3d_regions, backward_3d_regions, intensity_loss_3d, strip_order, batch_strip_order, q_order, validate_mesh, check_mesh,
+    forward_3d_regions, backward_3d_regions, intensity_loss_3d, strip_order, batch_strip_order, q_order, validate_mesh, check_mesh, fp32c_q_limit,
     profile_enable, profile_reset, profile_read, release_workspace, version, tuning_info,
 )
 from .autograd import (  # noqa: F401

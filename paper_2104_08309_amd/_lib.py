@@ -20,6 +20,7 @@ EXPORTS = [
     "pft_forward_3d_poly", "pft_orientation_average", "pft_forward_3d_regions", "pft_backward_3d_regions",
     "pft_intensity_loss_3d", "pft_strip_order", "pft_forward_3d_ordered", "pft_batch_forward_ordered",
     "pft_q_order", "pft_backward_3d_ordered", "pft_forward_3d_noalloc", "pft_check_mesh", "pft_tuning_info",
+    "pft_fp32c_q_limit",
     "pft_validate_mesh", "pft_last_error", "pft_release_workspace", "pft_profile_enable",
     "pft_profile_reset", "pft_profile_read", "pft_version",
 ]
@@ -91,6 +92,7 @@ def load() -> ctypes.CDLL:
                                     vp],
         "pft_validate_mesh": [vp, i64, i64, P(i64), P(i64), vp],
         "pft_check_mesh": [vp, i64, i64, P(PftMeshCheck)],
+        "pft_fp32c_q_limit": [vp, cint, i64, vp, i64, P(ctypes.c_double)],
         "pft_last_error": [],
         "pft_release_workspace": [],
         "pft_profile_enable": [cint],

@@ -21,7 +21,7 @@ __all__ = [
     "forward_2d", "forward_3d", "forward_3d_noalloc", "forward_3d_poly", "backward_3d", "batch_forward", "batch_backward",
     "orientation_average", "forward_3d_regions", "backward_3d_regions", "intensity_loss_3d", "strip_order",
     "batch_strip_order", "q_order",
-    "validate_mesh", "check_mesh",
+    "validate_mesh", "check_mesh", "fp32c_q_limit",
     "profile_enable", "profile_reset", "profile_read", "release_workspace", "version", "mode_id", "tuning_info",
 ]
 
@@ -572,6 +572,20 @@ def check_mesh(tris, nv: Optional[int] = None) -> dict:
     rep = _lib.PftMeshCheck()
     check(_lib.load().pft_check_mesh(t.ctypes.data, t.shape[0], nv, ctypes.byref(rep)))
     return {name: int(getattr(rep, name)) for name, _ in rep._fields_}
+
+
+def fp32c_q_limit(verts, tris) -> float:
+    """pft_fp32c_q_limit on the host: the largest |Q| at which PFT_FP32C evaluates this triangle mesh
+    (PFT_FP32C_PHASE_MAX over the largest face centroid-to-vertex distance; inf for a mesh without
+    extent). Beyond it the FP32C outputs at that Q are NaN. Tensors are copied to the host."""
+    v = verts.detach().cpu().numpy() if isinstance(verts, torch.Tensor) else np.asarray(verts)
+    t = tris.detach().cpu().numpy() if isinstance(tris, torch.Tensor) else np.asarray(tris)
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(t, dtype=np.int32).reshape(-1, 3)
+    lim = ctypes.c_double(0.0)
+    check(_lib.load().pft_fp32c_q_limit(v.ctypes.data, _lib.PFT_F64, v.shape[0], t.ctypes.data, t.shape[0],
+                                        ctypes.byref(lim)))
+    return float(lim.value)
 
 
 def validate_mesh(tris: torch.Tensor, nv: int) -> Tuple[int, int]:

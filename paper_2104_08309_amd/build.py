@@ -77,5 +77,26 @@ def build(verbose: bool = False, jobs: int = 8, out: str = LIB, defines=(), buil
     return out
 
 
+UBENCH_SRC = os.path.join(HERE, "ubench", "valu_rates.hip")
+UBENCH_BIN = os.path.join(HERE, "ubench", "valu_rates")
+
+
+def build_ubench(verbose: bool = False, out: str = UBENCH_BIN) -> str:
+    """Compile the vector-ALU issue-rate microbenchmark (ubench/valu_rates.hip) with the library's
+    code-generation flags into a standalone executable; returns its path."""
+    hipcc = _hipcc()
+    flags = [f for f in COMMON if f not in ("-fPIC", "-I", INCLUDE, CSRC)]
+    tmp = out + ".tmp"
+    cmd = [hipcc, "-x", "hip"] + flags + [UBENCH_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {UBENCH_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    print(build_ubench(verbose="-v" in sys.argv))

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -963,6 +964,34 @@ pft_status pft_check_mesh(const int32_t* tris, int64_t nf, int64_t nv, pft_mesh_
   if (nf > INT32_MAX / 3 || nv > INT32_MAX) return fail(PFT_EINVAL, "mesh too large for 32-bit indices");
   if (report == nullptr || (nf > 0 && tris == nullptr)) return fail(PFT_EINVAL, "tris or report is NULL");
   count_mesh(tris, 0, nf, nv, report);
+  return PFT_OK;
+}
+
+pft_status pft_fp32c_q_limit(const void* verts, pft_dtype vdtype, int64_t nv, const int32_t* tris, int64_t nf,
+                             double* q_limit) {
+  if (vdtype != PFT_F32 && vdtype != PFT_F64) return fail(PFT_EUNSUPPORTED, "unknown vertex dtype");
+  if (nf < 0 || nv < 0) return fail(PFT_EINVAL, "negative count");
+  if (q_limit == nullptr || (nf > 0 && tris == nullptr) || (nv > 0 && verts == nullptr))
+    return fail(PFT_EINVAL, "verts, tris or q_limit is NULL");
+  auto vert = [&](int32_t i, int k) {
+    return vdtype == PFT_F64 ? static_cast<const double*>(verts)[3 * (int64_t)i + k]
+                             : (double)static_cast<const float*>(verts)[3 * (int64_t)i + k];
+  };
+  // rho: the largest distance from a face's centroid to one of its vertices (faces with an index
+  // outside [0, nv) are empty in the transform and skipped here)
+  double rho2 = 0.0;
+  for (int64_t f = 0; f < nf; ++f) {
+    const int32_t* ix = tris + 3 * f;
+    if (ix[0] < 0 || ix[1] < 0 || ix[2] < 0 || ix[0] >= nv || ix[1] >= nv || ix[2] >= nv) continue;
+    double g[3];
+    for (int k = 0; k < 3; ++k) g[k] = (vert(ix[0], k) + vert(ix[1], k) + vert(ix[2], k)) / 3.0;
+    for (int j = 0; j < 3; ++j) {
+      double d2 = 0.0;
+      for (int k = 0; k < 3; ++k) d2 += (vert(ix[j], k) - g[k]) * (vert(ix[j], k) - g[k]);
+      rho2 = std::max(rho2, d2);
+    }
+  }
+  *q_limit = rho2 > 0.0 ? kPhaseMax32 / std::sqrt(rho2) : std::numeric_limits<double>::infinity();
   return PFT_OK;
 }
 

@@ -162,8 +162,9 @@ __global__ __launch_bounds__(256) void batch_fwd_finish_kernel(const double2* pa
   }
   double st, ct;
   sincos(Q[0] * mi.t[0] + Q[1] * mi.t[1] + Q[2] * mi.t[2], &st, &ct);
-  const double Fr = ct * xr - st * xi;
-  const double Fi = ct * xi + st * xr;
+  double Fr = ct * xr - st * xi;
+  double Fi = ct * xi + st * xr;
+  if (!out_c128 && fp32c_phase_out_of_range(sqrt(Q2), mi)) Fr = Fi = quiet_nan();  // beyond the FP32C phase range
   if (out_c128) {
     static_cast<double2*>(out)[dst] = make_double2(Fr, Fi);
     if (intensity) static_cast<double*>(intensity)[dst] = Fr * Fr + Fi * Fi;

@@ -202,6 +202,7 @@ __global__ __launch_bounds__(kFinishBlock) void regions_finish_kernel(FwdArgs a,
       xr /= Q2;
       xi /= Q2;
     }
+    if (!out_c128 && fp32c_phase_out_of_range(qabs, mi)) xr = xi = quiet_nan();  // beyond the FP32C phase range
     const double fr = ct * xr - st * xi, fi = ct * xi + st * xr;
     if (valid && r.out_regions) store_complex(r.out_regions, out_c128, (int64_t)j * a.nq + dst, fr, fi);
     const double rho = r.rho[j];
@@ -262,6 +263,10 @@ __global__ __launch_bounds__(kFinishBlock) void dq_finish_kernel(DqArgs a, Regio
         gcr[c] = (v[2 * c] - Q[c] * v[7] * iq2) * iq2;
         gci[c] = (v[2 * c + 1] + Q[c] * v[6] * iq2) * iq2;
       }
+    }
+    if (!go_c128 && fp32c_phase_out_of_range(qabs, mi)) {  // beyond the FP32C phase range
+      fcr = fci = quiet_nan();
+      for (int c = 0; c < 3; ++c) gcr[c] = gci[c] = quiet_nan();
     }
     const double rho = r.rho[j];
     for (int c = 0; c < 3; ++c) {

@@ -177,8 +177,9 @@ __global__ __launch_bounds__(256) void fwd3d_finish_kernel(FwdArgs a, int out_c1
   }
   double st, ct;
   sincos(Q[0] * mi.t[0] + Q[1] * mi.t[1] + Q[2] * mi.t[2], &st, &ct);
-  const double Fr = ct * xr - st * xi;
-  const double Fi = ct * xi + st * xr;
+  double Fr = ct * xr - st * xi;
+  double Fi = ct * xi + st * xr;
+  if (!out_c128 && fp32c_phase_out_of_range(sqrt(Q2), mi)) Fr = Fi = quiet_nan();  // beyond the FP32C phase range
   if (out_c128) {
     if (a.out) static_cast<double2*>(a.out)[dst] = make_double2(Fr, Fi);
     if (a.intensity) static_cast<double*>(a.intensity)[dst] = Fr * Fr + Fi * Fi;

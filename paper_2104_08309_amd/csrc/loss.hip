@@ -40,6 +40,8 @@ __global__ __launch_bounds__(kLossBlock) void loss_finish_kernel(FwdArgs a, cons
       xr /= Q2;
       xi /= Q2;
     }
+    // beyond the FP32C phase range: NaN F, loss term and cotangent
+    if (!c128 && fp32c_phase_out_of_range(sqrt(Q2), mi)) xr = xi = quiet_nan();
     const double I = xr * xr + xi * xi;
     const double w = weight ? weight[dst] : 1.0;
     const double r = I - target[dst];

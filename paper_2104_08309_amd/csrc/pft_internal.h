@@ -84,11 +84,30 @@ constexpr double kTau02D = 0.01;
 // ---------------------------------------------------------------------------
 // Records
 // ---------------------------------------------------------------------------
-// Per-mesh quantities (device): vertex mean t, radius R = max |v - t|.
+// Per-mesh quantities (device): vertex mean t, radius R = max |v - t|, and
+// rho, the largest distance from a face's centroid (vertex mean) to one of its
+// vertices over the mesh's faces (the face prologue raises it from 0; the
+// FP32C phase-range check reads it).
 struct MeshInfo {
   double t[3];
   double R;
+  double rho;
+  double pad;
 };
+
+// FP32C phase range. The binary32 form takes every phase it evaluates relative
+// to a face origin: the half-vertex phases Q.u/2 (u = vertex - face centroid),
+// the edge half-differences Q.(b - a)/2 and the midpoint phases, all in turns.
+// With |Q| rho <= kPhaseMax32 radians each of them is at most
+// kPhaseMax32 / (2 pi) + 1/2 < 21 turns, inside the hardware sine's domain and
+// rounded to within 2^-20 turn (6e-6 rad) in binary32. The FP32C finish steps
+// write NaN (F, |F|^2, the loss term, the cotangent records) for every Q beyond
+// it; the binary64 form has no such bound.
+constexpr double kPhaseMax32 = PFT_FP32C_PHASE_MAX;
+__host__ __device__ __forceinline__ bool fp32c_phase_out_of_range(double qabs, const MeshInfo& mi) {
+  return qabs * mi.rho > kPhaseMax32;
+}
+__host__ __device__ __forceinline__ double quiet_nan() { return __builtin_nan(""); }
 
 // FP64 face record: geometry relative to the mesh centre t.
 struct alignas(16) Face64 {
@@ -183,13 +202,13 @@ hipError_t launch_mesh_info_single(const void* verts, int vdtype, int dim, int64
 // With order / meta (device, [nf]; NULL: the list order), record m is face order[m] with its
 // vertex list rotated by meta[m] & 3, and pad[2] holds the link meta[m] >> 2 (0, 1 or 2).
 hipError_t launch_face64(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
-                         const MeshInfo* info, double tau, Face64* out, hipStream_t s,
+                         MeshInfo* info, double tau, Face64* out, hipStream_t s,
                          const int32_t* order = nullptr, const uint8_t* meta = nullptr);
 hipError_t launch_face32(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32* out, hipStream_t s);
 hipError_t launch_face32b(const Face64* f64, int64_t nf, double tau, double tau_rel, Face32B* out, hipStream_t s);
 hipError_t launch_face64_batch(const void* verts, int vdtype, const int32_t* tris, const int64_t* d_vert_off,
                                const int64_t* d_tri_off, const int32_t* d_face_mesh, int64_t nf_total,
-                               const MeshInfo* info, double tau, Face64* out, hipStream_t s,
+                               MeshInfo* info, double tau, Face64* out, hipStream_t s,
                                const int32_t* order = nullptr, const uint8_t* meta = nullptr);
 hipError_t launch_fill_face_mesh(const int64_t* d_tri_off, int64_t n_meshes, int64_t nf_total, int32_t* face_mesh,
                                  hipStream_t s);
@@ -267,7 +286,7 @@ struct PolyArgs {
 
 // prologue.hip: records of polygon faces (face_off: device CSR offsets into face_verts)
 hipError_t launch_poly_records(const void* verts, int vdtype, int64_t nv, const int64_t* face_off,
-                               const int32_t* face_verts, int64_t nf, const MeshInfo* info, double tau, FaceP64* f64,
+                               const int32_t* face_verts, int64_t nf, MeshInfo* info, double tau, FaceP64* f64,
                                VtxP64* v64, hipStream_t s);
 // (the binary64 records must have been built with the FP32C threshold tau)
 hipError_t launch_poly_records32(const FaceP64* f64, const VtxP64* v64, int64_t nf, double tau_rel, FaceP32* f32,

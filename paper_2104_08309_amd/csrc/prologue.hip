@@ -65,6 +65,8 @@ __global__ __launch_bounds__(256) void mesh_info_kernel(const void* verts, int v
     MeshInfo m;
     for (int k = 0; k < 3; ++k) m.t[k] = t[k];
     m.R = sqrt(red[0][0]);
+    m.rho = 0.0;  // raised by the face prologue
+    m.pad = 0.0;
     info[mesh] = m;
   }
 }
@@ -106,6 +108,34 @@ __device__ inline void empty_face64(Face64& f) {
   f.pad[0] = f.pad[1] = f.pad[2] = 0.0;
 }
 
+// Largest squared distance from a face record's centroid to its vertices (u0, u1, -u0 - u1).
+__device__ inline double face_extent2(const Face64& f) {
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double w = -f.u0[k] - f.u1[k];
+    d0 += f.u0[k] * f.u0[k];
+    d1 += f.u1[k] * f.u1[k];
+    d2 += w * w;
+  }
+  return fmax(d0, fmax(d1, d2));
+}
+
+// Raise info[mesh].rho to sqrt(ext2) over the lanes of the wavefront. Every lane
+// of the wavefront must reach this call (lanes without a face pass ext2 = 0);
+// the lanes of the first lane's mesh are reduced to one atomic, any other lane
+// (a wavefront that straddles two meshes of a batch) raises its own. rho >= 0,
+// so its binary64 pattern orders like an unsigned integer.
+__device__ inline void raise_rho(MeshInfo* info, int64_t mesh, double ext2) {
+  const int64_t mesh0 = __shfl(mesh, 0);
+  double r = mesh == mesh0 ? ext2 : 0.0;
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off));
+  if ((threadIdx.x & 63) == 0 && r > 0.0)
+    atomicMax(reinterpret_cast<unsigned long long*>(&info[mesh0].rho), (unsigned long long)__double_as_longlong(sqrt(r)));
+  if (mesh != mesh0 && ext2 > 0.0)
+    atomicMax(reinterpret_cast<unsigned long long*>(&info[mesh].rho),
+              (unsigned long long)__double_as_longlong(sqrt(ext2)));
+}
+
 // The edge-sharing flags of position m kept in Face64::pad[2] for the FP32C record
 // builder: 1 = linked to the previous position, 2 = traversal reversed. The Face64
 // record itself keeps the outward (rotated) vertex order.
@@ -115,36 +145,40 @@ __device__ __forceinline__ int order_code(const uint8_t* meta, int64_t m) {
 }
 
 __global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdtype, int64_t nv, const int32_t* tris,
-                                                     int64_t nf, const MeshInfo* info, double tau, Face64* out,
+                                                     int64_t nf, MeshInfo* info, double tau, Face64* out,
                                                      const int32_t* order, const uint8_t* meta) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nf) return;
-  // the face at this position of the (optional) edge-sharing order, its vertex list rotated
-  const int64_t src = order ? (int64_t)order[m] : m;
-  const int rot = meta ? (meta[m] & 3) : 0;
-  const int code = order_code(meta, m);
-  Face64 f;
-  const bool in_list = src >= 0 && src < nf && rot < 3;
-  const int32_t ia = in_list ? tris[3 * src + rot] : -1;
-  const int32_t ib = in_list ? tris[3 * src + (rot + 1) % 3] : -1;
-  const int32_t ic = in_list ? tris[3 * src + (rot + 2) % 3] : -1;
-  if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) {
-    empty_face64(f);
-  } else {
-    double a[3], b[3], c[3];
-    load_vertex(verts, vdtype, 3, ia, a);
-    load_vertex(verts, vdtype, 3, ib, b);
-    load_vertex(verts, vdtype, 3, ic, c);
-    const MeshInfo mi = info[0];
-    for (int k = 0; k < 3; ++k) {
-      a[k] -= mi.t[k];
-      b[k] -= mi.t[k];
-      c[k] -= mi.t[k];
+  double ext2 = 0.0;
+  if (m < nf) {
+    // the face at this position of the (optional) edge-sharing order, its vertex list rotated
+    const int64_t src = order ? (int64_t)order[m] : m;
+    const int rot = meta ? (meta[m] & 3) : 0;
+    const int code = order_code(meta, m);
+    Face64 f;
+    const bool in_list = src >= 0 && src < nf && rot < 3;
+    const int32_t ia = in_list ? tris[3 * src + rot] : -1;
+    const int32_t ib = in_list ? tris[3 * src + (rot + 1) % 3] : -1;
+    const int32_t ic = in_list ? tris[3 * src + (rot + 2) % 3] : -1;
+    if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) {
+      empty_face64(f);
+    } else {
+      double a[3], b[3], c[3];
+      load_vertex(verts, vdtype, 3, ia, a);
+      load_vertex(verts, vdtype, 3, ib, b);
+      load_vertex(verts, vdtype, 3, ic, c);
+      const MeshInfo mi = info[0];
+      for (int k = 0; k < 3; ++k) {
+        a[k] -= mi.t[k];
+        b[k] -= mi.t[k];
+        c[k] -= mi.t[k];
+      }
+      make_face64(a, b, c, tau, f);
+      f.pad[2] = (double)code;
+      ext2 = face_extent2(f);
     }
-    make_face64(a, b, c, tau, f);
-    f.pad[2] = (double)code;
+    out[m] = f;
   }
-  out[m] = f;
+  raise_rho(info, 0, ext2);
 }
 
 // One thread per polygon face: vertex mean g, area vector N = sum_k u_k x u_{k+1}
@@ -152,71 +186,76 @@ __global__ __launch_bounds__(256) void face64_kernel(const void* verts, int vdty
 // with an out-of-range index or zero area becomes empty (all-zero records).
 __global__ __launch_bounds__(256) void poly64_kernel(const void* verts, int vdtype, int64_t nv,
                                                      const int64_t* face_off, const int32_t* face_verts, int64_t nf,
-                                                     const MeshInfo* info, double tau, FaceP64* fout,
+                                                     MeshInfo* info, double tau, FaceP64* fout,
                                                      VtxP64* vout) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nf) return;
-  const int64_t b = face_off[m], e = face_off[m + 1];
-  const int n = (int)(e - b);
-  bool ok = n >= 3;
-  for (int64_t k = b; k < e; ++k) ok = ok && face_verts[k] >= 0 && face_verts[k] < nv;
-  const MeshInfo mi = info[0];
-  FaceP64 f;
-  f.v0 = (int32_t)b;
-  f.nv = n;
-  f.pad[0] = f.pad[1] = 0;
-  double g[3] = {0.0, 0.0, 0.0};
-  if (ok) {
-    for (int64_t k = b; k < e; ++k) {
-      double r[3];
-      load_vertex(verts, vdtype, 3, face_verts[k], r);
-      for (int c = 0; c < 3; ++c) g[c] += r[c] - mi.t[c];
-    }
-    for (int c = 0; c < 3; ++c) g[c] /= (double)n;
-  }
-  double N[3] = {0.0, 0.0, 0.0}, L2 = 0.0;
-  double u0[3] = {0.0, 0.0, 0.0}, uprev[3] = {0.0, 0.0, 0.0};
-  for (int64_t k = b; k < e; ++k) {
-    double u[3] = {0.0, 0.0, 0.0};
+  double ext2 = 0.0;
+  if (m < nf) {
+    const int64_t b = face_off[m], e = face_off[m + 1];
+    const int n = (int)(e - b);
+    bool ok = n >= 3;
+    for (int64_t k = b; k < e; ++k) ok = ok && face_verts[k] >= 0 && face_verts[k] < nv;
+    const MeshInfo mi = info[0];
+    FaceP64 f;
+    f.v0 = (int32_t)b;
+    f.nv = n;
+    f.pad[0] = f.pad[1] = 0;
+    double g[3] = {0.0, 0.0, 0.0};
     if (ok) {
-      load_vertex(verts, vdtype, 3, face_verts[k], u);
-      for (int c = 0; c < 3; ++c) u[c] -= mi.t[c] + g[c];
+      for (int64_t k = b; k < e; ++k) {
+        double r[3];
+        load_vertex(verts, vdtype, 3, face_verts[k], r);
+        for (int c = 0; c < 3; ++c) g[c] += r[c] - mi.t[c];
+      }
+      for (int c = 0; c < 3; ++c) g[c] /= (double)n;
     }
-    VtxP64 r;
-    r.u[0] = u[0];
-    r.u[1] = u[1];
-    r.u[2] = u[2];
-    r.pad = 0.0;
-    vout[k] = r;
-    if (k == b) {
-      for (int c = 0; c < 3; ++c) u0[c] = u[c];
-    } else {
-      N[0] += uprev[1] * u[2] - uprev[2] * u[1];
-      N[1] += uprev[2] * u[0] - uprev[0] * u[2];
-      N[2] += uprev[0] * u[1] - uprev[1] * u[0];
+    double N[3] = {0.0, 0.0, 0.0}, L2 = 0.0;
+    double u0[3] = {0.0, 0.0, 0.0}, uprev[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = b; k < e; ++k) {
+      double u[3] = {0.0, 0.0, 0.0};
+      if (ok) {
+        load_vertex(verts, vdtype, 3, face_verts[k], u);
+        for (int c = 0; c < 3; ++c) u[c] -= mi.t[c] + g[c];
+        ext2 = fmax(ext2, u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      }
+      VtxP64 r;
+      r.u[0] = u[0];
+      r.u[1] = u[1];
+      r.u[2] = u[2];
+      r.pad = 0.0;
+      vout[k] = r;
+      if (k == b) {
+        for (int c = 0; c < 3; ++c) u0[c] = u[c];
+      } else {
+        N[0] += uprev[1] * u[2] - uprev[2] * u[1];
+        N[1] += uprev[2] * u[0] - uprev[0] * u[2];
+        N[2] += uprev[0] * u[1] - uprev[1] * u[0];
+        double d2 = 0.0;
+        for (int c = 0; c < 3; ++c) d2 += (u[c] - uprev[c]) * (u[c] - uprev[c]);
+        L2 = fmax(L2, d2);
+      }
+      for (int c = 0; c < 3; ++c) uprev[c] = u[c];
+    }
+    if (n >= 1) {  // closing edge
+      N[0] += uprev[1] * u0[2] - uprev[2] * u0[1];
+      N[1] += uprev[2] * u0[0] - uprev[0] * u0[2];
+      N[2] += uprev[0] * u0[1] - uprev[1] * u0[0];
       double d2 = 0.0;
-      for (int c = 0; c < 3; ++c) d2 += (u[c] - uprev[c]) * (u[c] - uprev[c]);
+      for (int c = 0; c < 3; ++c) d2 += (u0[c] - uprev[c]) * (u0[c] - uprev[c]);
       L2 = fmax(L2, d2);
     }
-    for (int c = 0; c < 3; ++c) uprev[c] = u[c];
+    const double N2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
+    ok = ok && N2 > 0.0 && L2 > 0.0;
+    for (int c = 0; c < 3; ++c) {
+      f.g[c] = ok ? g[c] : 0.0;
+      f.N[c] = ok ? N[c] : 0.0;
+    }
+    f.thr = ok ? tau * tau * N2 / L2 : -1.0;
+    f.invN = ok ? 1.0 / sqrt(N2) : 0.0;
+    fout[m] = f;
+    if (!ok) ext2 = 0.0;
   }
-  if (n >= 1) {  // closing edge
-    N[0] += uprev[1] * u0[2] - uprev[2] * u0[1];
-    N[1] += uprev[2] * u0[0] - uprev[0] * u0[2];
-    N[2] += uprev[0] * u0[1] - uprev[1] * u0[0];
-    double d2 = 0.0;
-    for (int c = 0; c < 3; ++c) d2 += (u0[c] - uprev[c]) * (u0[c] - uprev[c]);
-    L2 = fmax(L2, d2);
-  }
-  const double N2 = N[0] * N[0] + N[1] * N[1] + N[2] * N[2];
-  ok = ok && N2 > 0.0 && L2 > 0.0;
-  for (int c = 0; c < 3; ++c) {
-    f.g[c] = ok ? g[c] : 0.0;
-    f.N[c] = ok ? N[c] : 0.0;
-  }
-  f.thr = ok ? tau * tau * N2 / L2 : -1.0;
-  f.invN = ok ? 1.0 / sqrt(N2) : 0.0;
-  fout[m] = f;
+  raise_rho(info, 0, ext2);
 }
 
 // FP32C polygon records: orthonormal in-plane basis (e1 along the first edge of
@@ -295,39 +334,43 @@ __global__ __launch_bounds__(256) void face_mesh_kernel(const int64_t* tri_off, 
 __global__ __launch_bounds__(256) void face64_batch_kernel(const void* verts, int vdtype, const int32_t* tris,
                                                            const int64_t* vert_off, const int64_t* tri_off,
                                                            const int32_t* face_mesh, int64_t nf_total,
-                                                           const MeshInfo* info, double tau, Face64* out,
+                                                           MeshInfo* info, double tau, Face64* out,
                                                            const int32_t* order, const uint8_t* meta) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= nf_total) return;
-  const int32_t mesh = face_mesh[m];
-  const int64_t vb = vert_off[mesh];
-  const int64_t nv = vert_off[mesh + 1] - vb;
-  // the face at this position of the (optional) edge-sharing order (within its mesh), rotated
-  const int64_t src = order ? (int64_t)order[m] : m;
-  const int rot = meta ? (meta[m] & 3) : 0;
-  const int code = order_code(meta, m);
-  const bool in_list = src >= 0 && src < nf_total && rot < 3;
-  const int32_t ia = in_list ? tris[3 * src + rot] : -1;
-  const int32_t ib = in_list ? tris[3 * src + (rot + 1) % 3] : -1;
-  const int32_t ic = in_list ? tris[3 * src + (rot + 2) % 3] : -1;
-  Face64 f;
-  if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) {
-    empty_face64(f);
-  } else {
-    double a[3], b[3], c[3];
-    load_vertex(verts, vdtype, 3, vb + ia, a);
-    load_vertex(verts, vdtype, 3, vb + ib, b);
-    load_vertex(verts, vdtype, 3, vb + ic, c);
-    const MeshInfo mi = info[mesh];
-    for (int k = 0; k < 3; ++k) {
-      a[k] -= mi.t[k];
-      b[k] -= mi.t[k];
-      c[k] -= mi.t[k];
+  double ext2 = 0.0;
+  const int32_t mesh = m < nf_total ? face_mesh[m] : -1;
+  if (m < nf_total) {
+    const int64_t vb = vert_off[mesh];
+    const int64_t nv = vert_off[mesh + 1] - vb;
+    // the face at this position of the (optional) edge-sharing order (within its mesh), rotated
+    const int64_t src = order ? (int64_t)order[m] : m;
+    const int rot = meta ? (meta[m] & 3) : 0;
+    const int code = order_code(meta, m);
+    const bool in_list = src >= 0 && src < nf_total && rot < 3;
+    const int32_t ia = in_list ? tris[3 * src + rot] : -1;
+    const int32_t ib = in_list ? tris[3 * src + (rot + 1) % 3] : -1;
+    const int32_t ic = in_list ? tris[3 * src + (rot + 2) % 3] : -1;
+    Face64 f;
+    if (ia < 0 || ib < 0 || ic < 0 || ia >= nv || ib >= nv || ic >= nv) {
+      empty_face64(f);
+    } else {
+      double a[3], b[3], c[3];
+      load_vertex(verts, vdtype, 3, vb + ia, a);
+      load_vertex(verts, vdtype, 3, vb + ib, b);
+      load_vertex(verts, vdtype, 3, vb + ic, c);
+      const MeshInfo mi = info[mesh];
+      for (int k = 0; k < 3; ++k) {
+        a[k] -= mi.t[k];
+        b[k] -= mi.t[k];
+        c[k] -= mi.t[k];
+      }
+      make_face64(a, b, c, tau, f);
+      f.pad[2] = (double)code;
+      ext2 = face_extent2(f);
     }
-    make_face64(a, b, c, tau, f);
-    f.pad[2] = (double)code;
+    out[m] = f;
   }
-  out[m] = f;
+  raise_rho(info, mesh, ext2);
 }
 
 
@@ -498,7 +541,7 @@ hipError_t launch_mesh_info_single(const void* verts, int vdtype, int dim, int64
 }
 
 hipError_t launch_face64(const void* verts, int vdtype, int64_t nv, const int32_t* tris, int64_t nf,
-                         const MeshInfo* info, double tau, Face64* out, hipStream_t s, const int32_t* order,
+                         MeshInfo* info, double tau, Face64* out, hipStream_t s, const int32_t* order,
                          const uint8_t* meta) {
   if (nf <= 0) return hipSuccess;
   face64_kernel<<<grid_for(nf), 256, 0, s>>>(verts, vdtype, nv, tris, nf, info, tau, out, order, meta);
@@ -506,7 +549,7 @@ hipError_t launch_face64(const void* verts, int vdtype, int64_t nv, const int32_
 }
 
 hipError_t launch_poly_records(const void* verts, int vdtype, int64_t nv, const int64_t* face_off,
-                               const int32_t* face_verts, int64_t nf, const MeshInfo* info, double tau, FaceP64* f64,
+                               const int32_t* face_verts, int64_t nf, MeshInfo* info, double tau, FaceP64* f64,
                                VtxP64* v64, hipStream_t s) {
   if (nf <= 0) return hipSuccess;
   poly64_kernel<<<grid_for(nf), 256, 0, s>>>(verts, vdtype, nv, face_off, face_verts, nf, info, tau, f64, v64);
@@ -541,7 +584,7 @@ hipError_t launch_fill_face_mesh(const int64_t* d_tri_off, int64_t n_meshes, int
 
 hipError_t launch_face64_batch(const void* verts, int vdtype, const int32_t* tris, const int64_t* d_vert_off,
                                const int64_t* d_tri_off, const int32_t* d_face_mesh, int64_t nf_total,
-                               const MeshInfo* info, double tau, Face64* out, hipStream_t s,
+                               MeshInfo* info, double tau, Face64* out, hipStream_t s,
                                const int32_t* order, const uint8_t* meta) {
   if (nf_total <= 0) return hipSuccess;
   face64_batch_kernel<<<grid_for(nf_total), 256, 0, s>>>(verts, vdtype, tris, d_vert_off, d_tri_off, d_face_mesh,

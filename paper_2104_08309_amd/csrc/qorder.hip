@@ -131,8 +131,11 @@ __global__ __launch_bounds__(256) void qrec32_kernel(const void* q, int qdtype, 
   double Q[3];
   load_q3(q, qdtype, j, Q);
   const float2 g = grad_out[j];
+  const MeshInfo& mi = info[mesh_of(q_off, n_meshes, j)];
   double hr, hi;
-  centred_cotangent((double)g.x, (double)g.y, Q, info[mesh_of(q_off, n_meshes, j)].t, hr, hi);
+  centred_cotangent((double)g.x, (double)g.y, Q, mi.t, hr, hi);
+  // beyond the FP32C phase range: a NaN cotangent, so every vertex gradient is NaN
+  if (fp32c_phase_out_of_range(sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]), mi)) hr = hi = quiet_nan();
   QRec32 r;
   r.q[0] = Q[0];
   r.q[1] = Q[1];

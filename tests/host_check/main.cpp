@@ -2,6 +2,7 @@
 // the edge-sharing face order on random and broken meshes, and every entry point's synchronous
 // argument validation (each call below returns before any GPU work). Exits non-zero on a failed check.
 #include <cstdint>
+#include <cmath>
 #include <cstdio>
 #include <random>
 #include <vector>
@@ -82,6 +83,16 @@ int main() {
     CHECK(c.bad_index == 0 && c.open_edges == 0 && c.nonmanifold_edges == 0 && c.misoriented_edges == 0);
     CHECK(pft_check_mesh(tet, 3, 4, &c) == PFT_OK && c.open_edges == 3);
     CHECK(pft_check_mesh(nullptr, 2, 4, &c) == PFT_EINVAL);
+    // the FP32C |Q| bound: a regular tetrahedron of circumradius 1 has faces of extent sqrt(8)/3
+    const double a = 1.0 / std::sqrt(3.0);
+    const double tv[12] = {a, a, a, a, -a, -a, -a, a, -a, -a, -a, a};
+    double lim = 0.0;
+    CHECK(pft_fp32c_q_limit(tv, PFT_F64, 4, tet, 4, &lim) == PFT_OK);
+    CHECK(std::fabs(lim - PFT_FP32C_PHASE_MAX / (std::sqrt(8.0) / 3.0)) < 1e-12 * lim);
+    const int32_t tet_bad[12] = {0, 2, 1, 0, 1, 3, 0, 3, 2, 1, 2, 40};
+    CHECK(pft_fp32c_q_limit(tv, PFT_F64, 4, tet_bad, 4, &lim) == PFT_OK);
+    CHECK(pft_fp32c_q_limit(tv, PFT_F64, 4, tet, 4, nullptr) == PFT_EINVAL);
+    CHECK(pft_fp32c_q_limit(nullptr, PFT_F64, 0, nullptr, 0, &lim) == PFT_OK && std::isinf(lim));
   }
   CHECK(pft_strip_order(nullptr, 3, 3, nullptr, nullptr) == PFT_EINVAL);
   CHECK(pft_strip_order(nullptr, -1, 3, nullptr, nullptr) == PFT_EINVAL);

@@ -53,3 +53,59 @@ def test_validation():
     assert lib.pft_check_mesh(None, 2, 3, rep) == _lib.PFT_EINVAL
     assert lib.pft_check_mesh(None, 0, 3, None) == _lib.PFT_EINVAL
     assert lib.pft_check_mesh(None, 0, 3, rep) == _lib.PFT_OK
+
+
+def _rho_by_definition(v, t):
+    """Largest distance from a triangle's centroid to one of its corners, face by face."""
+    best = 0.0
+    for f in t:
+        p = v[f]
+        g = p.mean(axis=0)
+        best = max(best, max(np.linalg.norm(p[k] - g) for k in range(3)))
+    return best
+
+
+@pytest.mark.parametrize("mesh", ["icosphere", "box", "ellipsoid", "hull"])
+def test_fp32c_q_limit(mesh):
+    """pft_fp32c_q_limit (host) is PFT_FP32C_PHASE_MAX over the largest face extent."""
+    rng = np.random.default_rng(4)
+    if mesh == "icosphere":
+        v, t = mg.icosphere(3, 50.0)
+    elif mesh == "box":
+        v, t = mg.box(40.0, 3.0, 7.0, origin=(1.0, 2.0, 3.0))
+    elif mesh == "ellipsoid":
+        v, t = mg.ellipsoid_uv([30.0, 20.0, 15.0], 9, centre=(5.0, 0.0, -5.0))
+    else:
+        v, t = mg.convex_hull_mesh(rng.normal(size=(32, 3)) * 40.0)
+    assert pft.fp32c_q_limit(v, t) == pytest.approx(128.0 / _rho_by_definition(v, t), rel=1e-12)
+    # float32 vertices: the limit of the rounded vertices
+    import ctypes
+    v32 = np.ascontiguousarray(v, dtype=np.float32)
+    t32 = np.ascontiguousarray(t, dtype=np.int32)
+    lim = ctypes.c_double()
+    assert _lib.load().pft_fp32c_q_limit(v32.ctypes.data, _lib.PFT_F32, len(v32), t32.ctypes.data, len(t32),
+                                         ctypes.byref(lim)) == 0
+    assert lim.value == pytest.approx(128.0 / _rho_by_definition(v32.astype(np.float64), t), rel=1e-12)
+
+
+def test_fp32c_q_limit_edge_cases():
+    import ctypes
+    lib = _lib.load()
+    assert pft.fp32c_q_limit(np.zeros((0, 3)), np.zeros((0, 3), dtype=np.int32)) == float("inf")
+    v, t = mg.box(2.0, 2.0, 2.0)
+    # a face with an out-of-range index is empty in the transform and skipped here
+    far = np.concatenate([v, [[1e6, 0.0, 0.0]]])
+    assert pft.fp32c_q_limit(far, np.concatenate([t, [[0, 1, 99]]])) == pytest.approx(pft.fp32c_q_limit(v, t))
+    # a face with extent always counts, even when degenerate (zero area)
+    line = np.concatenate([v, [[10.0, 0.0, 0.0]]])
+    assert pft.fp32c_q_limit(line, np.concatenate([t, [[0, 8, 0]]])) < pft.fp32c_q_limit(v, t)
+    lim = ctypes.c_double()
+    vv = np.ascontiguousarray(v)
+    tt = np.ascontiguousarray(t, dtype=np.int32)
+    assert lib.pft_fp32c_q_limit(vv.ctypes.data, _lib.PFT_F64, len(vv), tt.ctypes.data, len(tt), None) == _lib.PFT_EINVAL
+    assert lib.pft_fp32c_q_limit(None, _lib.PFT_F64, len(vv), tt.ctypes.data, len(tt), ctypes.byref(lim)) == \
+        _lib.PFT_EINVAL
+    assert lib.pft_fp32c_q_limit(vv.ctypes.data, _lib.PFT_F64, -1, tt.ctypes.data, len(tt), ctypes.byref(lim)) == \
+        _lib.PFT_EINVAL
+    assert lib.pft_fp32c_q_limit(vv.ctypes.data, 7, len(vv), tt.ctypes.data, len(tt), ctypes.byref(lim)) == \
+        _lib.PFT_EUNSUPPORTED
