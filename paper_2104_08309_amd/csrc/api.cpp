@@ -282,6 +282,22 @@ void choose_face_splits(int64_t nq, int64_t nf, int qpt, int* splits, int64_t* p
   *splits = (int)cdiv(nf, p);
 }
 
+// Face splits of a single-mesh forward (sets a.splits and a.faces_per_split; returns the double2 partial
+// entries they need), capped so that the partials fit in max_partials entries when that is > 0.
+int64_t plan_forward(int64_t nq, int64_t nf, bool c128, int64_t max_partials, FwdArgs& a) {
+  int splits;
+  int64_t per;
+  choose_face_splits(nq, nf, c128 ? 1 : kQPT, &splits, &per);
+  if (max_partials > 0 && (int64_t)splits * nq > max_partials && nf > 0) {
+    const int64_t cap = std::max<int64_t>(1, max_partials / nq);
+    per = cdiv(cdiv(nf, cap), kTileF) * kTileF;
+    splits = (int)cdiv(nf, per);
+  }
+  a.splits = splits;
+  a.faces_per_split = per;
+  return (int64_t)splits * nq;
+}
+
 void choose_q_splits(int64_t nq, int64_t nf, int tile, int* splits, int64_t* per) {
   const int64_t fblocks = std::max<int64_t>(1, cdiv(nf, tile));
   int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, fblocks), std::max<int64_t>(1, cdiv(nq, kBlock))));
@@ -738,15 +754,9 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   MeshInfo* info = ar.get<MeshInfo>(1);
   Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
   Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
-  int splits;
-  int64_t per;
-  choose_face_splits(nq, nf, c128 ? 1 : kQPT, &splits, &per);
-  if (max_partials > 0 && (int64_t)splits * nq > max_partials && nf > 0) {
-    const int64_t cap = std::max<int64_t>(1, max_partials / nq);
-    per = cdiv(cdiv(nf, cap), kTileF) * kTileF;
-    splits = (int)cdiv(nf, per);
-  }
-  double2* partial = ar.get<double2>((size_t)splits * nq);
+  FwdArgs a;
+  const int64_t n_partial = plan_forward(nq, nf, c128, max_partials, a);
+  double2* partial = ar.get<double2>((size_t)n_partial);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
   hipError_t e = launch_mesh_info_single(verts, vdtype, 3, nv, info, s);
   if (e == hipSuccess)
@@ -759,7 +769,6 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   else if (sort_q)
     st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s);
   if (st != PFT_OK) return st;
-  FwdArgs a;
   a.f64 = f64;
   a.f32 = f32;
   a.info = info;
@@ -768,8 +777,6 @@ pft_status forward3d_core(Arena& ar, const void* verts, int vdtype, int64_t nv, 
   a.qdtype = qdtype;
   a.nq = nq;
   a.perm = perm;
-  a.splits = splits;
-  a.faces_per_split = per;
   a.split_face = nullptr;
   a.partial = partial;
   a.out = out;
@@ -1312,10 +1319,8 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
   Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
   Face64* f64o = ordered ? ar.get<Face64>(nf) : f64;
   Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
-  int splits;
-  int64_t per;
-  choose_face_splits(nq, nf, c128 ? 1 : kQPT, &splits, &per);
-  double2* partial = ar.get<double2>((size_t)splits * nq);
+  FwdArgs a;
+  double2* partial = ar.get<double2>((size_t)plan_forward(nq, nf, c128, -1, a));
   QRec32* rec = c128 ? nullptr : ar.get<QRec32>(nq);
   QRec64* rec64 = c128 ? ar.get<QRec64>(nq) : nullptr;
   double* loss_part = ar.get<double>(loss_blocks(nq));
@@ -1329,7 +1334,6 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
   if (e != hipSuccess) return hip_fail(e, "loss prologue");
   uint32_t* perm = nullptr;
   if ((st = build_qorder(ar, q, qdtype, nq, nullptr, 1, &perm, s)) != PFT_OK) return st;
-  FwdArgs a;
   a.f64 = f64o;
   a.f32 = f32;
   a.info = info;
@@ -1338,8 +1342,6 @@ pft_status pft_intensity_loss_3d(const void* verts, pft_dtype vdtype, int64_t nv
   a.qdtype = qdtype;
   a.nq = nq;
   a.perm = perm;
-  a.splits = splits;
-  a.faces_per_split = per;
   a.split_face = nullptr;
   a.partial = partial;
   a.out = out;

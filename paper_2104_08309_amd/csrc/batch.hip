@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
     } else {
       // QPT Q per thread, strided by the block size
       Face32* tile = reinterpret_cast<Face32*>(smem);
-      double Qd[QPT][3];
+      QLow<QPT> ql;
       float qx[QPT], qy[QPT], qz[QPT], Q2[QPT];
       bool small[QPT], active[QPT];
       bool any_small = false;
@@ -76,20 +76,25 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
       for (int k = 0; k < QPT; ++k) {
         const int qo = lane + k * kBlock;
         active[k] = qo < it.nq;
-        Qd[k][0] = Qd[k][1] = Qd[k][2] = 0.0;
-        if (active[k]) load_q3(q, qdtype, perm ? (int64_t)perm[it.q0 + qo] : it.q0 + qo, Qd[k]);
-        qx[k] = (float)Qd[k][0];
-        qy[k] = (float)Qd[k][1];
-        qz[k] = (float)Qd[k][2];
+        double Qd[3] = {0.0, 0.0, 0.0};
+        if (active[k]) load_q3(q, qdtype, perm ? (int64_t)perm[it.q0 + qo] : it.q0 + qo, Qd);
+        qx[k] = (float)Qd[0];
+        qy[k] = (float)Qd[1];
+        qz[k] = (float)Qd[2];
+        ql.set(k, Qd, qx[k], qy[k], qz[k]);
         Q2[k] = qx[k] * qx[k] + qy[k] * qy[k] + qz[k] * qz[k];
-        const double Q2d = Qd[k][0] * Qd[k][0] + Qd[k][1] * Qd[k][1] + Qd[k][2] * Qd[k][2];
+        const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
         small[k] = sqrt(Q2d) * R < tau0;
         any_small |= small[k];
       }
-      float sr[QPT], si[QPT], cr[QPT], ci[QPT];
-      double xr[QPT], xi[QPT];
+      float qmax = 0.0f;
 #pragma unroll
-      for (int k = 0; k < QPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
+      for (int k = 0; k < QPT; ++k) qmax = fmaxf(qmax, sqrtf(Q2[k]));
+      const bool check =
+          __builtin_amdgcn_readfirstlane((int)sinc_range_test_needed(wave_max(qmax), info[it.mesh].rho)) != 0;
+      float sr[QPT], si[QPT], cr[QPT], ci[QPT];
+#pragma unroll
+      for (int k = 0; k < QPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f;
       FwdCarry<QPT> carry;  // shared edge term from the previous face of the item
       carry.reset();
       for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
@@ -101,18 +106,27 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* _
         float tr[QPT], ti[QPT];
 #pragma unroll
         for (int k = 0; k < QPT; ++k) tr[k] = ti[k] = 0.0f;
-        fwd_tile_fp32c<QPT, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, carry);
+        if (check)
+          fwd_tile_fp32c<QPT, SHARE, true>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
+        else
+          fwd_tile_fp32c<QPT, SHARE, false>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
 #pragma unroll
         for (int k = 0; k < QPT; ++k) {
           kahan_add(sr[k], cr[k], tr[k]);
           kahan_add(si[k], ci[k], ti[k]);
         }
-        if (any_small) {
+      }
+      // small-|Q| lanes: the binary64 tetrahedron fan over the item's faces, after the surface sums
+      double xr[QPT], xi[QPT];
 #pragma unroll
-          for (int k = 0; k < QPT; ++k)
-            if (small[k])
-              for (int j = 0; j < nt; ++j) tet_term_f64(f64[t0 + j], Qd[k], xr[k], xi[k], kZeroOrigin);
-        }
+      for (int k = 0; k < QPT; ++k) xr[k] = xi[k] = 0.0;
+      if (any_small) {
+#pragma unroll
+        for (int k = 0; k < QPT; ++k)
+          if (small[k]) {
+            const double Qd[3] = {ql.qd(qx[k], k, 0), ql.qd(qy[k], k, 1), ql.qd(qz[k], k, 2)};
+            for (int64_t j = it.f0; j < f_end; ++j) tet_term_f64(f64[j], Qd, xr[k], xi[k], kZeroOrigin);
+          }
       }
 #pragma unroll
       for (int k = 0; k < QPT; ++k) {

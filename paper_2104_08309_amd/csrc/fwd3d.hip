@@ -1,10 +1,11 @@
 // Forward 3D transform of a closed triangle mesh: F(Q) for a list of Q.
 //
-// Layout: one thread per Q (a Q-tile of 256 per block), faces streamed
-// through LDS in tiles of kTileF records and broadcast to the wavefront. The
-// face range can be split over blockIdx.y when there are too few Q to fill
-// the GPU; each split writes a binary64 partial sum, and the finish kernel
-// adds the splits in a fixed order and applies exp(i Q.t) / |Q|^2.
+// Layout: Q-tiles of threads (binary64: one Q per thread; FP32C: kQPT Q per
+// thread), faces streamed through LDS in tiles of kTileF records and broadcast
+// to the wavefront. Each block's sums over its face range are binary64
+// partials; the finish kernel adds a Q's partials in a fixed order and applies
+// exp(i Q.t) / |Q|^2. The faces are split over blockIdx.y when there are too
+// few Q to fill the GPU.
 //
 // Two arithmetic forms:
 //  * fwd3d_fp64_kernel  -- IEEE binary64 throughout.
@@ -79,20 +80,20 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
   if (active) store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qi, make_double2(xr, xi));
 }
 
-// Each thread evaluates kQPT Q points (strided by the block size, so loads stay
-// coalesced) against every face record it reads from LDS: the record is loaded
-// once per kQPT terms and the kQPT evaluations are independent instruction
-// streams the scheduler can interleave. SHARE: the records are in an
-// edge-sharing order and each face takes one edge term from its predecessor in
-// the split (two edge terms per face instead of three).
+// One work item of the FP32C forward: the Q-tile `qt` (kBlock * kQPT Q; each thread evaluates kQPT of
+// them, strided by the block size, so loads stay coalesced) against the faces [f_begin, f_end), written
+// to dst[local Q index of the tile]. The face record is read from LDS once per kQPT terms and the kQPT
+// evaluations are independent instruction streams the scheduler can interleave. SHARE: the records are
+// in an edge-sharing order and each face takes one edge term from its predecessor in the range (two
+// edge terms per face instead of three). geo: (x, y, z) the apex of the small-|Q| tetrahedron fan
+// relative to t and w the radius of the small-|Q| test; apex: whether that apex is not t.
 template <bool SHARE>
-__global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs a) {
-  __shared__ Face32 tile[kTileF];
-  const int64_t qbase = (int64_t)blockIdx.x * (kBlock * kQPT) + threadIdx.x;
-  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
+__device__ __forceinline__ void fwd3d_fp32c_item(const FwdArgs& a, Face32* tile, int64_t qt, int64_t f_begin,
+                                                 int64_t f_end, double2* dst, double4 geo, bool apex) {
+  const int64_t qbase = qt * (kBlock * kQPT) + threadIdx.x;
   const double R = geo.w;
   const double o[3] = {geo.x, geo.y, geo.z};
-  double Qd[kQPT][3];
+  QLow<kQPT> ql;
   float qx[kQPT], qy[kQPT], qz[kQPT], Q2[kQPT];
   bool small[kQPT], active[kQPT];
   bool any_small = false;
@@ -100,58 +101,82 @@ __global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs 
   for (int k = 0; k < kQPT; ++k) {
     const int64_t qi = qbase + (int64_t)k * kBlock;
     active[k] = qi < a.nq;
-    Qd[k][0] = Qd[k][1] = Qd[k][2] = 0.0;
-    if (active[k]) load_q3(a.q, a.qdtype, a.perm ? (int64_t)a.perm[qi] : qi, Qd[k]);
-    qx[k] = (float)Qd[k][0];
-    qy[k] = (float)Qd[k][1];
-    qz[k] = (float)Qd[k][2];
+    double Qd[3] = {0.0, 0.0, 0.0};
+    if (active[k]) load_q3(a.q, a.qdtype, a.perm ? (int64_t)a.perm[qi] : qi, Qd);
+    qx[k] = (float)Qd[0];
+    qy[k] = (float)Qd[1];
+    qz[k] = (float)Qd[2];
+    ql.set(k, Qd, qx[k], qy[k], qz[k]);
     Q2[k] = qx[k] * qx[k] + qy[k] * qy[k] + qz[k] * qz[k];
-    const double Q2d = Qd[k][0] * Qd[k][0] + Qd[k][1] * Qd[k][1] + Qd[k][2] * Qd[k][2];
+    const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
     small[k] = sqrt(Q2d) * R < a.tau0;
     any_small |= small[k];
   }
-  int64_t f_begin, f_end;
-  split_faces(a, f_begin, f_end);
-  float sr[kQPT], si[kQPT], cr[kQPT], ci[kQPT];
-  double xr[kQPT], xi[kQPT];
+  float qmax = 0.0f;
 #pragma unroll
-  for (int k = 0; k < kQPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f, xr[k] = xi[k] = 0.0;
+  for (int k = 0; k < kQPT; ++k) qmax = fmaxf(qmax, sqrtf(Q2[k]));
+  const bool check = __builtin_amdgcn_readfirstlane((int)sinc_range_test_needed(wave_max(qmax), a.info[0].rho)) != 0;
+  float sr[kQPT], si[kQPT], cr[kQPT], ci[kQPT];
+#pragma unroll
+  for (int k = 0; k < kQPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f;
   FwdCarry<kQPT> carry;  // shared edge term from the previous face (SHARE)
-  carry.reset();         // no previous face at the start of the split
+  carry.reset();         // no previous face at the start of the range
   for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
     const int nt = (int)min((int64_t)kTileF, f_end - t0);
     __syncthreads();
     {
       const uint4* src = reinterpret_cast<const uint4*>(a.f32 + t0);
-      uint4* dst = reinterpret_cast<uint4*>(tile);
-      for (int i = threadIdx.x; i < nt * (int)(sizeof(Face32) / 16); i += kBlock) dst[i] = src[i];
+      uint4* d = reinterpret_cast<uint4*>(tile);
+      for (int i = threadIdx.x; i < nt * (int)(sizeof(Face32) / 16); i += kBlock) d[i] = src[i];
     }
     __syncthreads();
     float tr[kQPT], ti[kQPT];
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
-    fwd_tile_fp32c<kQPT, SHARE>(tile, nt, qx, qy, qz, Q2, Qd, small, tr, ti, carry);
+    if (check)
+      fwd_tile_fp32c<kQPT, SHARE, true>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
+    else
+      fwd_tile_fp32c<kQPT, SHARE, false>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) {
       kahan_add(sr[k], cr[k], tr[k]);
       kahan_add(si[k], ci[k], ti[k]);
     }
-    if (any_small) {
+  }
+  // small-|Q| lanes: the binary64 tetrahedron fan over the range's faces, after the surface sums (the
+  // rare wavefronts that hold such a lane pay for it; the others keep no binary64 sums live above)
+  double xr[kQPT], xi[kQPT];
 #pragma unroll
-      for (int k = 0; k < kQPT; ++k)
-        if (small[k])
-          for (int j = 0; j < nt; ++j) tet_term_f64(a.f64[t0 + j], Qd[k], xr[k], xi[k], o);
-    }
+  for (int k = 0; k < kQPT; ++k) xr[k] = xi[k] = 0.0;
+  if (any_small) {
+#pragma unroll
+    for (int k = 0; k < kQPT; ++k)
+      if (small[k]) {
+        const double Qd[3] = {ql.qd(qx[k], k, 0), ql.qd(qy[k], k, 1), ql.qd(qz[k], k, 2)};
+        for (int64_t j = f_begin; j < f_end; ++j) tet_term_f64(a.f64[j], Qd, xr[k], xi[k], o);
+        if (apex) apex_phase(Qd, o, xr[k], xi[k]);
+      }
   }
 #pragma unroll
   for (int k = 0; k < kQPT; ++k) {
     if (active[k]) {
-      if (small[k] && a.split_geo) apex_phase(Qd[k], o, xr[k], xi[k]);
       const double2 v = small[k] ? make_double2(xr[k], xi[k])
                                  : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
-      store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qbase + (int64_t)k * kBlock, v);
+      store_stream(dst + threadIdx.x + k * kBlock, v);
     }
   }
+}
+
+// The FP32C forward: blockIdx.x is the Q-tile and blockIdx.y the face split.
+template <bool SHARE>
+__global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs a) {
+  __shared__ Face32 tile[kTileF];
+  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
+  int64_t f_begin, f_end;
+  split_faces(a, f_begin, f_end);
+  const int64_t qt = blockIdx.x;
+  fwd3d_fp32c_item<SHARE>(a, tile, qt, f_begin, f_end, a.partial + (int64_t)blockIdx.y * a.nq + qt * (kBlock * kQPT),
+                          geo, a.split_geo != nullptr);
 }
 
 // Sum the splits in order, apply exp(i Q.t) and 1/|Q|^2, write F and |F|^2 at
@@ -162,12 +187,8 @@ __global__ __launch_bounds__(256) void fwd3d_finish_kernel(FwdArgs a, int out_c1
   const int64_t dst = a.perm ? (int64_t)a.perm[qi] : qi;
   double Q[3];
   load_q3(a.q, a.qdtype, dst, Q);
-  double xr = 0.0, xi = 0.0;
-  for (int s = 0; s < a.splits; ++s) {
-    const double2 v = load_stream(a.partial + (int64_t)s * a.nq + qi);
-    xr += v.x;
-    xi += v.y;
-  }
+  double xr, xi;
+  fwd_partial_sum(a, qi, xr, xi);
   const MeshInfo mi = a.info[0];
   const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
   const bool small = sqrt(Q2) * mi.R < a.tau0;

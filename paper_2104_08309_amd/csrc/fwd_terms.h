@@ -65,21 +65,38 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 // ---------------------------------------------------------------------------
 // FP32-compensated per-(Q, face) term
 // ---------------------------------------------------------------------------
-// Per (Q, face), in binary32 on the record's face-local quantities:
-//   QN = Q.N, s_j = Q.(|N| e_j), |P|^2 = s1^2 + s2^2, w_l = P.d_l (w_2 = -w_0 - w_1),
-//   half-vertex phases p_k = Q.u_k / (4 pi) in turns (p_2 = -p_0 - p_1),
-//   eta_l = p_{l+1} - p_l, edge midpoint phase t_l = r - p_{l+2} with r = Q.g / (2 pi),
-//   E_l = 2 pi sinc(2 pi eta_l) exp(2 pi i t_l),  T = (QN / |P|^2) sum_l w_l E_l,
+// Per (Q, face), in binary32 on the record's face-local quantities (Face32):
+//   QN = Q.N' = Q.n/2, s_j = Q.e_j/2, |P'|^2 = s1^2 + s2^2 = |P|^2 / (4|N|^2),
+//   w_l = s2 al_l + s1 be_l = P.d_l / (4 pi |N|) (w_2 = -w_0 - w_1),
+//   edge half-phases eta_l = Q.d_l / (4 pi) = s1 al_l - s2 be_l in turns,
+//   half-vertex phases p_k = Q.u_k / (4 pi) (p_2 = -p_0 - p_1, eta_l = p_{l+1} - p_l),
+//   edge midpoint phase t_l = r - p_{l+2} with r = Q.g / (2 pi),
+//   E_l = 2 pi sinc(2 pi eta_l) exp(2 pi i t_l),  T = (QN / |P'|^2) sum_l w_l E_l,
 // the face term (Q.N)/|P|^2 exp(iQ.g) S of the 3D section written in turns. The
 // 2 pi sinc comes from sinc2pi_poly (no transcendental instruction) and the
 // midpoint exponentials from the hardware sine and cosine of turns.
 //
-// The origin phase r is formed in binary64 and reduced to [-1/2, 1/2] before it
-// is rounded to binary32. In an edge-sharing order (Face32::flags) edge 0 is the
-// previous record's edge 1, whose E is carried in registers: it depends only on
-// the edge (its midpoint, and |eta| since the sinc is even). Near-degenerate
-// pairs (Q nearly along the face normal, and empty faces) are replaced by the
-// face's simplex series in binary64.
+// Where the midpoint phases come from. In an edge-sharing order (Face32::flags)
+// edge 0 of a linked face is the previous record's edge 1: the same segment, so
+// the same midpoint. Its phase t_0 = r + p_0 + p_1 is carried in registers
+// (reduced to [-1/2, 1/2] turn), and the two new midpoint phases follow from it
+// and the face's own half-vertex phases without the origin phase:
+//   t_1 = t_0 - (2 p_0 + p_1) = t_0 - eta_2,   t_2 = t_0 + (-p_0 - 2 p_1) = t_0 + eta_1.
+// Each carried step rounds once in binary32 (at most 2^-25 turn for a phase in
+// [-1/2, 1/2]), so the chain is re-anchored every kAnchor faces: there, and at
+// every face that does not follow its predecessor across an edge, the origin
+// phase r = Q.g / (2 pi) is formed in binary64 and reduced to [-1/2, 1/2]
+// before it is rounded to binary32. The edge term sinc(eta) exp(i Q.m) of the
+// carried edge is carried too (its sinc and the cosine and sine of its
+// midpoint phase): it depends only on the edge, since the sinc is even.
+// Near-degenerate pairs (Q nearly along the face normal, and empty faces) are
+// replaced by the face's simplex series in binary64.
+
+#ifndef PFT_ANCHOR
+#define PFT_ANCHOR 64
+#endif
+constexpr int kAnchor = PFT_ANCHOR;  // faces between binary64 origin phases in a chain (divides kTileF)
+static_assert(kTileF % kAnchor == 0 && kAnchor % 2 == 0, "anchor interval: even, and divides the face tile");
 
 // Inputs of the binary64 series fix-up for one pair.
 struct SeriesInputs {
@@ -104,23 +121,68 @@ __device__ __forceinline__ void face_series_fp32c(const SeriesInputs& sd, float&
   Ti = (float)(-QN * (cf * sr - sf * si));
 }
 
-// What one thread carries from face to face within a face range.
+// What one thread carries from face to face within a face range: the edge 1 of
+// the previous record, as its 2 pi sinc(2 pi eta), the cosine and sine of its
+// midpoint phase, and that phase in turns reduced to [-1/2, 1/2].
 template <int NQ>
 struct FwdCarry {
-  float er[NQ], ei[NQ];  // E of the previous record's edge 1
+  float c[NQ], cs[NQ], sn[NQ], t[NQ];
   bool prev;             // there is a previous record in this range (uniform)
   __device__ __forceinline__ void reset() { prev = false; }
 };
 
+// The binary64 Q of a thread's NQ points held as binary32 pairs: Q = hi + lo with
+// hi = (float)Q (the binary32 Q of the edge arithmetic) and lo = (float)(Q - hi),
+// i.e. Q to 48 bits (relative error <= 2^-48), for the binary64 origin phase at
+// the anchors, in half the registers of a binary64 copy.
+template <int NQ>
+struct QLow {
+  float lo[NQ][3];
+  __device__ __forceinline__ void set(int k, const double* Q, float hx, float hy, float hz) {
+    lo[k][0] = (float)(Q[0] - (double)hx);
+    lo[k][1] = (float)(Q[1] - (double)hy);
+    lo[k][2] = (float)(Q[2] - (double)hz);
+  }
+  __device__ __forceinline__ double qd(float hi, int k, int j) const { return (double)hi + (double)lo[k][j]; }
+  // The same inside the face loop: the empty asm statement makes the pair opaque at the anchor, so the
+  // compiler forms the binary64 value there instead of hoisting nine binary64 registers out of the loop.
+  __device__ __forceinline__ double qd_here(float hi, int k, int j) const {
+    float h = hi, l = lo[k][j];
+    asm volatile("" : "+v"(h), "+v"(l));
+    return (double)h + (double)l;
+  }
+};
+
+// Largest |Q| over the wavefront's lanes (every lane gets the same value).
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Whether any edge half-phase |eta| = |Q.d| / (4 pi) of a wavefront can exceed
+// the polynomial sinc's range: |d| <= 2 rho for a face whose vertices lie within
+// rho of its centroid, so |eta| <= qmax rho / (2 pi). A wavefront that passes
+// this test never meets an argument beyond kSincPolyMax (1e-3 of margin for
+// rounding) and skips the per-lane range test; each lane's value is the same
+// either way.
+__device__ __forceinline__ bool sinc_range_test_needed(float qmax, double rho) {
+  return (double)qmax * rho * kInv2PiD > 0.999 * (double)kSincPolyMax;
+}
+
 // One face record against a thread's NQ Q points: adds each term to tr[k], ti[k]
-// (lanes with small[k] set are left for the caller's small-|Q| path).
-template <int NQ, bool SHARE>
+// (lanes with small[k] set are left for the caller's small-|Q| path). CHECK:
+// test each edge half-phase against the polynomial sinc's range; anchor: form
+// the origin phase in binary64 even when the face is linked. `cin` holds the
+// previous record's edge 1 (edge 0 of a linked face); the face's own edge 1 goes
+// to `cout` (SHARE only; the two may be the same object).
+template <int NQ, bool SHARE, bool CHECK>
 __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx, const float* qy, const float* qz,
-                                               const float* Q2, const double (*Qd)[3], const bool* small, float* tr,
-                                               float* ti, FwdCarry<NQ>& c) {
+                                               const float* Q2, const QLow<NQ>& ql, const bool* small, float* tr,
+                                               float* ti, bool anchor, FwdCarry<NQ>& cin, FwdCarry<NQ>& cout) {
   const uint32_t flags = __builtin_amdgcn_readfirstlane(f.flags);
-  const bool linked = SHARE && c.prev && (flags & kFaceLinked) != 0u;
-  float QN[NQ], P2[NQ], w0[NQ], w1[NQ], p0[NQ], p1[NQ], r[NQ], c1[NQ], c2[NQ];
+  const bool linked = SHARE && cin.prev && (flags & kFaceLinked) != 0u;
+  float QN[NQ], P2[NQ], w0[NQ], w1[NQ], x1[NQ], x2[NQ], c1[NQ], c2[NQ];
   float m = 0.0f;
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
@@ -130,89 +192,102 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
     P2[k] = s1 * s1 + s2 * s2;
     w0[k] = s2 * f.al[0] + s1 * f.be[0];
     w1[k] = s2 * f.al[1] + s1 * f.be[1];
-    p0[k] = s1 * f.ga[0] + s2 * f.de[0];
-    p1[k] = s1 * f.ga[1] + s2 * f.de[1];
-    // eta_1 = p_2 - p_1 and eta_2 = p_0 - p_2 with p_2 = -p_0 - p_1
-    const float x1 = fmaf(-2.0f, p1[k], -p0[k]), x2 = fmaf(2.0f, p0[k], p1[k]);
-    c1[k] = sinc2pi_poly(x1);
-    c2[k] = sinc2pi_poly(x2);
-    m = fmaxf(m, fmaxf(fabsf(x1), fabsf(x2)));
+    // edge half-phases eta_1, eta_2 (eta_0 = -eta_1 - eta_2)
+    x1[k] = s1 * f.al[1] - s2 * f.be[1];
+    x2[k] = s1 * f.al[2] - s2 * f.be[2];
+    c1[k] = sinc2pi_poly(x1[k]);
+    c2[k] = sinc2pi_poly(x2[k]);
+    if (CHECK) m = fmaxf(m, fmaxf(fabsf(x1[k]), fabsf(x2[k])));
   }
-  if (__builtin_expect(m > kSincPolyMax, 0)) {  // long edges at large |Q|: the sine quotient
+  if (CHECK && __builtin_expect(m > kSincPolyMax, 0)) {  // long edges at large |Q|: the sine quotient
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-      c1[k] = sinc2pi_wide(fmaf(-2.0f, p1[k], -p0[k]), c1[k]);
-      c2[k] = sinc2pi_wide(fmaf(2.0f, p0[k], p1[k]), c2[k]);
+      c1[k] = sinc2pi_wide(x1[k], c1[k]);
+      c2[k] = sinc2pi_wide(x2[k], c2[k]);
     }
   }
-#pragma unroll
-  for (int k = 0; k < NQ; ++k) {
-    const double ph = Qd[k][0] * f.gt[0] + Qd[k][1] * f.gt[1] + Qd[k][2] * f.gt[2];
-    r[k] = (float)(ph - rint(ph));
-  }
-  float e0r[NQ], e0i[NQ];
-  if (linked) {
+  // Edge 0 where it is not the carried edge: its midpoint phase t_0 = r + p_0 + p_1 = r + (eta_2 - eta_1)/3
+  // from the binary64 origin phase (also at an anchor, replacing the carried phase), and its term when
+  // unlinked.
+  if (!linked || anchor) {
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-      e0r[k] = c.er[k];
-      e0i[k] = c.ei[k];
+      const double ph =
+          ql.qd_here(qx[k], k, 0) * f.gt[0] + ql.qd_here(qy[k], k, 1) * f.gt[1] + ql.qd_here(qz[k], k, 2) * f.gt[2];
+      const float r = (float)(ph - rint(ph));
+      cin.t[k] = r + (x2[k] - x1[k]) * (1.0f / 3.0f);
     }
-  } else {  // edge 0 too (first face of a chain, or the list order)
-    float c0[NQ];
-    float m0 = 0.0f;
+    if (!linked) {  // first face of a chain, or the list order
+      float m0 = 0.0f;
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const float x0 = p1[k] - p0[k];
-      c0[k] = sinc2pi_poly(x0);
-      m0 = fmaxf(m0, fabsf(x0));
-    }
-    if (__builtin_expect(m0 > kSincPolyMax, 0)) {
+      for (int k = 0; k < NQ; ++k) {
+        const float x0 = -(x1[k] + x2[k]);
+        cin.c[k] = sinc2pi_poly(x0);
+        if (CHECK) m0 = fmaxf(m0, fabsf(x0));
+        cin.cs[k] = cos_turns(cin.t[k]);
+        cin.sn[k] = sin_turns(cin.t[k]);
+      }
+      if (CHECK && __builtin_expect(m0 > kSincPolyMax, 0)) {
 #pragma unroll
-      for (int k = 0; k < NQ; ++k) c0[k] = sinc2pi_wide(p1[k] - p0[k], c0[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const float t0 = r[k] + p0[k] + p1[k];
-      e0r[k] = c0[k] * cos_turns(t0);
-      e0i[k] = c0[k] * sin_turns(t0);
+        for (int k = 0; k < NQ; ++k) cin.c[k] = sinc2pi_wide(-(x1[k] + x2[k]), cin.c[k]);
+      }
     }
   }
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
-    const float t1 = r[k] - p0[k], t2 = r[k] - p1[k];
-    const float e1r = c1[k] * cos_turns(t1), e1i = c1[k] * sin_turns(t1);
-    const float e2r = c2[k] * cos_turns(t2), e2i = c2[k] * sin_turns(t2);
-    const float w2 = -(w0[k] + w1[k]);
-    const float Sr = w0[k] * e0r[k] + w1[k] * e1r + w2 * e2r;
-    const float Si = w0[k] * e0i[k] + w1[k] * e1i + w2 * e2i;
-    const float co = QN[k] * rcp_f(P2[k]);
-    float Tr = co * Sr, Ti = co * Si;
+    // t_1 = t_0 - eta_2, t_2 = t_0 + eta_1
+    const float t1 = cin.t[k] - x2[k], t2 = cin.t[k] + x1[k];
+    const float e1c = cos_turns(t1), e1s = sin_turns(t1);
+    const float e2c = cos_turns(t2), e2s = sin_turns(t2);
+    // w_l times the edge's sinc; w_2 = -(w_0 + w_1)
+    const float a0 = w0[k] * cin.c[k], a1 = w1[k] * c1[k], a2 = (w0[k] + w1[k]) * c2[k];
+    float Sr = a0 * cin.cs[k] + a1 * e1c - a2 * e2c;
+    float Si = a0 * cin.sn[k] + a1 * e1s - a2 * e2s;
+    float co = QN[k] * rcp_f(P2[k]);
     // |Q_perp| L < tau or |Q_perp| < tau_rel |Q| (and every pair of an empty face): the series
     if (P2[k] < fmaf(f.kap, Q2[k], f.thr) && !small[k]) {
+      // half-vertex phases from the edge half-phases: p_0 = (2 eta_2 + eta_1)/3, p_1 = -(2 eta_1 + eta_2)/3
       SeriesInputs sd;
-      sd.p0 = p0[k];
-      sd.p1 = p1[k];
-      sd.QN = QN[k];
-      sd.r = r[k];
-      face_series_fp32c(sd, Tr, Ti);
+      sd.p0 = (2.0f * x2[k] + x1[k]) * (1.0f / 3.0f);
+      sd.p1 = -(2.0f * x1[k] + x2[k]) * (1.0f / 3.0f);
+      sd.QN = QN[k] * f.nN;
+      sd.r = t1 + sd.p0;
+      face_series_fp32c(sd, Sr, Si);
+      co = 1.0f;
     }
-    tr[k] += Tr;
-    ti[k] += Ti;
-    c.er[k] = e1r;
-    c.ei[k] = e1i;
+    tr[k] = fmaf(co, Sr, tr[k]);
+    ti[k] = fmaf(co, Si, ti[k]);
+    if (SHARE) {
+      cout.c[k] = c1[k];
+      cout.cs[k] = e1c;
+      cout.sn[k] = e1s;
+      cout.t[k] = t1 - rintf(t1);
+    }
   }
-  c.prev = true;
+  cout.prev = true;
 }
 
 // One LDS tile of FP32C face records against the NQ Q points of a thread
 // (plain binary32 sums inside the tile). SHARE: the records are in an
-// edge-sharing order; `c` carries the shared edge's term and the origin phase
+// edge-sharing order; `c` carries the shared edge's term and midpoint phase
 // across faces and tiles of one face range (reset it at the range's start).
-template <int NQ, bool SHARE>
+// The origin phase is formed in binary64 at every kAnchor-th face of a tile.
+// Faces go in pairs that pass the carry between two register sets, so no copy
+// of it is needed from one face to the next.
+template <int NQ, bool SHARE, bool CHECK>
 __device__ __forceinline__ void fwd_tile_fp32c(const Face32* tile, int nt, const float* qx, const float* qy,
-                                               const float* qz, const float* Q2, const double (*Qd)[3],
+                                               const float* qz, const float* Q2, const QLow<NQ>& ql,
                                                const bool* small, float* tr, float* ti, FwdCarry<NQ>& c) {
-  for (int j = 0; j < nt; ++j) fwd_face_fp32c<NQ, SHARE>(tile[j], qx, qy, qz, Q2, Qd, small, tr, ti, c);
+  FwdCarry<NQ> d;
+  int j = 0;
+  for (; j + 2 <= nt; j += 2) {
+    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j], qx, qy, qz, Q2, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
+    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j + 1], qx, qy, qz, Q2, ql, small, tr, ti, false, d, c);
+  }
+  if (j < nt) {
+    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j], qx, qy, qz, Q2, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
+    c = d;
+  }
 }
 
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {

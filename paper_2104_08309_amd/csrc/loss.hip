@@ -4,7 +4,7 @@
 // g = dL/dRe F + i dL/dIm F = 4 w (|F|^2 - I) F. With F = exp(iQ.t) F_c (F_c the
 // transform of the mesh centred on t), the adjoint's centred cotangent is
 // g exp(-iQ.t) = 4 w (|F|^2 - I) F_c, and |F| = |F_c|: neither needs the
-// translation phase. The finish kernel below adds the face-split partials of
+// translation phase. The finish kernel below adds the forward's partials of
 // each Q in a fixed order (as the forward's finish), forms F_c, the loss term
 // and the cotangent in binary64, writes the adjoint's Q record in the visiting
 // order (so no separate gather is needed), optionally F and |F|^2 at the
@@ -28,12 +28,8 @@ __global__ __launch_bounds__(kLossBlock) void loss_finish_kernel(FwdArgs a, cons
     const int64_t dst = a.perm ? (int64_t)a.perm[qi] : qi;
     double Q[3];
     load_q3(a.q, a.qdtype, dst, Q);
-    double xr = 0.0, xi = 0.0;
-    for (int s = 0; s < a.splits; ++s) {
-      const double2 v = load_stream(a.partial + (int64_t)s * a.nq + qi);
-      xr += v.x;
-      xi += v.y;
-    }
+    double xr, xi;
+    fwd_partial_sum(a, qi, xr, xi);
     const MeshInfo mi = a.info[0];
     const double Q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
     if (!(sqrt(Q2) * mi.R < a.tau0)) {

@@ -68,6 +68,16 @@ __device__ __forceinline__ double2 load_stream(const double2* p) {
   return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
 }
 
+// Sum of the forward's binary64 partials (one per face split) of the visited Q number qi, in split order.
+__device__ __forceinline__ void fwd_partial_sum(const FwdArgs& a, int64_t qi, double& xr, double& xi) {
+  xr = xi = 0.0;
+  for (int s = 0; s < a.splits; ++s) {
+    const double2 v = load_stream(a.partial + (int64_t)s * a.nq + qi);
+    xr += v.x;
+    xi += v.y;
+  }
+}
+
 // sin(2 pi x), cos(2 pi x) for x in turns (hardware transcendental unit; valid for |x| <= 256).
 __device__ __forceinline__ float sin_turns(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ float cos_turns(float x) { return __builtin_amdgcn_cosf(x); }

@@ -123,27 +123,29 @@ static_assert(sizeof(Face64) == 128, "Face64 layout");
 // FP32C forward face record (staged in LDS). The in-plane geometry is held in
 // an orthonormal basis e1, e2 of the face plane (e1 along b - a, e2 = n x e1,
 // with a, b, c the vertices in the record's traversal order and n that order's
-// unit normal): with s_j = Q . (|N| e_j), the in-plane part of Q,
-// P = Q x N = s2 e1 - s1 e2, so |P|^2 = s1^2 + s2^2, P . d_l = s2 (e1 . d_l) - s1 (e2 . d_l)
-// and the half-vertex phases Q . u_k / 2 = s1 (e1 . u_k)/(2|N|) + s2 (e2 . u_k)/(2|N|).
+// unit normal). With the half components sigma_j = Q . e_j / 2 of the in-plane
+// part of Q, and the edge coefficients al_l = (e1 . d_l)/(2 pi), be_l = -(e2 . d_l)/(2 pi):
+//   eta_l = Q . d_l / (4 pi) = sigma1 al_l - sigma2 be_l      (edge half-phase, turns)
+//   w'_l = sigma2 al_l + sigma1 be_l = (P . d_l) / (4 pi |N|)  (P = Q x N; the edge weight)
+//   |P|^2 / (4 |N|^2) = sigma1^2 + sigma2^2,   Q . n / 2 = Q . N'  (N' = N / (2 |N|)),
+// so the face term (Q.N)/|P|^2 sum_l (P.d_l) E_l equals (Q.N')/(sigma1^2 + sigma2^2) sum_l w'_l E_l.
 // In an edge-sharing order the traversal may be the reverse of the outward
 // (counter-clockwise) one, so that the edge shared with the next face is edge
-// 1: the edge sum S is the same for both traversals (each edge's P . d and
-// sinc are unchanged when both the normal and the edge flip), and N below
-// stays the outward normal, so the face term (Q.N)/|P|^2 S is unchanged.
+// 1: the edge sum is the same for both traversals (each edge's P . d and
+// sinc are unchanged when both the normal and the edge flip), and N' below
+// stays the outward normal, so the face term is unchanged.
 struct alignas(16) Face32 {
   double gt[3];   // centroid / (2 pi), binary64: face origin phase in turns is Q . gt
-  float N[3];     // outward (b - a) x (c - a) of the counter-clockwise traversal, for Q.N
-  float E1[3];    // |N| e1
-  float E2[3];    // |N| e2
-  float al[2];    // (e1 . d_l) / (2 pi), l = 0, 1 (d_0 = b - a, d_1 = c - b)
-  float be[2];    // -(e2 . d_l) / (2 pi)
-  float ga[2];    // (e1 . u_k) / (4 pi |N|), k = 0, 1 (u_0 = a - g, u_1 = b - g)
-  float de[2];    // (e2 . u_k) / (4 pi |N|)
-  float thr;      // tau^2 |N|^2 / L^2 (1 for an empty face: its series term is Q.N = 0 times a sum)
-  float kap;      // tau_rel^2 |N|^2
+  float N[3];     // N' = N / (2 |N|), N the outward (b - a) x (c - a) of the counter-clockwise traversal
+  float E1[3];    // e1 / 2
+  float E2[3];    // e2 / 2
+  float al[3];    // (e1 . d_l) / (2 pi), l = 0, 1, 2 (d_0 = b - a, d_1 = c - b, d_2 = a - c)
+  float be[3];    // -(e2 . d_l) / (2 pi)
+  float thr;      // tau^2 / (4 L^2) (1 for an empty face: its series term is Q.N = 0 times a sum)
+  float kap;      // tau_rel^2 / 4
+  float nN;       // 2 |N| = 4 A: the series branch's Q . N = nN (Q . N')
   uint32_t flags; // kFaceLinked: edge 0 is the previous record's edge 1 (edge-sharing order)
-  float pad[2];
+  float pad[3];
 };
 static_assert(sizeof(Face32) == 112, "Face32 layout");
 constexpr uint32_t kFaceLinked = 1u;

@@ -410,43 +410,43 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
     d0[k] = u1[k] - u0[k];
     d1[k] = -u0[k] - 2.0 * u1[k];
   }
-  for (int k = 0; k < 3; ++k) {
-    r.gt[k] = f.g[k] * kInv2Pi;
-    r.N[k] = (float)f.N[k];
-  }
+  for (int k = 0; k < 3; ++k) r.gt[k] = f.g[k] * kInv2Pi;
   auto dot = [](const double* x, const double* y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
   const double nN = sqrt(N2), nd0 = sqrt(dot(d0, d0));
   if (ok && nd0 > 0.0) {
-    for (int k = 0; k < 3; ++k) e1[k] = d0[k] / nd0;
+    double d2[3];
+    for (int k = 0; k < 3; ++k) {
+      e1[k] = d0[k] / nd0;
+      d2[k] = -d0[k] - d1[k];
+    }
     // e2 = n x e1 = (N x d0) / (|N| |d0|), with the traversal's normal
     e2[0] = (Nt[1] * d0[2] - Nt[2] * d0[1]) / (nN * nd0);
     e2[1] = (Nt[2] * d0[0] - Nt[0] * d0[2]) / (nN * nd0);
     e2[2] = (Nt[0] * d0[1] - Nt[1] * d0[0]) / (nN * nd0);
     for (int k = 0; k < 3; ++k) {
-      r.E1[k] = (float)(nN * e1[k]);
-      r.E2[k] = (float)(nN * e2[k]);
+      r.N[k] = (float)(0.5 * f.N[k] / nN);
+      r.E1[k] = (float)(0.5 * e1[k]);
+      r.E2[k] = (float)(0.5 * e2[k]);
     }
-    r.al[0] = (float)(dot(e1, d0) * kInv2Pi);
-    r.al[1] = (float)(dot(e1, d1) * kInv2Pi);
-    r.be[0] = (float)(-dot(e2, d0) * kInv2Pi);
-    r.be[1] = (float)(-dot(e2, d1) * kInv2Pi);
-    r.ga[0] = (float)(dot(e1, u0) * kInv4Pi / nN);
-    r.ga[1] = (float)(dot(e1, u1) * kInv4Pi / nN);
-    r.de[0] = (float)(dot(e2, u0) * kInv4Pi / nN);
-    r.de[1] = (float)(dot(e2, u1) * kInv4Pi / nN);
-    r.thr = (float)(tau * tau * N2 / L2);
-    r.kap = (float)(tau_rel * tau_rel * N2);
+    const double* d[3] = {d0, d1, d2};
+    for (int l = 0; l < 3; ++l) {
+      r.al[l] = (float)(dot(e1, d[l]) * kInv2Pi);
+      r.be[l] = (float)(-dot(e2, d[l]) * kInv2Pi);
+    }
+    r.thr = (float)(0.25 * tau * tau / L2);
+    r.kap = (float)(0.25 * tau_rel * tau_rel);
+    r.nN = (float)(2.0 * nN);
     r.flags = link ? kFaceLinked : 0u;
   } else {
     // empty face: every weight is zero; thr > 0 sends every pair to the series, whose term is
     // Q.N = 0 times a finite sum, so its contribution is exactly zero (the edge form would be 0/0)
-    for (int k = 0; k < 3; ++k) r.N[k] = r.E1[k] = r.E2[k] = 0.0f;
-    r.al[0] = r.al[1] = r.be[0] = r.be[1] = r.ga[0] = r.ga[1] = r.de[0] = r.de[1] = 0.0f;
+    for (int k = 0; k < 3; ++k) r.N[k] = r.E1[k] = r.E2[k] = r.al[k] = r.be[k] = 0.0f;
     r.thr = 1.0f;
     r.kap = 0.0f;
+    r.nN = 0.0f;
     r.flags = 0u;
   }
-  r.pad[0] = r.pad[1] = 0.0f;
+  r.pad[0] = r.pad[1] = r.pad[2] = 0.0f;
   out[m] = r;
 }
 
