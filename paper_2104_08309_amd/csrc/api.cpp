@@ -269,14 +269,16 @@ int time_candidates(int n, F run, hipStream_t s, std::vector<float>& ms) {
   return best;
 }
 
-void choose_face_splits(int64_t nq, int64_t nf, int qpt, int* splits, int64_t* per) {
+// Face splits of a Q-parallel forward whose blocks hold qtile Q each: about kTargetBlocks blocks, with
+// at least min_faces faces per split.
+void choose_face_splits(int64_t nq, int64_t nf, int64_t qtile, int64_t min_faces, int* splits, int64_t* per) {
   if (nf <= 0) {
     *splits = 1;
     *per = 0;
     return;
   }
-  const int64_t qblocks = cdiv(nq, (int64_t)kBlock * qpt);
-  int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, qblocks), cdiv(nf, kMinFacesPerSplit)));
+  const int64_t qblocks = cdiv(nq, qtile);
+  int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, qblocks), cdiv(nf, min_faces)));
   int64_t p = cdiv(cdiv(nf, s), kTileF) * kTileF;
   *per = p;
   *splits = (int)cdiv(nf, p);
@@ -287,7 +289,8 @@ void choose_face_splits(int64_t nq, int64_t nf, int qpt, int* splits, int64_t* p
 int64_t plan_forward(int64_t nq, int64_t nf, bool c128, int64_t max_partials, FwdArgs& a) {
   int splits;
   int64_t per;
-  choose_face_splits(nq, nf, c128 ? 1 : kQPT, &splits, &per);
+  choose_face_splits(nq, nf, c128 ? kBlock : kFwdQTile, c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves,
+                     &splits, &per);
   if (max_partials > 0 && (int64_t)splits * nq > max_partials && nf > 0) {
     const int64_t cap = std::max<int64_t>(1, max_partials / nq);
     per = cdiv(cdiv(nf, cap), kTileF) * kTileF;
@@ -836,12 +839,13 @@ pft_status region_radii(Arena& ar, const int64_t* off, int64_t nreg, const Face6
   return e == hipSuccess ? PFT_OK : hip_fail(e, "region radii");
 }
 
-pft_status plan_regions(Arena& ar, const int64_t* off, int64_t nreg, int64_t nq, int qpt, RegionPlan& p,
+pft_status plan_regions(Arena& ar, const int64_t* off, int64_t nreg, int64_t nq, int64_t qtile, int64_t min_faces,
+                        RegionPlan& p,
                         hipStream_t s) {
   const int64_t nf = off[nreg];
   int s0 = 0;
   int64_t per = 0;
-  choose_face_splits(nq, nf, qpt, &s0, &per);
+  choose_face_splits(nq, nf, qtile, min_faces, &s0, &per);
   if (per <= 0) per = kTileF;
   for (int64_t j = 0; j < nreg; ++j) {
     p.region_split.push_back((int32_t)p.split_face.size());
@@ -1415,7 +1419,8 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   ensure_pool();
   Arena ar(s);
   RegionPlan plan;
-  if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? 1 : kQPT, plan, s)) != PFT_OK) return st;
+  if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : kFwdQTile,
+                           c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves, plan, s)) != PFT_OK) return st;
   MeshInfo* info = ar.get<MeshInfo>(1);
   Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
   Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
@@ -1573,7 +1578,8 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
   if (want_q) {
     // dL/dQ (and dL/drho from the same partials): the grad_Q kernel
     RegionPlan plan;
-    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? 1 : kQPTDQ, plan, s)) != PFT_OK) return st;
+    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : (int64_t)kBlock * kQPTDQ, kMinFacesPerSplit, plan,
+                             s)) != PFT_OK) return st;
     double2* partial = ar.get<double2>((size_t)std::max(plan.splits, 1) * 4 * nq);
     if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
     DqArgs d;
@@ -1609,7 +1615,8 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
   } else {
     // dL/drho only: the forward's partials per region
     RegionPlan plan;
-    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? 1 : kQPT, plan, s)) != PFT_OK) return st;
+    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : kFwdQTile,
+                           c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves, plan, s)) != PFT_OK) return st;
     Face32* f32 = c128 ? nullptr : ar.get<Face32>(nf);
     double2* partial = ar.get<double2>((size_t)std::max(plan.splits, 1) * nq);
     if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
@@ -1797,7 +1804,7 @@ static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, voi
       pairs += (double)(b->tri_offsets[i + 1] - b->tri_offsets[i]) * (double)(b->q_offsets[i + 1] - b->q_offsets[i]);
     key = tune_key("batch_forward", mode, share, n, pairs, p.nf);
     if (!tuned_tiles(key, &chosen))
-      for (int qpt : {1, 2})
+      for (int qpt : {1, 2, 3})
         for (int64_t cf : {2048, 4096, 8192}) {
           BatchTiles t;
           t.qpt = qpt;

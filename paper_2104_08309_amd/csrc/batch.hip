@@ -23,8 +23,9 @@ __device__ __forceinline__ int64_t next_item(uint32_t* counter, int* slot) {
   return it;
 }
 
+// QPT = 3 keeps the single-mesh forward's register budget (kFwdWaves waves per SIMD); 1 and 2 fit more.
 template <int MODE, bool SHARE = false, int QPT = 1>
-__global__ __launch_bounds__(kBlock) void batch_fwd_kernel(const BatchItemFwd* __restrict__ items, int64_t n_items,
+__global__ __launch_bounds__(kBlock, QPT >= 3 ? kFwdWaves : 1) void batch_fwd_kernel(const BatchItemFwd* __restrict__ items, int64_t n_items,
                                                           uint32_t* counter, const Face64* __restrict__ f64,
                                                           const Face32* __restrict__ f32, const void* q, int qdtype,
                                                           const uint32_t* __restrict__ perm, double2* partial,

@@ -1,9 +1,10 @@
 // Forward 3D transform of a closed triangle mesh: F(Q) for a list of Q.
 //
 // Layout: Q-tiles of threads (binary64: one Q per thread; FP32C: kQPT Q per
-// thread), faces streamed through LDS in tiles of kTileF records and broadcast
-// to the wavefront. Each block's sums over its face range are binary64
-// partials; the finish kernel adds a Q's partials in a fixed order and applies
+// thread, each wavefront of a block on its own share of the faces), faces
+// streamed through LDS in tiles of kTileF records and broadcast to the
+// wavefront. Each block's sums over its face range are binary64 partials; the
+// finish kernel adds a Q's partials in a fixed order and applies
 // exp(i Q.t) / |Q|^2. The faces are split over blockIdx.y when there are too
 // few Q to fill the GPU.
 //
@@ -80,26 +81,41 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
   if (active) store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qi, make_double2(xr, xi));
 }
 
-// One work item of the FP32C forward: the Q-tile `qt` (kBlock * kQPT Q; each thread evaluates kQPT of
-// them, strided by the block size, so loads stay coalesced) against the faces [f_begin, f_end), written
-// to dst[local Q index of the tile]. The face record is read from LDS once per kQPT terms and the kQPT
-// evaluations are independent instruction streams the scheduler can interleave. SHARE: the records are
-// in an edge-sharing order and each face takes one edge term from its predecessor in the range (two
-// edge terms per face instead of three). geo: (x, y, z) the apex of the small-|Q| tetrahedron fan
-// relative to t and w the radius of the small-|Q| test; apex: whether that apex is not t.
+// The FP32C forward. A block holds one Q-tile of kFwdQTile = 64 kQPT Q, the same in each of its
+// kFwdSplitWaves wavefronts (lane l holds the tile's Q l, l + 64, ...; kQPT per thread, so each face
+// record read from LDS serves kQPT independent instruction streams), and blockIdx.y names a face split.
+// Each wavefront takes its own contiguous share of the split's faces and streams them through its own
+// LDS tile of kTileF records, with wavefront-local ordering only: no block barrier inside the face
+// loop. At the end the wavefronts' binary64 partials of each Q are added in wavefront order, so a
+// block writes one partial per Q, as a block of the split layout did. SHARE: the records are in an
+// edge-sharing order and each face takes one edge term from its predecessor in the wavefront's range
+// (two edge terms per face instead of three). Small-|Q| lanes (|Q| R < tau0, R the split's radius) take
+// the binary64 tetrahedron fan about the split's apex.
 template <bool SHARE>
-__device__ __forceinline__ void fwd3d_fp32c_item(const FwdArgs& a, Face32* tile, int64_t qt, int64_t f_begin,
-                                                 int64_t f_end, double2* dst, double4 geo, bool apex) {
-  const int64_t qbase = qt * (kBlock * kQPT) + threadIdx.x;
+__global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs a) {
+  static_assert(kBlock == 64 * kFwdSplitWaves, "one wavefront per share of the split");
+  __shared__ Face32 tiles[kFwdSplitWaves][kTileF];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  Face32* tile = tiles[w];
+  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
   const double R = geo.w;
   const double o[3] = {geo.x, geo.y, geo.z};
+  int64_t f_begin, f_end;
+  split_faces(a, f_begin, f_end);
+  {  // this wavefront's share
+    const int64_t per = (f_end - f_begin + kFwdSplitWaves - 1) / kFwdSplitWaves;
+    const int64_t b = min(f_end, f_begin + w * per);
+    f_end = min(f_end, b + per);
+    f_begin = b;
+  }
+  const int64_t qbase = (int64_t)blockIdx.x * kFwdQTile + lane;
   QLow<kQPT> ql;
   float qx[kQPT], qy[kQPT], qz[kQPT], Q2[kQPT];
   bool small[kQPT], active[kQPT];
   bool any_small = false;
 #pragma unroll
   for (int k = 0; k < kQPT; ++k) {
-    const int64_t qi = qbase + (int64_t)k * kBlock;
+    const int64_t qi = qbase + (int64_t)k * 64;
     active[k] = qi < a.nq;
     double Qd[3] = {0.0, 0.0, 0.0};
     if (active[k]) load_q3(a.q, a.qdtype, a.perm ? (int64_t)a.perm[qi] : qi, Qd);
@@ -123,13 +139,15 @@ __device__ __forceinline__ void fwd3d_fp32c_item(const FwdArgs& a, Face32* tile,
   carry.reset();         // no previous face at the start of the range
   for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
     const int nt = (int)min((int64_t)kTileF, f_end - t0);
-    __syncthreads();
+    // the wavefront's previous tile has been read (its LDS reads were issued in order before these
+    // writes); its writes are complete before any lane reads the tile
+    wave_lds_fence();
     {
       const uint4* src = reinterpret_cast<const uint4*>(a.f32 + t0);
       uint4* d = reinterpret_cast<uint4*>(tile);
-      for (int i = threadIdx.x; i < nt * (int)(sizeof(Face32) / 16); i += kBlock) d[i] = src[i];
+      for (int i = lane; i < nt * (int)(sizeof(Face32) / 16); i += 64) d[i] = src[i];
     }
-    __syncthreads();
+    wave_lds_fence();
     float tr[kQPT], ti[kQPT];
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
@@ -154,29 +172,31 @@ __device__ __forceinline__ void fwd3d_fp32c_item(const FwdArgs& a, Face32* tile,
       if (small[k]) {
         const double Qd[3] = {ql.qd(qx[k], k, 0), ql.qd(qy[k], k, 1), ql.qd(qz[k], k, 2)};
         for (int64_t j = f_begin; j < f_end; ++j) tet_term_f64(a.f64[j], Qd, xr[k], xi[k], o);
-        if (apex) apex_phase(Qd, o, xr[k], xi[k]);
+        if (a.split_geo) apex_phase(Qd, o, xr[k], xi[k]);
       }
   }
+  // the wavefronts' partials of each Q, added in wavefront order
+  __syncthreads();  // every wavefront is done with its tile
+  double2* red = reinterpret_cast<double2*>(&tiles[0][0]);
+  static_assert(sizeof(tiles) >= sizeof(double2) * kFwdSplitWaves * kQPT * 64, "reduction fits the tiles");
 #pragma unroll
-  for (int k = 0; k < kQPT; ++k) {
-    if (active[k]) {
-      const double2 v = small[k] ? make_double2(xr[k], xi[k])
-                                 : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
-      store_stream(dst + threadIdx.x + k * kBlock, v);
+  for (int k = 0; k < kQPT; ++k)
+    red[(w * kQPT + k) * 64 + lane] = small[k] ? make_double2(xr[k], xi[k])
+                                               : make_double2((double)sr[k] - (double)cr[k],
+                                                              (double)si[k] - (double)ci[k]);
+  __syncthreads();
+  for (int j = (int)threadIdx.x; j < kFwdQTile; j += kBlock) {  // j = k * 64 + lane of the tile
+    const int64_t qi = (int64_t)blockIdx.x * kFwdQTile + j;
+    if (qi >= a.nq) continue;
+    const int k = j >> 6, l = j & 63;
+    double2 v = red[k * 64 + l];
+    for (int u = 1; u < kFwdSplitWaves; ++u) {
+      const double2 x = red[(u * kQPT + k) * 64 + l];
+      v.x += x.x;
+      v.y += x.y;
     }
+    store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qi, v);
   }
-}
-
-// The FP32C forward: blockIdx.x is the Q-tile and blockIdx.y the face split.
-template <bool SHARE>
-__global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs a) {
-  __shared__ Face32 tile[kTileF];
-  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
-  int64_t f_begin, f_end;
-  split_faces(a, f_begin, f_end);
-  const int64_t qt = blockIdx.x;
-  fwd3d_fp32c_item<SHARE>(a, tile, qt, f_begin, f_end, a.partial + (int64_t)blockIdx.y * a.nq + qt * (kBlock * kQPT),
-                          geo, a.split_geo != nullptr);
 }
 
 // Sum the splits in order, apply exp(i Q.t) and 1/|Q|^2, write F and |F|^2 at
@@ -219,7 +239,7 @@ hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s) {
-  dim3 grid((unsigned)((a.nq + kBlock * kQPT - 1) / (kBlock * kQPT)), (unsigned)a.splits);
+  dim3 grid((unsigned)((a.nq + kFwdQTile - 1) / kFwdQTile), (unsigned)a.splits);
   if (a.share_edges)
     fwd3d_fp32c_kernel<true><<<grid, kBlock, 0, s>>>(a);
   else

@@ -153,6 +153,15 @@ struct QLow {
   }
 };
 
+// Orders a wavefront's LDS accesses around a tile it stages for itself: its stores are complete before
+// any lane reads, and its earlier reads before it overwrites (a wavefront's LDS instructions execute in
+// order; the fence also keeps the compiler from moving accesses across it).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Largest |Q| over the wavefront's lanes (every lane gets the same value).
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll

@@ -23,6 +23,8 @@ constexpr int kTileFB = 8;         // faces per block in the binary64 adjoint
 #define PFT_QPT 3
 #endif
 constexpr int kQPT = PFT_QPT;      // Q per thread in the FP32C forward
+constexpr int kFwdSplitWaves = kBlock / 64;     // wavefronts of an FP32C forward block, each on its own faces
+constexpr int kFwdQTile = 64 * kQPT;            // Q of an FP32C forward block (shared by its wavefronts)
 #ifndef PFT_FWD_WAVES
 #define PFT_FWD_WAVES 4
 #endif
