@@ -34,6 +34,11 @@ enum Op {
   kMul,          // v_mul_f32
   kAdd,          // v_add_f32
   kFmaSgpr,      // v_fma_f32 with a wave-uniform (SGPR) operand
+  kFmaVop3,      // v_fma_f32 (VOP3 encoding: destination not the addend), all operands in VGPRs
+  kFmacSgpr,     // v_fmac_f32 (VOP2) with its first source a wave-uniform (SGPR) value
+  kFmaak,        // v_fmaak_f32 (VOP2 with a literal addend)
+  kMulNeg,       // v_mul_f32 in its VOP3 encoding with a negated source
+  kFmaNegInl,    // v_fma_f32 (VOP3) with an inline constant and a negated source
   kSin,          // v_sin_f32 (argument in turns)
   kCos,          // v_cos_f32
   kRcp,          // v_rcp_f32
@@ -64,6 +69,11 @@ __global__ __launch_bounds__(kBlock) void f32_kernel(float* out, unsigned long l
       if (OP == kMul) a[j] = a[j] * b[j];
       if (OP == kAdd) a[j] = a[j] + c[j];
       if (OP == kFmaSgpr) a[j] = fmaf(a[j], b[j], s1);
+      if (OP == kFmaVop3) a[j] = fmaf(a[j], b[j], c[j]);
+      if (OP == kFmacSgpr) a[j] = fmaf(s1, b[j], a[j]);
+      if (OP == kFmaak) a[j] = fmaf(a[j], b[j], 0.1234567f);
+      if (OP == kMulNeg) a[j] = (-a[j]) * b[j];
+      if (OP == kFmaNegInl) a[j] = fmaf(-2.0f, a[j], -c[j]);
       if (OP == kSin) a[j] = __builtin_amdgcn_sinf(a[j]);
       if (OP == kCos) a[j] = __builtin_amdgcn_cosf(a[j]);
       if (OP == kRcp) a[j] = __builtin_amdgcn_rcpf(a[j]);
@@ -183,6 +193,11 @@ int main(int argc, char** argv) {
   run(d, "v_mul_f32", f32_kernel<kMul>, iters, ops_per_iter(kMul));
   run(d, "v_add_f32", f32_kernel<kAdd>, iters, ops_per_iter(kAdd));
   run(d, "v_fma_f32 (one SGPR operand)", f32_kernel<kFmaSgpr>, iters, ops_per_iter(kFmaSgpr));
+  run(d, "v_fma_f32 (VOP3, VGPR operands)", f32_kernel<kFmaVop3>, iters, ops_per_iter(kFmaVop3));
+  run(d, "v_fmac_f32 (SGPR first source)", f32_kernel<kFmacSgpr>, iters, ops_per_iter(kFmacSgpr));
+  run(d, "v_fmaak_f32 (literal addend)", f32_kernel<kFmaak>, iters, ops_per_iter(kFmaak));
+  run(d, "v_mul_f32_e64 (negated source)", f32_kernel<kMulNeg>, iters, ops_per_iter(kMulNeg));
+  run(d, "v_fma_f32 (inline const, neg)", f32_kernel<kFmaNegInl>, iters, ops_per_iter(kFmaNegInl));
   run(d, "v_sin_f32", f32_kernel<kSin>, iters, ops_per_iter(kSin));
   run(d, "v_cos_f32", f32_kernel<kCos>, iters, ops_per_iter(kCos));
   run(d, "v_rcp_f32", f32_kernel<kRcp>, iters, ops_per_iter(kRcp));
