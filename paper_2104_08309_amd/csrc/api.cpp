@@ -1762,7 +1762,7 @@ static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, voi
     q_part.assign(n, 0);
     q_chunks.assign(n, 1);
     int64_t P = 0;
-    const int64_t qtile = c128 ? kBlock : (int64_t)kBlock * t.qpt;  // Q per item (one block)
+    const int64_t qtile = c128 ? kBlock : (int64_t)64 * t.qpt;  // Q per item (a block in binary64, a wavefront in FP32C)
     for (int64_t i = 0; i < n; ++i) {
       const int64_t nqi = b->q_offsets[i + 1] - b->q_offsets[i];
       const int64_t nfi = b->tri_offsets[i + 1] - b->tri_offsets[i];

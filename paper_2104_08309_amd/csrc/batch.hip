@@ -1,11 +1,12 @@
 // Batched transform of many independent meshes in one persistent launch.
 //
-// The host cuts every mesh into work items -- (mesh, Q-tile of <= 256 Q,
-// face chunk) for the forward, (mesh, face tile of <= kTileFB faces, Q chunk)
-// for the adjoint -- and orders them by decreasing cost (longest processing
-// time first). A grid sized to the GPU's resident capacity pulls items from a
-// device counter until the list is exhausted; every block reaches the exit
-// test on each iteration, so the grid always drains. Each item writes its own
+// The host cuts every mesh into work items -- (mesh, Q-tile, face chunk) for
+// the forward, (mesh, face tile of <= kTileFB faces, Q chunk) for the adjoint
+// -- and orders them by decreasing cost (longest processing time first). A
+// grid sized to the GPU's resident capacity pulls items from a device counter
+// until the list is exhausted (the FP32C forward per wavefront, the others per
+// block); every puller reaches the exit test on each iteration, so the grid
+// always drains. Each item writes its own
 // partial slot, and a finish kernel adds the partials of each Q (or face) in a
 // fixed order, so results do not depend on which block ran which item.
 #include "adj_terms.h"
@@ -23,14 +24,15 @@ __device__ __forceinline__ int64_t next_item(uint32_t* counter, int* slot) {
   return it;
 }
 
-// QPT = 3 keeps the single-mesh forward's register budget (kFwdWaves waves per SIMD); 1 and 2 fit more.
-template <int MODE, bool SHARE = false, int QPT = 1>
-__global__ __launch_bounds__(kBlock, QPT >= 3 ? kFwdWaves : 1) void batch_fwd_kernel(const BatchItemFwd* __restrict__ items, int64_t n_items,
-                                                          uint32_t* counter, const Face64* __restrict__ f64,
-                                                          const Face32* __restrict__ f32, const void* q, int qdtype,
-                                                          const uint32_t* __restrict__ perm, double2* partial,
-                                                          const MeshInfo* __restrict__ info, double tau0) {
-  __shared__ __align__(16) unsigned char smem[kTileF * sizeof(Face64)];
+// The binary64 batched forward: blocks pull (mesh, Q-tile of kBlock Q, face chunk) items, one Q per
+// thread, the chunk's faces staged through LDS for the whole block.
+__global__ __launch_bounds__(kBlock) void batch_fwd_fp64_kernel(const BatchItemFwd* __restrict__ items,
+                                                               int64_t n_items, uint32_t* counter,
+                                                               const Face64* __restrict__ f64, const void* q,
+                                                               int qdtype, const uint32_t* __restrict__ perm,
+                                                               double2* partial, const MeshInfo* __restrict__ info,
+                                                               double tau0) {
+  __shared__ Face64 tile[kTileF];
   __shared__ int slot;
   for (;;) {
     const int64_t idx = next_item(counter, &slot);
@@ -39,103 +41,125 @@ __global__ __launch_bounds__(kBlock, QPT >= 3 ? kFwdWaves : 1) void batch_fwd_ke
     const int lane = threadIdx.x;
     const int64_t f_end = it.f0 + it.nf;
     const double R = info[it.mesh].R;
-    if (MODE == PFT_FP64) {
-      // one Q per thread
-      const bool active = lane < it.nq;
+    const bool active = lane < it.nq;
+    double Qd[3] = {0.0, 0.0, 0.0};
+    if (active) load_q3(q, qdtype, perm ? (int64_t)perm[it.q0 + lane] : it.q0 + lane, Qd);
+    const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
+    const bool small = sqrt(Q2d) * R < tau0;
+    double xr = 0.0, xi = 0.0;
+    for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
+      const int nt = (int)min((int64_t)kTileF, f_end - t0);
+      __syncthreads();
+      for (int i = lane; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
+        reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f64 + t0)[i];
+      __syncthreads();
+      if (!small) {
+        for (int j = 0; j < nt; ++j) {
+          double Tr, Ti;
+          face_term_f64(tile[j], Qd, Tr, Ti);
+          xr += Tr;
+          xi += Ti;
+        }
+      } else {
+        for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Qd, xr, xi, kZeroOrigin);
+      }
+    }
+    if (active) store_stream(partial + it.part + lane, make_double2(xr, xi));
+  }
+}
+
+// The next work item of a wavefront (one lane takes it from the counter, every lane gets it).
+__device__ __forceinline__ int64_t wave_next_item(uint32_t* counter) {
+  int idx = 0;
+  if ((threadIdx.x & 63) == 0) idx = (int)atomicAdd(counter, 1u);
+  return (int64_t)(uint32_t)__shfl(idx, 0);
+}
+
+// The FP32C batched forward: every wavefront is an independent worker. It pulls (mesh, Q-tile of 64 QPT
+// Q, face chunk) items from the counter (longest first), holds QPT Q per lane (strided by 64), streams the
+// chunk's faces through its own LDS tile with wavefront-local ordering and writes its binary64 partials;
+// no block barrier anywhere, so a wavefront never waits for the others of its block. QPT = 2 and 3 keep
+// the single-mesh forward's register budget (kFwdWaves waves per SIMD), QPT = 1 one wavefront more.
+template <bool SHARE, int QPT>
+__global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void batch_fwd_fp32c_kernel(
+    const BatchItemFwd* __restrict__ items, int64_t n_items, uint32_t* counter, const Face64* __restrict__ f64,
+    const Face32* __restrict__ f32, const void* q, int qdtype, const uint32_t* __restrict__ perm, double2* partial,
+    const MeshInfo* __restrict__ info, double tau0) {
+  __shared__ Face32 tiles[kBlock / 64][kTileF];
+  const int lane = (int)(threadIdx.x & 63);
+  Face32* tile = tiles[threadIdx.x >> 6];
+  for (;;) {
+    const int64_t idx = wave_next_item(counter);
+    if (idx >= n_items) break;
+    const BatchItemFwd it = items[idx];
+    const int64_t f_end = it.f0 + it.nf;
+    const MeshInfo& mi = info[it.mesh];
+    const double R = mi.R;
+    QLow<QPT> ql;
+    float qx[QPT], qy[QPT], qz[QPT], Q2[QPT];
+    bool small[QPT], active[QPT];
+    bool any_small = false;
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) {
+      const int qo = lane + k * 64;
+      active[k] = qo < it.nq;
       double Qd[3] = {0.0, 0.0, 0.0};
-      if (active) load_q3(q, qdtype, perm ? (int64_t)perm[it.q0 + lane] : it.q0 + lane, Qd);
+      if (active[k]) load_q3(q, qdtype, perm ? (int64_t)perm[it.q0 + qo] : it.q0 + qo, Qd);
+      qx[k] = (float)Qd[0];
+      qy[k] = (float)Qd[1];
+      qz[k] = (float)Qd[2];
+      ql.set(k, Qd, qx[k], qy[k], qz[k]);
+      Q2[k] = qx[k] * qx[k] + qy[k] * qy[k] + qz[k] * qz[k];
       const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
-      const bool small = sqrt(Q2d) * R < tau0;
-      Face64* tile = reinterpret_cast<Face64*>(smem);
-      double xr = 0.0, xi = 0.0;
-      for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
-        const int nt = (int)min((int64_t)kTileF, f_end - t0);
-        __syncthreads();
-        for (int i = lane; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
-          reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f64 + t0)[i];
-        __syncthreads();
-        if (!small) {
-          for (int j = 0; j < nt; ++j) {
-            double Tr, Ti;
-            face_term_f64(tile[j], Qd, Tr, Ti);
-            xr += Tr;
-            xi += Ti;
-          }
-        } else {
-          for (int j = 0; j < nt; ++j) tet_term_f64(tile[j], Qd, xr, xi, kZeroOrigin);
-        }
-      }
-      if (active) store_stream(partial + it.part + lane, make_double2(xr, xi));
-    } else {
-      // QPT Q per thread, strided by the block size
-      Face32* tile = reinterpret_cast<Face32*>(smem);
-      QLow<QPT> ql;
-      float qx[QPT], qy[QPT], qz[QPT], Q2[QPT];
-      bool small[QPT], active[QPT];
-      bool any_small = false;
+      small[k] = sqrt(Q2d) * R < tau0;
+      any_small |= small[k];
+    }
+    float qmax = 0.0f;
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) qmax = fmaxf(qmax, sqrtf(Q2[k]));
+    const bool check = __builtin_amdgcn_readfirstlane((int)sinc_range_test_needed(wave_max(qmax), mi.rho)) != 0;
+    float sr[QPT], si[QPT], cr[QPT], ci[QPT];
+#pragma unroll
+    for (int k = 0; k < QPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f;
+    FwdCarry<QPT> carry;  // shared edge term from the previous face of the item
+    carry.reset();
+    for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
+      const int nt = (int)min((int64_t)kTileF, f_end - t0);
+      wave_lds_fence();
+      for (int i = lane; i < nt * (int)(sizeof(Face32) / 16); i += 64)
+        reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f32 + t0)[i];
+      wave_lds_fence();
+      float tr[QPT], ti[QPT];
+#pragma unroll
+      for (int k = 0; k < QPT; ++k) tr[k] = ti[k] = 0.0f;
+      if (check)
+        fwd_tile_fp32c<QPT, SHARE, true>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
+      else
+        fwd_tile_fp32c<QPT, SHARE, false>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
 #pragma unroll
       for (int k = 0; k < QPT; ++k) {
-        const int qo = lane + k * kBlock;
-        active[k] = qo < it.nq;
-        double Qd[3] = {0.0, 0.0, 0.0};
-        if (active[k]) load_q3(q, qdtype, perm ? (int64_t)perm[it.q0 + qo] : it.q0 + qo, Qd);
-        qx[k] = (float)Qd[0];
-        qy[k] = (float)Qd[1];
-        qz[k] = (float)Qd[2];
-        ql.set(k, Qd, qx[k], qy[k], qz[k]);
-        Q2[k] = qx[k] * qx[k] + qy[k] * qy[k] + qz[k] * qz[k];
-        const double Q2d = Qd[0] * Qd[0] + Qd[1] * Qd[1] + Qd[2] * Qd[2];
-        small[k] = sqrt(Q2d) * R < tau0;
-        any_small |= small[k];
+        kahan_add(sr[k], cr[k], tr[k]);
+        kahan_add(si[k], ci[k], ti[k]);
       }
-      float qmax = 0.0f;
+    }
+    // small-|Q| lanes: the binary64 tetrahedron fan over the item's faces, after the surface sums
+    double xr[QPT], xi[QPT];
 #pragma unroll
-      for (int k = 0; k < QPT; ++k) qmax = fmaxf(qmax, sqrtf(Q2[k]));
-      const bool check =
-          __builtin_amdgcn_readfirstlane((int)sinc_range_test_needed(wave_max(qmax), info[it.mesh].rho)) != 0;
-      float sr[QPT], si[QPT], cr[QPT], ci[QPT];
+    for (int k = 0; k < QPT; ++k) xr[k] = xi[k] = 0.0;
+    if (any_small) {
 #pragma unroll
-      for (int k = 0; k < QPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f;
-      FwdCarry<QPT> carry;  // shared edge term from the previous face of the item
-      carry.reset();
-      for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
-        const int nt = (int)min((int64_t)kTileF, f_end - t0);
-        __syncthreads();
-        for (int i = lane; i < nt * (int)(sizeof(Face32) / 16); i += kBlock)
-          reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f32 + t0)[i];
-        __syncthreads();
-        float tr[QPT], ti[QPT];
-#pragma unroll
-        for (int k = 0; k < QPT; ++k) tr[k] = ti[k] = 0.0f;
-        if (check)
-          fwd_tile_fp32c<QPT, SHARE, true>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
-        else
-          fwd_tile_fp32c<QPT, SHARE, false>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
-#pragma unroll
-        for (int k = 0; k < QPT; ++k) {
-          kahan_add(sr[k], cr[k], tr[k]);
-          kahan_add(si[k], ci[k], ti[k]);
+      for (int k = 0; k < QPT; ++k)
+        if (small[k]) {
+          const double Qd[3] = {ql.qd(qx[k], k, 0), ql.qd(qy[k], k, 1), ql.qd(qz[k], k, 2)};
+          for (int64_t j = it.f0; j < f_end; ++j) tet_term_f64(f64[j], Qd, xr[k], xi[k], kZeroOrigin);
         }
-      }
-      // small-|Q| lanes: the binary64 tetrahedron fan over the item's faces, after the surface sums
-      double xr[QPT], xi[QPT];
+    }
 #pragma unroll
-      for (int k = 0; k < QPT; ++k) xr[k] = xi[k] = 0.0;
-      if (any_small) {
-#pragma unroll
-        for (int k = 0; k < QPT; ++k)
-          if (small[k]) {
-            const double Qd[3] = {ql.qd(qx[k], k, 0), ql.qd(qy[k], k, 1), ql.qd(qz[k], k, 2)};
-            for (int64_t j = it.f0; j < f_end; ++j) tet_term_f64(f64[j], Qd, xr[k], xi[k], kZeroOrigin);
-          }
-      }
-#pragma unroll
-      for (int k = 0; k < QPT; ++k) {
-        if (active[k]) {
-          const double2 v = small[k] ? make_double2(xr[k], xi[k])
-                                     : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
-          store_stream(partial + it.part + lane + k * kBlock, v);
-        }
+    for (int k = 0; k < QPT; ++k) {
+      if (active[k]) {
+        const double2 v = small[k] ? make_double2(xr[k], xi[k])
+                                   : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
+        store_stream(partial + it.part + lane + k * 64, v);
       }
     }
   }
@@ -265,16 +289,16 @@ __global__ __launch_bounds__(256) void batch_bwd_reduce_kernel(const double* par
 int batch_fwd_blocks_per_cu(int mode, bool share, int qpt) {
   int nb = 0;
   if (mode == PFT_FP64)
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_kernel<PFT_FP64>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_fwd_fp64_kernel, kBlock, 0);
   else if (share)
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, qpt >= 3 ? batch_fwd_kernel<PFT_FP32C, true, 3> : qpt == 2 ? batch_fwd_kernel<PFT_FP32C, true, 2>
-                                                                        : batch_fwd_kernel<PFT_FP32C, true, 1>,
+        &nb, qpt >= 3 ? batch_fwd_fp32c_kernel<true, 3> : qpt == 2 ? batch_fwd_fp32c_kernel<true, 2>
+                                                                  : batch_fwd_fp32c_kernel<true, 1>,
         kBlock, 0);
   else
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, qpt >= 3 ? batch_fwd_kernel<PFT_FP32C, false, 3> : qpt == 2 ? batch_fwd_kernel<PFT_FP32C, false, 2>
-                                                                         : batch_fwd_kernel<PFT_FP32C, false, 1>,
+        &nb, qpt >= 3 ? batch_fwd_fp32c_kernel<false, 3> : qpt == 2 ? batch_fwd_fp32c_kernel<false, 2>
+                                                                   : batch_fwd_fp32c_kernel<false, 1>,
         kBlock, 0);
   return nb > 0 ? nb : 1;
 }
@@ -293,16 +317,14 @@ hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items
                             double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s,
                             bool share, int qpt) {
   if (n_items <= 0) return hipSuccess;
-#define PFT_BATCH_FWD(M, SH, QP) \
-  batch_fwd_kernel<M, SH, QP><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial, info, tau0)
+#define PFT_BATCH_FWD(SH, QP) \
+  batch_fwd_fp32c_kernel<SH, QP><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial, info, tau0)
   if (mode == PFT_FP64)
-    PFT_BATCH_FWD(PFT_FP64, false, 1);
+    batch_fwd_fp64_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, q, qdtype, perm, partial, info, tau0);
   else if (share)
-    qpt >= 3 ? PFT_BATCH_FWD(PFT_FP32C, true, 3) : qpt == 2 ? PFT_BATCH_FWD(PFT_FP32C, true, 2)
-                                                            : PFT_BATCH_FWD(PFT_FP32C, true, 1);
+    qpt >= 3 ? PFT_BATCH_FWD(true, 3) : qpt == 2 ? PFT_BATCH_FWD(true, 2) : PFT_BATCH_FWD(true, 1);
   else
-    qpt >= 3 ? PFT_BATCH_FWD(PFT_FP32C, false, 3) : qpt == 2 ? PFT_BATCH_FWD(PFT_FP32C, false, 2)
-                                                             : PFT_BATCH_FWD(PFT_FP32C, false, 1);
+    qpt >= 3 ? PFT_BATCH_FWD(false, 3) : qpt == 2 ? PFT_BATCH_FWD(false, 2) : PFT_BATCH_FWD(false, 1);
 #undef PFT_BATCH_FWD
   return hipGetLastError();
 }

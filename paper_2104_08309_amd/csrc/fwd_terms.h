@@ -242,36 +242,51 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
       }
     }
   }
+  float Sr[NQ], Si[NQ], co[NQ], t1[NQ];
+  bool need[NQ];
+  bool any = false;
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     // t_1 = t_0 - eta_2, t_2 = t_0 + eta_1
-    const float t1 = cin.t[k] - x2[k], t2 = cin.t[k] + x1[k];
-    const float e1c = cos_turns(t1), e1s = sin_turns(t1);
+    t1[k] = cin.t[k] - x2[k];
+    const float t2 = cin.t[k] + x1[k];
+    const float e1c = cos_turns(t1[k]), e1s = sin_turns(t1[k]);
     const float e2c = cos_turns(t2), e2s = sin_turns(t2);
     // w_l times the edge's sinc; w_2 = -(w_0 + w_1)
     const float a0 = w0[k] * cin.c[k], a1 = w1[k] * c1[k], a2 = (w0[k] + w1[k]) * c2[k];
-    float Sr = a0 * cin.cs[k] + a1 * e1c - a2 * e2c;
-    float Si = a0 * cin.sn[k] + a1 * e1s - a2 * e2s;
-    float co = QN[k] * rcp_f(P2[k]);
+    Sr[k] = a0 * cin.cs[k] + a1 * e1c - a2 * e2c;
+    Si[k] = a0 * cin.sn[k] + a1 * e1s - a2 * e2s;
+    co[k] = QN[k] * rcp_f(P2[k]);
     // |Q_perp| L < tau or |Q_perp| < tau_rel |Q| (and every pair of an empty face): the series
-    if (P2[k] < fmaf(f.kap, Q2[k], f.thr) && !small[k]) {
-      // half-vertex phases from the edge half-phases: p_0 = (2 eta_2 + eta_1)/3, p_1 = -(2 eta_1 + eta_2)/3
-      SeriesInputs sd;
-      sd.p0 = (2.0f * x2[k] + x1[k]) * (1.0f / 3.0f);
-      sd.p1 = -(2.0f * x1[k] + x2[k]) * (1.0f / 3.0f);
-      sd.QN = QN[k] * f.nN;
-      sd.r = t1 + sd.p0;
-      face_series_fp32c(sd, Sr, Si);
-      co = 1.0f;
-    }
-    tr[k] = fmaf(co, Sr, tr[k]);
-    ti[k] = fmaf(co, Si, ti[k]);
+    need[k] = P2[k] < fmaf(f.kap, Q2[k], f.thr) && !small[k];
+    any |= need[k];
     if (SHARE) {
       cout.c[k] = c1[k];
       cout.cs[k] = e1c;
       cout.sn[k] = e1s;
-      cout.t[k] = t1 - rintf(t1);
     }
+  }
+  // one branch per face for the rare lanes that need the series (of any of their NQ points)
+  if (__builtin_expect(any, 0)) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      if (need[k]) {
+        // half-vertex phases from the edge half-phases: p_0 = (2 eta_2 + eta_1)/3, p_1 = -(2 eta_1 + eta_2)/3
+        SeriesInputs sd;
+        sd.p0 = (2.0f * x2[k] + x1[k]) * (1.0f / 3.0f);
+        sd.p1 = -(2.0f * x1[k] + x2[k]) * (1.0f / 3.0f);
+        sd.QN = QN[k] * f.nN;
+        sd.r = t1[k] + sd.p0;
+        face_series_fp32c(sd, Sr[k], Si[k]);
+        co[k] = 1.0f;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    tr[k] = fmaf(co[k], Sr[k], tr[k]);
+    ti[k] = fmaf(co[k], Si[k], ti[k]);
+    if (SHARE) cout.t[k] = t1[k] - rintf(t1[k]);
   }
   cout.prev = true;
 }

@@ -450,7 +450,7 @@ struct BatchItemFwd {   // one (mesh, Q-tile, face-chunk) work item
   int32_t mesh;
   int32_t chunk;        // face-chunk index within the mesh
   int64_t q0;           // first global Q index of the tile
-  int32_t nq;           // Q in the tile (<= kBlock for FP64, <= kBlock * (Q per thread) for FP32C)
+  int32_t nq;           // Q in the tile (<= kBlock for FP64, <= 64 * (Q per thread) for FP32C)
   int32_t pad;
   int64_t f0;           // first global face index of the chunk
   int64_t nf;           // faces in the chunk
