@@ -36,6 +36,15 @@ COMMON = [
 ]
 
 
+# Per-source code generation: the FP32C forward's face loop (single-mesh and batched) is scheduled for
+# instruction-level parallelism; measured on MI355X 1.3 % (config 2) and 0.9 % (config 4) faster at the
+# same register use, with bitwise-identical results. The other kernels keep the default scheduler.
+FILE_FLAGS = {
+    "fwd3d.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+    "batch.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
+
 def _hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):
@@ -47,7 +56,8 @@ def _compile(src: str, hipcc: str, verbose: bool, build_dir: str, defines, src_d
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]
     flags = [f if f != CSRC else src_dir for f in COMMON]
-    cmd = [hipcc] + lang + flags + [f"-D{d}" for d in defines] + ["-c", os.path.join(src_dir, src), "-o", obj]
+    cmd = [hipcc] + lang + flags + FILE_FLAGS.get(src, []) + [f"-D{d}" for d in defines] + \
+        ["-c", os.path.join(src_dir, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

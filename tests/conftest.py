@@ -9,9 +9,9 @@ if ROOT not in sys.path:
 
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
-# Text of the paper (for the appendix's embedded two-sphere mesh); PFT_PAPER_TEXT overrides the
-# location of the read-only copy in the build container. Absent elsewhere: the tests that need it skip.
-PAPER_TEXT = os.environ.get("PFT_PAPER_TEXT", "/root/reference/PAPER.md")
+# Text of the paper (for the appendix's embedded two-sphere mesh), from the file PFT_PAPER_TEXT names;
+# without it the tests that need the text skip.
+PAPER_TEXT = os.environ.get("PFT_PAPER_TEXT", "")
 
 
 def pytest_configure(config):
@@ -22,7 +22,7 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def paper_text():
     """The paper's text, or a skip when no copy is available."""
-    if not os.path.exists(PAPER_TEXT):
+    if not PAPER_TEXT or not os.path.exists(PAPER_TEXT):
         pytest.skip("paper text not available (set PFT_PAPER_TEXT)")
     with open(PAPER_TEXT) as f:
         return f.read()
