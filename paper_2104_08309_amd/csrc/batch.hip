@@ -68,11 +68,12 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_fp64_kernel(const BatchItemF
   }
 }
 
-// The next work item of a wavefront (one lane takes it from the counter, every lane gets it).
+// The next work item of a wavefront (lane 0 takes it from the counter; the value is read back as a
+// wavefront-uniform scalar, so the item's fields load into scalar registers).
 __device__ __forceinline__ int64_t wave_next_item(uint32_t* counter) {
   int idx = 0;
   if ((threadIdx.x & 63) == 0) idx = (int)atomicAdd(counter, 1u);
-  return (int64_t)(uint32_t)__shfl(idx, 0);
+  return (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(idx);
 }
 
 // The FP32C batched forward: every wavefront is an independent worker. It pulls (mesh, Q-tile of 64 QPT
@@ -86,8 +87,10 @@ __global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void 
     const Face32* __restrict__ f32, const void* q, int qdtype, const uint32_t* __restrict__ perm, double2* partial,
     const MeshInfo* __restrict__ info, double tau0) {
   __shared__ Face32 tiles[kBlock / 64][kTileF];
+  __shared__ float qlo[kBlock / 64][3 * QPT * 64];
   const int lane = (int)(threadIdx.x & 63);
-  Face32* tile = tiles[threadIdx.x >> 6];
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  Face32* tile = tiles[w];
   for (;;) {
     const int64_t idx = wave_next_item(counter);
     if (idx >= n_items) break;
@@ -95,7 +98,9 @@ __global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void 
     const int64_t f_end = it.f0 + it.nf;
     const MeshInfo& mi = info[it.mesh];
     const double R = mi.R;
-    QLow<QPT> ql;
+    QLowLds<QPT> ql;
+    ql.lo = qlo[w];
+    ql.lane = lane;
     float qx[QPT], qy[QPT], qz[QPT], Q2[QPT];
     bool small[QPT], active[QPT];
     bool any_small = false;
@@ -133,9 +138,9 @@ __global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void 
 #pragma unroll
       for (int k = 0; k < QPT; ++k) tr[k] = ti[k] = 0.0f;
       if (check)
-        fwd_tile_fp32c<QPT, SHARE, true>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
+        fwd_tile_fp32c<QPT, SHARE, true>(tile, nt, qx, qy, qz, ql, small, tr, ti, carry);
       else
-        fwd_tile_fp32c<QPT, SHARE, false>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
+        fwd_tile_fp32c<QPT, SHARE, false>(tile, nt, qx, qy, qz, ql, small, tr, ti, carry);
 #pragma unroll
       for (int k = 0; k < QPT; ++k) {
         kahan_add(sr[k], cr[k], tr[k]);
@@ -158,7 +163,8 @@ __global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void 
     for (int k = 0; k < QPT; ++k) {
       if (active[k]) {
         const double2 v = small[k] ? make_double2(xr[k], xi[k])
-                                   : make_double2((double)sr[k] - (double)cr[k], (double)si[k] - (double)ci[k]);
+                                   : make_double2(((double)sr[k] - (double)cr[k]) * kInvSumScale32,
+                                                  ((double)si[k] - (double)ci[k]) * kInvSumScale32);
         store_stream(partial + it.part + lane + k * 64, v);
       }
     }

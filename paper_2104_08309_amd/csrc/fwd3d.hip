@@ -95,7 +95,10 @@ template <bool SHARE>
 __global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs a) {
   static_assert(kBlock == 64 * kFwdSplitWaves, "one wavefront per share of the split");
   __shared__ Face32 tiles[kFwdSplitWaves][kTileF];
-  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  __shared__ float qlo[kFwdSplitWaves][3 * kQPT * 64];
+  // the wavefront index as a wavefront-uniform (scalar) value, so the face range and tile addresses
+  // derived from it stay in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
   Face32* tile = tiles[w];
   const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
   const double R = geo.w;
@@ -109,7 +112,9 @@ __global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs 
     f_begin = b;
   }
   const int64_t qbase = (int64_t)blockIdx.x * kFwdQTile + lane;
-  QLow<kQPT> ql;
+  QLowLds<kQPT> ql;
+  ql.lo = qlo[w];
+  ql.lane = lane;
   float qx[kQPT], qy[kQPT], qz[kQPT], Q2[kQPT];
   bool small[kQPT], active[kQPT];
   bool any_small = false;
@@ -152,9 +157,9 @@ __global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs 
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) tr[k] = ti[k] = 0.0f;
     if (check)
-      fwd_tile_fp32c<kQPT, SHARE, true>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
+      fwd_tile_fp32c<kQPT, SHARE, true>(tile, nt, qx, qy, qz, ql, small, tr, ti, carry);
     else
-      fwd_tile_fp32c<kQPT, SHARE, false>(tile, nt, qx, qy, qz, Q2, ql, small, tr, ti, carry);
+      fwd_tile_fp32c<kQPT, SHARE, false>(tile, nt, qx, qy, qz, ql, small, tr, ti, carry);
 #pragma unroll
     for (int k = 0; k < kQPT; ++k) {
       kahan_add(sr[k], cr[k], tr[k]);
@@ -182,8 +187,8 @@ __global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs 
 #pragma unroll
   for (int k = 0; k < kQPT; ++k)
     red[(w * kQPT + k) * 64 + lane] = small[k] ? make_double2(xr[k], xi[k])
-                                               : make_double2((double)sr[k] - (double)cr[k],
-                                                              (double)si[k] - (double)ci[k]);
+                                               : make_double2(((double)sr[k] - (double)cr[k]) * kInvSumScale32,
+                                                              ((double)si[k] - (double)ci[k]) * kInvSumScale32);
   __syncthreads();
   for (int j = (int)threadIdx.x; j < kFwdQTile; j += kBlock) {  // j = k * 64 + lane of the tile
     const int64_t qi = (int64_t)blockIdx.x * kFwdQTile + j;

@@ -92,6 +92,10 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 // Near-degenerate pairs (Q nearly along the face normal, and empty faces) are
 // replaced by the face's simplex series in binary64.
 
+// The FP32C forward sums tau_rel times each face term (Face32::N); partial sums are divided by it once.
+constexpr float kSumScale32 = (float)kTauRel32;
+constexpr double kInvSumScale32 = 1.0 / kTauRel32;
+
 #ifndef PFT_ANCHOR
 #define PFT_ANCHOR 64
 #endif
@@ -153,6 +157,24 @@ struct QLow {
   }
 };
 
+// The same low parts kept in a wavefront's slice of LDS (64 * 3 * NQ floats, lane-major so a wavefront's
+// access is one conflict-free row) instead of nine registers: only the anchors, the chain starts and the
+// small-|Q| fan read them. Each lane reads only what it wrote itself.
+template <int NQ>
+struct QLowLds {
+  float* lo;  // this wavefront's slice
+  int lane;
+  __device__ __forceinline__ void set(int k, const double* Q, float hx, float hy, float hz) {
+    lo[(k * 3 + 0) * 64 + lane] = (float)(Q[0] - (double)hx);
+    lo[(k * 3 + 1) * 64 + lane] = (float)(Q[1] - (double)hy);
+    lo[(k * 3 + 2) * 64 + lane] = (float)(Q[2] - (double)hz);
+  }
+  __device__ __forceinline__ double qd(float hi, int k, int j) const {
+    return (double)hi + (double)lo[(k * 3 + j) * 64 + lane];
+  }
+  __device__ __forceinline__ double qd_here(float hi, int k, int j) const { return qd(hi, k, j); }
+};
+
 // Orders a wavefront's LDS accesses around a tile it stages for itself: its stores are complete before
 // any lane reads, and its earlier reads before it overwrites (a wavefront's LDS instructions execute in
 // order; the fence also keeps the compiler from moving accesses across it).
@@ -185,9 +207,9 @@ __device__ __forceinline__ bool sinc_range_test_needed(float qmax, double rho) {
 // the origin phase in binary64 even when the face is linked. `cin` holds the
 // previous record's edge 1 (edge 0 of a linked face); the face's own edge 1 goes
 // to `cout` (SHARE only; the two may be the same object).
-template <int NQ, bool SHARE, bool CHECK>
+template <int NQ, bool SHARE, bool CHECK, class QL>
 __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx, const float* qy, const float* qz,
-                                               const float* Q2, const QLow<NQ>& ql, const bool* small, float* tr,
+                                               const QL& ql, const bool* small, float* tr,
                                                float* ti, bool anchor, FwdCarry<NQ>& cin, FwdCarry<NQ>& cout) {
   const uint32_t flags = __builtin_amdgcn_readfirstlane(f.flags);
   const bool linked = SHARE && cin.prev && (flags & kFaceLinked) != 0u;
@@ -258,7 +280,7 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
     Si[k] = a0 * cin.sn[k] + a1 * e1s - a2 * e2s;
     co[k] = QN[k] * rcp_f(P2[k]);
     // |Q_perp| L < tau or |Q_perp| < tau_rel |Q| (and every pair of an empty face): the series
-    need[k] = P2[k] < fmaf(f.kap, Q2[k], f.thr) && !small[k];
+    need[k] = P2[k] < fmaf(QN[k], QN[k], f.thr) && !small[k];
     any |= need[k];
     if (SHARE) {
       cout.c[k] = c1[k];
@@ -278,6 +300,8 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
         sd.QN = QN[k] * f.nN;
         sd.r = t1[k] + sd.p0;
         face_series_fp32c(sd, Sr[k], Si[k]);
+        Sr[k] *= kSumScale32;  // the edge terms are summed tau_rel times their value
+        Si[k] *= kSumScale32;
         co[k] = 1.0f;
       }
     }
@@ -298,18 +322,18 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
 // The origin phase is formed in binary64 at every kAnchor-th face of a tile.
 // Faces go in pairs that pass the carry between two register sets, so no copy
 // of it is needed from one face to the next.
-template <int NQ, bool SHARE, bool CHECK>
+template <int NQ, bool SHARE, bool CHECK, class QL>
 __device__ __forceinline__ void fwd_tile_fp32c(const Face32* tile, int nt, const float* qx, const float* qy,
-                                               const float* qz, const float* Q2, const QLow<NQ>& ql,
+                                               const float* qz, const QL& ql,
                                                const bool* small, float* tr, float* ti, FwdCarry<NQ>& c) {
   FwdCarry<NQ> d;
   int j = 0;
   for (; j + 2 <= nt; j += 2) {
-    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j], qx, qy, qz, Q2, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
-    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j + 1], qx, qy, qz, Q2, ql, small, tr, ti, false, d, c);
+    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j], qx, qy, qz, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
+    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j + 1], qx, qy, qz, ql, small, tr, ti, false, d, c);
   }
   if (j < nt) {
-    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j], qx, qy, qz, Q2, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
+    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j], qx, qy, qz, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
     c = d;
   }
 }

@@ -129,8 +129,11 @@ static_assert(sizeof(Face64) == 128, "Face64 layout");
 // part of Q, and the edge coefficients al_l = (e1 . d_l)/(2 pi), be_l = -(e2 . d_l)/(2 pi):
 //   eta_l = Q . d_l / (4 pi) = sigma1 al_l - sigma2 be_l      (edge half-phase, turns)
 //   w'_l = sigma2 al_l + sigma1 be_l = (P . d_l) / (4 pi |N|)  (P = Q x N; the edge weight)
-//   |P|^2 / (4 |N|^2) = sigma1^2 + sigma2^2,   Q . n / 2 = Q . N'  (N' = N / (2 |N|)),
-// so the face term (Q.N)/|P|^2 sum_l (P.d_l) E_l equals (Q.N')/(sigma1^2 + sigma2^2) sum_l w'_l E_l.
+//   |P|^2 / (4 |N|^2) = sigma1^2 + sigma2^2,   tau_rel (Q . n) / 2 = Q . N'  (N' = tau_rel N / (2 |N|)),
+// so tau_rel times the face term (Q.N)/|P|^2 sum_l (P.d_l) E_l equals (Q.N')/(sigma1^2 + sigma2^2)
+// sum_l w'_l E_l: the kernels sum that and divide by tau_rel once per partial sum. The factor tau_rel
+// (the relative series threshold) lets one fused multiply-add form the series test
+// |P'|^2 < (Q.N')^2 + thr, i.e. |Q_perp| < tau_rel |Q.n| or |Q_perp| L < tau.
 // In an edge-sharing order the traversal may be the reverse of the outward
 // (counter-clockwise) one, so that the edge shared with the next face is edge
 // 1: the edge sum is the same for both traversals (each edge's P . d and
@@ -138,16 +141,15 @@ static_assert(sizeof(Face64) == 128, "Face64 layout");
 // stays the outward normal, so the face term is unchanged.
 struct alignas(16) Face32 {
   double gt[3];   // centroid / (2 pi), binary64: face origin phase in turns is Q . gt
-  float N[3];     // N' = N / (2 |N|), N the outward (b - a) x (c - a) of the counter-clockwise traversal
+  float N[3];     // N' = tau_rel N / (2 |N|), N the outward (b - a) x (c - a) of the counter-clockwise traversal
   float E1[3];    // e1 / 2
   float E2[3];    // e2 / 2
   float al[3];    // (e1 . d_l) / (2 pi), l = 0, 1, 2 (d_0 = b - a, d_1 = c - b, d_2 = a - c)
   float be[3];    // -(e2 . d_l) / (2 pi)
   float thr;      // tau^2 / (4 L^2) (1 for an empty face: its series term is Q.N = 0 times a sum)
-  float kap;      // tau_rel^2 / 4
-  float nN;       // 2 |N| = 4 A: the series branch's Q . N = nN (Q . N')
+  float nN;       // 2 |N| / tau_rel: the series branch's Q . N = nN (Q . N')
   uint32_t flags; // kFaceLinked: edge 0 is the previous record's edge 1 (edge-sharing order)
-  float pad[3];
+  float pad[4];
 };
 static_assert(sizeof(Face32) == 112, "Face32 layout");
 constexpr uint32_t kFaceLinked = 1u;

@@ -424,7 +424,7 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
     e2[1] = (Nt[2] * d0[0] - Nt[0] * d0[2]) / (nN * nd0);
     e2[2] = (Nt[0] * d0[1] - Nt[1] * d0[0]) / (nN * nd0);
     for (int k = 0; k < 3; ++k) {
-      r.N[k] = (float)(0.5 * f.N[k] / nN);
+      r.N[k] = (float)(0.5 * tau_rel * f.N[k] / nN);
       r.E1[k] = (float)(0.5 * e1[k]);
       r.E2[k] = (float)(0.5 * e2[k]);
     }
@@ -434,19 +434,17 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
       r.be[l] = (float)(-dot(e2, d[l]) * kInv2Pi);
     }
     r.thr = (float)(0.25 * tau * tau / L2);
-    r.kap = (float)(0.25 * tau_rel * tau_rel);
-    r.nN = (float)(2.0 * nN);
+    r.nN = (float)(2.0 * nN / tau_rel);
     r.flags = link ? kFaceLinked : 0u;
   } else {
     // empty face: every weight is zero; thr > 0 sends every pair to the series, whose term is
     // Q.N = 0 times a finite sum, so its contribution is exactly zero (the edge form would be 0/0)
     for (int k = 0; k < 3; ++k) r.N[k] = r.E1[k] = r.E2[k] = r.al[k] = r.be[k] = 0.0f;
     r.thr = 1.0f;
-    r.kap = 0.0f;
     r.nN = 0.0f;
     r.flags = 0u;
   }
-  r.pad[0] = r.pad[1] = r.pad[2] = 0.0f;
+  r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0.0f;
   out[m] = r;
 }
 
