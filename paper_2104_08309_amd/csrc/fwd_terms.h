@@ -93,7 +93,6 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 // replaced by the face's simplex series in binary64.
 
 // The FP32C forward sums tau_rel times each face term (Face32::N); partial sums are divided by it once.
-constexpr float kSumScale32 = (float)kTauRel32;
 constexpr double kInvSumScale32 = 1.0 / kTauRel32;
 
 #ifndef PFT_ANCHOR
@@ -105,7 +104,7 @@ static_assert(kTileF % kAnchor == 0 && kAnchor % 2 == 0, "anchor interval: even,
 // Inputs of the binary64 series fix-up for one pair.
 struct SeriesInputs {
   float p0, p1;  // half-vertex phases psi_0, psi_1 in turns
-  float QN;      // Q . N
+  float QN;      // Q . N, times whatever factor the caller's sums carry (the term is linear in it)
   float r;       // face origin phase Q.g in turns (any integer offset)
 };
 
@@ -297,11 +296,9 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
         SeriesInputs sd;
         sd.p0 = (2.0f * x2[k] + x1[k]) * (1.0f / 3.0f);
         sd.p1 = -(2.0f * x1[k] + x2[k]) * (1.0f / 3.0f);
-        sd.QN = QN[k] * f.nN;
+        sd.QN = QN[k] * f.nN;  // tau_rel Q.N through the record's own N', as in the edge form
         sd.r = t1[k] + sd.p0;
-        face_series_fp32c(sd, Sr[k], Si[k]);
-        Sr[k] *= kSumScale32;  // the edge terms are summed tau_rel times their value
-        Si[k] *= kSumScale32;
+        face_series_fp32c(sd, Sr[k], Si[k]);  // tau_rel times the face term, like the edge form's
         co[k] = 1.0f;
       }
     }

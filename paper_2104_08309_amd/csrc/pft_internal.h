@@ -147,7 +147,7 @@ struct alignas(16) Face32 {
   float al[3];    // (e1 . d_l) / (2 pi), l = 0, 1, 2 (d_0 = b - a, d_1 = c - b, d_2 = a - c)
   float be[3];    // -(e2 . d_l) / (2 pi)
   float thr;      // tau^2 / (4 L^2) (1 for an empty face: its series term is Q.N = 0 times a sum)
-  float nN;       // 2 |N| / tau_rel: the series branch's Q . N = nN (Q . N')
+  float nN;       // 2 |N|: the series branch takes tau_rel Q . N as nN (Q . N'), scaled like the edge terms
   uint32_t flags; // kFaceLinked: edge 0 is the previous record's edge 1 (edge-sharing order)
   float pad[4];
 };

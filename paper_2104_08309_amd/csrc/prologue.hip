@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
       r.be[l] = (float)(-dot(e2, d[l]) * kInv2Pi);
     }
     r.thr = (float)(0.25 * tau * tau / L2);
-    r.nN = (float)(2.0 * nN / tau_rel);
+    r.nN = (float)(2.0 * nN);
     r.flags = link ? kFaceLinked : 0u;
   } else {
     // empty face: every weight is zero; thr > 0 sends every pair to the series, whose term is
