@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void 
     const BatchItemFwd* __restrict__ items, int64_t n_items, uint32_t* counter, const Face64* __restrict__ f64,
     const Face32* __restrict__ f32, const void* q, int qdtype, const uint32_t* __restrict__ perm, double2* partial,
     const MeshInfo* __restrict__ info, double tau0) {
-  __shared__ Face32 tiles[kBlock / 64][kTileF];
+  __shared__ Face32 tiles[kBlock / 64][kTileF32];
   __shared__ float qlo[kBlock / 64][3 * QPT * 64];
   const int lane = (int)(threadIdx.x & 63);
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -128,8 +128,8 @@ __global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void 
     for (int k = 0; k < QPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f;
     FwdCarry<QPT> carry;  // shared edge term from the previous face of the item
     carry.reset();
-    for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF) {
-      const int nt = (int)min((int64_t)kTileF, f_end - t0);
+    for (int64_t t0 = it.f0; t0 < f_end; t0 += kTileF32) {
+      const int nt = (int)min((int64_t)kTileF32, f_end - t0);
       wave_lds_fence();
       for (int i = lane; i < nt * (int)(sizeof(Face32) / 16); i += 64)
         reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(f32 + t0)[i];

@@ -5,8 +5,9 @@
 // streamed through LDS in tiles of kTileF records and broadcast to the
 // wavefront. Each block's sums over its face range are binary64 partials; the
 // finish kernel adds a Q's partials in a fixed order and applies
-// exp(i Q.t) / |Q|^2. The faces are split over blockIdx.y when there are too
-// few Q to fill the GPU.
+// exp(i Q.t) / |Q|^2. The faces are split when there are too few Q to fill
+// the GPU (over blockIdx.y in binary64; in FP32C the split is part of the
+// one-dimensional block index).
 //
 // Two arithmetic forms:
 //  * fwd3d_fp64_kernel  -- IEEE binary64 throughout.
@@ -31,14 +32,14 @@ __device__ __forceinline__ void apex_phase(const double* Q, const double* o, dou
   xr = r;
 }
 
-// Face range of this block's split: from the split table when the splits
-// follow region boundaries, else equal ranges.
-__device__ __forceinline__ void split_faces(const FwdArgs& a, int64_t& b, int64_t& e) {
+// Face range of split `sp`: from the split table when the splits follow region boundaries, else equal
+// ranges.
+__device__ __forceinline__ void split_faces(const FwdArgs& a, int64_t sp, int64_t& b, int64_t& e) {
   if (a.split_face) {
-    b = a.split_face[blockIdx.y];
-    e = a.split_face[blockIdx.y + 1];
+    b = a.split_face[sp];
+    e = a.split_face[sp + 1];
   } else {
-    b = (int64_t)blockIdx.y * a.faces_per_split;
+    b = sp * a.faces_per_split;
     e = min(a.nf, b + a.faces_per_split);
   }
 }
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
   const double o[3] = {geo.x, geo.y, geo.z};
   const bool small = sqrt(Q2) * geo.w < a.tau0;
   int64_t f_begin, f_end;
-  split_faces(a, f_begin, f_end);
+  split_faces(a, blockIdx.y, f_begin, f_end);
   double xr = 0.0, xi = 0.0;
   for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
     const int nt = (int)min((int64_t)kTileF, f_end - t0);
@@ -83,35 +84,49 @@ __global__ __launch_bounds__(kBlock) void fwd3d_fp64_kernel(FwdArgs a) {
 
 // The FP32C forward. A block holds one Q-tile of kFwdQTile = 64 kQPT Q, the same in each of its
 // kFwdSplitWaves wavefronts (lane l holds the tile's Q l, l + 64, ...; kQPT per thread, so each face
-// record read from LDS serves kQPT independent instruction streams), and blockIdx.y names a face split.
+// record read from LDS serves kQPT independent instruction streams), and one face split. The grid is
+// one-dimensional and its blocks go to the dies in turn (block b to die b mod kXcds), so the block
+// index is read as (die, rank on the die) and the k-th group of `splits` blocks a die receives holds
+// every split of one Q-tile: a Q-tile's Q and permutation entries are fetched into that die's L2 once
+// and served from there to its other splits (the Q-tile count is padded to a multiple of kXcds; the
+// padding blocks exit at once).
 // Each wavefront takes its own contiguous share of the split's faces and streams them through its own
-// LDS tile of kTileF records, with wavefront-local ordering only: no block barrier inside the face
-// loop. At the end the wavefronts' binary64 partials of each Q are added in wavefront order, so a
-// block writes one partial per Q, as a block of the split layout did. SHARE: the records are in an
+// LDS tile of kTileF32 records, with wavefront-local ordering only: no block barrier after the start.
+// A wavefront that is done leaves its binary64 partials in its own tile and counts itself done; the
+// last of the block's wavefronts adds their partials of each Q in wavefront order and writes them (one
+// partial per Q and block), and the others exit at once. SHARE: the records are in an
 // edge-sharing order and each face takes one edge term from its predecessor in the wavefront's range
 // (two edge terms per face instead of three). Small-|Q| lanes (|Q| R < tau0, R the split's radius) take
 // the binary64 tetrahedron fan about the split's apex.
 template <bool SHARE>
-__global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs a) {
-  static_assert(kBlock == 64 * kFwdSplitWaves, "one wavefront per share of the split");
-  __shared__ Face32 tiles[kFwdSplitWaves][kTileF];
+__global__ __launch_bounds__(kFwdBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs a) {
+  __shared__ Face32 tiles[kFwdSplitWaves][kTileF32];
   __shared__ float qlo[kFwdSplitWaves][3 * kQPT * 64];
+  __shared__ uint32_t done;  // wavefronts of the block that have left their partials
+  static_assert(sizeof(Face32) * kTileF32 >= sizeof(double2) * kQPT * 64, "a wavefront's partials fit its tile");
+  // (Q-tile, split) of this block from its die and rank on the die
+  const uint32_t rank = blockIdx.x / kXcds;
+  const uint32_t qtile = blockIdx.x % kXcds + kXcds * (rank / (uint32_t)a.splits);
+  const uint32_t sp = rank % (uint32_t)a.splits;
+  if ((int64_t)qtile * kFwdQTile >= a.nq) return;  // padding of the Q-tile count (whole block)
+  if (threadIdx.x == 0) done = 0u;
+  __syncthreads();
   // the wavefront index as a wavefront-uniform (scalar) value, so the face range and tile addresses
   // derived from it stay in scalar registers
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
   Face32* tile = tiles[w];
-  const double4 geo = a.split_geo ? a.split_geo[blockIdx.y] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
+  const double4 geo = a.split_geo ? a.split_geo[sp] : make_double4(0.0, 0.0, 0.0, a.info[0].R);
   const double R = geo.w;
   const double o[3] = {geo.x, geo.y, geo.z};
   int64_t f_begin, f_end;
-  split_faces(a, f_begin, f_end);
+  split_faces(a, sp, f_begin, f_end);
   {  // this wavefront's share
     const int64_t per = (f_end - f_begin + kFwdSplitWaves - 1) / kFwdSplitWaves;
     const int64_t b = min(f_end, f_begin + w * per);
     f_end = min(f_end, b + per);
     f_begin = b;
   }
-  const int64_t qbase = (int64_t)blockIdx.x * kFwdQTile + lane;
+  const int64_t qbase = (int64_t)qtile * kFwdQTile + lane;
   QLowLds<kQPT> ql;
   ql.lo = qlo[w];
   ql.lane = lane;
@@ -142,8 +157,8 @@ __global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs 
   for (int k = 0; k < kQPT; ++k) sr[k] = si[k] = cr[k] = ci[k] = 0.0f;
   FwdCarry<kQPT> carry;  // shared edge term from the previous face (SHARE)
   carry.reset();         // no previous face at the start of the range
-  for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF) {
-    const int nt = (int)min((int64_t)kTileF, f_end - t0);
+  for (int64_t t0 = f_begin; t0 < f_end; t0 += kTileF32) {
+    const int nt = (int)min((int64_t)kTileF32, f_end - t0);
     // the wavefront's previous tile has been read (its LDS reads were issued in order before these
     // writes); its writes are complete before any lane reads the tile
     wave_lds_fence();
@@ -180,27 +195,32 @@ __global__ __launch_bounds__(kBlock, kFwdWaves) void fwd3d_fp32c_kernel(FwdArgs 
         if (a.split_geo) apex_phase(Qd, o, xr[k], xi[k]);
       }
   }
-  // the wavefronts' partials of each Q, added in wavefront order
-  __syncthreads();  // every wavefront is done with its tile
-  double2* red = reinterpret_cast<double2*>(&tiles[0][0]);
-  static_assert(sizeof(tiles) >= sizeof(double2) * kFwdSplitWaves * kQPT * 64, "reduction fits the tiles");
+  // this wavefront's partials into its own tile (it reads no more records)
+  wave_lds_fence();
+  double2* red = reinterpret_cast<double2*>(tiles[w]);
 #pragma unroll
   for (int k = 0; k < kQPT; ++k)
-    red[(w * kQPT + k) * 64 + lane] = small[k] ? make_double2(xr[k], xi[k])
-                                               : make_double2(((double)sr[k] - (double)cr[k]) * kInvSumScale32,
-                                                              ((double)si[k] - (double)ci[k]) * kInvSumScale32);
-  __syncthreads();
-  for (int j = (int)threadIdx.x; j < kFwdQTile; j += kBlock) {  // j = k * 64 + lane of the tile
-    const int64_t qi = (int64_t)blockIdx.x * kFwdQTile + j;
-    if (qi >= a.nq) continue;
-    const int k = j >> 6, l = j & 63;
-    double2 v = red[k * 64 + l];
+    red[k * 64 + lane] = small[k] ? make_double2(xr[k], xi[k])
+                                  : make_double2(((double)sr[k] - (double)cr[k]) * kInvSumScale32,
+                                                 ((double)si[k] - (double)ci[k]) * kInvSumScale32);
+  // count this wavefront done once its partials are visible to the block; the last one adds them all
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  int last = 0;
+  if (lane == 0) last = atomicAdd(&done, 1u) == (uint32_t)(kFwdSplitWaves - 1) ? 1 : 0;
+  if (__builtin_amdgcn_readfirstlane(last) == 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  // the lane index anew (from the lane mask, not threadIdx), so no Q index is kept live across the loop
+  const int l = (int)__lane_id();
+#pragma unroll
+  for (int k = 0; k < kQPT; ++k) {
+    const int64_t qi = (int64_t)qtile * kFwdQTile + k * 64 + l;
+    double2 v = reinterpret_cast<const double2*>(tiles[0])[k * 64 + l];
     for (int u = 1; u < kFwdSplitWaves; ++u) {
-      const double2 x = red[(u * kQPT + k) * 64 + l];
+      const double2 x = reinterpret_cast<const double2*>(tiles[u])[k * 64 + l];
       v.x += x.x;
       v.y += x.y;
     }
-    store_stream(a.partial + (int64_t)blockIdx.y * a.nq + qi, v);
+    if (qi < a.nq) store_stream(a.partial + (int64_t)sp * a.nq + qi, v);
   }
 }
 
@@ -244,11 +264,13 @@ hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s) {
-  dim3 grid((unsigned)((a.nq + kFwdQTile - 1) / kFwdQTile), (unsigned)a.splits);
+  const int64_t qtiles = (a.nq + kFwdQTile - 1) / kFwdQTile;
+  const int64_t blocks = (qtiles + kXcds - 1) / kXcds * kXcds * a.splits;
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
   if (a.share_edges)
-    fwd3d_fp32c_kernel<true><<<grid, kBlock, 0, s>>>(a);
+    fwd3d_fp32c_kernel<true><<<(unsigned)blocks, kFwdBlock, 0, s>>>(a);
   else
-    fwd3d_fp32c_kernel<false><<<grid, kBlock, 0, s>>>(a);
+    fwd3d_fp32c_kernel<false><<<(unsigned)blocks, kFwdBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 

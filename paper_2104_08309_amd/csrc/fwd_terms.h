@@ -96,10 +96,10 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 constexpr double kInvSumScale32 = 1.0 / kTauRel32;
 
 #ifndef PFT_ANCHOR
-#define PFT_ANCHOR 64
+#define PFT_ANCHOR kTileF32
 #endif
-constexpr int kAnchor = PFT_ANCHOR;  // faces between binary64 origin phases in a chain (divides kTileF)
-static_assert(kTileF % kAnchor == 0 && kAnchor % 2 == 0, "anchor interval: even, and divides the face tile");
+constexpr int kAnchor = PFT_ANCHOR;  // faces between binary64 origin phases in a chain (divides kTileF32)
+static_assert(kTileF32 % kAnchor == 0 && kAnchor % 2 == 0, "anchor interval: even, and divides the face tile");
 
 // Inputs of the binary64 series fix-up for one pair.
 struct SeriesInputs {
@@ -316,7 +316,7 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
 // (plain binary32 sums inside the tile). SHARE: the records are in an
 // edge-sharing order; `c` carries the shared edge's term and midpoint phase
 // across faces and tiles of one face range (reset it at the range's start).
-// The origin phase is formed in binary64 at every kAnchor-th face of a tile.
+// The origin phase is formed in binary64 at every kAnchor-th face of a tile (of kTileF32 faces).
 // Faces go in pairs that pass the carry between two register sets, so no copy
 // of it is needed from one face to the next.
 template <int NQ, bool SHARE, bool CHECK, class QL>

@@ -17,14 +17,26 @@ constexpr int kBlock = 256;        // threads per block for the Q-parallel kerne
 #ifndef PFT_TILEF
 #define PFT_TILEF 64
 #endif
-constexpr int kTileF = PFT_TILEF;  // faces staged in LDS per tile (forward)
+constexpr int kTileF = PFT_TILEF;  // faces staged in LDS per tile (binary64 forward and grad_Q)
+#ifndef PFT_TILEF32
+#define PFT_TILEF32 64
+#endif
+// faces per LDS tile of an FP32C forward wavefront (also the binary64 re-anchoring interval of its carried
+// phases); 6 KiB of records plus 2.25 KiB of Q low parts per wavefront, so the LDS holds more wavefronts
+// than the 4 per SIMD the registers allow
+constexpr int kTileF32 = PFT_TILEF32;
 constexpr int kTileFB = 8;         // faces per block in the binary64 adjoint
 #ifndef PFT_QPT
 #define PFT_QPT 3
 #endif
 constexpr int kQPT = PFT_QPT;      // Q per thread in the FP32C forward
-constexpr int kFwdSplitWaves = kBlock / 64;     // wavefronts of an FP32C forward block, each on its own faces
-constexpr int kFwdQTile = 64 * kQPT;            // Q of an FP32C forward block (shared by its wavefronts)
+#ifndef PFT_FWD_BLOCK_WAVES
+#define PFT_FWD_BLOCK_WAVES 4
+#endif
+constexpr int kFwdSplitWaves = PFT_FWD_BLOCK_WAVES;  // wavefronts of an FP32C forward block, each on its own faces
+constexpr int kFwdBlock = 64 * kFwdSplitWaves;       // threads of an FP32C forward block
+constexpr int kFwdQTile = 64 * kQPT;                 // Q of an FP32C forward block (shared by its wavefronts)
+constexpr int kXcds = 8;                             // accelerator dies (each with its own L2) of the target
 #ifndef PFT_FWD_WAVES
 #define PFT_FWD_WAVES 4
 #endif
@@ -149,9 +161,8 @@ struct alignas(16) Face32 {
   float thr;      // tau^2 / (4 L^2) (1 for an empty face: its series term is Q.N = 0 times a sum)
   float nN;       // 2 |N|: the series branch takes tau_rel Q . N as nN (Q . N'), scaled like the edge terms
   uint32_t flags; // kFaceLinked: edge 0 is the previous record's edge 1 (edge-sharing order)
-  float pad[4];
 };
-static_assert(sizeof(Face32) == 112, "Face32 layout");
+static_assert(sizeof(Face32) == 96, "Face32 layout");
 constexpr uint32_t kFaceLinked = 1u;
 // Edge-sharing order metadata (pft_strip_order, one byte per position): the face's
 // vertex list rotated by (meta & 3), edge 0 shared with the previous position's

@@ -444,7 +444,6 @@ __global__ __launch_bounds__(256) void face32_kernel(const Face64* in, int64_t n
     r.nN = 0.0f;
     r.flags = 0u;
   }
-  r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0.0f;
   out[m] = r;
 }
 
