@@ -301,9 +301,16 @@ int64_t plan_forward(int64_t nq, int64_t nf, bool c128, int64_t max_partials, Fw
   return (int64_t)splits * nq;
 }
 
+// Q-splits of the vertex adjoint (blocks of `tile` faces): about kTargetBlocks blocks, at least kBlock Q per
+// split; from kXcds splits up, a multiple of kXcds, so that each die takes whole Q-splits.
 void choose_q_splits(int64_t nq, int64_t nf, int tile, int* splits, int64_t* per) {
   const int64_t fblocks = std::max<int64_t>(1, cdiv(nf, tile));
-  int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, fblocks), std::max<int64_t>(1, cdiv(nq, kBlock))));
+  const int64_t smax = std::max<int64_t>(1, cdiv(nq, kBlock));
+  int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, fblocks), smax));
+  if (s >= kXcds) {
+    s = cdiv(s, kXcds) * kXcds;
+    if (s > smax) s -= kXcds;
+  }
   const int64_t p = std::max<int64_t>(1, cdiv(nq, s));
   *per = p;
   *splits = (int)std::max<int64_t>(1, cdiv(nq, p));

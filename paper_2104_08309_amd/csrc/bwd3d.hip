@@ -21,7 +21,8 @@
 // the edge form cancels like 1/(|Q_perp| L)^2).
 //
 // Layout: a block owns a tile of faces (records in LDS) and loops over a
-// range of Q (the Q-split on blockIdx.y), kQPTB Q per thread per pass.
+// range of Q (a Q-split), kQPTB Q per thread per pass; the grid is one-
+// dimensional over (face tile, Q-split) pairs (adj_block).
 // Each thread adds its weights to private slots in LDS (one per face and
 // corner; binary64 or binary32 by form), and a fixed-order binary64 block sum
 // at the end writes the per-split partials. The Q list is reordered and paired
@@ -33,40 +34,59 @@
 namespace pft {
 namespace {
 
+// (face tile, Q-split) of this block. Blocks go to the dies in turn (block b to die b mod kXcds); when the
+// split count is a multiple of kXcds, each die takes its own qsplits / kXcds Q-splits across all face tiles,
+// so each Q record is fetched into one die's L2 only (face tile fastest within a die).
+__device__ __forceinline__ void adj_block(const BwdArgs& a, int64_t ftiles, int64_t& ft, int64_t& qs) {
+  const int64_t b = blockIdx.x;
+  if (a.qsplits % kXcds == 0) {
+    const int64_t rank = b / kXcds;
+    ft = rank % ftiles;
+    qs = (b % kXcds) * (a.qsplits / kXcds) + rank / ftiles;
+  } else {
+    ft = b % ftiles;
+    qs = b / ftiles;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void bwd3d_fp64_kernel(BwdArgs a, const double* gram) {
   __shared__ Face64 tile[kTileFB];
   __shared__ double gtile[kTileFB][8];
   __shared__ double acc[kTileFB * 3][kBlock];
   const int tid = threadIdx.x;
-  const int64_t f0 = (int64_t)blockIdx.x * kTileFB;
+  int64_t ft, qs;
+  adj_block(a, (a.nf + kTileFB - 1) / kTileFB, ft, qs);
+  const int64_t f0 = ft * kTileFB;
   const int nt = (int)min((int64_t)kTileFB, a.nf - f0);
   for (int i = tid; i < nt * (int)(sizeof(Face64) / 16); i += kBlock)
     reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(a.f64 + f0)[i];
   for (int i = tid; i < nt * 8; i += kBlock) gtile[i / 8][i % 8] = gram[(f0 + i / 8) * 8 + i % 8];
   for (int v = 0; v < nt * 3; ++v) acc[v][tid] = 0.0;
   __syncthreads();
-  const int64_t qb = (int64_t)blockIdx.y * a.q_per_split;
+  const int64_t qb = qs * a.q_per_split;
   const int64_t qe = min(a.nq, qb + a.q_per_split);
   adj_tile_f64(tile, gtile, nt, qb, qe, a.rec64, acc);
   __syncthreads();
-  adj_block_sum(acc, nt, a.partial + ((int64_t)blockIdx.y * a.nf + f0) * 3);
+  adj_block_sum(acc, nt, a.partial + (qs * a.nf + f0) * 3);
 }
 
 __global__ __launch_bounds__(kBlock) void bwd3d_fp32c_kernel(BwdArgs a) {
   __shared__ Face32B tile[kTileFB32];
   __shared__ float acc[kTileFB32 * 3][kBlock];
   const int tid = threadIdx.x;
-  const int64_t f0 = (int64_t)blockIdx.x * kTileFB32;
+  int64_t ft, qs;
+  adj_block(a, (a.nf + kTileFB32 - 1) / kTileFB32, ft, qs);
+  const int64_t f0 = ft * kTileFB32;
   const int nt = (int)min((int64_t)kTileFB32, a.nf - f0);
   for (int i = tid; i < nt * (int)(sizeof(Face32B) / 16); i += kBlock)
     reinterpret_cast<uint4*>(tile)[i] = reinterpret_cast<const uint4*>(a.f32 + f0)[i];
   for (int v = 0; v < nt * 3; ++v) acc[v][tid] = 0.0f;
   __syncthreads();
-  const int64_t qb = (int64_t)blockIdx.y * a.q_per_split;
+  const int64_t qb = qs * a.q_per_split;
   const int64_t qe = min(a.nq, qb + a.q_per_split);
   adj_tile_fp32c(tile, nt, qb, qe, a.rec, acc);
   __syncthreads();
-  adj_block_sum(acc, nt, a.partial + ((int64_t)blockIdx.y * a.nf + f0) * 3);
+  adj_block_sum(acc, nt, a.partial + (qs * a.nf + f0) * 3);
 }
 
 __global__ __launch_bounds__(256) void gram64_kernel(const Face64* f64, int64_t nf, double* gram) {
@@ -163,14 +183,16 @@ hipError_t launch_gram64(const Face64* f64, int64_t nf, double* gram, hipStream_
 }
 
 hipError_t launch_bwd3d_fp64(const BwdArgs& a, const double* gram, hipStream_t s) {
-  dim3 grid((unsigned)((a.nf + kTileFB - 1) / kTileFB), (unsigned)a.qsplits);
-  bwd3d_fp64_kernel<<<grid, kBlock, 0, s>>>(a, gram);
+  const int64_t blocks = (a.nf + kTileFB - 1) / kTileFB * a.qsplits;
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  bwd3d_fp64_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(a, gram);
   return hipGetLastError();
 }
 
 hipError_t launch_bwd3d_fp32c(const BwdArgs& a, hipStream_t s) {
-  dim3 grid((unsigned)((a.nf + kTileFB32 - 1) / kTileFB32), (unsigned)a.qsplits);
-  bwd3d_fp32c_kernel<<<grid, kBlock, 0, s>>>(a);
+  const int64_t blocks = (a.nf + kTileFB32 - 1) / kTileFB32 * a.qsplits;
+  if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+  bwd3d_fp32c_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 
