@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpft.so")
 
-SOURCES = ["api.cpp", "prologue.hip", "fwd3d.hip", "bwd3d.hip", "fwd2d.hip", "batch.hip", "qorder.hip", "orient.hip",
+SOURCES = ["api.cpp", "prologue.hip", "fwd3d.hip", "fwd3d_list.hip", "bwd3d.hip", "fwd2d.hip", "batch.hip", "qorder.hip", "orient.hip",
            "fwdpoly.hip", "dq3d.hip", "loss.hip", "noalloc.hip"]
 
 ARCH = os.environ.get("PFT_OFFLOAD_ARCH", "gfx950")
@@ -36,11 +36,13 @@ COMMON = [
 ]
 
 
-# Per-source code generation: the FP32C forward's face loop (single-mesh and batched) is scheduled for
-# instruction-level parallelism; measured on MI355X 1.3 % (config 2) and 0.9 % (config 4) faster at the
-# same register use, with bitwise-identical results. The other kernels keep the default scheduler.
+# Per-source code generation: the batched FP32C forward and the list-order single-mesh forward are
+# scheduled for instruction-level parallelism (measured faster than the default scheduler, with the
+# same registers and bitwise-identical results). The edge-sharing single-mesh forward (fwd3d.hip)
+# keeps the default scheduler: with its transcendental instructions grouped per face, the ILP
+# scheduler spilled registers there at the same speed.
 FILE_FLAGS = {
-    "fwd3d.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+    "fwd3d_list.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
     "batch.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
 }
 

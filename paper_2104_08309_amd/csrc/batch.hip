@@ -137,10 +137,12 @@ __global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void 
       float tr[QPT], ti[QPT];
 #pragma unroll
       for (int k = 0; k < QPT; ++k) tr[k] = ti[k] = 0.0f;
+      // transcendentals in one run per face at 2 Q per thread (measured neutral at 1; at 3 the run
+      // would add register pressure to a variant that already spills)
       if (check)
-        fwd_tile_fp32c<QPT, SHARE, true>(tile, nt, qx, qy, qz, ql, small, tr, ti, carry);
+        fwd_tile_fp32c<QPT, SHARE, true, (QPT == 2)>(tile, nt, qx, qy, qz, ql, small, tr, ti, carry);
       else
-        fwd_tile_fp32c<QPT, SHARE, false>(tile, nt, qx, qy, qz, ql, small, tr, ti, carry);
+        fwd_tile_fp32c<QPT, SHARE, false, (QPT == 2)>(tile, nt, qx, qy, qz, ql, small, tr, ti, carry);
 #pragma unroll
       for (int k = 0; k < QPT; ++k) {
         kahan_add(sr[k], cr[k], tr[k]);

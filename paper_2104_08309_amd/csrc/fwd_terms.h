@@ -200,13 +200,22 @@ __device__ __forceinline__ bool sinc_range_test_needed(float qmax, double rho) {
   return (double)qmax * rho * kInv2PiD > 0.999 * (double)kSincPolyMax;
 }
 
+// S = sum_l w_l sinc_l e^{2 pi i t_l} of one face and Q from the carried edge 0 (its sinc c0 and
+// exponential e0) and the new edges 1 and 2, with w_2 = -(w_0 + w_1).
+__device__ __forceinline__ void edge_sum(float w0, float w1, float c0, float c1, float c2, float e0c, float e0s,
+                                         float e1c, float e1s, float e2c, float e2s, float& Sr, float& Si) {
+  const float a0 = w0 * c0, a1 = w1 * c1, a2 = (w0 + w1) * c2;
+  Sr = a0 * e0c + a1 * e1c - a2 * e2c;
+  Si = a0 * e0s + a1 * e1s - a2 * e2s;
+}
+
 // One face record against a thread's NQ Q points: adds each term to tr[k], ti[k]
 // (lanes with small[k] set are left for the caller's small-|Q| path). CHECK:
 // test each edge half-phase against the polynomial sinc's range; anchor: form
 // the origin phase in binary64 even when the face is linked. `cin` holds the
 // previous record's edge 1 (edge 0 of a linked face); the face's own edge 1 goes
 // to `cout` (SHARE only; the two may be the same object).
-template <int NQ, bool SHARE, bool CHECK, class QL>
+template <int NQ, bool SHARE, bool CHECK, bool TC, class QL>
 __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx, const float* qy, const float* qz,
                                                const QL& ql, const bool* small, float* tr,
                                                float* ti, bool anchor, FwdCarry<NQ>& cin, FwdCarry<NQ>& cout) {
@@ -266,25 +275,57 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
   float Sr[NQ], Si[NQ], co[NQ], t1[NQ];
   bool need[NQ];
   bool any = false;
+  if constexpr (TC) {
+    // The face's transcendental instructions back to back. On this target every switch between
+    // transcendental and ordinary vector instructions costs issue cycles, so one run of 5 NQ is cheaper
+    // than the several shorter ones the compiler forms by itself; the scheduling barriers keep it from
+    // interleaving them (at the price of a few more live registers).
+    float t2[NQ], e1c[NQ], e1s[NQ], e2c[NQ], e2s[NQ], rp[NQ];
 #pragma unroll
-  for (int k = 0; k < NQ; ++k) {
-    // t_1 = t_0 - eta_2, t_2 = t_0 + eta_1
-    t1[k] = cin.t[k] - x2[k];
-    const float t2 = cin.t[k] + x1[k];
-    const float e1c = cos_turns(t1[k]), e1s = sin_turns(t1[k]);
-    const float e2c = cos_turns(t2), e2s = sin_turns(t2);
-    // w_l times the edge's sinc; w_2 = -(w_0 + w_1)
-    const float a0 = w0[k] * cin.c[k], a1 = w1[k] * c1[k], a2 = (w0[k] + w1[k]) * c2[k];
-    Sr[k] = a0 * cin.cs[k] + a1 * e1c - a2 * e2c;
-    Si[k] = a0 * cin.sn[k] + a1 * e1s - a2 * e2s;
-    co[k] = QN[k] * rcp_f(P2[k]);
-    // |Q_perp| L < tau or |Q_perp| < tau_rel |Q| (and every pair of an empty face): the series
-    need[k] = P2[k] < fmaf(QN[k], QN[k], f.thr) && !small[k];
-    any |= need[k];
-    if (SHARE) {
-      cout.c[k] = c1[k];
-      cout.cs[k] = e1c;
-      cout.sn[k] = e1s;
+    for (int k = 0; k < NQ; ++k) {
+      // t_1 = t_0 - eta_2, t_2 = t_0 + eta_1
+      t1[k] = cin.t[k] - x2[k];
+      t2[k] = cin.t[k] + x1[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      e1c[k] = cos_turns(t1[k]);
+      e1s[k] = sin_turns(t1[k]);
+      e2c[k] = cos_turns(t2[k]);
+      e2s[k] = sin_turns(t2[k]);
+      rp[k] = rcp_f(P2[k]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      edge_sum(w0[k], w1[k], cin.c[k], c1[k], c2[k], cin.cs[k], cin.sn[k], e1c[k], e1s[k], e2c[k], e2s[k], Sr[k], Si[k]);
+      co[k] = QN[k] * rp[k];
+      // |Q_perp| L < tau or |Q_perp| < tau_rel |Q| (and every pair of an empty face): the series
+      need[k] = P2[k] < fmaf(QN[k], QN[k], f.thr) && !small[k];
+      any |= need[k];
+      if (SHARE) {
+        cout.c[k] = c1[k];
+        cout.cs[k] = e1c[k];
+        cout.sn[k] = e1s[k];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      t1[k] = cin.t[k] - x2[k];
+      const float t2 = cin.t[k] + x1[k];
+      const float e1c = cos_turns(t1[k]), e1s = sin_turns(t1[k]);
+      const float e2c = cos_turns(t2), e2s = sin_turns(t2);
+      edge_sum(w0[k], w1[k], cin.c[k], c1[k], c2[k], cin.cs[k], cin.sn[k], e1c, e1s, e2c, e2s, Sr[k], Si[k]);
+      co[k] = QN[k] * rcp_f(P2[k]);
+      need[k] = P2[k] < fmaf(QN[k], QN[k], f.thr) && !small[k];
+      any |= need[k];
+      if (SHARE) {
+        cout.c[k] = c1[k];
+        cout.cs[k] = e1c;
+        cout.sn[k] = e1s;
+      }
     }
   }
   // one branch per face for the rare lanes that need the series (of any of their NQ points)
@@ -318,19 +359,20 @@ __device__ __forceinline__ void fwd_face_fp32c(const Face32& f, const float* qx,
 // across faces and tiles of one face range (reset it at the range's start).
 // The origin phase is formed in binary64 at every kAnchor-th face of a tile (of kTileF32 faces).
 // Faces go in pairs that pass the carry between two register sets, so no copy
-// of it is needed from one face to the next.
-template <int NQ, bool SHARE, bool CHECK, class QL>
+// of it is needed from one face to the next. TC: each face's transcendental
+// instructions in one run (fwd_face_fp32c).
+template <int NQ, bool SHARE, bool CHECK, bool TC, class QL>
 __device__ __forceinline__ void fwd_tile_fp32c(const Face32* tile, int nt, const float* qx, const float* qy,
                                                const float* qz, const QL& ql,
                                                const bool* small, float* tr, float* ti, FwdCarry<NQ>& c) {
   FwdCarry<NQ> d;
   int j = 0;
   for (; j + 2 <= nt; j += 2) {
-    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j], qx, qy, qz, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
-    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j + 1], qx, qy, qz, ql, small, tr, ti, false, d, c);
+    fwd_face_fp32c<NQ, SHARE, CHECK, TC>(tile[j], qx, qy, qz, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
+    fwd_face_fp32c<NQ, SHARE, CHECK, TC>(tile[j + 1], qx, qy, qz, ql, small, tr, ti, false, d, c);
   }
   if (j < nt) {
-    fwd_face_fp32c<NQ, SHARE, CHECK>(tile[j], qx, qy, qz, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
+    fwd_face_fp32c<NQ, SHARE, CHECK, TC>(tile[j], qx, qy, qz, ql, small, tr, ti, (j % kAnchor) == 0, c, d);
     c = d;
   }
 }

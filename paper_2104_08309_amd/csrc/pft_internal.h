@@ -333,6 +333,7 @@ struct FwdArgs {
 };
 hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s);
+hipError_t launch_fwd3d_fp32c_list(const FwdArgs& a, hipStream_t s);  // list order (fwd3d_list.hip)
 hipError_t launch_fwd3d_finish(const FwdArgs& a, int out_c128, hipStream_t s);
 
 // Closed regions of constant density (dq3d.hip): region j owns the splits

@@ -10,6 +10,9 @@
 // one wave64 instruction occupies at the measured clock, lane operations per CU
 // per cycle at that clock and at the nominal 2.4 GHz. Built with the library's
 // flags (packed FP32 disabled), so each statement is one unpacked instruction.
+// The last two classes issue the same sines and FMAs with the sines in one run or spread out (held in
+// place by scheduling barriers): the difference is the cost of switching between the transcendental
+// unit and ordinary vector instructions.
 //
 // Usage: valu_rates [iters]   (default 4096; prints one line per class)
 #include <hip/hip_runtime.h>
@@ -44,12 +47,63 @@ enum Op {
   kRcp,          // v_rcp_f32
   kMix1to15,     // one v_sin_f32 per 15 v_fmac_f32, on separate chains
   kMix1to13,     // one v_sin_f32 per 13 v_fmac_f32 (the forward's share of transcendentals)
+  kRun6,         // 6 v_sin_f32 in one run, then 90 v_fmac_f32 (scheduling barrier between)
+  kSpread6,      // 6 x (1 v_sin_f32 + 15 v_fmac_f32), each group fenced by a scheduling barrier
   kOpsF32
 };
 
 // Instructions per chain-iteration of each class, counted per thread.
 __host__ __device__ constexpr int ops_per_iter(int op) {
-  return op == kMix1to15 ? kChains : op == kMix1to13 ? kChains - 2 : kChains;
+  return op == kMix1to15 ? kChains : op == kMix1to13 ? kChains - 2 : (op == kRun6 || op == kSpread6) ? 96 : kChains;
+}
+
+// The switch between the transcendental unit and ordinary vector instructions: the same 6 sines and 90
+// FMAs per iteration (6 sine chains, 10 FMA chains), the sines in one run or spread one per 15 FMAs.
+template <int OP>
+__global__ __launch_bounds__(kBlock) void mix_kernel(float* out, unsigned long long* clk, int iters, float) {
+  float t[6], a[10], b[10], c[10];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) t[j] = 1e-3f * (float)(threadIdx.x + j) + 0.1f;
+#pragma unroll
+  for (int j = 0; j < 10; ++j) {
+    a[j] = 1e-3f * (float)(threadIdx.x + j) + 0.1f;
+    b[j] = 0.999f - 1e-5f * (float)(threadIdx.x + j);
+    c[j] = 1e-4f * (float)(j + (threadIdx.x & 3));
+  }
+  const unsigned long long t0 = clock64(), w0 = wall_clock64();
+  for (int i = 0; i < iters; ++i) {
+    if (OP == kRun6) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) t[j] = __builtin_amdgcn_sinf(t[j]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 9; ++r)
+#pragma unroll
+        for (int j = 0; j < 10; ++j) a[j] = fmaf(b[j], c[j], a[j]);
+    } else {
+#pragma unroll
+      for (int g = 0; g < 6; ++g) {
+        t[g] = __builtin_amdgcn_sinf(t[g]);
+#pragma unroll
+        for (int j = 0; j < 15; ++j) {
+          const int q = (g * 15 + j) % 10;
+          a[q] = fmaf(b[q], c[q], a[q]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  const unsigned long long t1 = clock64(), w1 = wall_clock64();
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) s += t[j];
+#pragma unroll
+  for (int j = 0; j < 10; ++j) s += a[j];
+  out[(size_t)blockIdx.x * kBlock + threadIdx.x] = s;
+  if (threadIdx.x == 0) {
+    clk[2 * blockIdx.x] = t1 - t0;
+    clk[2 * blockIdx.x + 1] = w1 - w0;
+  }
 }
 
 template <int OP>
@@ -203,6 +257,8 @@ int main(int argc, char** argv) {
   run(d, "v_rcp_f32", f32_kernel<kRcp>, iters, ops_per_iter(kRcp));
   run(d, "1 v_sin_f32 : 15 v_fmac_f32", f32_kernel<kMix1to15>, iters, ops_per_iter(kMix1to15));
   run(d, "1 v_sin_f32 : 13 v_fmac_f32", f32_kernel<kMix1to13>, iters, ops_per_iter(kMix1to13));
+  run(d, "6 v_sin_f32 in one run + 90 fmac", mix_kernel<kRun6>, iters, ops_per_iter(kRun6));
+  run(d, "6 x (1 v_sin_f32 + 15 fmac)", mix_kernel<kSpread6>, iters, ops_per_iter(kSpread6));
   run(d, "v_fma_f64", f64_kernel<kFma64>, iters, kChains / 2);
   run(d, "v_add_f64", f64_kernel<kAdd64>, iters, kChains / 2);
   CHECK_HIP(hipFree(d.out));
