@@ -178,6 +178,13 @@ std::map<std::string, ProfRec> g_prof;
 #define PFT_TARGET_BLOCKS 16384
 #endif
 constexpr int64_t kTargetBlocks = PFT_TARGET_BLOCKS;  // 64 blocks of 256 threads per CU on 256 CUs: short tails
+#ifndef PFT_TARGET_BLOCKS_F32
+#define PFT_TARGET_BLOCKS_F32 49152
+#endif
+// the same for the FP32C forward's face splits: its blocks of four wavefronts share one Q-tile and exit
+// wavefront by wavefront, and three times as many (shorter) blocks measured 1.5-4 % faster on the larger
+// workloads (2.1M Q x 1e5 faces, 65 536 Q x 81 920 faces); the adjoint keeps kTargetBlocks
+constexpr int64_t kTargetBlocksF32 = PFT_TARGET_BLOCKS_F32;
 #ifndef PFT_MIN_FACES_PER_SPLIT
 #define PFT_MIN_FACES_PER_SPLIT 128
 #endif
@@ -269,16 +276,17 @@ int time_candidates(int n, F run, hipStream_t s, std::vector<float>& ms) {
   return best;
 }
 
-// Face splits of a Q-parallel forward whose blocks hold qtile Q each: about kTargetBlocks blocks, with
-// at least min_faces faces per split.
-void choose_face_splits(int64_t nq, int64_t nf, int64_t qtile, int64_t min_faces, int* splits, int64_t* per) {
+// Face splits of a Q-parallel forward whose blocks hold qtile Q each: about `target` blocks, with at
+// least min_faces faces per split.
+void choose_face_splits(int64_t nq, int64_t nf, int64_t qtile, int64_t min_faces, int64_t target, int* splits,
+                        int64_t* per) {
   if (nf <= 0) {
     *splits = 1;
     *per = 0;
     return;
   }
   const int64_t qblocks = cdiv(nq, qtile);
-  int64_t s = std::max<int64_t>(1, std::min(cdiv(kTargetBlocks, qblocks), cdiv(nf, min_faces)));
+  int64_t s = std::max<int64_t>(1, std::min(cdiv(target, qblocks), cdiv(nf, min_faces)));
   int64_t p = cdiv(cdiv(nf, s), kTileF) * kTileF;
   *per = p;
   *splits = (int)cdiv(nf, p);
@@ -290,7 +298,7 @@ int64_t plan_forward(int64_t nq, int64_t nf, bool c128, int64_t max_partials, Fw
   int splits;
   int64_t per;
   choose_face_splits(nq, nf, c128 ? kBlock : kFwdQTile, c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves,
-                     &splits, &per);
+                     c128 ? kTargetBlocks : kTargetBlocksF32, &splits, &per);
   if (max_partials > 0 && (int64_t)splits * nq > max_partials && nf > 0) {
     const int64_t cap = std::max<int64_t>(1, max_partials / nq);
     per = cdiv(cdiv(nf, cap), kTileF) * kTileF;
@@ -847,12 +855,12 @@ pft_status region_radii(Arena& ar, const int64_t* off, int64_t nreg, const Face6
 }
 
 pft_status plan_regions(Arena& ar, const int64_t* off, int64_t nreg, int64_t nq, int64_t qtile, int64_t min_faces,
-                        RegionPlan& p,
+                        int64_t target, RegionPlan& p,
                         hipStream_t s) {
   const int64_t nf = off[nreg];
   int s0 = 0;
   int64_t per = 0;
-  choose_face_splits(nq, nf, qtile, min_faces, &s0, &per);
+  choose_face_splits(nq, nf, qtile, min_faces, target, &s0, &per);
   if (per <= 0) per = kTileF;
   for (int64_t j = 0; j < nreg; ++j) {
     p.region_split.push_back((int32_t)p.split_face.size());
@@ -1427,7 +1435,8 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   Arena ar(s);
   RegionPlan plan;
   if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : kFwdQTile,
-                           c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves, plan, s)) != PFT_OK) return st;
+                           c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves,
+                           c128 ? kTargetBlocks : kTargetBlocksF32, plan, s)) != PFT_OK) return st;
   MeshInfo* info = ar.get<MeshInfo>(1);
   Face64* f64 = ar.get<Face64>(std::max<int64_t>(nf, 1));
   Face32* f32 = c128 ? nullptr : ar.get<Face32>(std::max<int64_t>(nf, 1));
@@ -1585,8 +1594,8 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
   if (want_q) {
     // dL/dQ (and dL/drho from the same partials): the grad_Q kernel
     RegionPlan plan;
-    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : (int64_t)kBlock * kQPTDQ, kMinFacesPerSplit, plan,
-                             s)) != PFT_OK) return st;
+    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : (int64_t)kBlock * kQPTDQ, kMinFacesPerSplit,
+                             kTargetBlocks, plan, s)) != PFT_OK) return st;
     double2* partial = ar.get<double2>((size_t)std::max(plan.splits, 1) * 4 * nq);
     if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
     DqArgs d;
@@ -1623,7 +1632,8 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
     // dL/drho only: the forward's partials per region
     RegionPlan plan;
     if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : kFwdQTile,
-                           c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves, plan, s)) != PFT_OK) return st;
+                           c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves,
+                           c128 ? kTargetBlocks : kTargetBlocksF32, plan, s)) != PFT_OK) return st;
     Face32* f32 = c128 ? nullptr : ar.get<Face32>(nf);
     double2* partial = ar.get<double2>((size_t)std::max(plan.splits, 1) * nq);
     if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
