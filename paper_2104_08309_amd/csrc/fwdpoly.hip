@@ -220,15 +220,28 @@ __device__ __forceinline__ void poly_tile_fp32c(const FaceP32* fh, const VtxP32*
     for (int m = 1; m <= F.nv; ++m) {
       const VtxP32 ea = V[m - 1];                   // edge m-1 -> m
       const VtxP32 vb = V[m < F.nv ? m : 0];
+      float pb[NQ], x[NQ], c[NQ], big = 0.0f;
 #pragma unroll
       for (int k = 0; k < NQ; ++k) {
-        const float pb = m < F.nv ? s1[k] * vb.ga + s2[k] * vb.de : p0[k];
+        pb[k] = m < F.nv ? s1[k] * vb.ga + s2[k] * vb.de : p0[k];
+        x[k] = pb[k] - pa[k];
+        c[k] = sinc2pi_poly(x[k]);
+        big = fmaxf(big, fabsf(x[k]));
+      }
+      // the sine quotient for this lane's edges beyond the polynomial's range (a lane's value does not
+      // depend on the other lanes of its wavefront)
+      if (__builtin_expect(big > kSincPolyMax, 0)) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) c[k] = sinc2pi_wide(x[k], c[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) {
         const float w = s2[k] * ea.al + s1[k] * ea.be;
-        const float aw = w * sinc2pi_turns(pb - pa[k]);
-        const float t = r[k] + pa[k] + pb;
+        const float aw = w * c[k];
+        const float t = r[k] + pa[k] + pb[k];
         Sr[k] += aw * cos_turns(t);
         Si[k] += aw * sin_turns(t);
-        pa[k] = pb;
+        pa[k] = pb[k];
       }
     }
 #pragma unroll
