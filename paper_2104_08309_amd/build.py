@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpft.so")
 
-SOURCES = ["api.cpp", "prologue.hip", "fwd3d.hip", "fwd3d_list.hip", "bwd3d.hip", "fwd2d.hip", "batch.hip", "qorder.hip", "orient.hip",
+SOURCES = ["api.cpp", "prologue.hip", "fwd3d.hip", "bwd3d.hip", "fwd2d.hip", "batch.hip", "qorder.hip", "orient.hip",
            "fwdpoly.hip", "dq3d.hip", "loss.hip", "noalloc.hip"]
 
 ARCH = os.environ.get("PFT_OFFLOAD_ARCH", "gfx950")
@@ -36,13 +36,11 @@ COMMON = [
 ]
 
 
-# Per-source code generation: the batched FP32C forward and the list-order single-mesh forward are
-# scheduled for instruction-level parallelism (measured faster than the default scheduler, with the
-# same registers and bitwise-identical results). The edge-sharing single-mesh forward (fwd3d.hip)
-# keeps the default scheduler: with its transcendental instructions grouped per face, the ILP
-# scheduler spilled registers there at the same speed.
+# Per-source code generation: the batched FP32C forward's face loop is scheduled for instruction-level
+# parallelism (measured faster than the default scheduler, with the same registers and bitwise-identical
+# results). The single-mesh forward (fwd3d.hip) keeps the default scheduler: at 2 Q per thread it is
+# faster there for both face orders, and the ILP scheduler spilled registers.
 FILE_FLAGS = {
-    "fwd3d_list.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
     "batch.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
 }
 

@@ -297,7 +297,9 @@ void choose_face_splits(int64_t nq, int64_t nf, int64_t qtile, int64_t min_faces
 int64_t plan_forward(int64_t nq, int64_t nf, bool c128, int64_t max_partials, FwdArgs& a) {
   int splits;
   int64_t per;
-  choose_face_splits(nq, nf, c128 ? kBlock : kFwdQTile, c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves,
+  a.qpt = fwd_qpt(nq);
+  choose_face_splits(nq, nf, c128 ? kBlock : fwd_qtile(a.qpt),
+                     c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves,
                      c128 ? kTargetBlocks : kTargetBlocksF32, &splits, &per);
   if (max_partials > 0 && (int64_t)splits * nq > max_partials && nf > 0) {
     const int64_t cap = std::max<int64_t>(1, max_partials / nq);
@@ -1434,7 +1436,7 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   ensure_pool();
   Arena ar(s);
   RegionPlan plan;
-  if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : kFwdQTile,
+  if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : fwd_qtile(fwd_qpt(nq)),
                            c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves,
                            c128 ? kTargetBlocks : kTargetBlocksF32, plan, s)) != PFT_OK) return st;
   MeshInfo* info = ar.get<MeshInfo>(1);
@@ -1473,6 +1475,7 @@ pft_status pft_forward_3d_regions(const void* verts, pft_dtype vdtype, int64_t n
   a.intensity = intensity;
   a.tau0 = c128 ? kTau0F64 : kTauRegion32;
   a.share_edges = ordered ? 1 : 0;
+  a.qpt = fwd_qpt(nq);  // as in plan_regions' Q-tile
   a.split_geo = split_geo;
   if (plan.splits > 0) {
     const char* nm = main_name(true, mode);
@@ -1631,7 +1634,7 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
   } else {
     // dL/drho only: the forward's partials per region
     RegionPlan plan;
-    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : kFwdQTile,
+    if ((st = plan_regions(ar, region_offsets, nreg, nq, c128 ? kBlock : fwd_qtile(fwd_qpt(nq)),
                            c128 ? kMinFacesPerSplit : kMinFacesPerSplit * kFwdSplitWaves,
                            c128 ? kTargetBlocks : kTargetBlocksF32, plan, s)) != PFT_OK) return st;
     Face32* f32 = c128 ? nullptr : ar.get<Face32>(nf);
@@ -1657,6 +1660,7 @@ pft_status pft_backward_3d_regions(const void* verts, pft_dtype vdtype, int64_t 
     a.out = nullptr;
     a.intensity = nullptr;
     a.tau0 = c128 ? kTau0F64 : kTauRegion32;
+    a.qpt = fwd_qpt(nq);  // as in plan_regions' Q-tile
     double* region_R = nullptr;
     double4* split_geo = nullptr;
     if ((st = region_radii(ar, region_offsets, nreg, f64, plan.d_region_split, plan.splits, &region_R, &split_geo, s)) !=

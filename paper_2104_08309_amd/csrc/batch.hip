@@ -79,10 +79,10 @@ __device__ __forceinline__ int64_t wave_next_item(uint32_t* counter) {
 // The FP32C batched forward: every wavefront is an independent worker. It pulls (mesh, Q-tile of 64 QPT
 // Q, face chunk) items from the counter (longest first), holds QPT Q per lane (strided by 64), streams the
 // chunk's faces through its own LDS tile with wavefront-local ordering and writes its binary64 partials;
-// no block barrier anywhere, so a wavefront never waits for the others of its block. QPT = 2 and 3 keep
-// the single-mesh forward's register budget (kFwdWaves waves per SIMD), QPT = 1 one wavefront more.
+// no block barrier anywhere, so a wavefront never waits for the others of its block. QPT = 2 and 3 run
+// at kBatchFwdWaves waves per SIMD, QPT = 1 one wavefront more.
 template <bool SHARE, int QPT>
-__global__ __launch_bounds__(kBlock, QPT >= 2 ? kFwdWaves : kFwdWaves + 1) void batch_fwd_fp32c_kernel(
+__global__ __launch_bounds__(kBlock, QPT >= 2 ? kBatchFwdWaves : kBatchFwdWaves + 1) void batch_fwd_fp32c_kernel(
     const BatchItemFwd* __restrict__ items, int64_t n_items, uint32_t* counter, const Face64* __restrict__ f64,
     const Face32* __restrict__ f32, const void* q, int qdtype, const uint32_t* __restrict__ perm, double2* partial,
     const MeshInfo* __restrict__ info, double tau0) {

@@ -23,24 +23,38 @@ constexpr int kTileF = PFT_TILEF;  // faces staged in LDS per tile (binary64 for
 #endif
 // faces per LDS tile of an FP32C forward wavefront (also the binary64 re-anchoring interval of its carried
 // phases); 6 KiB of records plus 2.25 KiB of Q low parts per wavefront, so the LDS holds more wavefronts
-// than the 4 per SIMD the registers allow
+// than the 5 per SIMD the registers allow
 constexpr int kTileF32 = PFT_TILEF32;
 constexpr int kTileFB = 8;         // faces per block in the binary64 adjoint
 #ifndef PFT_QPT
-#define PFT_QPT 3
+#define PFT_QPT 2
 #endif
-constexpr int kQPT = PFT_QPT;      // Q per thread in the FP32C forward
+#ifndef PFT_QPT_LARGE
+#define PFT_QPT_LARGE 3
+#endif
+#ifndef PFT_FWD_LARGE_NQ
+#define PFT_FWD_LARGE_NQ (1 << 20)
+#endif
+// Q per thread in the FP32C forward: kQPT (5 waves per SIMD) below kFwdLargeNq Q, where the face splits
+// and the tail matter more, kQPTLarge (4 waves per SIMD; fewer face-record reads and per-face branches
+// per pair) from kFwdLargeNq Q on. Each Q's arithmetic is the same in both, so is its value.
+constexpr int kQPT = PFT_QPT;
+constexpr int kQPTLarge = PFT_QPT_LARGE;
+constexpr int64_t kFwdLargeNq = PFT_FWD_LARGE_NQ;
+inline int fwd_qpt(int64_t nq) { return nq >= kFwdLargeNq ? kQPTLarge : kQPT; }
+__host__ __device__ constexpr int fwd_waves(int qpt) { return qpt >= 3 ? 4 : 5; }  // waves per SIMD
 #ifndef PFT_FWD_BLOCK_WAVES
 #define PFT_FWD_BLOCK_WAVES 4
 #endif
 constexpr int kFwdSplitWaves = PFT_FWD_BLOCK_WAVES;  // wavefronts of an FP32C forward block, each on its own faces
 constexpr int kFwdBlock = 64 * kFwdSplitWaves;       // threads of an FP32C forward block
-constexpr int kFwdQTile = 64 * kQPT;                 // Q of an FP32C forward block (shared by its wavefronts)
+__host__ __device__ constexpr int fwd_qtile(int qpt) { return 64 * qpt; }  // Q of an FP32C forward block
 constexpr int kXcds = 8;                             // accelerator dies (each with its own L2) of the target
-#ifndef PFT_FWD_WAVES
-#define PFT_FWD_WAVES 4
+#ifndef PFT_BATCH_FWD_WAVES
+#define PFT_BATCH_FWD_WAVES 4
 #endif
-constexpr int kFwdWaves = PFT_FWD_WAVES;  // waves per SIMD the FP32C forward's registers must allow
+// the same for the batched FP32C forward at 2 and 3 Q per thread (at 1 Q, one wavefront more)
+constexpr int kBatchFwdWaves = PFT_BATCH_FWD_WAVES;
 #ifndef PFT_QPT_BATCH
 #define PFT_QPT_BATCH 1
 #endif
@@ -327,13 +341,13 @@ struct FwdArgs {
   void* intensity;
   double tau0;
   int share_edges = 0;  // FP32C: records are in edge-sharing order (Face32::link), reuse the shared edge's term
+  int qpt = kQPT;       // FP32C: Q per thread (kQPT or kQPTLarge, fwd_qpt), set with the splits
   // [splits] (x, y, z) the centre of the split's region relative to t, w its radius: the small-|Q| test of
   // a split uses that radius and its tetrahedron fan that apex (NULL: the mesh's R, apex t)
   const double4* split_geo = nullptr;
 };
 hipError_t launch_fwd3d_fp64(const FwdArgs& a, hipStream_t s);
 hipError_t launch_fwd3d_fp32c(const FwdArgs& a, hipStream_t s);
-hipError_t launch_fwd3d_fp32c_list(const FwdArgs& a, hipStream_t s);  // list order (fwd3d_list.hip)
 hipError_t launch_fwd3d_finish(const FwdArgs& a, int out_c128, hipStream_t s);
 
 // Closed regions of constant density (dq3d.hip): region j owns the splits
