@@ -190,7 +190,7 @@ constexpr int64_t kTargetBlocksF32 = PFT_TARGET_BLOCKS_F32;
 #endif
 constexpr int64_t kMinFacesPerSplit = PFT_MIN_FACES_PER_SPLIT;
 #ifndef PFT_BATCH_CHUNK_F
-#define PFT_BATCH_CHUNK_F 4096
+#define PFT_BATCH_CHUNK_F 2048
 #endif
 #ifndef PFT_BATCH_CHUNK_Q
 #define PFT_BATCH_CHUNK_Q 65536

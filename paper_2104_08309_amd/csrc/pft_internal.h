@@ -53,10 +53,10 @@ constexpr int kXcds = 8;                             // accelerator dies (each w
 #ifndef PFT_BATCH_FWD_WAVES
 #define PFT_BATCH_FWD_WAVES 4
 #endif
-// the same for the batched FP32C forward at 2 and 3 Q per thread (at 1 Q, one wavefront more)
+// the same for the batched FP32C forward at 3 Q per thread (at 1 and 2 Q, one wavefront more)
 constexpr int kBatchFwdWaves = PFT_BATCH_FWD_WAVES;
 #ifndef PFT_QPT_BATCH
-#define PFT_QPT_BATCH 1
+#define PFT_QPT_BATCH 2
 #endif
 constexpr int kQPTBatch = PFT_QPT_BATCH;  // Q per thread in the batched FP32C forward
 #ifndef PFT_QPTB
