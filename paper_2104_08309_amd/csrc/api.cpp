@@ -190,7 +190,7 @@ constexpr int64_t kTargetBlocksF32 = PFT_TARGET_BLOCKS_F32;
 #endif
 constexpr int64_t kMinFacesPerSplit = PFT_MIN_FACES_PER_SPLIT;
 #ifndef PFT_BATCH_CHUNK_F
-#define PFT_BATCH_CHUNK_F 2048
+#define PFT_BATCH_CHUNK_F 512
 #endif
 #ifndef PFT_BATCH_CHUNK_Q
 #define PFT_BATCH_CHUNK_Q 65536
@@ -1777,9 +1777,11 @@ static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, voi
   }
   // work items: (mesh, Q-tile, face chunk), longest first, for given tile sizes; returns the number of
   // partial slots they need
-  auto make_items = [&](const BatchTiles& t, std::vector<BatchItemFwd>& items, std::vector<int64_t>& q_part,
-                        std::vector<int32_t>& q_chunks) {
-    items.clear();
+  // The mesh's work items as up to four runs of equal-size items (full or last face chunk x full or last
+  // Q-tile), longest items first over all meshes; returns the partial slots and sets n_items.
+  auto make_groups = [&](const BatchTiles& t, std::vector<BatchGroupFwd>& groups, std::vector<int64_t>& q_part,
+                         std::vector<int32_t>& q_chunks, int64_t& n_items) {
+    groups.clear();
     q_part.assign(n, 0);
     q_chunks.assign(n, 1);
     int64_t P = 0;
@@ -1795,25 +1797,40 @@ static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, voi
       }
       q_part[i] = P;
       q_chunks[i] = (int32_t)C;
-      for (int64_t c = 0; c < C; ++c) {
-        for (int64_t t0 = 0; t0 < nqi; t0 += qtile) {
-          BatchItemFwd it;
-          it.mesh = (int32_t)i;
-          it.chunk = (int32_t)c;
-          it.q0 = b->q_offsets[i] + t0;
-          it.nq = (int32_t)std::min<int64_t>(qtile, nqi - t0);
-          it.pad = 0;
-          it.f0 = b->tri_offsets[i] + c * cf;
-          it.nf = nfi > 0 ? std::min<int64_t>(cf, nfi - c * cf) : 0;
-          it.part = P + c * nqi + t0;
-          items.push_back(it);
+      const int64_t T = cdiv(nqi, qtile);
+      // chunks [0, C-1) of cf faces and the last one; Q-tiles [0, T-1) of qtile Q and the last one
+      const int64_t last_nf = nfi > 0 ? nfi - (C - 1) * cf : 0, last_nq = nqi - (T - 1) * qtile;
+      for (int cl = 0; cl < 2 && T > 0; ++cl) {
+        const int64_t c0 = cl == 0 ? 0 : C - 1, nc = cl == 0 ? C - 1 : 1;
+        for (int tl = 0; tl < 2; ++tl) {
+          const int64_t t0 = tl == 0 ? 0 : T - 1, ntq = tl == 0 ? T - 1 : 1;
+          if (nc <= 0 || ntq <= 0) continue;
+          BatchGroupFwd g;
+          g.first = nc * ntq;  // the group's item count until the prefix pass below
+          g.f_base = b->tri_offsets[i] + c0 * cf;
+          g.q_base = b->q_offsets[i] + t0 * qtile;
+          g.part_base = P + c0 * nqi + t0 * qtile;
+          g.part_stride = nqi;
+          g.mesh = (int32_t)i;
+          g.ntq = (int32_t)ntq;
+          g.cf = (int32_t)cf;
+          g.qtile = (int32_t)qtile;
+          g.nf = (int32_t)(cl == 0 ? cf : last_nf);
+          g.nq = (int32_t)(tl == 0 ? qtile : last_nq);
+          groups.push_back(g);
         }
       }
       P += C * nqi;
     }
-    std::stable_sort(items.begin(), items.end(), [](const BatchItemFwd& x, const BatchItemFwd& y) {
-      return x.nf * (int64_t)x.nq > y.nf * (int64_t)y.nq;
+    std::stable_sort(groups.begin(), groups.end(), [](const BatchGroupFwd& x, const BatchGroupFwd& y) {
+      return (int64_t)x.nf * x.nq > (int64_t)y.nf * y.nq;
     });
+    n_items = 0;
+    for (BatchGroupFwd& g : groups) {
+      const int64_t cnt = g.first;
+      g.first = n_items;
+      n_items += cnt;
+    }
     return P;
   };
   BatchTiles chosen;
@@ -1826,18 +1843,19 @@ static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, voi
     key = tune_key("batch_forward", mode, share, n, pairs, p.nf);
     if (!tuned_tiles(key, &chosen))
       for (int qpt : {1, 2, 3})
-        for (int64_t cf : {2048, 4096, 8192}) {
+        for (int64_t cf : {512, 1024, 2048, 4096}) {
           BatchTiles t;
           t.qpt = qpt;
           t.chunk_f = cf;
           cands.push_back(t);
         }
   }
-  std::vector<BatchItemFwd> items;
+  std::vector<BatchGroupFwd> groups;
   std::vector<int64_t> q_part;
   std::vector<int32_t> q_chunks;
-  int64_t Pmax = make_items(chosen, items, q_part, q_chunks);
-  for (const BatchTiles& t : cands) Pmax = std::max(Pmax, make_items(t, items, q_part, q_chunks));
+  int64_t n_items_max = 0;
+  int64_t Pmax = make_groups(chosen, groups, q_part, q_chunks, n_items_max);
+  for (const BatchTiles& t : cands) Pmax = std::max(Pmax, make_groups(t, groups, q_part, q_chunks, n_items_max));
   double2* partial = ar.get<double2>(std::max<int64_t>(Pmax, 1));
   uint32_t* counter = ar.get<uint32_t>(1);
   if (ar.failed) return fail(PFT_ENOMEM, "temporary allocation failed");
@@ -1845,22 +1863,23 @@ static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, voi
   if ((st = build_qorder(ar, b->q, b->qdtype, nq_total, p.d_q_off, n, &perm, s)) != PFT_OK) return st;
   const double tau0 = c128 ? kTau0F64 : kTau0F32;
   auto run = [&](const BatchTiles& t, bool profile) -> pft_status {
-    make_items(t, items, q_part, q_chunks);
-    BatchItemFwd* d_items;
+    int64_t n_items = 0;
+    make_groups(t, groups, q_part, q_chunks, n_items);
+    if (groups.size() > 0x7fffffff || n_items > 0xffffffffLL) return fail(PFT_EINVAL, "too many batch work items");
+    BatchGroupFwd* d_groups;
     int64_t* d_q_part;
     int32_t* d_q_chunks;
     pft_status rs;
-    if ((rs = upload(ar, items, &d_items, s)) != PFT_OK) return rs;
+    if ((rs = upload(ar, groups, &d_groups, s)) != PFT_OK) return rs;
     if ((rs = upload(ar, q_part, &d_q_part, s)) != PFT_OK) return rs;
     if ((rs = upload(ar, q_chunks, &d_q_chunks, s)) != PFT_OK) return rs;
     hipError_t e = launch_zero_u32(counter, 1, s);
     if (e != hipSuccess) return hip_fail(e, "counter reset");
-    const int64_t n_items = (int64_t)items.size();
     const int grid = (int)std::min<int64_t>(std::max<int64_t>(n_items, 1),
                                             (int64_t)num_cus() * batch_fwd_blocks_per_cu(mode, share, t.qpt));
     if (profile) prof_begin("batch_fwd", s);
-    e = launch_batch_fwd(mode, d_items, n_items, counter, p.f64, f32, b->q, b->qdtype, perm, partial, p.info, tau0,
-                         grid, s, share, t.qpt);
+    e = launch_batch_fwd(mode, d_groups, (int)groups.size(), n_items, counter, p.f64, f32, b->q, b->qdtype, perm,
+                         partial, p.info, tau0, grid, s, share, t.qpt);
     if (profile) prof_end("batch_fwd", s);
     if (e != hipSuccess) return hip_fail(e, "batch forward");
     e = launch_batch_fwd_finish(partial, p.d_q_off, n, d_q_part, d_q_chunks, p.info, b->q, b->qdtype, perm, nq_total,

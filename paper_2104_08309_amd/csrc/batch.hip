@@ -1,8 +1,9 @@
 // Batched transform of many independent meshes in one persistent launch.
 //
 // The host cuts every mesh into work items -- (mesh, Q-tile, face chunk) for
-// the forward, (mesh, face tile of <= kTileFB faces, Q chunk) for the adjoint
-// -- and orders them by decreasing cost (longest processing time first). A
+// the forward, described by runs of equal-size items (BatchGroupFwd), (mesh,
+// face tile of <= kTileFB faces, Q chunk) for the adjoint -- and orders them
+// by decreasing cost (longest processing time first). A
 // grid sized to the GPU's resident capacity pulls items from a device counter
 // until the list is exhausted (the FP32C forward per wavefront, the others per
 // block); every puller reaches the exit test on each iteration, so the grid
@@ -24,10 +25,33 @@ __device__ __forceinline__ int64_t next_item(uint32_t* counter, int* slot) {
   return it;
 }
 
+// Work item `idx` of the forward from its group (binary search over the groups' first items; with a
+// wavefront-uniform idx the search runs on scalar loads).
+__device__ __forceinline__ BatchItemFwd group_item(const BatchGroupFwd* __restrict__ g, int n_groups, int64_t idx) {
+  int lo = 0, hi = n_groups;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (g[mid].first <= idx) lo = mid; else hi = mid;
+  }
+  const BatchGroupFwd G = g[lo];
+  const int64_t k = idx - G.first;
+  const int64_t dc = k / G.ntq, dt = k - dc * G.ntq;
+  BatchItemFwd it;
+  it.mesh = G.mesh;
+  it.chunk = 0;
+  it.q0 = G.q_base + dt * G.qtile;
+  it.nq = G.nq;
+  it.pad = 0;
+  it.f0 = G.f_base + dc * G.cf;
+  it.nf = G.nf;
+  it.part = G.part_base + dc * G.part_stride + dt * G.qtile;
+  return it;
+}
+
 // The binary64 batched forward: blocks pull (mesh, Q-tile of kBlock Q, face chunk) items, one Q per
 // thread, the chunk's faces staged through LDS for the whole block.
-__global__ __launch_bounds__(kBlock) void batch_fwd_fp64_kernel(const BatchItemFwd* __restrict__ items,
-                                                               int64_t n_items, uint32_t* counter,
+__global__ __launch_bounds__(kBlock) void batch_fwd_fp64_kernel(const BatchGroupFwd* __restrict__ groups,
+                                                               int n_groups, int64_t n_items, uint32_t* counter,
                                                                const Face64* __restrict__ f64, const void* q,
                                                                int qdtype, const uint32_t* __restrict__ perm,
                                                                double2* partial, const MeshInfo* __restrict__ info,
@@ -37,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void batch_fwd_fp64_kernel(const BatchItemF
   for (;;) {
     const int64_t idx = next_item(counter, &slot);
     if (idx >= n_items) break;
-    const BatchItemFwd it = items[idx];
+    const BatchItemFwd it = group_item(groups, n_groups, idx);
     const int lane = threadIdx.x;
     const int64_t f_end = it.f0 + it.nf;
     const double R = info[it.mesh].R;
@@ -84,7 +108,8 @@ __device__ __forceinline__ int64_t wave_next_item(uint32_t* counter) {
 // outside the face loop; measured 6 % faster on the 512-mesh batch than at kBatchFwdWaves).
 template <bool SHARE, int QPT>
 __global__ __launch_bounds__(kBlock, QPT >= 3 ? kBatchFwdWaves : kBatchFwdWaves + 1) void batch_fwd_fp32c_kernel(
-    const BatchItemFwd* __restrict__ items, int64_t n_items, uint32_t* counter, const Face64* __restrict__ f64,
+    const BatchGroupFwd* __restrict__ groups, int n_groups, int64_t n_items, uint32_t* counter,
+    const Face64* __restrict__ f64,
     const Face32* __restrict__ f32, const void* q, int qdtype, const uint32_t* __restrict__ perm, double2* partial,
     const MeshInfo* __restrict__ info, double tau0) {
   __shared__ Face32 tiles[kBlock / 64][kTileF32];
@@ -95,7 +120,7 @@ __global__ __launch_bounds__(kBlock, QPT >= 3 ? kBatchFwdWaves : kBatchFwdWaves 
   for (;;) {
     const int64_t idx = wave_next_item(counter);
     if (idx >= n_items) break;
-    const BatchItemFwd it = items[idx];
+    const BatchItemFwd it = group_item(groups, n_groups, idx);
     const int64_t f_end = it.f0 + it.nf;
     const MeshInfo& mi = info[it.mesh];
     const double R = mi.R;
@@ -322,15 +347,17 @@ int batch_bwd_blocks_per_cu(int mode) {
   return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
+hipError_t launch_batch_fwd(int mode, const BatchGroupFwd* groups, int n_groups, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const Face32* f32, const void* q, int qdtype, const uint32_t* perm,
                             double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s,
                             bool share, int qpt) {
   if (n_items <= 0) return hipSuccess;
 #define PFT_BATCH_FWD(SH, QP) \
-  batch_fwd_fp32c_kernel<SH, QP><<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, f32, q, qdtype, perm, partial, info, tau0)
+  batch_fwd_fp32c_kernel<SH, QP><<<grid, kBlock, 0, s>>>(groups, n_groups, n_items, counter, f64, f32, q, qdtype, perm, \
+                                                          partial, info, tau0)
   if (mode == PFT_FP64)
-    batch_fwd_fp64_kernel<<<grid, kBlock, 0, s>>>(items, n_items, counter, f64, q, qdtype, perm, partial, info, tau0);
+    batch_fwd_fp64_kernel<<<grid, kBlock, 0, s>>>(groups, n_groups, n_items, counter, f64, q, qdtype, perm, partial, info,
+                                                  tau0);
   else if (share)
     qpt >= 3 ? PFT_BATCH_FWD(true, 3) : qpt == 2 ? PFT_BATCH_FWD(true, 2) : PFT_BATCH_FWD(true, 1);
   else

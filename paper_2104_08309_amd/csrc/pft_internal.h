@@ -484,6 +484,23 @@ struct BatchItemFwd {   // one (mesh, Q-tile, face-chunk) work item
   int64_t nf;           // faces in the chunk
   int64_t part;         // partial slot base (in units of Q): partial[part + Q offset in the tile]
 };
+// A run of equal-size forward work items of one mesh: item k of the group is the (k / ntq)-th of its face
+// chunks and the (k % ntq)-th of its Q-tiles. The host orders the groups by decreasing item size and
+// numbers the items group after group (`first`); a puller finds an item's group by binary search, so the
+// item list itself is never stored.
+struct BatchGroupFwd {
+  int64_t first;        // index of the group's first item in the global work order
+  int64_t f_base;       // first global face of its first chunk
+  int64_t q_base;       // first global Q of its first Q-tile
+  int64_t part_base;    // partial slot of its first item
+  int64_t part_stride;  // partial slots per face chunk (the mesh's Q count)
+  int32_t mesh;
+  int32_t ntq;          // Q-tiles per chunk in the group
+  int32_t cf;           // faces between consecutive chunks
+  int32_t qtile;        // Q between consecutive Q-tiles
+  int32_t nf;           // faces of each item
+  int32_t nq;           // Q of each item
+};
 struct BatchItemBwd {   // one (mesh, face-tile, Q-chunk) work item
   int32_t mesh;
   int32_t qchunk;
@@ -496,7 +513,7 @@ struct BatchItemBwd {   // one (mesh, face-tile, Q-chunk) work item
 };
 int batch_fwd_blocks_per_cu(int mode, bool share = false, int qpt = 1);
 int batch_bwd_blocks_per_cu(int mode);
-hipError_t launch_batch_fwd(int mode, const BatchItemFwd* items, int64_t n_items, uint32_t* counter,
+hipError_t launch_batch_fwd(int mode, const BatchGroupFwd* groups, int n_groups, int64_t n_items, uint32_t* counter,
                             const Face64* f64, const Face32* f32, const void* q, int qdtype, const uint32_t* perm,
                             double2* partial, const MeshInfo* info, double tau0, int grid, hipStream_t s,
                             bool share = false, int qpt = 1);
