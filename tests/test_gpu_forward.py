@@ -233,6 +233,32 @@ def test_config2_full_size_sampled(gpu):
         assert e < tol
 
 
+def test_large_q_instance_both_orders(gpu):
+    """From 2^20 Q on, the FP32C forward holds 3 Q per thread instead of 2 (another kernel instance and
+    other face splits): both face orders against the oracle on a sample, and the same Q evaluated in a
+    list just below the threshold (the 2-Q instance) agree to rounding."""
+    v, t = mg.icosphere(3, 2.0)
+    v = v + np.array([0.2, -0.1, 0.3])
+    rng = np.random.default_rng(21)
+    nq = (1 << 20) + 1000
+    q = np.concatenate([special_q(3.0), mg.q_random_ball(nq - special_q(3.0).shape[0], 6.0, rng)])
+    idx = np.concatenate([np.arange(special_q(3.0).shape[0]), rng.choice(nq, 200, replace=False)])
+    want = O.ft3d(v, t, q[idx].astype(np.float32).astype(np.float64))
+    V, T, Q = dev(v), dev(t, torch.int32), dev(q, torch.float32)
+    step(f"large-Q instance, edge-sharing order ({nq} Q)")
+    Fe = host(pft.forward_3d(V, T, Q, mode="fp32c"))
+    assert np.all(np.isfinite(Fe))
+    assert nrel(Fe[idx], want) < TOL_FP32C
+    step(f"large-Q instance, list order ({nq} Q)")
+    Fl = host(pft.forward_3d(V, T, Q, mode="fp32c", order=None))
+    assert nrel(Fl[idx], want) < TOL_FP32C
+    assert nrel(Fl, Fe) < 2e-6
+    m = (1 << 20) - 1000
+    step(f"2-Q instance on the first {m} of the same Q")
+    Fs = host(pft.forward_3d(V, T, dev(q[:m], torch.float32), mode="fp32c"))
+    assert nrel(Fs, Fe[:m]) < 2e-6
+
+
 def test_config3_full_size_sampled(gpu):
     """Union of 20 balls (~1e5 faces) on the full 128^3 grid (FP32C, c64 + |F|^2); oracle on a sample."""
     cfg = mg.config3()
