@@ -196,6 +196,12 @@ constexpr int64_t kMinFacesPerSplit = PFT_MIN_FACES_PER_SPLIT;
 #define PFT_BATCH_CHUNK_Q 65536
 #endif
 constexpr int64_t kBatchChunkF = PFT_BATCH_CHUNK_F;  // faces per batched forward item
+#ifndef PFT_BATCH_PARTIAL_CAP_MIB
+#define PFT_BATCH_PARTIAL_CAP_MIB 4096
+#endif
+// Device memory the batched forward's partial slots (Q x face chunks, 16 B each) may take: with more, the
+// face chunks are made longer (fewer slots) and tuner candidates beyond it are not tried.
+constexpr int64_t kBatchPartialCapBytes = (int64_t)PFT_BATCH_PARTIAL_CAP_MIB << 20;
 constexpr int64_t kBatchChunkQ = PFT_BATCH_CHUNK_Q;  // Q per batched adjoint item
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -1854,6 +1860,18 @@ static pft_status batch_forward_impl(const pft_mesh_batch* b, pft_mode mode, voi
   std::vector<int64_t> q_part;
   std::vector<int32_t> q_chunks;
   int64_t n_items_max = 0;
+  {  // keep the partial slots within kBatchPartialCapBytes: longer chunks for the choice, fewer candidates
+    int64_t max_nf = 1;
+    for (int64_t i = 0; i < n; ++i) max_nf = std::max<int64_t>(max_nf, b->tri_offsets[i + 1] - b->tri_offsets[i]);
+    const int64_t cap_slots = kBatchPartialCapBytes / (int64_t)sizeof(double2);
+    while (make_groups(chosen, groups, q_part, q_chunks, n_items_max) > cap_slots && chosen.chunk_f < max_nf)
+      chosen.chunk_f *= 2;
+    cands.erase(std::remove_if(cands.begin(), cands.end(),
+                               [&](const BatchTiles& t) {
+                                 return make_groups(t, groups, q_part, q_chunks, n_items_max) > cap_slots;
+                               }),
+                cands.end());
+  }
   int64_t Pmax = make_groups(chosen, groups, q_part, q_chunks, n_items_max);
   for (const BatchTiles& t : cands) Pmax = std::max(Pmax, make_groups(t, groups, q_part, q_chunks, n_items_max));
   double2* partial = ar.get<double2>(std::max<int64_t>(Pmax, 1));
