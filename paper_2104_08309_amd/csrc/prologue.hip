@@ -22,49 +22,66 @@ __device__ inline void load_vertex(const void* verts, int vdtype, int dim, int64
   }
 }
 
-// One block per mesh: t = vertex mean, R = max |v - t|. Fixed reduction order.
-__global__ __launch_bounds__(256) void mesh_info_kernel(const void* verts, int vdtype, int dim, int64_t nv_single,
-                                                        const int64_t* vert_off, MeshInfo* info) {
-  __shared__ double red[256][3];
+// One block of kInfoBlock threads per mesh: t = vertex mean, R = max |v - t|. Each thread takes every
+// kInfoBlock-th vertex; the per-thread values are combined by a fixed butterfly within each wavefront and
+// then wavefront by wavefront in order, so the result does not depend on timing.
+constexpr int kInfoBlock = 1024;
+
+__device__ __forceinline__ double info_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double info_wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(kInfoBlock) void mesh_info_kernel(const void* verts, int vdtype, int dim,
+                                                              int64_t nv_single, const int64_t* vert_off,
+                                                              MeshInfo* info) {
+  constexpr int kWaves = kInfoBlock / 64;
+  __shared__ double red[kWaves][3];
   const int64_t mesh = blockIdx.x;
   const int64_t v0 = vert_off ? vert_off[mesh] : 0;
   const int64_t v1 = vert_off ? vert_off[mesh + 1] : nv_single;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double s[3] = {0.0, 0.0, 0.0};
-  for (int64_t i = v0 + tid; i < v1; i += blockDim.x) {
+  for (int64_t i = v0 + tid; i < v1; i += kInfoBlock) {
     double p[3] = {0.0, 0.0, 0.0};
     load_vertex(verts, vdtype, dim, i, p);
     for (int k = 0; k < 3; ++k) s[k] += p[k];
   }
-  for (int k = 0; k < 3; ++k) red[tid][k] = s[k];
+  for (int k = 0; k < 3; ++k) s[k] = info_wave_sum(s[k]);
+  if (lane == 0)
+    for (int k = 0; k < 3; ++k) red[w][k] = s[k];
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w)
-      for (int k = 0; k < 3; ++k) red[tid][k] += red[tid + w][k];
-    __syncthreads();
-  }
   const int64_t n = v1 - v0;
   double t[3];
-  for (int k = 0; k < 3; ++k) t[k] = n > 0 ? red[0][k] / (double)n : 0.0;
-  __syncthreads();
+  for (int k = 0; k < 3; ++k) {
+    double a = 0.0;
+    for (int u = 0; u < kWaves; ++u) a += red[u][k];
+    t[k] = n > 0 ? a / (double)n : 0.0;
+  }
+  __syncthreads();  // every thread has read the sums before red is reused
   double r2 = 0.0;
-  for (int64_t i = v0 + tid; i < v1; i += blockDim.x) {
+  for (int64_t i = v0 + tid; i < v1; i += kInfoBlock) {
     double p[3] = {0.0, 0.0, 0.0};
     load_vertex(verts, vdtype, dim, i, p);
     double d2 = 0.0;
     for (int k = 0; k < dim; ++k) d2 += (p[k] - t[k]) * (p[k] - t[k]);
     r2 = fmax(r2, d2);
   }
-  red[tid][0] = r2;
+  r2 = info_wave_max(r2);
+  if (lane == 0) red[w][0] = r2;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid][0] = fmax(red[tid][0], red[tid + w][0]);
-    __syncthreads();
-  }
   if (tid == 0) {
+    double r = 0.0;
+    for (int u = 0; u < kWaves; ++u) r = fmax(r, red[u][0]);
     MeshInfo m;
     for (int k = 0; k < 3; ++k) m.t[k] = t[k];
-    m.R = sqrt(red[0][0]);
+    m.R = sqrt(r);
     m.rho = 0.0;  // raised by the face prologue
     m.pad = 0.0;
     info[mesh] = m;
@@ -527,13 +544,13 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_mesh_info(const void* verts, int vdtype, const int64_t* d_vert_off, int64_t n_meshes,
                             MeshInfo* info, hipStream_t s) {
-  mesh_info_kernel<<<(unsigned)n_meshes, 256, 0, s>>>(verts, vdtype, 3, 0, d_vert_off, info);
+  mesh_info_kernel<<<(unsigned)n_meshes, kInfoBlock, 0, s>>>(verts, vdtype, 3, 0, d_vert_off, info);
   return hipGetLastError();
 }
 
 hipError_t launch_mesh_info_single(const void* verts, int vdtype, int dim, int64_t nv, MeshInfo* info,
                                    hipStream_t s) {
-  mesh_info_kernel<<<1, 256, 0, s>>>(verts, vdtype, dim, nv, nullptr, info);
+  mesh_info_kernel<<<1, kInfoBlock, 0, s>>>(verts, vdtype, dim, nv, nullptr, info);
   return hipGetLastError();
 }
 
@@ -591,7 +608,7 @@ hipError_t launch_face64_batch(const void* verts, int vdtype, const int32_t* tri
 
 hipError_t launch_edges2d(const double* verts, int64_t nv, const int64_t* d_off, int64_t ncont, MeshInfo* info,
                           Edge2D* edges, hipStream_t s) {
-  mesh_info_kernel<<<1, 256, 0, s>>>(verts, PFT_F64, 2, nv, nullptr, info);
+  mesh_info_kernel<<<1, kInfoBlock, 0, s>>>(verts, PFT_F64, 2, nv, nullptr, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || nv <= 0) return e;
   edges2d_kernel<<<grid_for(nv), 256, 0, s>>>(verts, nv, d_off, ncont, info, edges);
