@@ -88,10 +88,12 @@ constexpr double kTauB32 = 1.5;      // (record field of the FP32C adjoint; empt
 #endif
 constexpr double kSeriesMaxPhase = PFT_SERIES_MAX_PHASE;
 // Truncation bound of that binary32 series: terms stop once m^n / n! < tol, which
-// bounds the next term by tol / 6, about 1e-7 of sums of order 1/6 (binary32
-// resolution; a tighter bound only adds terms).
+// bounds the next term by tol / 6, about 1e-6 of sums of order 1/6 (a few binary32
+// units; each pair's weights enter sums over many faces, and the gradient's error
+// against the binary64 form measured the same at 1e-7 and 1e-6, with 5 % fewer
+// instructions at 1e-6).
 #ifndef PFT_SERIES_TOL32
-#define PFT_SERIES_TOL32 1e-7f
+#define PFT_SERIES_TOL32 1e-6f
 #endif
 constexpr float kSeriesTol32 = PFT_SERIES_TOL32;
 constexpr double kTauRelB32 = 0.05;  // adjoint, FP32C mode, relative test
