@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 #              (cross and dot products with Q, three edge sincs, two half-vertex phases, the
 #              face-origin phase, the complex products and the accumulation); the kernel's edge sharing
 #              and polynomial sinc do less work for the same result, which this count credits;
-#   adjoint  = 181.5 flop (counted): on this workload every pair takes the adjoint's barycentric-series
+#   adjoint  = 165.8 flop (counted): on this workload every pair takes the adjoint's barycentric-series
 #              branch (largest centred vertex phase 2.07 < 3), whose operation count depends on the
 #              number of terms, so the basis is the hardware count of the FP32, transcendental and FP64
 #              operations the adjoint kernel executes per pair here (SQ_INSTS_VALU_FLOPS_FP32, _TRANS
@@ -43,7 +43,7 @@ sys.path.insert(0, ROOT)
 #              the corner-weighted moment vector (42) and the accumulation of A
 #              and B (32).
 FLOP_FWD = 104.0
-FLOP_BWD = 181.5
+FLOP_BWD = 165.8
 FLOP_DQ = 246.0
 FLOP_2D = 21.0    # per edge-Q pair of the 2D edge sum (binary64)
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (AMD published)
