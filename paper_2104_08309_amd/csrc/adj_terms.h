@@ -3,6 +3,7 @@
 // kernels. The formulas are stated at the top of bwd3d.hip.
 #pragma once
 
+#include "moment_poly.h"
 #include "pft_device.h"
 
 namespace pft {
@@ -88,6 +89,91 @@ PFT_HD __forceinline__ void bary_moments(T d0, T d1, T m, T tol, T* yr, T* yi, T
   }
   yr[0] = y0r; yi[0] = y0i;
   yr[1] = y1r; yi[1] = y1i;
+}
+
+// The same moments in binary32 from a polynomial q(x) = sum_n i^n a_n x^n of exp(ix)
+// fitted on [-M, M] (moment_poly.h): J = sum_n i^n a_n n! H_n / (n+2)! and
+// Y_k = sum_n i^n a_n n! h_n(d0, d1, d2, d_k) / (n+3)!, exact for q, so the error is
+// the simplex average of q - exp(ix) at phases within [-M, M] (J within err/2, Y_k
+// within err/6) for every lane with max |d_k| <= M. The degree is fixed by P.
+template <class P>
+__device__ __forceinline__ void bary_moments_poly(float d0, float d1, float* yr, float* yi, float& jr, float& ji) {
+  static_assert(P::N >= 5, "the first five terms are written out");
+  const float d2 = -d0 - d1;
+  const float e2 = d0 * d1 + d2 * (d0 + d1);
+  const float e3 = d0 * d1 * d2;
+  // n = 0..4 written out: H_0 = 1, H_1 = 0, H_2 = -e2, H_3 = e3, H_4 = e2^2
+  const float H2 = -e2, H3 = e3, H4 = e2 * e2;
+  float a0 = d0, a1 = d1;  // h_1(d0,d1,d2,d_k) = d_k (H_1 = 0)
+  float y0r = P::cy[0], y1r = P::cy[0];
+  jr = P::cj[0];
+  float y0i = P::cy[1] * a0, y1i = P::cy[1] * a1;
+  a0 = H2 + d0 * a0;
+  a1 = H2 + d1 * a1;
+  y0r -= P::cy[2] * a0;
+  y1r -= P::cy[2] * a1;
+  jr -= P::cj[2] * H2;
+  a0 = H3 + d0 * a0;
+  a1 = H3 + d1 * a1;
+  y0i -= P::cy[3] * a0;
+  y1i -= P::cy[3] * a1;
+  ji = -P::cj[3] * H3;
+  a0 = H4 + d0 * a0;
+  a1 = H4 + d1 * a1;
+  y0r += P::cy[4] * a0;
+  y1r += P::cy[4] * a1;
+  jr += P::cj[4] * H4;
+  float Hm3 = H2, Hm2 = H3, Hm1 = H4;  // H_{n-3}, H_{n-2}, H_{n-1} at n = 5
+#pragma unroll
+  for (int n = 5; n <= P::N; ++n) {
+    const float H = -e2 * Hm2 + e3 * Hm3;
+    a0 = H + d0 * a0;
+    a1 = H + d1 * a1;
+    const float c3 = P::cy[n], c2 = P::cj[n];
+    // i^n cycles (+i, -1, -i, +1) over n = 1, 2, 3, 0 (mod 4)
+    if ((n & 3) == 1) {
+      y0i += c3 * a0; y1i += c3 * a1; ji += c2 * H;
+    } else if ((n & 3) == 2) {
+      y0r -= c3 * a0; y1r -= c3 * a1; jr -= c2 * H;
+    } else if ((n & 3) == 3) {
+      y0i -= c3 * a0; y1i -= c3 * a1; ji -= c2 * H;
+    } else {
+      y0r += c3 * a0; y1r += c3 * a1; jr += c2 * H;
+    }
+    Hm3 = Hm2;
+    Hm2 = Hm1;
+    Hm1 = H;
+  }
+  yr[0] = y0r; yi[0] = y0i;
+  yr[1] = y1r; yi[1] = y1i;
+}
+
+// Binary32 moments for the lanes that take the series branch (max |d_k| = m <= 3):
+// the wavefront takes the lowest-degree polynomial whose range covers the largest m
+// among its active lanes (a wavefront-uniform choice, so no lane waits on another's
+// branch), after at most three comparisons.
+static_assert(kSeriesMaxPhase <= kMomentPolyMaxPhase, "the series branch must stay within the fitted range");
+__device__ __forceinline__ void bary_moments_f32(float d0, float d1, float m, float* yr, float* yi, float& jr,
+                                                 float& ji) {
+  static_assert(kMomentPolyBuckets == 7, "the dispatch below names seven polynomials");
+  if (__any(m > MomentPoly3::M)) {
+    if (__any(m > MomentPoly5::M))
+      bary_moments_poly<MomentPoly6>(d0, d1, yr, yi, jr, ji);
+    else if (__any(m > MomentPoly4::M))
+      bary_moments_poly<MomentPoly5>(d0, d1, yr, yi, jr, ji);
+    else
+      bary_moments_poly<MomentPoly4>(d0, d1, yr, yi, jr, ji);
+  } else if (__any(m > MomentPoly1::M)) {
+    if (__any(m > MomentPoly2::M))
+      bary_moments_poly<MomentPoly3>(d0, d1, yr, yi, jr, ji);
+    else
+      bary_moments_poly<MomentPoly2>(d0, d1, yr, yi, jr, ji);
+  } else {
+    if (__any(m > MomentPoly0::M))
+      bary_moments_poly<MomentPoly1>(d0, d1, yr, yi, jr, ji);
+    else
+      bary_moments_poly<MomentPoly0>(d0, d1, yr, yi, jr, ji);
+  }
 }
 
 // Edge form of the barycentric moments (|Q.(v - g)| beyond the series range):
@@ -290,10 +376,10 @@ __device__ __forceinline__ void adj_term_fp32c(const Face32B& f, float qx, float
   const float m = fmaxf(fabsf(q0), fmaxf(fabsf(q1), fabsf(q2)));
   // (an empty face has an all-zero record: m = 0, finite weights, times N = 0 later)
   if (m <= (float)kSeriesMaxPhase) {
-    // barycentric moments by their series in binary32 (terms decrease from the
-    // start for |delta| <= 3; no cancellation with the face's size in Q)
+    // barycentric moments in binary32 from the fitted polynomial of exp(ix) (every
+    // term is bounded for |delta| <= 3; no cancellation with the face's size in Q)
     float yr[2], yi[2], jr, ji;
-    bary_moments<float, 29>(q0, q1, m, kSeriesTol32, yr, yi, jr, ji);
+    bary_moments_f32(q0, q1, m, yr, yi, jr, ji);
     R[0] = zr * yr[0] - zi * yi[0];
     R[1] = zr * yr[1] - zi * yi[1];
     R[2] = (zr * jr - zi * ji) - R[0] - R[1];

@@ -10,7 +10,9 @@
 //
 // Writing Bt_k = B_{m,k} / |N_m| = exp(iQ.g) Y_k, Y_k is evaluated either
 //  (series)    Y_k = sum_n i^n h_n(delta_a, delta_b, delta_c, delta_k) / (n+3)!,
-//              the barycentric moment of the simplex (node k doubled), or
+//              the barycentric moment of the simplex (node k doubled); the binary32
+//              form replaces 1/n! by the coefficients of a polynomial of exp(ix)
+//              fitted on the lanes' phase range and stops at its degree, or
 //  (edge form) from lambda_k = 1/3 + beta_k.(r - g), beta_k = N x d_{k+1} / |N|^2,
 //              and the centred face integral J_c = i |N| S / |P|^2 differentiated in Q:
 //              |P|^2 Y_k = (i/2) S + sum_l (d_{k+1}.d_l) sinc_l e_l

@@ -80,22 +80,14 @@ constexpr double kTauF64 = 0.05;     // forward and adjoint, FP64 mode
 constexpr double kTauF32 = 0.1;      // forward, FP32C mode (series in FP64)
 constexpr double kTauRel32 = 0.02;   // forward, FP32C mode, relative test
 constexpr double kTauB32 = 1.5;      // (record field of the FP32C adjoint; empty-face flag)
-// The adjoint evaluates each face's barycentric moments by their series when the
+// The adjoint evaluates each face's barycentric moments by their series (binary64)
+// or by a polynomial of exp(ix) fitted on [-3, 3] (binary32, moment_poly.h) when the
 // largest centred vertex phase |Q.(v_k - g)| is at most this, by the
 // differentiated edge sums otherwise (there |Q_perp| L > 4.5).
 #ifndef PFT_SERIES_MAX_PHASE
 #define PFT_SERIES_MAX_PHASE 3.0
 #endif
 constexpr double kSeriesMaxPhase = PFT_SERIES_MAX_PHASE;
-// Truncation bound of that binary32 series: terms stop once m^n / n! < tol, which
-// bounds the next term by tol / 6, about 1e-6 of sums of order 1/6 (a few binary32
-// units; each pair's weights enter sums over many faces, and the gradient's error
-// against the binary64 form measured the same at 1e-7 and 1e-6, with 5 % fewer
-// instructions at 1e-6).
-#ifndef PFT_SERIES_TOL32
-#define PFT_SERIES_TOL32 1e-6f
-#endif
-constexpr float kSeriesTol32 = PFT_SERIES_TOL32;
 constexpr double kTauRelB32 = 0.05;  // adjoint, FP32C mode, relative test
 // Whole-mesh series (fan of tetrahedra from the vertex mean) when |Q| R < tau0.
 constexpr double kTau0F64 = 0.01;
