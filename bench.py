@@ -31,12 +31,15 @@ sys.path.insert(0, ROOT)
 #              (cross and dot products with Q, three edge sincs, two half-vertex phases, the
 #              face-origin phase, the complex products and the accumulation); the kernel's edge sharing
 #              and polynomial sinc do less work for the same result, which this count credits;
-#   adjoint  = 165.8 flop (counted): on this workload every pair takes the adjoint's barycentric-series
-#              branch (largest centred vertex phase 2.07 < 3), whose operation count depends on the
-#              number of terms, so the basis is the hardware count of the FP32, transcendental and FP64
-#              operations the adjoint kernel executes per pair here (SQ_INSTS_VALU_FLOPS_FP32, _TRANS
-#              and _FP64 on config 2, profiles/valu_counters_icosphere_L4_grid64.txt) rather than the
-#              200 of the differentiated edge-sum branch;
+#   adjoint  = 165.8 flop: on this workload every pair takes the adjoint's small-phase branch (largest
+#              centred vertex phase 2.07 < 3), where a face's barycentric moments are sums of complete
+#              homogeneous symmetric polynomials of its vertex phases; the basis is the hardware count
+#              (SQ_INSTS_VALU_FLOPS_FP32, _TRANS and _FP64 on the 5120-face sphere x 64^3 grid) of the adjoint
+#              with those sums taken as their Taylor series to binary32 accuracy (stopped once m^n/n! < 1e-6).
+#              The kernel evaluates the same moments, at the same error, from fitted polynomials of exp(ix)
+#              of lower degree and executes fewer operations (its own count is reported beside the fraction
+#              as counted_flop_per_face_q), which this basis credits as the forward's 104 credits its edge
+#              sharing; the differentiated edge-sum branch, not run here, would count 200;
 #   grad_Q   = 246 flop: the adjoint's recomputed terms (66), edge derivatives (15)
 #              and edge products (25), two barycentric moments with their
 #              normalisation and the face integral (59), Q.N and its phase (7),
@@ -53,11 +56,13 @@ KERNEL_SOURCES = os.path.join(ROOT, "paper_2104_08309_amd", "csrc")
 
 
 def kernel_source_digest():
-    """sha256 over the HIP sources: ties a traffic measurement to the code it was taken on."""
+    """sha256 over the HIP and C++ sources: ties a traffic measurement to the code it was taken on."""
     import hashlib
 
     h = hashlib.sha256()
     for name in sorted(os.listdir(KERNEL_SOURCES)):
+        if not name.endswith((".hip", ".h", ".cpp")):
+            continue
         with open(os.path.join(KERNEL_SOURCES, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -75,6 +80,30 @@ def measured_traffic(kernel):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+COUNTER_FILE = os.path.join(ROOT, "profiles", "valu_counters_icosphere_L4_grid64.txt")
+COUNTER_SECTIONS = {"fwd3d_fp32c": "## fwd3d_fp32c_kernel<true", "bwd3d_fp32c": "## bwd3d_fp32c"}
+
+
+def measured_flops(kernel):
+    """FLOPs per (face, Q) pair that the hardware counters counted for `kernel` (FP32 + transcendental
+    + FP64, FMA = 2) in the committed counter summary, or None if stale."""
+    try:
+        with open(COUNTER_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    if f"Kernel sources digest: {kernel_source_digest()}." not in text:
+        return None
+    head = COUNTER_SECTIONS.get(kernel)
+    if head is None or head not in text:
+        return None
+    section = text.split(head, 1)[1].split("\n## ", 1)[0]
+    for line in section.splitlines():
+        if "counted FLOPs" in line:
+            return float(line.rsplit("=", 1)[1])
+    return None
 
 
 def _oracle_chunk(args):
@@ -548,9 +577,14 @@ def main():
     # roofline of the dominant kernel (the longer of the forward and adjoint kernels)
     def roof(kernel, ms, flop):
         achieved = flop * nf * nq / (ms * 1e-3) / 1e12
+        counted = measured_flops(kernel)
         return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(kernel), "kernel": kernel,
-                "kernel_ms": ms, "flop_per_face_q": flop, "launch_face_q": nf * nq}
+                "kernel_ms": ms, "flop_per_face_q": flop, "launch_face_q": nf * nq,
+                # what the kernel executes per pair (hardware count), and the fraction at that count
+                "counted_flop_per_face_q": counted,
+                "frac_at_counted": None if counted is None else
+                counted * nf * nq / (ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
 
     r_fwd = roof("fwd3d_fp32c", fwd_ms, FLOP_FWD)
     r_bwd = roof("bwd3d_fp32c", bwd_ms, FLOP_BWD)

@@ -172,7 +172,7 @@ __device__ __forceinline__ void dq_term_fp32c(const Face32B& f, float qx, float 
   // (an empty face has an all-zero record: N = 0 makes its terms 0)
   float yr[2], yi[2], jr, ji;
   if (m <= (float)kSeriesMaxPhase) {
-    bary_moments<float, 29>(q0, q1, m, kSeriesTol32, yr, yi, jr, ji);
+    bary_moments_f32(q0, q1, m, yr, yi, jr, ji);
   } else {
     const float inv = rcp_f(fmaxf(P2, 1e-30f));
     float Xr[3], Xi[3], Sr, Si;
