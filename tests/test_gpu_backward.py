@@ -135,3 +135,39 @@ def test_config4_full_size_sampled_vertices(gpu):
     lhs = got64.sum(axis=0)
     rhs = np.real(np.sum(np.conj(g)[:, None] * 1j * q * F[:, None], axis=0))
     assert np.max(np.abs(lhs - rhs)) < 1e-9 * np.max(np.abs(got64)) * np.sqrt(v.shape[0])
+
+
+def test_fp32c_moment_polynomial_ranges(gpu):
+    """The FP32C adjoint and grad_Q take a face's small-phase moments from a polynomial chosen per
+    wavefront by the largest centred vertex phase m among its lanes. Below 8192 Q the list order is
+    kept, so each block of 64 Q on one |Q| shell makes the wavefronts of one range: shells at
+    |Q| rho = 0.4 ... 2.95 (rho the largest centroid-to-vertex distance) reach every range up to the
+    series/edge switch at m = 3, and a mixed block (small and large |Q| alternating) makes the small
+    lanes run the highest degree. Vertex gradient and dL/dQ against the oracle."""
+    v, t = mg.icosphere(2, 2.0)
+    c = v[t].mean(axis=1)
+    rho_f = np.linalg.norm(v[t] - c[:, None, :], axis=2).max()
+    rng = np.random.default_rng(81)
+    blocks = []
+    for m in (0.4, 0.65, 0.95, 1.3, 1.7, 2.1, 2.6, 2.95):
+        d = rng.normal(size=(128, 3))
+        blocks.append(d / np.linalg.norm(d, axis=1, keepdims=True) * (m / rho_f))
+    d = rng.normal(size=(128, 3))
+    mags = np.where(np.arange(128) % 2 == 0, 0.3, 2.9) / rho_f
+    blocks.append(d / np.linalg.norm(d, axis=1, keepdims=True) * mags[:, None])
+    q = np.concatenate(blocks)
+    g = (rng.normal(size=q.shape[0]) + 1j * rng.normal(size=q.shape[0])).astype(np.complex64)
+    step("moment ranges: vertex adjoint fp32c")
+    e = nrel(run_bwd(v, t, q, g, "fp32c"), O.grad3d(v, t, q, g))
+    print(f"moment ranges: vertex gradient rel err {e:.3e}")
+    assert e < TOL_FP32C
+    step("moment ranges: dL/dQ fp32c")
+    off = np.array([0, t.shape[0]])
+    rho = np.array([1.0])
+    _, _, gq = pft.backward_3d_regions(dev(v, torch.float64), dev(t, torch.int32), off, dev(rho, torch.float64),
+                                       dev(q, torch.float64), dev(g), mode="fp32c", need_verts=False, need_rho=False)
+    torch.cuda.synchronize()
+    want = O.grad3d_regions(v, t, off, rho, q, g)[2]
+    e = nrel(host(gq).astype(np.float64), want)
+    print(f"moment ranges: dL/dQ rel err {e:.3e}")
+    assert e < TOL_FP32C
