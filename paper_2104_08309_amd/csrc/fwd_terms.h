@@ -2,6 +2,7 @@
 // forms, shared by the single-mesh and batched kernels (formulas in pft_device.h).
 #pragma once
 
+#include "moment_poly.h"
 #include "pft_device.h"
 
 namespace pft {
@@ -90,7 +91,8 @@ PFT_HD __forceinline__ void face_term_f64(const Face64& f, const double* Q, doub
 // carried edge is carried too (its sinc and the cosine and sine of its
 // midpoint phase): it depends only on the edge, since the sinc is even.
 // Near-degenerate pairs (Q nearly along the face normal, and empty faces) are
-// replaced by the face's simplex series in binary64.
+// replaced by the face's simplex series (binary32 through a fitted polynomial at
+// small phases, binary64 beyond).
 
 // The FP32C forward sums tau_rel times each face term (Face32::N); partial sums are divided by it once.
 constexpr double kInvSumScale32 = 1.0 / kTauRel32;
@@ -101,19 +103,68 @@ constexpr double kInvSumScale32 = 1.0 / kTauRel32;
 constexpr int kAnchor = PFT_ANCHOR;  // faces between binary64 origin phases in a chain (divides kTileF32)
 static_assert(kTileF32 % kAnchor == 0 && kAnchor % 2 == 0, "anchor interval: even, and divides the face tile");
 
-// Inputs of the binary64 series fix-up for one pair.
+// Inputs of the series fix-up for one pair.
 struct SeriesInputs {
   float p0, p1;  // half-vertex phases psi_0, psi_1 in turns
   float QN;      // Q . N, times whatever factor the caller's sums carry (the term is linear in it)
   float r;       // face origin phase Q.g in turns (any integer offset)
 };
 
-// Q nearly along the face normal: simplex series of the face in binary64,
+// The face integral J = sum_n i^n h_n(d) / (n+2)! (normalised by twice the area) in
+// binary32 from the polynomial P of exp(ix) fitted on [-P::M, P::M]: J = sum_n i^n
+// a_n n! h_n(d) / (n+2)!, within P's fit error / 2 of the exact J for every
+// triangle with max |d_k| <= P::M (the simplex average of the fit error).
+template <class P>
+__device__ __forceinline__ void face_integral_poly(float d0, float d1, float& jr, float& ji) {
+  static_assert(P::N >= 5, "the first five terms are written out");
+  const float d2 = -d0 - d1;
+  const float e2 = d0 * d1 + d2 * (d0 + d1);
+  const float e3 = d0 * d1 * d2;
+  // H_0 = 1, H_1 = 0, H_2 = -e2, H_3 = e3, H_4 = e2^2, H_n = -e2 H_{n-2} + e3 H_{n-3}
+  const float H2 = -e2, H3 = e3, H4 = e2 * e2;
+  jr = P::cj[0] - P::cj[2] * H2;
+  jr += P::cj[4] * H4;
+  ji = -P::cj[3] * H3;
+  float Hm3 = H2, Hm2 = H3, Hm1 = H4;
+#pragma unroll
+  for (int n = 5; n <= P::N; ++n) {
+    const float H = -e2 * Hm2 + e3 * Hm3;
+    const float c = P::cj[n];
+    if ((n & 3) == 1) {
+      ji += c * H;
+    } else if ((n & 3) == 2) {
+      jr -= c * H;
+    } else if ((n & 3) == 3) {
+      ji -= c * H;
+    } else {
+      jr += c * H;
+    }
+    Hm3 = Hm2;
+    Hm2 = Hm1;
+    Hm1 = H;
+  }
+}
+
+// Q nearly along the face normal: the face's simplex series,
 // T = -i (Q.N) exp(i Q.g) sum_n i^n h_n(delta) / (n+2)!, delta_k = 4 pi psi_k,
 // from the binary32 phases of the edge form (their rounding is that of the
-// edge form's own inputs). Terms stop at 1e-10 of the sum, far below binary32
-// resolution.
+// edge form's own inputs). A lane whose largest |delta_k| is within the fitted
+// polynomial's range (always so for |Q_perp| L < 0.1, and for the relative test
+// while 0.02 |Q| rho stays below it) evaluates it in binary32, within 1e-7 of J;
+// a lane beyond it sums the series in binary64 to 1e-10 of the sum. The choice is
+// per lane, so a Q's value does not depend on the other lanes of its wavefront.
 __device__ __forceinline__ void face_series_fp32c(const SeriesInputs& sd, float& Tr, float& Ti) {
+  constexpr float kFourPiF = 12.566370614359172954f;
+  const float d0 = kFourPiF * sd.p0, d1 = kFourPiF * sd.p1;
+  const float m = fmaxf(fabsf(d0), fmaxf(fabsf(d1), fabsf(d0 + d1)));
+  if (m <= FacePoly::M) {
+    float sr, si;
+    face_integral_poly<FacePoly>(d0, d1, sr, si);
+    const float cf = cos_turns(sd.r), sf = sin_turns(sd.r);
+    Tr = sd.QN * (cf * si + sf * sr);
+    Ti = -sd.QN * (cf * sr - sf * si);
+    return;
+  }
   constexpr double kFourPi = 12.566370614359172954;
   const double q0 = kFourPi * (double)sd.p0, q1 = kFourPi * (double)sd.p1;
   double sr, si;

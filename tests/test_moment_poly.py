@@ -126,6 +126,36 @@ def test_moment_error_within_the_bound():
         assert worst_j <= eps / 2 and worst_y <= eps / 6, (M, worst_j, worst_y)
 
 
+def test_face_polynomial():
+    """The forward's near-degenerate face integral: the fit on [-M, M] and J within err/2 of the
+    converged series for triangles whose largest centred phase is at most M."""
+    src = _header()
+    m = re.search(r"struct FacePoly \{\s+static constexpr float M = ([0-9.]+)f;\s+static constexpr int N = (\d+);\s+"
+                  r"static constexpr float cj\[N \+ 1\] = \{([^}]*)\};", src)
+    M, N = float(m.group(1)), int(m.group(2))
+    cj = np.array([float(x.strip().rstrip("f")) for x in m.group(3).split(",")], np.float64)
+    eps = float(re.search(r"kFacePolyErr = ([0-9.e+-]+);", src).group(1))
+    n = np.arange(N + 1)
+    a = cj * np.array([math.factorial(k + 2) / math.factorial(k) for k in n])
+    x = np.linspace(-M, M, 40001)
+    q = sum((1j ** k) * a[k] * x ** k for k in range(N + 1))
+    assert np.max(np.abs(q - np.exp(1j * x))) <= eps
+    rng = np.random.default_rng(8)
+    worst = 0.0
+    for t in range(60):
+        d = rng.normal(size=3)
+        d -= d.mean()
+        d *= M / np.max(np.abs(d)) * (1.0 if t % 3 == 0 else rng.uniform(0.05, 1.0))
+        e2 = d[0] * d[1] + d[2] * (d[0] + d[1])
+        e3 = d[0] * d[1] * d[2]
+        H = [1.0, 0.0, -e2, e3]
+        for k in range(4, N + 1):
+            H.append(-e2 * H[k - 2] + e3 * H[k - 3])
+        J = sum((1j ** k) * cj[k] * H[k] for k in range(N + 1))
+        worst = max(worst, abs(J - _exact(d[0], d[1])[0]))
+    assert worst <= eps / 2, worst
+
+
 def test_exact_moments_against_quadrature():
     """The series the bound is measured against is the simplex average itself."""
     for d in ([0.4, -1.1, 0.7], [2.0, -0.5, -1.5], [0.0, 0.0, 0.0]):
