@@ -167,8 +167,10 @@ __global__ __launch_bounds__(kBlock) void fwdpoly_fp64_kernel(FwdArgs a, PolyArg
 
 // ---------------------------------------------------------------------------
 // FP32-compensated: the vertex loop in binary32 turns (hardware sin / cos),
-// the face origin phase reduced in binary64, the fan series in binary64 from
-// the binary32 phases, Kahan sums across tiles.
+// the face origin phase reduced in binary64, the fan series from the binary32
+// phases (each fan triangle in binary32 through the fitted polynomial of exp(ix)
+// when its centred phases stay within its range, in binary64 otherwise; chosen
+// per lane and triangle), Kahan sums across tiles.
 // ---------------------------------------------------------------------------
 __device__ void poly_series_fp32c(const FaceP32& F, const VtxP32* V, float s1, float s2, float QN, float r,
                                   float& Tr, float& Ti) {
@@ -182,10 +184,21 @@ __device__ void poly_series_fp32c(const FaceP32& F, const VtxP32* V, float s1, f
     const double pc = kFourPi * (double)(s1 * vc.ga + s2 * vc.de);
     const double two_a = ((double)vb.x - v0.x) * ((double)vc.y - v0.y) - ((double)vc.x - v0.x) * ((double)vb.y - v0.y);
     const double qt = (pa + pb + pc) / 3.0;
-    double sr, si;
-    face_series_f64(pa - qt, pb - qt, pc - qt, sr, si, 1e-10);
-    double st, ct;
-    sincos(qt, &st, &ct);
+    const float da = (float)(pa - qt), db = (float)(pb - qt);
+    double sr, si, st, ct;
+    if (fmaxf(fabsf(da), fmaxf(fabsf(db), fabsf(da + db))) <= FacePoly::M && fabs(qt) <= 1.0) {
+      // small phases: binary32 face integral and binary32 sine / cosine of the fan triangle's centroid phase
+      float fr, fi;
+      face_integral_poly<FacePoly>(da, db, fr, fi);
+      const float q32 = (float)qt * kInv2PiF;
+      sr = fr;
+      si = fi;
+      st = sin_turns(q32);
+      ct = cos_turns(q32);
+    } else {
+      face_series_f64(pa - qt, pb - qt, pc - qt, sr, si, 1e-10);
+      sincos(qt, &st, &ct);
+    }
     jr += two_a * (ct * sr - st * si);
     ji += two_a * (ct * si + st * sr);
   }
