@@ -274,3 +274,29 @@ def test_config3_full_size_sampled(gpu):
     print(f"config3 fp32c: rel err {e:.3e}")
     assert e < TOL_FP32C
     assert np.allclose(I[idx], np.abs(F[idx].astype(np.complex128)) ** 2, rtol=1e-5)
+
+
+def test_near_normal_face_series_both_precisions(gpu):
+    """Q within 1 degree of a box face's normal takes the face's simplex series (relative test
+    |Q_perp| < 0.02 |Q.n|). Its centred vertex phases grow like |Q_perp| times the face size: up to
+    |Q| = 20 they stay within the binary32 polynomial's half radian, from |Q| = 80 some lanes take
+    the binary64 series. Each magnitude group against the oracle."""
+    v, t = mg.box(1.0, 1.3, 0.7, origin=(0.3, -0.2, 0.1))
+    rng = np.random.default_rng(83)
+    groups = []
+    for s in (5.0, 20.0, 80.0, 120.0):
+        qs = []
+        for axis in range(3):
+            d = rng.uniform(-0.012, 0.012, size=(64, 3))
+            d[:, axis] = rng.choice([-1.0, 1.0], size=64)
+            qs.append(d / np.linalg.norm(d, axis=1, keepdims=True) * s)
+        groups.append(np.concatenate(qs))
+    q = np.concatenate(groups)
+    want = O.ft3d(v, t, q)
+    step("near-normal series fp32c")
+    got = run(v, t, q, "fp32c")
+    for i, s in enumerate((5.0, 20.0, 80.0, 120.0)):
+        sl = slice(i * 192, (i + 1) * 192)
+        e = nrel(got[sl], want[sl])
+        print(f"|Q| = {s}: rel err {e:.3e}")
+        assert e < TOL_FP32C, s
